@@ -1,0 +1,306 @@
+/*
+ * libmofem - matrix-oriented FEM (MO-FEM) multiterm Sylvester solves on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: M. Frittelli, I. Sgura, "Matrix-oriented FEM formulation for
+ * stationary and time-dependent PDEs on x-normal domains" (arXiv 2109.01173).
+ * Equation numbers below follow the article's sequential numbering.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All floating point data are IEEE float64 ("double").
+ *  - A nodal matrix U has q_s rows (s = base coordinate of the x-normal
+ *    domain, the paper's y) and q_t columns (t = normalised coordinate, the
+ *    paper's x); it is stored row-major and contiguous (leading dimension
+ *    q_t).  Left factors act on s, right factors on t, as in eq. (70).
+ *  - A batch is `batch` such matrices, item b starting at `b * stride`
+ *    elements (stride >= q_s * q_t).
+ *  - Pointers documented "device" must be device memory of the current HIP
+ *    device; "host" pointers are ordinary CPU memory.  Every array argument
+ *    is owned by the caller and must stay valid until the call (or, for
+ *    asynchronous calls, the work queued on `stream`) has finished.
+ *  - Opaque handles (mofem_op_t, mofem_prec_t) are owned by the library:
+ *    created by *_create / *_setup, released by *_destroy.  They hold the
+ *    banded matrices and eigenbases in device memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Device work is queued asynchronously on it; functions that return
+ *    host-side results (iteration counts, residuals) synchronise it.
+ *  - Functions return MOFEM_OK (0) or a negative error code; nothing is
+ *    thrown across the ABI.  mofem_last_error() returns a thread-local,
+ *    human-readable message for the most recent failure on that thread.
+ *
+ * Banded ("DIA") storage of a 1D matrix K of size n x n with half-width kb:
+ *      band[d * n + i] = K[i][i + d - kb],   d = 0 .. 2 kb,   i = 0 .. n-1
+ * with zeros where the column i + d - kb falls outside [0, n).  P_k finite
+ * element matrices have half-width kb = k (lumped P1: kb = 1).
+ */
+#ifndef MOFEM_H
+#define MOFEM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Error codes                                                              */
+/* ------------------------------------------------------------------------ */
+#define MOFEM_OK              0
+#define MOFEM_E_ARG          -1  /* invalid argument (NULL, sizes, flags)     */
+#define MOFEM_E_HIP          -2  /* a HIP runtime call failed                 */
+#define MOFEM_E_NOMEM        -3  /* device or host allocation failed          */
+#define MOFEM_E_BREAKDOWN    -4  /* PCG breakdown: <Q, L(Q)> <= 0 or not finite */
+#define MOFEM_E_MAXIT        -5  /* tolerance not reached within maxit        */
+#define MOFEM_E_UNSUPPORTED  -6  /* valid request the library does not cover  */
+#define MOFEM_E_NOTFINITE    -7  /* NaN or Inf in the input or a residual     */
+#define MOFEM_E_NUMERIC      -8  /* setup failed numerically (matrix not SPD,
+                                    eigen-iteration did not converge)          */
+
+/* Library version as 10000*major + 100*minor + patch. */
+int mofem_version(void);
+
+/* Thread-local message for the last failing call on this thread ("" if none).
+   The pointer stays valid until the next libmofem call on this thread. */
+const char* mofem_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* a0. One-dimensional assembly (host only)                                 */
+/* ------------------------------------------------------------------------ */
+/* Weight functions w(x) for the integrals of Sec. 3.2, eqs. (29)-(31).  The
+   "profile" kinds describe the boundary curve of the x-normal domain,
+   L(x) = p0 + p1 * sin(p2 * x + p3), and its derived weights. */
+enum {
+  MOFEM_W_ONE = 0,          /* w = 1                                         */
+  MOFEM_W_POLY = 1,         /* w = p0 + p1 x + p2 x^2 + p3 x^3               */
+  MOFEM_W_PROFILE = 2,      /* w = L(x)                                      */
+  MOFEM_W_PROFILE_D = 3,    /* w = L'(x)                                     */
+  MOFEM_W_PROFILE_INV = 4,  /* w = 1 / L(x)                                  */
+  MOFEM_W_PROFILE_D2L = 5,  /* w = L'(x)^2 / L(x)                            */
+  MOFEM_W_CALLBACK = 6      /* w = fn(x, ctx)                                */
+};
+typedef double (*mofem_weight_fn)(double x, void* ctx);
+typedef struct {
+  int kind;             /* one of MOFEM_W_*                                   */
+  double p[4];          /* parameters of POLY / PROFILE kinds                 */
+  mofem_weight_fn fn;   /* CALLBACK only                                      */
+  void* ctx;            /* CALLBACK only, passed through                      */
+} mofem_weight;
+
+/* Assemble K_ij = int_{x0}^{x1} psi_i^(di)(x) psi_j^(dj)(x) w(x) dx over a
+   uniform mesh of m_elem elements with P_k Lagrange elements (equispaced
+   element nodes), Sec. 3.1 eq. (23) and Sec. 3.2 eqs. (29)-(31).
+     order   1..4 = P_k with nq-point Gauss-Legendre quadrature per element
+             0    = lumped P1 (Sec. 3.3): the integrand is replaced by its
+                    element-wise linear interpolant, i.e. integrated with the
+                    two-point nodal (trapezoid) rule on each element.
+     di, dj  derivative orders (0 or 1) of the row / column function.
+     w       weight (NULL = 1).   nq  quadrature points (0 = 12; 1..32).
+     band    host output, (2 kb + 1) * n doubles, kb = max(order, 1),
+             n = kb * m_elem + 1, DIA layout above.
+   Errors: MOFEM_E_ARG for order/di/dj/nq/m_elem out of range or NULL band. */
+int mofem_assemble_1d(int order, int m_elem, double x0, double x1, int di, int dj,
+                      const mofem_weight* w, int nq, double* band);
+
+/* Dense generalised symmetric-definite eigen-decomposition (host only),
+   the one-dimensional diagonalisation of Sec. 4, eq. (55), done once per
+   geometry:  K V = M V diag(lam),  V^T M V = I,  lam ascending.
+     K, M   host DIA bands (half-width kb) of symmetric n x n matrices, M
+            positive definite.
+     trim   1 = use rows/columns 1 .. n-2 only (homogeneous Dirichlet),
+            0 = all n.  Let q = n - 2*trim.
+     lam    host output, q doubles.
+     V      host output, q*q doubles, row-major, column j = eigenvector j.
+   Errors: MOFEM_E_NUMERIC if M is not positive definite or the iteration
+   fails to converge; MOFEM_E_ARG on bad sizes. */
+int mofem_geneig_host(int n, int kb, const double* K, const double* M, int trim,
+                      double* lam, double* V);
+
+/* ------------------------------------------------------------------------ */
+/* a2/a3. Multiterm operator  Y = sum_t c_t op(L_t) X op(R_t)               */
+/* ------------------------------------------------------------------------ */
+#define MOFEM_MAX_TERMS 8
+typedef struct {
+  int kb;               /* common band half-width, 1..4                       */
+  int elem_order;       /* k of the P_k matrices (0 = unknown); with k >= 2
+                           and element-structured bands the apply skips the
+                           structural zeros of the left factors              */
+  int n_s, n_t;         /* full node counts of the s and t matrices           */
+  int trim_s, trim_t;   /* 1 = homogeneous Dirichlet: drop first/last node    */
+  int full_input;       /* 0: X is q_s x q_t (the unknowns).
+                           1: X is n_s x n_t (all nodes) and only the rows of
+                           the left and the columns of the right factors are
+                           trimmed - the full-node load of eq. (74).          */
+  int n_terms;          /* 1 .. MOFEM_MAX_TERMS                               */
+  const double* left[MOFEM_MAX_TERMS];   /* host DIA bands, n_s rows          */
+  const double* right[MOFEM_MAX_TERMS];  /* host DIA bands, n_t rows          */
+  int left_transpose[MOFEM_MAX_TERMS];   /* 1 = use L_t^T                     */
+  int right_transpose[MOFEM_MAX_TERMS];  /* 1 = use R_t^T                     */
+  double coef[MOFEM_MAX_TERMS];          /* c_t                               */
+  int scaled[MOFEM_MAX_TERMS];           /* 1 = term is also multiplied by the
+                                            per-item scale s_b of the apply   */
+} mofem_op_desc;
+typedef struct mofem_op_s* mofem_op_t;
+
+/* Upload the operator (eq. (73), (75), (91), (92) or (28) are all of this
+   form).  Copies the host bands; the descriptor may be freed afterwards.
+   q_s = n_s - 2 trim_s, q_t = n_t - 2 trim_t.
+   Errors: MOFEM_E_ARG (sizes, kb, n_terms), MOFEM_E_NOMEM, MOFEM_E_HIP. */
+int mofem_op_create(const mofem_op_desc* desc, mofem_op_t* op);
+int mofem_op_destroy(mofem_op_t op);
+/* Output and input shapes of the operator. */
+int mofem_op_shape(mofem_op_t op, int* q_s, int* q_t, int* in_s, int* in_t);
+
+/* Y_b = sum_t c_t (scaled_t ? s_b : 1) op(L_t) X_b op(R_t) for b < batch.
+     X          device, input items (q_s x q_t, or n_s x n_t if full_input),
+                item b at X + b * in_stride.
+     Y          device, output items q_s x q_t at Y + b * stride.  Must not
+                overlap X.
+     item_scale device [batch] or NULL (s_b = 1).
+     dot_xy     device [batch] or NULL: receives <X_b, Y_b>_F (Frobenius,
+                eq. (77)'s sum(sum(X o Y)); square operators only).
+   Asynchronous on `stream`.  Errors: MOFEM_E_ARG. */
+int mofem_op_apply(mofem_op_t op, const double* X, long long in_stride, double* Y,
+                   long long stride, int batch, const double* item_scale,
+                   double* dot_xy, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* a1/a4. Single-term spectral preconditioner                              */
+/*   P(U) = a Ms U Mt + bs Ks U Mt + bt Ms U Kt + d Ks U Kt                  */
+/*   P^{-1}(R) = V_s ((V_s^T R V_t) ./ D) V_t^T,                             */
+/*   D_ij = a + s_b (bs lam_i + bt mu_j + d lam_i mu_j)                      */
+/* (the reduced spectral solve of Sec. 4, eqs. (55)-(59), applied as the    */
+/*  single-term preconditioner of Sec. 5, eq. (80), and Sec. 6, eq. (95)).   */
+/* ------------------------------------------------------------------------ */
+enum {
+  MOFEM_PREC_F64 = 0,     /* FP64 MFMA transforms                           */
+  MOFEM_PREC_F32 = 1,     /* FP32 MFMA transforms, FP32 intermediates       */
+  MOFEM_PREC_BF16 = 2,    /* BF16 operands, FP32 accumulation               */
+  MOFEM_PREC_BF16X3 = 3   /* split BF16 (hi + lo), three products per term,
+                             FP32 accumulation                              */
+};
+typedef struct {
+  int kb;                       /* band half-width of the four matrices       */
+  int n_s, n_t, trim_s, trim_t; /* as in mofem_op_desc                        */
+  const double* Ks;             /* host DIA bands, symmetric                  */
+  const double* Ms;             /* host DIA bands, symmetric positive definite */
+  const double* Kt;
+  const double* Mt;
+  double alpha, beta_s, beta_t, delta;   /* coefficients of D                 */
+  int precision;                /* MOFEM_PREC_*                               */
+} mofem_prec_desc;
+typedef struct mofem_prec_s* mofem_prec_t;
+
+/* Solve the two generalised eigenproblems in FP64 on the host (once per
+   geometry), upload V_s, V_t and their transposes in FP64 and in the working
+   precision.  Errors: MOFEM_E_ARG, MOFEM_E_NUMERIC, MOFEM_E_NOMEM, MOFEM_E_HIP. */
+int mofem_prec_setup(const mofem_prec_desc* desc, mofem_prec_t* prec);
+int mofem_prec_destroy(mofem_prec_t prec);
+/* Change a, bs, bt, d (e.g. a new gamma, tau or diffusion coefficient)
+   without a new eigen-decomposition. */
+int mofem_prec_set_coeffs(mofem_prec_t prec, double alpha, double beta_s,
+                          double beta_t, double delta);
+/* Change the transform precision (MOFEM_PREC_*) of an existing handle. */
+int mofem_prec_set_precision(mofem_prec_t prec, int precision);
+/* Copy the eigenvalues (host, q_s and q_t doubles; either may be NULL). */
+int mofem_prec_eigenvalues(mofem_prec_t prec, double* lam, double* mu);
+/* Bytes of device workspace mofem_prec_apply needs for `batch` items, for any
+   precision (a workspace stays valid across mofem_prec_set_precision). */
+size_t mofem_prec_workspace_size(mofem_prec_t prec, int batch);
+
+/* Z_b = P^{-1}(R_b) for b < batch (R, Z device, q_s x q_t items, `stride`
+   apart; Z may not overlap R).  item_scale: device [batch] or NULL (s_b).
+   workspace: device, mofem_prec_workspace_size bytes, or NULL to use a
+   buffer the handle allocates on first use and keeps.
+   Asynchronous on `stream`.  Errors: MOFEM_E_ARG, MOFEM_E_NOMEM. */
+int mofem_prec_apply(mofem_prec_t prec, const double* R, double* Z, long long stride,
+                     int batch, const double* item_scale, void* workspace,
+                     size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* a5/a6/a8. MO-PCG (Sec. 5, eqs. (77)-(78)) on a batch of equations        */
+/*           L_b(U_b) = Rhs_b                                               */
+/* ------------------------------------------------------------------------ */
+#define MOFEM_PCG_FLEXIBLE   1u  /* beta = <Z+, R+ - R> / <Z, R> (needed when
+                                    the preconditioner is inexact: BF16)    */
+#define MOFEM_PCG_ZERO_GUESS 2u  /* ignore U on entry, start from 0          */
+#define MOFEM_PCG_TAU_STOP   4u  /* stop when ||R_s|| <= tol ||R_0|| (the rule
+                                    of Sec. 6) instead of tol ||Rhs||         */
+/* Bytes of device workspace mofem_pcg_solve needs. */
+size_t mofem_pcg_workspace_size(mofem_op_t op, mofem_prec_t prec, int batch);
+
+/* Solve every item to   ||Rhs_b - L_b(U_b)||_F <= tol ||Rhs_b||_F   on the
+   FP64 true residual (recomputed at exit; if the recurrence drifted, the
+   solve restarts from the true residual).  The recurrence scalars and all
+   inner products are FP64 on the device; only the preconditioner runs in
+   the handle's precision.
+     Rhs        device, q_s x q_t items at `stride`.
+     U          device, in: initial guess (unless ZERO_GUESS), out: solution.
+     item_scale device [batch] or NULL, passed to op and preconditioner.
+     iters_out, relres_out  host [batch] or NULL.
+   Errors: MOFEM_E_MAXIT (U holds the last iterate, relres_out its true
+   relative residual), MOFEM_E_BREAKDOWN, MOFEM_E_NOTFINITE, MOFEM_E_ARG,
+   MOFEM_E_NOMEM.  Synchronises `stream` once per iteration (a few bytes). */
+int mofem_pcg_solve(mofem_op_t op, mofem_prec_t prec, const double* Rhs, double* U,
+                    long long stride, int batch, const double* item_scale,
+                    double tol, int maxit, unsigned flags, void* workspace,
+                    size_t ws_bytes, int* iters_out, double* relres_out, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* a7. IMEX Euler step (Sec. 6, eqs. (87)-(96); DIB kinetics Sec. 7)        */
+/* ------------------------------------------------------------------------ */
+enum { MOFEM_KIN_NONE = 0, MOFEM_KIN_DIB = 1 };
+typedef struct {
+  mofem_op_t op;        /* L_c = Mass + c * Stiffness: its `scaled` terms are
+                           multiplied by c = d * tau per species             */
+  mofem_prec_t prec;    /* preconditioner of the same split (a = 1, b = c)    */
+  mofem_op_t mass;      /* the one-term right-hand-side operator M3 (.) M     */
+  double tau;           /* time step                                          */
+  double d[2];          /* diffusion coefficient per species                  */
+  int n_species;        /* 1 (heat) or 2 (reaction-diffusion system)          */
+  int kinetics;         /* MOFEM_KIN_*                                        */
+  double kin[10];       /* DIB: rho, A1, A2, B, C, D, alpha, gamma, k2, k3   */
+  double tol;           /* per-step PCG tolerance (relative)                  */
+  int maxit;
+  unsigned flags;       /* MOFEM_PCG_* (ZERO_GUESS is ignored: U^n is the guess) */
+} mofem_imex_desc;
+size_t mofem_imex_workspace_size(const mofem_imex_desc* desc, int batch);
+
+/* Advance `batch` independent instances by one step:
+   U^{n+1} = L_c^{-1}[ Mass(U^n + tau f(U^n, V^n)) ] per species (eqs. (91),
+   (93)), kinetics evaluated explicitly at U^n.
+     state  device, n_species * batch items of q_s x q_t at `stride`, species
+            major: item (sp, b) at state + (sp * batch + b) * stride.
+            Updated in place.
+     iters_out  host [n_species * batch] or NULL.
+   Errors as mofem_pcg_solve. */
+int mofem_imex_step(const mofem_imex_desc* desc, double* state, long long stride,
+                    int batch, void* workspace, size_t ws_bytes, int* iters_out,
+                    void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Kernel tracing                                                           */
+/* ------------------------------------------------------------------------ */
+/* While enabled, every kernel the library launches is bracketed by a pair of
+   HIP events recorded on the launch stream, tagged with a kernel class and
+   the number of batch items the launch processed.  Costs two event records
+   per launch; off by default.  Process-wide and thread-safe. */
+enum {
+  MOFEM_TRACE_BAND = 0,         /* multiterm operator / load (k_band)          */
+  MOFEM_TRACE_GEMM_F64 = 1,     /* one FP64 transform product                  */
+  MOFEM_TRACE_GEMM_BF16X3 = 2,  /* one split-BF16 transform product            */
+  MOFEM_TRACE_GEMM_BF16 = 3,    /* one BF16 transform product                  */
+  MOFEM_TRACE_VEC = 4,          /* PCG vector kernels and reductions           */
+  MOFEM_TRACE_CLASSES = 5
+};
+/* on != 0: discard earlier records and start recording; on == 0: stop. */
+int mofem_trace_enable(int on);
+/* Synchronise the recorded events and return, for one class, the summed
+   kernel time in milliseconds, the number of launches and the summed batch
+   items processed (any pointer may be NULL).  Errors: MOFEM_E_ARG (class). */
+int mofem_trace_read(int cls, double* total_ms, long long* launches, double* items);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MOFEM_H */

@@ -1,0 +1,974 @@
+// C-ABI entry points of libmofem: operator and preconditioner handles, the
+// batched MO-PCG driver (Sec. 5, eqs. (77)-(78)) and the IMEX Euler step
+// (Sec. 6, eqs. (89)-(96); DIB kinetics Sec. 7).
+//
+// Every step of the solve runs in this library's kernels (k_band.hip,
+// k_gemm.hip, k_vec.hip); the host only sequences launches, keeps per-item
+// convergence flags and reads a few bytes of residual norms per iteration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "mofem_internal.h"
+
+using namespace mofem;
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess)                                                              \
+      return fail(MOFEM_E_HIP, std::string("HIP error in ") + #expr + ": " +           \
+                                   hipGetErrorString(_e));                             \
+  } while (0)
+
+namespace {
+
+template <class T>
+int dev_alloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(MOFEM_E_NOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  }
+  return MOFEM_OK;
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// bump allocator over a caller-provided device workspace
+struct Carve {
+  char* base;
+  size_t used = 0, cap;
+  Carve(void* b, size_t c) : base((char*)b), cap(c) {}
+  template <class T>
+  T* take(size_t count) {
+    size_t off = align_up(used, 256);
+    used = off + align_up(count * sizeof(T), 256);
+    return used <= cap ? (T*)(base + off) : nullptr;
+  }
+};
+
+// ---- kernel tracing: HIP event pairs around every launch -------------------
+struct TraceRec {
+  int cls;
+  double items;
+  hipEvent_t e0, e1;
+};
+struct TraceState {
+  std::mutex mu;
+  bool on = false;
+  std::vector<TraceRec> recs;
+  std::vector<hipEvent_t> pool;
+  double total_ms[MOFEM_TRACE_CLASSES] = {};
+  long long launches[MOFEM_TRACE_CLASSES] = {};
+  double items[MOFEM_TRACE_CLASSES] = {};
+};
+TraceState& trace_state() {
+  static TraceState t;
+  return t;
+}
+hipEvent_t trace_event(TraceState& t) {
+  if (!t.pool.empty()) {
+    hipEvent_t e = t.pool.back();
+    t.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+// caller holds the mutex
+void trace_resolve(TraceState& t) {
+  for (TraceRec& r : t.recs) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.e1) == hipSuccess && hipEventElapsedTime(&ms, r.e0, r.e1) == hipSuccess) {
+      t.total_ms[r.cls] += ms;
+      t.launches[r.cls] += 1;
+      t.items[r.cls] += r.items;
+    }
+    t.pool.push_back(r.e0);
+    t.pool.push_back(r.e1);
+  }
+  t.recs.clear();
+}
+// RAII: records e0 now and e1 when the scope (one kernel launch) ends
+struct TraceScope {
+  hipStream_t s;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int cls;
+  double items;
+  TraceScope(int c, double n, hipStream_t st) : s(st), cls(c), items(n) {
+    TraceState& t = trace_state();
+    std::lock_guard<std::mutex> g(t.mu);
+    if (!t.on) return;
+    e0 = trace_event(t);
+    e1 = trace_event(t);
+    if (e0 && e1) (void)hipEventRecord(e0, s);
+  }
+  ~TraceScope() {
+    if (!e0 || !e1) return;
+    TraceState& t = trace_state();
+    std::lock_guard<std::mutex> g(t.mu);
+    (void)hipEventRecord(e1, s);
+    t.recs.push_back({cls, items, e0, e1});
+    if (t.recs.size() > 16384) trace_resolve(t);
+  }
+};
+
+}  // namespace
+
+extern "C" int mofem_trace_enable(int on) {
+  clear_error();
+  TraceState& t = trace_state();
+  std::lock_guard<std::mutex> g(t.mu);
+  if (on) {
+    trace_resolve(t);
+    for (int c = 0; c < MOFEM_TRACE_CLASSES; ++c) {
+      t.total_ms[c] = 0.0;
+      t.launches[c] = 0;
+      t.items[c] = 0.0;
+    }
+  }
+  t.on = on != 0;
+  return MOFEM_OK;
+}
+
+extern "C" int mofem_trace_read(int cls, double* total_ms, long long* launches, double* items) {
+  clear_error();
+  if (cls < 0 || cls >= MOFEM_TRACE_CLASSES) return fail(MOFEM_E_ARG, "trace_read: unknown class");
+  TraceState& t = trace_state();
+  std::lock_guard<std::mutex> g(t.mu);
+  trace_resolve(t);
+  if (total_ms) *total_ms = t.total_ms[cls];
+  if (launches) *launches = t.launches[cls];
+  if (items) *items = t.items[cls];
+  return MOFEM_OK;
+}
+
+// ============================================================================
+// operator
+// ============================================================================
+struct mofem_op_s {
+  int kb = 0, nt = 0, qs = 0, qt = 0, ns_in = 0, nt_in = 0;
+  int off_s = 0, off_t = 0, ph_s = 0, full_input = 0, pattern = 0, scaled_mask = 0;
+  int n_rowblk = 0, n_tiles = 0;
+  double* d_left = nullptr;
+  double* d_right = nullptr;
+  double* d_partial = nullptr;  // dot partials for mofem_op_apply
+  int partial_batch = 0;
+};
+
+static bool element_structured(const std::vector<double>& left, int qs, int nt, int kb, int ph) {
+  const int W = 2 * kb + 1;
+  for (int i = 0; i < qs; ++i) {
+    int g = i + ph;
+    int phase = g % kb;
+    int dlo = phase == 0 ? 0 : kb - phase, dhi = phase == 0 ? 2 * kb : 2 * kb - phase;
+    for (int t = 0; t < nt; ++t)
+      for (int d = 0; d < W; ++d)
+        if ((d < dlo || d > dhi) && left[((size_t)i * nt + t) * W + d] != 0.0) return false;
+  }
+  return true;
+}
+
+extern "C" int mofem_op_create(const mofem_op_desc* desc, mofem_op_t* out) {
+  clear_error();
+  if (!desc || !out) return fail(MOFEM_E_ARG, "op_create: NULL argument");
+  *out = nullptr;
+  const mofem_op_desc& D = *desc;
+  if (D.kb < 1 || D.kb > 4) return fail(MOFEM_E_ARG, "op_create: kb must be 1..4");
+  if (D.n_terms < 1 || D.n_terms > MOFEM_MAX_TERMS || !band_supported_terms(D.n_terms))
+    return fail(MOFEM_E_ARG, "op_create: n_terms must be 1..6");
+  if ((D.trim_s != 0 && D.trim_s != 1) || (D.trim_t != 0 && D.trim_t != 1))
+    return fail(MOFEM_E_ARG, "op_create: trim flags must be 0 or 1");
+  if (D.n_s - 2 * D.trim_s < 1 || D.n_t - 2 * D.trim_t < 1 || D.n_s < D.kb + 1 || D.n_t < D.kb + 1)
+    return fail(MOFEM_E_ARG, "op_create: matrices too small for the band");
+  for (int t = 0; t < D.n_terms; ++t)
+    if (!D.left[t] || !D.right[t]) return fail(MOFEM_E_ARG, "op_create: NULL band");
+
+  const int kb = D.kb, W = 2 * kb + 1, nt = D.n_terms;
+  const int ns = D.n_s, ntt = D.n_t;
+  const int qs = ns - 2 * D.trim_s, qt = ntt - 2 * D.trim_t;
+  std::vector<double> left((size_t)qs * nt * W, 0.0), right((size_t)nt * W * qt, 0.0);
+  int mask = 0;
+  for (int t = 0; t < nt; ++t) {
+    const double* Lb = D.left[t];
+    const double* Rb = D.right[t];
+    const double c = D.coef[t];
+    if (D.scaled[t]) mask |= 1 << t;
+    for (int i = 0; i < qs; ++i) {
+      int gi = i + D.trim_s;
+      for (int d = 0; d < W; ++d) {
+        int ga = gi + d - kb;  // node index of the input row
+        bool ok = D.full_input ? (ga >= 0 && ga < ns) : (ga >= D.trim_s && ga < ns - D.trim_s);
+        if (!ok) continue;
+        double v = D.left_transpose[t] ? Lb[(size_t)(2 * kb - d) * ns + ga] : Lb[(size_t)d * ns + gi];
+        left[((size_t)i * nt + t) * W + d] = c * v;
+      }
+    }
+    for (int j = 0; j < qt; ++j) {
+      int gj = j + D.trim_t;
+      for (int d = 0; d < W; ++d) {
+        int gb = gj + d - kb;  // node index of the input column
+        bool ok = D.full_input ? (gb >= 0 && gb < ntt) : (gb >= D.trim_t && gb < ntt - D.trim_t);
+        if (!ok) continue;
+        // coefficient R[gb][gj] (or R^T[gb][gj] = R[gj][gb])
+        double v = D.right_transpose[t] ? Rb[(size_t)d * ntt + gj] : Rb[(size_t)(2 * kb - d) * ntt + gb];
+        right[((size_t)t * W + d) * qt + j] = v;
+      }
+    }
+  }
+  for (double v : left)
+    if (!std::isfinite(v)) return fail(MOFEM_E_NOTFINITE, "op_create: non-finite band entry");
+  for (double v : right)
+    if (!std::isfinite(v)) return fail(MOFEM_E_NOTFINITE, "op_create: non-finite band entry");
+
+  auto* op = new mofem_op_s();
+  op->kb = kb;
+  op->nt = nt;
+  op->qs = qs;
+  op->qt = qt;
+  op->full_input = D.full_input;
+  op->ns_in = D.full_input ? ns : qs;
+  op->nt_in = D.full_input ? ntt : qt;
+  op->off_s = D.full_input ? D.trim_s : 0;
+  op->off_t = D.full_input ? D.trim_t : 0;
+  op->ph_s = D.trim_s;
+  op->scaled_mask = mask;
+  op->pattern = (D.elem_order >= 2 && D.elem_order == kb && element_structured(left, qs, nt, kb, op->ph_s)) ? 1 : 0;
+  int TI = band_rows_per_block(kb), SW = band_cols_per_block(kb);
+  op->n_rowblk = (qs + op->ph_s + TI - 1) / TI;
+  op->n_tiles = ((qt + SW - 1) / SW) * op->n_rowblk;
+  int rc = dev_alloc(&op->d_left, left.size());
+  if (rc == MOFEM_OK) rc = dev_alloc(&op->d_right, right.size());
+  if (rc != MOFEM_OK) {
+    mofem_op_destroy(op);
+    return rc;
+  }
+  if (hipMemcpy(op->d_left, left.data(), left.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(op->d_right, right.data(), right.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+    mofem_op_destroy(op);
+    return fail(MOFEM_E_HIP, "op_create: upload failed");
+  }
+  *out = op;
+  return MOFEM_OK;
+}
+
+extern "C" int mofem_op_destroy(mofem_op_t op) {
+  if (!op) return MOFEM_OK;
+  if (op->d_left) (void)hipFree(op->d_left);
+  if (op->d_right) (void)hipFree(op->d_right);
+  if (op->d_partial) (void)hipFree(op->d_partial);
+  delete op;
+  return MOFEM_OK;
+}
+
+extern "C" int mofem_op_shape(mofem_op_t op, int* qs, int* qt, int* in_s, int* in_t) {
+  clear_error();
+  if (!op) return fail(MOFEM_E_ARG, "op_shape: NULL handle");
+  if (qs) *qs = op->qs;
+  if (qt) *qt = op->qt;
+  if (in_s) *in_s = op->ns_in;
+  if (in_t) *in_t = op->nt_in;
+  return MOFEM_OK;
+}
+
+namespace {
+int op_launch(mofem_op_t op, const double* X, long long in_stride, double* Y, long long stride, int batch,
+              const double* item_scale, double* partial, const int* active, hipStream_t s,
+              int n_items = -1) {
+  TraceScope trace(MOFEM_TRACE_BAND, n_items < 0 ? batch : n_items, s);
+  BandArgs a{};
+  a.X = X;
+  a.in_stride = in_stride;
+  a.ld_x = op->nt_in;
+  a.Y = Y;
+  a.out_stride = stride;
+  a.ld_y = op->qt;
+  a.qs = op->qs;
+  a.qt = op->qt;
+  a.ns_in = op->ns_in;
+  a.nt_in = op->nt_in;
+  a.off_s = op->off_s;
+  a.off_t = op->off_t;
+  a.ph_s = op->ph_s;
+  a.n_rowblk = op->n_rowblk;
+  a.left = op->d_left;
+  a.right = op->d_right;
+  a.scaled_mask = op->scaled_mask;
+  a.item_scale = item_scale;
+  a.dot_partial = partial;
+  a.n_partial = op->n_tiles;
+  a.active = active;
+  if (launch_band_apply(a, op->kb, op->nt, batch, op->pattern != 0, s) != 0)
+    return fail(MOFEM_E_UNSUPPORTED, "op_apply: unsupported band/term combination");
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(MOFEM_E_HIP, std::string("op_apply launch: ") + hipGetErrorString(e));
+  return MOFEM_OK;
+}
+}  // namespace
+
+extern "C" int mofem_op_apply(mofem_op_t op, const double* X, long long in_stride, double* Y, long long stride,
+                              int batch, const double* item_scale, double* dot_xy, void* stream) {
+  clear_error();
+  if (!op || !X || !Y) return fail(MOFEM_E_ARG, "op_apply: NULL argument");
+  if (batch < 0) return fail(MOFEM_E_ARG, "op_apply: negative batch");
+  if (batch == 0) return MOFEM_OK;
+  if (in_stride < (long long)op->ns_in * op->nt_in || stride < (long long)op->qs * op->qt)
+    return fail(MOFEM_E_ARG, "op_apply: stride smaller than one item");
+  if (dot_xy && op->full_input) return fail(MOFEM_E_ARG, "op_apply: <X, Y> needs a square operator");
+  hipStream_t s = (hipStream_t)stream;
+  double* partial = nullptr;
+  if (dot_xy) {
+    if (op->partial_batch < batch) {
+      if (op->d_partial) {
+        HIP_TRY(hipStreamSynchronize(s));
+        (void)hipFree(op->d_partial);
+        op->d_partial = nullptr;
+      }
+      int rc = dev_alloc(&op->d_partial, (size_t)batch * op->n_tiles);
+      if (rc != MOFEM_OK) return rc;
+      op->partial_batch = batch;
+    }
+    partial = op->d_partial;
+  }
+  int rc = op_launch(op, X, in_stride, Y, stride, batch, item_scale, partial, nullptr, s);
+  if (rc != MOFEM_OK) return rc;
+  if (dot_xy && launch_reduce(partial, op->n_tiles, dot_xy, batch, s) != 0)
+    return fail(MOFEM_E_HIP, "op_apply: reduce launch failed");
+  return MOFEM_OK;
+}
+
+// ============================================================================
+// preconditioner
+// ============================================================================
+struct mofem_prec_s {
+  int qs = 0, qt = 0, ps = 0, pt = 0;  // sizes and padded sizes
+  double alpha = 0, bs = 0, bt = 0, dl = 0;
+  int precision = MOFEM_PREC_F64;
+  std::vector<double> h_lam, h_mu;
+  double* lam = nullptr;
+  double* mu = nullptr;
+  double *Vs = nullptr, *VsT = nullptr, *Vt = nullptr, *VtT = nullptr;  // FP64 padded
+  unsigned short *Vs_h = nullptr, *Vs_l = nullptr, *VsT_h = nullptr, *VsT_l = nullptr;
+  unsigned short *Vt_h = nullptr, *Vt_l = nullptr, *VtT_h = nullptr, *VtT_l = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+};
+
+namespace {
+unsigned short host_bf16(float x) {
+  unsigned u;
+  std::memcpy(&u, &x, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)(u >> 16);  // inf / nan
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+  return (unsigned short)(u >> 16);
+}
+float host_bf16_to_f(unsigned short h) {
+  unsigned u = ((unsigned)h) << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+// padded copy (rows x cols -> pr x pc, zero padding), optionally transposed
+std::vector<double> padded(const std::vector<double>& V, int q, int pr, int pc, bool transpose) {
+  std::vector<double> P((size_t)pr * pc, 0.0);
+  for (int i = 0; i < q; ++i)
+    for (int j = 0; j < q; ++j) P[(size_t)i * pc + j] = transpose ? V[(size_t)j * q + i] : V[(size_t)i * q + j];
+  return P;
+}
+
+int upload_f64(double** d, const std::vector<double>& h) {
+  int rc = dev_alloc(d, h.size());
+  if (rc) return rc;
+  HIP_TRY(hipMemcpy(*d, h.data(), h.size() * 8, hipMemcpyHostToDevice));
+  return MOFEM_OK;
+}
+int upload_split(unsigned short** hi, unsigned short** lo, const std::vector<double>& h) {
+  std::vector<unsigned short> vh(h.size()), vl(h.size());
+  for (size_t i = 0; i < h.size(); ++i) {
+    float f = (float)h[i];
+    unsigned short a = host_bf16(f);
+    vh[i] = a;
+    vl[i] = host_bf16(f - host_bf16_to_f(a));
+  }
+  int rc = dev_alloc(hi, vh.size());
+  if (rc) return rc;
+  rc = dev_alloc(lo, vl.size());
+  if (rc) return rc;
+  HIP_TRY(hipMemcpy(*hi, vh.data(), vh.size() * 2, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(*lo, vl.data(), vl.size() * 2, hipMemcpyHostToDevice));
+  return MOFEM_OK;
+}
+}  // namespace
+
+extern "C" int mofem_prec_destroy(mofem_prec_t p) {
+  if (!p) return MOFEM_OK;
+  void* ptrs[] = {p->lam, p->mu, p->Vs, p->VsT, p->Vt, p->VtT, p->Vs_h, p->Vs_l, p->VsT_h,
+                  p->VsT_l, p->Vt_h, p->Vt_l, p->VtT_h, p->VtT_l, p->ws};
+  for (void* x : ptrs)
+    if (x) (void)hipFree(x);
+  delete p;
+  return MOFEM_OK;
+}
+
+extern "C" int mofem_prec_setup(const mofem_prec_desc* desc, mofem_prec_t* out) {
+  clear_error();
+  if (!desc || !out) return fail(MOFEM_E_ARG, "prec_setup: NULL argument");
+  *out = nullptr;
+  const mofem_prec_desc& D = *desc;
+  if (D.kb < 1 || D.kb > 4) return fail(MOFEM_E_ARG, "prec_setup: kb must be 1..4");
+  if (!D.Ks || !D.Ms || !D.Kt || !D.Mt) return fail(MOFEM_E_ARG, "prec_setup: NULL band");
+  if ((D.trim_s != 0 && D.trim_s != 1) || (D.trim_t != 0 && D.trim_t != 1))
+    return fail(MOFEM_E_ARG, "prec_setup: trim flags must be 0 or 1");
+  if (D.precision < MOFEM_PREC_F64 || D.precision > MOFEM_PREC_BF16X3)
+    return fail(MOFEM_E_ARG, "prec_setup: unknown precision");
+  if (D.precision == MOFEM_PREC_F32) return fail(MOFEM_E_UNSUPPORTED, "prec_setup: FP32 transforms are not built");
+  const int qs = D.n_s - 2 * D.trim_s, qt = D.n_t - 2 * D.trim_t;
+  if (qs < 1 || qt < 1) return fail(MOFEM_E_ARG, "prec_setup: empty matrices");
+
+  auto* p = new mofem_prec_s();
+  p->qs = qs;
+  p->qt = qt;
+  p->ps = pad_up(qs);
+  p->pt = pad_up(qt);
+  p->alpha = D.alpha;
+  p->bs = D.beta_s;
+  p->bt = D.beta_t;
+  p->dl = D.delta;
+  p->precision = D.precision;
+  std::vector<double> Vs((size_t)qs * qs), Vt((size_t)qt * qt);
+  p->h_lam.resize(qs);
+  p->h_mu.resize(qt);
+  int rc = mofem_geneig_host(D.n_s, D.kb, D.Ks, D.Ms, D.trim_s, p->h_lam.data(), Vs.data());
+  if (rc == MOFEM_OK) rc = mofem_geneig_host(D.n_t, D.kb, D.Kt, D.Mt, D.trim_t, p->h_mu.data(), Vt.data());
+  if (rc != MOFEM_OK) {
+    std::string msg = mofem_last_error();
+    mofem_prec_destroy(p);
+    return fail(rc, "prec_setup: " + msg);
+  }
+  auto Vs_p = padded(Vs, qs, p->ps, p->ps, false), VsT_p = padded(Vs, qs, p->ps, p->ps, true);
+  auto Vt_p = padded(Vt, qt, p->pt, p->pt, false), VtT_p = padded(Vt, qt, p->pt, p->pt, true);
+  rc = upload_f64(&p->lam, p->h_lam);
+  if (!rc) rc = upload_f64(&p->mu, p->h_mu);
+  if (!rc) rc = upload_f64(&p->Vs, Vs_p);
+  if (!rc) rc = upload_f64(&p->VsT, VsT_p);
+  if (!rc) rc = upload_f64(&p->Vt, Vt_p);
+  if (!rc) rc = upload_f64(&p->VtT, VtT_p);
+  if (!rc) rc = upload_split(&p->Vs_h, &p->Vs_l, Vs_p);
+  if (!rc) rc = upload_split(&p->VsT_h, &p->VsT_l, VsT_p);
+  if (!rc) rc = upload_split(&p->Vt_h, &p->Vt_l, Vt_p);
+  if (!rc) rc = upload_split(&p->VtT_h, &p->VtT_l, VtT_p);
+  if (rc) {
+    mofem_prec_destroy(p);
+    return rc;
+  }
+  *out = p;
+  return MOFEM_OK;
+}
+
+extern "C" int mofem_prec_set_coeffs(mofem_prec_t p, double a, double bs, double bt, double d) {
+  clear_error();
+  if (!p) return fail(MOFEM_E_ARG, "prec_set_coeffs: NULL handle");
+  p->alpha = a;
+  p->bs = bs;
+  p->bt = bt;
+  p->dl = d;
+  return MOFEM_OK;
+}
+
+extern "C" int mofem_prec_set_precision(mofem_prec_t p, int precision) {
+  clear_error();
+  if (!p) return fail(MOFEM_E_ARG, "prec_set_precision: NULL handle");
+  if (precision == MOFEM_PREC_F32) return fail(MOFEM_E_UNSUPPORTED, "FP32 transforms are not built");
+  if (precision < MOFEM_PREC_F64 || precision > MOFEM_PREC_BF16X3) return fail(MOFEM_E_ARG, "unknown precision");
+  p->precision = precision;
+  return MOFEM_OK;
+}
+
+extern "C" int mofem_prec_eigenvalues(mofem_prec_t p, double* lam, double* mu) {
+  clear_error();
+  if (!p) return fail(MOFEM_E_ARG, "prec_eigenvalues: NULL handle");
+  if (lam) std::memcpy(lam, p->h_lam.data(), sizeof(double) * p->qs);
+  if (mu) std::memcpy(mu, p->h_mu.data(), sizeof(double) * p->qt);
+  return MOFEM_OK;
+}
+
+extern "C" size_t mofem_prec_workspace_size(mofem_prec_t p, int batch) {
+  if (!p || batch < 1) return 0;
+  // sized for the widest precision (FP64 intermediates), so that a workspace
+  // stays valid when mofem_prec_set_precision switches the handle
+  size_t items = (size_t)p->ps * p->pt * batch;
+  return 2 * align_up(items * 8, 256) + 1024;
+}
+
+namespace {
+int prec_launch(mofem_prec_t p, const double* R, double* Z, long long stride, int batch,
+                const double* item_scale, void* ws, size_t ws_bytes, const int* active, hipStream_t s,
+                int n_items = -1) {
+  const double items_done = n_items < 0 ? batch : n_items;
+  const size_t items = (size_t)p->ps * p->pt;
+  GemmArgs g{};
+  g.lam = p->lam;
+  g.mu = p->mu;
+  g.alpha = p->alpha;
+  g.beta_s = p->bs;
+  g.beta_t = p->bt;
+  g.delta = p->dl;
+  g.item_scale = item_scale;
+  g.out_scale = 1.0;
+  g.active = active;
+  const int prec = p->precision == MOFEM_PREC_F64 ? GEMM_F64 : p->precision == MOFEM_PREC_BF16 ? GEMM_BF16 : GEMM_BF16X3;
+  const int tcls = prec == GEMM_F64 ? MOFEM_TRACE_GEMM_F64 : prec == GEMM_BF16 ? MOFEM_TRACE_GEMM_BF16
+                                                                                : MOFEM_TRACE_GEMM_BF16X3;
+  auto gemm = [&](int amode, int omode) -> int {
+    TraceScope trace(tcls, items_done, s);
+    return launch_gemm(g, prec, amode, omode, batch, s);
+  };
+  Carve c(ws, ws_bytes);
+  if (prec == GEMM_F64) {
+    double* T1 = c.take<double>(items * batch);  // T' then W
+    double* T2 = c.take<double>(items * batch);  // S'
+    if (!T1 || !T2) return fail(MOFEM_E_ARG, "prec_apply: workspace too small");
+    const long long istr = (long long)items;
+    // G1: T' = (R V_t)^T
+    g.M = p->qs; g.N = p->qt; g.K = p->qt;
+    g.a64 = R; g.a_stride = stride; g.b64 = p->VtT; g.b_stride = 0;
+    g.c64 = T1; g.c_stride = istr; g.divide = 0;
+    if (gemm(A_F64_RAW, O_PAD_T)) return fail(MOFEM_E_HIP, "gemm launch");
+    // G2: S' = (V_s^T T ./ D)^T
+    g.M = p->qs; g.N = p->qt; g.K = p->qs;
+    g.a64 = p->VsT; g.a_stride = 0; g.b64 = T1; g.b_stride = istr;
+    g.c64 = T2; g.c_stride = istr; g.divide = 1;
+    if (gemm(A_PADDED, O_PAD_T)) return fail(MOFEM_E_HIP, "gemm launch");
+    // G3: W = V_s S
+    g.M = p->qs; g.N = p->qt; g.K = p->qs;
+    g.a64 = p->Vs; g.a_stride = 0; g.b64 = T2; g.b_stride = istr;
+    g.c64 = T1; g.c_stride = istr; g.divide = 0;
+    if (gemm(A_PADDED, O_PAD_N)) return fail(MOFEM_E_HIP, "gemm launch");
+    // G4: Z = W V_t^T
+    g.M = p->qs; g.N = p->qt; g.K = p->qt;
+    g.a64 = T1; g.a_stride = istr; g.b64 = p->Vt; g.b_stride = 0;
+    g.c64 = Z; g.c_stride = stride; g.divide = 0;
+    if (gemm(A_PADDED, O_F64_RAW)) return fail(MOFEM_E_HIP, "gemm launch");
+  } else {
+    unsigned short* T1h = c.take<unsigned short>(items * batch);
+    unsigned short* T1l = c.take<unsigned short>(items * batch);
+    unsigned short* T2h = c.take<unsigned short>(items * batch);
+    unsigned short* T2l = c.take<unsigned short>(items * batch);
+    if (!T1h || !T1l || !T2h || !T2l) return fail(MOFEM_E_ARG, "prec_apply: workspace too small");
+    const long long istr = (long long)items;
+    g.M = p->qs; g.N = p->qt; g.K = p->qt;
+    g.a64 = R; g.a_stride = stride; g.b_hi = p->VtT_h; g.b_lo = p->VtT_l; g.b_stride = 0;
+    g.c_hi = T1h; g.c_lo = T1l; g.c_stride = istr; g.divide = 0;
+    if (gemm(A_F64_RAW, O_PAD_T)) return fail(MOFEM_E_HIP, "gemm launch");
+    g.M = p->qs; g.N = p->qt; g.K = p->qs;
+    g.a64 = nullptr; g.a_hi = p->VsT_h; g.a_lo = p->VsT_l; g.a_stride = 0;
+    g.b_hi = T1h; g.b_lo = T1l; g.b_stride = istr;
+    g.c_hi = T2h; g.c_lo = T2l; g.c_stride = istr; g.divide = 1;
+    if (gemm(A_PADDED, O_PAD_T)) return fail(MOFEM_E_HIP, "gemm launch");
+    g.M = p->qs; g.N = p->qt; g.K = p->qs;
+    g.a_hi = p->Vs_h; g.a_lo = p->Vs_l; g.a_stride = 0;
+    g.b_hi = T2h; g.b_lo = T2l; g.b_stride = istr;
+    g.c_hi = T1h; g.c_lo = T1l; g.c_stride = istr; g.divide = 0;
+    if (gemm(A_PADDED, O_PAD_N)) return fail(MOFEM_E_HIP, "gemm launch");
+    g.M = p->qs; g.N = p->qt; g.K = p->qt;
+    g.a_hi = T1h; g.a_lo = T1l; g.a_stride = istr;
+    g.b_hi = p->Vt_h; g.b_lo = p->Vt_l; g.b_stride = 0;
+    g.c64 = Z; g.c_stride = stride; g.divide = 0;
+    if (gemm(A_PADDED, O_F64_RAW)) return fail(MOFEM_E_HIP, "gemm launch");
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(MOFEM_E_HIP, std::string("prec_apply launch: ") + hipGetErrorString(e));
+  return MOFEM_OK;
+}
+
+int ensure_internal_ws(void** ws, size_t* have, size_t need, hipStream_t s) {
+  if (*have >= need) return MOFEM_OK;
+  if (*ws) {
+    HIP_TRY(hipStreamSynchronize(s));
+    (void)hipFree(*ws);
+    *ws = nullptr;
+    *have = 0;
+  }
+  char* p = nullptr;
+  int rc = dev_alloc(&p, need);
+  if (rc) return rc;
+  *ws = p;
+  *have = need;
+  return MOFEM_OK;
+}
+}  // namespace
+
+extern "C" int mofem_prec_apply(mofem_prec_t p, const double* R, double* Z, long long stride, int batch,
+                                const double* item_scale, void* workspace, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (!p || !R || !Z) return fail(MOFEM_E_ARG, "prec_apply: NULL argument");
+  if (batch < 0) return fail(MOFEM_E_ARG, "prec_apply: negative batch");
+  if (batch == 0) return MOFEM_OK;
+  if (stride < (long long)p->qs * p->qt) return fail(MOFEM_E_ARG, "prec_apply: stride smaller than one item");
+  hipStream_t s = (hipStream_t)stream;
+  size_t need = mofem_prec_workspace_size(p, batch);
+  if (!workspace) {
+    int rc = ensure_internal_ws(&p->ws, &p->ws_bytes, need, s);
+    if (rc) return rc;
+    workspace = p->ws;
+    ws_bytes = p->ws_bytes;
+  } else if (ws_bytes < need) {
+    return fail(MOFEM_E_ARG, "prec_apply: workspace too small");
+  }
+  return prec_launch(p, R, Z, stride, batch, item_scale, workspace, ws_bytes, nullptr, s);
+}
+
+// ============================================================================
+// MO-PCG
+// ============================================================================
+namespace {
+struct PcgWs {
+  double *R, *Z, *Q, *Y;
+  double *part_a, *part_b, *part_op;
+  double *rz, *rz_new, *qy, *rr, *zy, *alpha, *beta, *rhs2, *tmp;
+  int* active;
+  void* prec_ws;
+  size_t prec_bytes;
+};
+
+size_t pcg_bytes(mofem_op_t op, mofem_prec_t prec, int batch, size_t* prec_part) {
+  size_t n = (size_t)op->qs * op->qt;
+  size_t b = 0;
+  b += 4 * align_up(n * batch * 8, 256);
+  b += 2 * align_up((size_t)batch * kVecBlocks * 8, 256);
+  b += align_up((size_t)batch * op->n_tiles * 8, 256);
+  b += 9 * align_up((size_t)batch * 8, 256);
+  b += align_up((size_t)batch * 4, 256);
+  size_t pp = mofem_prec_workspace_size(prec, batch);
+  if (prec_part) *prec_part = pp;
+  return b + pp + 4096;
+}
+
+bool carve_pcg(mofem_op_t op, mofem_prec_t prec, int batch, void* ws, size_t bytes, PcgWs* w) {
+  Carve c(ws, bytes);
+  size_t n = (size_t)op->qs * op->qt;
+  w->R = c.take<double>(n * batch);
+  w->Z = c.take<double>(n * batch);
+  w->Q = c.take<double>(n * batch);
+  w->Y = c.take<double>(n * batch);
+  w->part_a = c.take<double>((size_t)batch * kVecBlocks);
+  w->part_b = c.take<double>((size_t)batch * kVecBlocks);
+  w->part_op = c.take<double>((size_t)batch * op->n_tiles);
+  w->rz = c.take<double>(batch);
+  w->rz_new = c.take<double>(batch);
+  w->qy = c.take<double>(batch);
+  w->rr = c.take<double>(batch);
+  w->zy = c.take<double>(batch);
+  w->alpha = c.take<double>(batch);
+  w->beta = c.take<double>(batch);
+  w->rhs2 = c.take<double>(batch);
+  w->tmp = c.take<double>(batch);
+  w->active = c.take<int>(batch);
+  w->prec_bytes = mofem_prec_workspace_size(prec, batch);
+  w->prec_ws = c.take<char>(w->prec_bytes);
+  return w->prec_ws != nullptr;
+}
+
+struct HostBuf {
+  double* d = nullptr;
+  int* i = nullptr;
+  int n = 0;
+  ~HostBuf() {
+    if (d) (void)hipHostFree(d);
+    if (i) (void)hipHostFree(i);
+  }
+  int init(int batch) {
+    n = batch;
+    if (hipHostMalloc((void**)&d, sizeof(double) * 4 * batch) != hipSuccess) return MOFEM_E_NOMEM;
+    if (hipHostMalloc((void**)&i, sizeof(int) * batch) != hipSuccess) return MOFEM_E_NOMEM;
+    return MOFEM_OK;
+  }
+};
+}  // namespace
+
+extern "C" size_t mofem_pcg_workspace_size(mofem_op_t op, mofem_prec_t prec, int batch) {
+  if (!op || !prec || batch < 1) return 0;
+  return pcg_bytes(op, prec, batch, nullptr);
+}
+
+extern "C" int mofem_pcg_solve(mofem_op_t op, mofem_prec_t prec, const double* Rhs, double* U, long long stride,
+                               int batch, const double* item_scale, double tol, int maxit, unsigned flags,
+                               void* workspace, size_t ws_bytes, int* iters_out, double* relres_out,
+                               void* stream) {
+  clear_error();
+  if (!op || !prec || !Rhs || !U) return fail(MOFEM_E_ARG, "pcg_solve: NULL argument");
+  if (batch < 0 || maxit < 0 || !(tol >= 0.0)) return fail(MOFEM_E_ARG, "pcg_solve: bad batch/maxit/tol");
+  if (batch == 0) return MOFEM_OK;
+  if (op->full_input) return fail(MOFEM_E_ARG, "pcg_solve: operator must map unknowns to unknowns");
+  if (op->qs != prec->qs || op->qt != prec->qt) return fail(MOFEM_E_ARG, "pcg_solve: operator and preconditioner sizes differ");
+  const long long n = (long long)op->qs * op->qt;
+  if (stride < n) return fail(MOFEM_E_ARG, "pcg_solve: stride smaller than one item");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t need = pcg_bytes(op, prec, batch, nullptr);
+  static thread_local void* own_ws = nullptr;
+  static thread_local size_t own_bytes = 0;
+  if (!workspace) {
+    int rc = ensure_internal_ws(&own_ws, &own_bytes, need, s);
+    if (rc) return rc;
+    workspace = own_ws;
+    ws_bytes = own_bytes;
+  } else if (ws_bytes < need) {
+    return fail(MOFEM_E_ARG, "pcg_solve: workspace too small");
+  }
+  PcgWs w{};
+  if (!carve_pcg(op, prec, batch, workspace, ws_bytes, &w)) return fail(MOFEM_E_ARG, "pcg_solve: workspace too small");
+  HostBuf hb;
+  if (hb.init(batch)) return fail(MOFEM_E_NOMEM, "pcg_solve: pinned host buffer");
+  const bool flexible = flags & MOFEM_PCG_FLEXIBLE;
+  const bool tau_stop = flags & MOFEM_PCG_TAU_STOP;
+  const int nt = op->n_tiles;
+
+  std::vector<int> active(batch, 1), iters(batch, 0), status(batch, MOFEM_OK);
+  std::vector<double> target2(batch, 0.0), rhs2(batch, 0.0);
+  int n_active = batch;
+  auto count_active = [&]() {
+    n_active = 0;
+    for (int b = 0; b < batch; ++b) n_active += active[b] != 0;
+  };
+  auto push_active = [&]() -> int {
+    count_active();
+    for (int b = 0; b < batch; ++b) hb.i[b] = active[b];
+    HIP_TRY(hipMemcpyAsync(w.active, hb.i, sizeof(int) * batch, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MOFEM_OK;
+  };
+  auto fetch = [&](const double* dev, double* host) -> int {
+    HIP_TRY(hipMemcpyAsync(hb.d, dev, sizeof(double) * batch, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::memcpy(host, hb.d, sizeof(double) * batch);
+    return MOFEM_OK;
+  };
+  int rc;
+#define TRY(x)                   \
+  do {                           \
+    if ((rc = (x)) != MOFEM_OK)  \
+      return rc;                 \
+  } while (0)
+#define LTRY(x)                                                            \
+  do {                                                                     \
+    TraceScope _trace(MOFEM_TRACE_VEC, n_active, s);                       \
+    if ((x) != 0) return fail(MOFEM_E_HIP, "pcg_solve: launch failed");    \
+  } while (0)
+
+
+  TRY(push_active());
+  // ||Rhs||^2
+  LTRY(launch_dot_partial(Rhs, Rhs, n, stride, batch, w.part_a, w.active, s));
+  LTRY(launch_reduce(w.part_a, kVecBlocks, w.rhs2, batch, s));
+  TRY(fetch(w.rhs2, rhs2.data()));
+  // R = Rhs - L(U)  (or Rhs with a zero guess)
+  if (flags & MOFEM_PCG_ZERO_GUESS) {
+    LTRY(launch_fill(U, 0.0, n, stride, batch, s));
+    LTRY(launch_copy(Rhs, w.R, n, stride, n, batch, s));
+    LTRY(launch_dot_partial(w.R, w.R, n, n, batch, w.part_a, w.active, s));
+  } else {
+    TRY(op_launch(op, U, stride, w.Y, n, batch, item_scale, nullptr, w.active, s, n_active));
+    LTRY(launch_residual(Rhs, w.Y, w.R, n, n, stride, batch, w.part_a, w.active, s));
+  }
+  LTRY(launch_reduce(w.part_a, kVecBlocks, w.rr, batch, s));
+  std::vector<double> rr(batch), qy(batch);
+  TRY(fetch(w.rr, rr.data()));
+  bool any = false;
+  for (int b = 0; b < batch; ++b) {
+    if (!std::isfinite(rr[b]) || !std::isfinite(rhs2[b])) {
+      status[b] = MOFEM_E_NOTFINITE;
+      active[b] = 0;
+      continue;
+    }
+    target2[b] = tol * tol * (tau_stop ? rr[b] : rhs2[b]);
+    if (rhs2[b] == 0.0 || rr[b] <= target2[b]) active[b] = 0;
+    any |= active[b] != 0;
+  }
+  TRY(push_active());
+  if (any) {
+    TRY(prec_launch(prec, w.R, w.Z, n, batch, item_scale, w.prec_ws, w.prec_bytes, w.active, s, n_active));
+    LTRY(launch_dot_partial(w.R, w.Z, n, n, batch, w.part_a, w.active, s));
+    LTRY(launch_reduce(w.part_a, kVecBlocks, w.rz, batch, s));
+    LTRY(launch_direction(w.Q, w.Z, nullptr, n, n, batch, w.active, s));
+  }
+  int it = 0;
+  std::vector<int> restart(batch, 0);
+  while (any && it < maxit) {
+    ++it;
+    // Y = L(Q), <Q, Y>
+    TRY(op_launch(op, w.Q, n, w.Y, n, batch, item_scale, w.part_op, w.active, s, n_active));
+    LTRY(launch_reduce(w.part_op, nt, w.qy, batch, s));
+    // alpha = <R, Z> / <Q, Y>; U += alpha Q; R -= alpha Y; <R, R>
+    LTRY(launch_cg_update(U, w.R, w.Q, w.Y, w.rz, w.qy, w.alpha, n, n, stride, batch, w.part_a, w.active, s));
+    LTRY(launch_reduce(w.part_a, kVecBlocks, w.rr, batch, s));
+    TRY(fetch(w.qy, qy.data()));
+    TRY(fetch(w.rr, rr.data()));
+    std::vector<int> check;
+    for (int b = 0; b < batch; ++b) {
+      if (!active[b]) continue;
+      iters[b] = it;
+      if (!std::isfinite(qy[b]) || qy[b] <= 0.0) {
+        status[b] = MOFEM_E_BREAKDOWN;
+        active[b] = 0;
+        continue;
+      }
+      if (!std::isfinite(rr[b])) {
+        status[b] = MOFEM_E_NOTFINITE;
+        active[b] = 0;
+        continue;
+      }
+      if (rr[b] <= target2[b]) check.push_back(b);
+    }
+    if (!check.empty()) {
+      // confirm on the true residual Rhs - L(U) for the items that claim convergence
+      std::vector<int> save = active;
+      for (int b = 0; b < batch; ++b) active[b] = 0;
+      for (int b : check) active[b] = 1;
+      TRY(push_active());
+      TRY(op_launch(op, U, stride, w.Z, n, batch, item_scale, nullptr, w.active, s, n_active));
+      LTRY(launch_residual(Rhs, w.Z, w.Z, n, n, stride, batch, w.part_b, w.active, s));
+      LTRY(launch_reduce(w.part_b, kVecBlocks, w.tmp, batch, s));
+      std::vector<double> tr(batch);
+      TRY(fetch(w.tmp, tr.data()));
+      active = save;
+      for (int b : check) {
+        if (tr[b] <= target2[b]) {
+          active[b] = 0;
+        } else {
+          // recurrence drifted: continue from the true residual with a fresh direction
+          restart[b] = 1;
+          LTRY(launch_copy(w.Z + (size_t)b * n, w.R + (size_t)b * n, n, n, n, 1, s));
+        }
+      }
+      TRY(push_active());
+    }
+    any = false;
+    for (int b = 0; b < batch; ++b) any |= active[b] != 0;
+    if (!any || it >= maxit) break;
+    // Z = P^{-1}(R); <R, Z>, <Z, Y>
+    TRY(prec_launch(prec, w.R, w.Z, n, batch, item_scale, w.prec_ws, w.prec_bytes, w.active, s, n_active));
+    LTRY(launch_dot2_partial(w.R, w.Z, w.Z, w.Y, n, n, batch, w.part_a, w.part_b, w.active, s));
+    LTRY(launch_reduce(w.part_a, kVecBlocks, w.rz_new, batch, s));
+    LTRY(launch_reduce(w.part_b, kVecBlocks, w.zy, batch, s));
+    LTRY(launch_beta(w.rz_new, w.rz, w.zy, w.alpha, w.beta, flexible ? 1 : 0, batch, w.active, s));
+    bool any_restart = false;
+    for (int b = 0; b < batch; ++b) any_restart |= restart[b] != 0;
+    if (any_restart) {
+      for (int b = 0; b < batch; ++b) {
+        hb.d[b] = restart[b] ? 0.0 : 1.0;
+        restart[b] = 0;
+      }
+      // beta := beta * keep  (zero for restarted items: a fresh direction Q = Z)
+      HIP_TRY(hipMemcpyAsync(w.tmp, hb.d, sizeof(double) * batch, hipMemcpyHostToDevice, s));
+      LTRY(launch_scale_items(w.beta, w.tmp, batch, s));
+      HIP_TRY(hipStreamSynchronize(s));
+    }
+    LTRY(launch_direction(w.Q, w.Z, w.beta, n, n, batch, w.active, s));
+  }
+  // final true residuals for every item
+  for (int b = 0; b < batch; ++b) active[b] = 1;
+  TRY(push_active());
+  TRY(op_launch(op, U, stride, w.Z, n, batch, item_scale, nullptr, w.active, s, n_active));
+  LTRY(launch_residual(Rhs, w.Z, w.Z, n, n, stride, batch, w.part_b, w.active, s));
+  LTRY(launch_reduce(w.part_b, kVecBlocks, w.tmp, batch, s));
+  std::vector<double> tr(batch);
+  TRY(fetch(w.tmp, tr.data()));
+  int result = MOFEM_OK;
+  for (int b = 0; b < batch; ++b) {
+    double rel = rhs2[b] > 0.0 ? std::sqrt(tr[b] / rhs2[b]) : std::sqrt(tr[b]);
+    if (relres_out) relres_out[b] = rel;
+    if (iters_out) iters_out[b] = iters[b];
+    if (status[b] == MOFEM_OK && !(tr[b] <= target2[b] || (rhs2[b] == 0.0 && tr[b] == 0.0))) status[b] = MOFEM_E_MAXIT;
+    if (status[b] != MOFEM_OK && result == MOFEM_OK) result = status[b];
+  }
+  if (result == MOFEM_E_MAXIT) return fail(result, "pcg_solve: tolerance not reached within maxit");
+  if (result == MOFEM_E_BREAKDOWN) return fail(result, "pcg_solve: breakdown, <Q, L(Q)> <= 0");
+  if (result == MOFEM_E_NOTFINITE) return fail(result, "pcg_solve: non-finite residual");
+  return result;
+#undef TRY
+#undef LTRY
+}
+
+// ============================================================================
+// IMEX Euler step
+// ============================================================================
+extern "C" size_t mofem_imex_workspace_size(const mofem_imex_desc* d, int batch) {
+  if (!d || !d->op || !d->prec || !d->mass || batch < 1 || d->n_species < 1 || d->n_species > 2) return 0;
+  size_t items = (size_t)d->n_species * batch;
+  size_t n = (size_t)d->op->qs * d->op->qt;
+  size_t b = align_up(items * n * 8, 256);                 // right-hand sides
+  if (d->kinetics == MOFEM_KIN_DIB) b += align_up(items * n * 8, 256);  // transformed states
+  b += align_up(items * 8, 256);                           // item scales
+  return b + pcg_bytes(d->op, d->prec, (int)items, nullptr) + 4096;
+}
+
+extern "C" int mofem_imex_step(const mofem_imex_desc* d, double* state, long long stride, int batch,
+                               void* workspace, size_t ws_bytes, int* iters_out, void* stream) {
+  clear_error();
+  if (!d || !state || !d->op || !d->prec || !d->mass) return fail(MOFEM_E_ARG, "imex_step: NULL argument");
+  if (d->n_species < 1 || d->n_species > 2) return fail(MOFEM_E_ARG, "imex_step: n_species must be 1 or 2");
+  if (d->kinetics == MOFEM_KIN_DIB && d->n_species != 2) return fail(MOFEM_E_ARG, "imex_step: DIB needs 2 species");
+  if (d->kinetics != MOFEM_KIN_NONE && d->kinetics != MOFEM_KIN_DIB) return fail(MOFEM_E_ARG, "imex_step: unknown kinetics");
+  if (batch < 1) return batch == 0 ? MOFEM_OK : fail(MOFEM_E_ARG, "imex_step: negative batch");
+  mofem_op_t op = d->op, mass = d->mass;
+  if (mass->full_input || mass->qs != op->qs || mass->qt != op->qt)
+    return fail(MOFEM_E_ARG, "imex_step: mass operator must map unknowns to unknowns of the same shape");
+  const long long n = (long long)op->qs * op->qt;
+  if (stride != n) return fail(MOFEM_E_ARG, "imex_step: items must be contiguous (stride = q_s * q_t)");
+  const int items = d->n_species * batch;
+  hipStream_t s = (hipStream_t)stream;
+  size_t need = mofem_imex_workspace_size(d, batch);
+  static thread_local void* own_ws = nullptr;
+  static thread_local size_t own_bytes = 0;
+  if (!workspace) {
+    int rc = ensure_internal_ws(&own_ws, &own_bytes, need, s);
+    if (rc) return rc;
+    workspace = own_ws;
+    ws_bytes = own_bytes;
+  } else if (ws_bytes < need) {
+    return fail(MOFEM_E_ARG, "imex_step: workspace too small");
+  }
+  Carve c(workspace, ws_bytes);
+  double* rhs = c.take<double>((size_t)items * n);
+  double* trans = d->kinetics == MOFEM_KIN_DIB ? c.take<double>((size_t)items * n) : nullptr;
+  double* scale = c.take<double>(items);
+  size_t pcg_need = pcg_bytes(op, d->prec, items, nullptr);
+  void* pcg_ws = c.take<char>(pcg_need);
+  if (!rhs || !scale || !pcg_ws || (d->kinetics == MOFEM_KIN_DIB && !trans))
+    return fail(MOFEM_E_ARG, "imex_step: workspace too small");
+  // per-item c = d_species * tau
+  std::vector<double> hs(items);
+  for (int sp = 0; sp < d->n_species; ++sp)
+    for (int b = 0; b < batch; ++b) hs[(size_t)sp * batch + b] = d->d[sp] * d->tau;
+  HIP_TRY(hipMemcpyAsync(scale, hs.data(), sizeof(double) * items, hipMemcpyHostToDevice, s));
+  // right-hand side: Mass(U + tau f(U, V))  (eq. (93))
+  const double* src = state;
+  long long src_stride = stride;
+  if (d->kinetics == MOFEM_KIN_DIB) {
+    if (launch_dib_source(state, state + (size_t)batch * n, trans, trans + (size_t)batch * n, n, n, batch,
+                          d->kin, d->tau, s) != 0)
+      return fail(MOFEM_E_HIP, "imex_step: kinetics launch failed");
+    src = trans;
+    src_stride = n;
+  }
+  int rc = op_launch(mass, src, src_stride, rhs, n, items, nullptr, nullptr, nullptr, s);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(s));
+  unsigned fl = d->flags & ~MOFEM_PCG_ZERO_GUESS;
+  std::vector<double> relres(items);
+  // the state is both the guess and the solution; all species in one batched solve
+  rc = mofem_pcg_solve(op, d->prec, rhs, state, n, items, scale, d->tol, d->maxit, fl, pcg_ws, pcg_need,
+                       iters_out, relres.data(), stream);
+  return rc;
+}

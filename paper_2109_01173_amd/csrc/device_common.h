@@ -1,0 +1,59 @@
+// Device-side helpers shared by the libmofem kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+namespace mofem {
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I in [B, E).
+template <int B, int E>
+struct StaticFor {
+  template <class F>
+  __device__ __forceinline__ static void run(F&& f) {
+    f(std::integral_constant<int, B>{});
+    StaticFor<B + 1, E>::run(f);
+  }
+};
+template <int E>
+struct StaticFor<E, E> {
+  template <class F>
+  __device__ __forceinline__ static void run(F&&) {}
+};
+
+// Whole-wave lane shifts through DPP (wave_shl:1 / wave_shr:1).  Lane l
+// receives the value of lane l+1 (shl) or l-1 (shr); the lane shifted in
+// from outside the wave receives 0.
+__device__ __forceinline__ double wave_shl1(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = __builtin_amdgcn_update_dpp(0, lo, 0x130, 0xf, 0xf, true);
+  hi = __builtin_amdgcn_update_dpp(0, hi, 0x130, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_shr1(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = __builtin_amdgcn_update_dpp(0, lo, 0x138, 0xf, 0xf, true);
+  hi = __builtin_amdgcn_update_dpp(0, hi, 0x138, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave (every lane receives the total).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// XCD-aware tile order.  Work-groups are dealt round-robin to the 8 XCDs of
+// an MI355X (dispatch id % 8).  Map dispatch id -> tile so that each XCD
+// receives one contiguous range of tiles (neighbouring tiles share halo data
+// through that XCD's L2).  Bijective for any tile count n.
+__device__ __forceinline__ int xcd_tile(int id, int n) {
+  const int nx = 8;
+  int q = n / nx, r = n % nx;
+  int x = id % nx, slot = id / nx;
+  return (x < r) ? x * (q + 1) + slot : r * (q + 1) + (x - r) * q + slot;
+}
+
+}  // namespace mofem

@@ -1,0 +1,6 @@
+// Band-width 4 instantiations of the multiterm operator kernel.
+#include "band_kernel.inl"
+
+namespace mofem {
+MOFEM_BAND_INSTANTIATE(4)
+}  // namespace mofem

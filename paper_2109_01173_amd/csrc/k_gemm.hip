@@ -1,0 +1,314 @@
+// Dense two-sided spectral transforms of the preconditioner on MFMA.
+//
+// The preconditioner inverse of Sec. 4 (eqs. (55)-(59)), used as the
+// single-term preconditioner of Sec. 5 (eq. (80)) and Sec. 6 (eq. (95)),
+//     Z = V_s ((V_s^T R V_t) ./ D) V_t^T,
+// is evaluated as four "NT" products C[m][n] = sum_k A[m][k] B[n][k] whose
+// operands are all contiguous along k:
+//     T' = (R V_t)^T       A = R        B = V_t^T   out transposed
+//     S' = (V_s^T T ./ D)^T A = V_s^T   B = T'      out transposed, divide by D
+//     W  = V_s S            A = V_s      B = S'      out row-major
+//     Z  = W V_t^T          A = W        B = V_t     out FP64 (the caller's R/Z layout)
+// so neither operand ever needs a transpose in LDS.  D is formed in the
+// epilogue from the eigenvalue vectors (never stored).
+//
+// Precisions:
+//   GEMM_F64     v_mfma_f64_16x16x4_f64, FP64 operands and accumulation.
+//   GEMM_BF16X3  v_mfma_f32_16x16x32_bf16 with split operands x = hi + lo
+//                (hi = bf16(x), lo = bf16(x - hi)); A B ~ Ah Bh + Ah Bl + Al Bh,
+//                FP32 accumulation, FP32-level accuracy.
+//   GEMM_BF16    the hi * hi product only.
+// Tiling: 256 threads = 4 waves, block tile 128 x 128, each wave 64 x 64
+// (4 x 4 MFMA tiles of 16 x 16).  Global -> register prefetch of the next k
+// tile overlaps the MFMAs of the current one.  Block order is XCD-aware.
+// Intermediates are padded to multiples of 128 in both dimensions and the
+// epilogue writes zeros into the padding, so consumers read whole tiles
+// without bounds checks.
+#include "device_common.h"
+#include "kernels.h"
+#include "mofem_internal.h"
+
+namespace mofem {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef unsigned short us8_t __attribute__((ext_vector_type(8)));
+
+constexpr int BM = 128, BN = 128;
+
+__device__ __forceinline__ unsigned short bf16_bits(float x) {
+  __bf16 h = (__bf16)x;   // round to nearest even
+  return __builtin_bit_cast(unsigned short, h);
+}
+__device__ __forceinline__ float bf16_to_f(unsigned short u) {
+  return __uint_as_float(((unsigned)u) << 16);
+}
+__device__ __forceinline__ void split_bf16(float x, unsigned short* hi, unsigned short* lo) {
+  unsigned short h = bf16_bits(x);
+  *hi = h;
+  *lo = bf16_bits(x - bf16_to_f(h));
+}
+
+__device__ __forceinline__ double eval_D(const GemmArgs& g, int row, int col, double s) {
+  double l = g.lam[row], m = g.mu[col];
+  return g.alpha + s * (g.beta_s * l + g.beta_t * m + g.delta * l * m);
+}
+
+// ------------------------------------------------------------------------------
+// FP64
+// ------------------------------------------------------------------------------
+template <int AMODE, int OMODE>
+__global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
+  constexpr int BK = 16;
+  constexpr int LDS_K = BK + 1;
+  __shared__ double As[BM][LDS_K];
+  __shared__ double Bs[BN][LDS_K];
+
+  const int b = blockIdx.y;
+  if (g.active && !g.active[b]) return;
+  const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
+  const int tile = xcd_tile(blockIdx.x, tm * tn);
+  const int m0 = (tile / tn) * BM, n0 = (tile % tn) * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  const int lda = (AMODE == A_F64_RAW) ? g.K : pad_up(g.K);
+  const int ldb = pad_up(g.K);
+  const double* __restrict__ A = g.a64 + (size_t)b * g.a_stride;
+  const double* __restrict__ B = g.b64 + (size_t)b * g.b_stride;
+
+  // global -> register staging: thread owns row tid/2, k segment (tid%2)*8
+  const int lrow = tid >> 1, lk = (tid & 1) * 8;
+  double ra[8], rb[8];
+  auto load_tile = [&](int k0) {
+    const int arow = m0 + lrow;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int kk = k0 + lk + e;
+      if (AMODE == A_F64_RAW)
+        ra[e] = (arow < g.M && kk < g.K) ? A[(size_t)arow * lda + kk] : 0.0;
+      else
+        ra[e] = A[(size_t)arow * lda + kk];
+      rb[e] = B[(size_t)(n0 + lrow) * ldb + kk];
+    }
+  };
+
+  d4_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = (d4_t){0.0, 0.0, 0.0, 0.0};
+
+  const int nk = (g.K + BK - 1) / BK;
+  load_tile(0);
+  for (int kt = 0; kt < nk; ++kt) {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      As[lrow][lk + e] = ra[e];
+      Bs[lrow][lk + e] = rb[e];
+    }
+    __syncthreads();
+    if (kt + 1 < nk) load_tile((kt + 1) * BK);
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = As[wm * 64 + i * 16 + (lane & 15)][ks * 4 + (lane >> 4)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = Bs[wn * 64 + j * 16 + (lane & 15)][ks * 4 + (lane >> 4)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+  }
+
+  // epilogue: acc[i][j][r] = C[row][col], row = 4 r + lane/16, col = lane%16 (per 16x16 tile)
+  const double s = g.item_scale ? g.item_scale[b] : 1.0;
+  double* __restrict__ C = g.c64 + (size_t)b * g.c_stride;
+  const int Mp = pad_up(g.M), Np = pad_up(g.N);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * 64 + i * 16 + 4 * r + (lane >> 4);
+        const int col = n0 + wn * 64 + j * 16 + (lane & 15);
+        const bool in = row < g.M && col < g.N;
+        double v = acc[i][j][r] * g.out_scale;
+        if (g.divide && in) v /= eval_D(g, row, col, s);
+        if (!in) v = 0.0;
+        if (OMODE == O_PAD_T) C[(size_t)col * Mp + row] = v;
+        else if (OMODE == O_PAD_N) C[(size_t)row * Np + col] = v;
+        else if (in) C[(size_t)row * g.N + col] = v;
+      }
+}
+
+// ------------------------------------------------------------------------------
+// split BF16 (NPROD = 3) and plain BF16 (NPROD = 1), FP32 accumulation
+// ------------------------------------------------------------------------------
+template <int NPROD, int AMODE, int OMODE>
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
+  constexpr int BK = 32;
+  constexpr int LDS_K = BK + 8;   // 80-byte rows keep 16-byte alignment
+  constexpr bool LO = (NPROD == 3);
+  __shared__ unsigned short Ah[BM][LDS_K];
+  __shared__ unsigned short Bh[BN][LDS_K];
+  __shared__ unsigned short Al[LO ? BM : 1][LDS_K];
+  __shared__ unsigned short Bl[LO ? BN : 1][LDS_K];
+
+  const int b = blockIdx.y;
+  if (g.active && !g.active[b]) return;
+  const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
+  const int tile = xcd_tile(blockIdx.x, tm * tn);
+  const int m0 = (tile / tn) * BM, n0 = (tile % tn) * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  const int Kp = pad_up(g.K);
+  const double* __restrict__ A64 = g.a64 + (size_t)b * g.a_stride;
+  const unsigned short* __restrict__ Ahg = (const unsigned short*)g.a_hi + (size_t)b * g.a_stride;
+  const unsigned short* __restrict__ Alg = (const unsigned short*)g.a_lo + (size_t)b * g.a_stride;
+  const unsigned short* __restrict__ Bhg = (const unsigned short*)g.b_hi + (size_t)b * g.b_stride;
+  const unsigned short* __restrict__ Blg = (const unsigned short*)g.b_lo + (size_t)b * g.b_stride;
+
+  // staging: thread owns row tid/2 and k segment (tid%2)*16 (16 values)
+  const int lrow = tid >> 1, lk = (tid & 1) * 16;
+  us8_t ah[2], al[2], bh[2], bl[2];
+  auto load_tile = [&](int k0) {
+    const int arow = m0 + lrow;
+    if (AMODE == A_F64_RAW) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int kk = k0 + lk + h * 8 + e;
+          double x = (arow < g.M && kk < g.K) ? A64[(size_t)arow * g.K + kk] : 0.0;
+          unsigned short hi, lo;
+          split_bf16((float)x, &hi, &lo);
+          ah[h][e] = hi;
+          al[h][e] = lo;
+        }
+    } else {
+      const us8_t* pa = (const us8_t*)(Ahg + (size_t)arow * Kp + k0 + lk);
+      ah[0] = pa[0];
+      ah[1] = pa[1];
+      if (LO) {
+        const us8_t* pl = (const us8_t*)(Alg + (size_t)arow * Kp + k0 + lk);
+        al[0] = pl[0];
+        al[1] = pl[1];
+      }
+    }
+    const us8_t* pb = (const us8_t*)(Bhg + (size_t)(n0 + lrow) * Kp + k0 + lk);
+    bh[0] = pb[0];
+    bh[1] = pb[1];
+    if (LO) {
+      const us8_t* pl = (const us8_t*)(Blg + (size_t)(n0 + lrow) * Kp + k0 + lk);
+      bl[0] = pl[0];
+      bl[1] = pl[1];
+    }
+  };
+
+  f4_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = (f4_t){0.f, 0.f, 0.f, 0.f};
+
+  const int nk = (g.K + BK - 1) / BK;
+  load_tile(0);
+  for (int kt = 0; kt < nk; ++kt) {
+    __syncthreads();
+    *(us8_t*)&Ah[lrow][lk] = ah[0];
+    *(us8_t*)&Ah[lrow][lk + 8] = ah[1];
+    *(us8_t*)&Bh[lrow][lk] = bh[0];
+    *(us8_t*)&Bh[lrow][lk + 8] = bh[1];
+    if (LO) {
+      *(us8_t*)&Al[lrow][lk] = al[0];
+      *(us8_t*)&Al[lrow][lk + 8] = al[1];
+      *(us8_t*)&Bl[lrow][lk] = bl[0];
+      *(us8_t*)&Bl[lrow][lk + 8] = bl[1];
+    }
+    __syncthreads();
+    if (kt + 1 < nk) load_tile((kt + 1) * BK);
+    bf8_t fa[4], fb[4], fal[4], fbl[4];
+    const int kq = (lane >> 4) * 8;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      fa[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Ah[wm * 64 + i * 16 + (lane & 15)][kq]);
+      if (LO) fal[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Al[wm * 64 + i * 16 + (lane & 15)][kq]);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      fb[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Bh[wn * 64 + j * 16 + (lane & 15)][kq]);
+      if (LO) fbl[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Bl[wn * 64 + j * 16 + (lane & 15)][kq]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (LO) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fal[i], fb[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fbl[j], acc[i][j], 0, 0, 0);
+        }
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+      }
+  }
+
+  // epilogue: acc[i][j][r] = C[row][col], row = 4*(lane/16) + r, col = lane%16
+  const double s = g.item_scale ? g.item_scale[b] : 1.0;
+  const int Mp = pad_up(g.M), Np = pad_up(g.N);
+  unsigned short* __restrict__ Ch = (unsigned short*)g.c_hi + (size_t)b * g.c_stride;
+  unsigned short* __restrict__ Cl = (unsigned short*)g.c_lo + (size_t)b * g.c_stride;
+  double* __restrict__ C64 = g.c64 + (size_t)b * g.c_stride;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+        const int col = n0 + wn * 64 + j * 16 + (lane & 15);
+        const bool in = row < g.M && col < g.N;
+        double v = (double)acc[i][j][r] * g.out_scale;
+        if (g.divide && in) v /= eval_D(g, row, col, s);
+        if (!in) v = 0.0;
+        if (OMODE == O_F64_RAW) {
+          if (in) C64[(size_t)row * g.N + col] = v;
+        } else {
+          unsigned short hi, lo;
+          split_bf16((float)v, &hi, &lo);
+          size_t idx = (OMODE == O_PAD_T) ? (size_t)col * Mp + row : (size_t)row * Np + col;
+          Ch[idx] = hi;
+          if (LO) Cl[idx] = lo;
+        }
+      }
+}
+
+template <int AMODE, int OMODE>
+static void launch_mode(const GemmArgs& g, int prec, int batch, hipStream_t s) {
+  const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
+  dim3 grid(tm * tn, batch);
+  if (prec == GEMM_F64)
+    hipLaunchKernelGGL((gemm_f64_kernel<AMODE, OMODE>), grid, dim3(256), 0, s, g);
+  else if (prec == GEMM_BF16X3)
+    hipLaunchKernelGGL((gemm_bf16_kernel<3, AMODE, OMODE>), grid, dim3(256), 0, s, g);
+  else
+    hipLaunchKernelGGL((gemm_bf16_kernel<1, AMODE, OMODE>), grid, dim3(256), 0, s, g);
+}
+
+int launch_gemm(const GemmArgs& g, int prec, int amode, int omode, int batch, hipStream_t s) {
+  if (prec != GEMM_F64 && prec != GEMM_BF16 && prec != GEMM_BF16X3) return -1;
+  if (amode == A_F64_RAW && omode == O_PAD_T) launch_mode<A_F64_RAW, O_PAD_T>(g, prec, batch, s);
+  else if (amode == A_PADDED && omode == O_PAD_T) launch_mode<A_PADDED, O_PAD_T>(g, prec, batch, s);
+  else if (amode == A_PADDED && omode == O_PAD_N) launch_mode<A_PADDED, O_PAD_N>(g, prec, batch, s);
+  else if (amode == A_PADDED && omode == O_F64_RAW) launch_mode<A_PADDED, O_F64_RAW>(g, prec, batch, s);
+  else return -1;
+  return 0;
+}
+
+}  // namespace mofem

@@ -1,0 +1,266 @@
+// Vector kernels of the MO-PCG recurrence (Sec. 5, eqs. (77)-(78)), FP64.
+//
+// Every nodal matrix of one batch item is treated as a flat contiguous array
+// of n = q_s * q_t doubles.  Each item is processed by kVecBlocks blocks of
+// 256 threads; a block owns one contiguous chunk, so its loads are
+// coalesced.  Frobenius products (sum(sum(X o Y)) of eq. (77)) are reduced
+// deterministically: per-block partial sums in a fixed order, then one block
+// per item adds the partials in a fixed order (no floating-point atomics),
+// so results are bitwise reproducible from run to run.  The scalar
+// recurrence (alpha, beta) is computed on the device from those sums.
+#include "device_common.h"
+#include "kernels.h"
+#include "mofem_internal.h"
+
+namespace mofem {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ void chunk_of(long long n, int blk, int nblk, long long* b, long long* e) {
+  long long c = (n + nblk - 1) / nblk;
+  *b = (long long)blk * c;
+  *e = *b + c < n ? *b + c : n;
+  if (*b > n) *b = n;
+}
+
+// block-wide sum in fixed order; result valid in thread 0
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double red[kThreads / 64];
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < kThreads / 64; ++i) t += red[i];
+  __syncthreads();
+  return t;
+}
+
+__global__ __launch_bounds__(kThreads) void reduce_kernel(const double* __restrict__ partial, int np,
+                                                          double* __restrict__ out) {
+  const int b = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < np; i += kThreads) s += partial[(size_t)b * np + i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) out[b] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void dot_kernel(const double* __restrict__ X, const double* __restrict__ Y,
+                                                       long long n, long long stride,
+                                                       double* __restrict__ partial, const int* active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  long long lo, hi;
+  chunk_of(n, blockIdx.x, gridDim.x, &lo, &hi);
+  const double* x = X + (size_t)b * stride;
+  const double* y = Y + (size_t)b * stride;
+  double s = 0.0;
+  for (long long i = lo + threadIdx.x; i < hi; i += kThreads) s = fma(x[i], y[i], s);
+  s = block_sum(s);
+  if (threadIdx.x == 0) partial[(size_t)b * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void dot2_kernel(const double* __restrict__ A, const double* __restrict__ B,
+                                                        const double* __restrict__ C, const double* __restrict__ D,
+                                                        long long n, long long stride, double* __restrict__ p1,
+                                                        double* __restrict__ p2, const int* active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  long long lo, hi;
+  chunk_of(n, blockIdx.x, gridDim.x, &lo, &hi);
+  const size_t off = (size_t)b * stride;
+  double s1 = 0.0, s2 = 0.0;
+  for (long long i = lo + threadIdx.x; i < hi; i += kThreads) {
+    s1 = fma(A[off + i], B[off + i], s1);
+    s2 = fma(C[off + i], D[off + i], s2);
+  }
+  s1 = block_sum(s1);
+  s2 = block_sum(s2);
+  if (threadIdx.x == 0) {
+    p1[(size_t)b * gridDim.x + blockIdx.x] = s1;
+    p2[(size_t)b * gridDim.x + blockIdx.x] = s2;
+  }
+}
+
+// R may alias Y (each element is read before it is written by the same thread)
+__global__ __launch_bounds__(kThreads) void residual_kernel(const double* __restrict__ Rhs, const double* Y,
+                                                            double* R, long long n, long long stride,
+                                                            long long rhs_stride, double* __restrict__ partial,
+                                                            const int* active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  long long lo, hi;
+  chunk_of(n, blockIdx.x, gridDim.x, &lo, &hi);
+  const double* f = Rhs + (size_t)b * rhs_stride;
+  const double* y = Y + (size_t)b * stride;
+  double* r = R + (size_t)b * stride;
+  double s = 0.0;
+  for (long long i = lo + threadIdx.x; i < hi; i += kThreads) {
+    double v = f[i] - y[i];
+    r[i] = v;
+    s = fma(v, v, s);
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0 && partial) partial[(size_t)b * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void cg_update_kernel(double* __restrict__ U, double* __restrict__ R,
+                                                             const double* __restrict__ Q, const double* __restrict__ Y,
+                                                             const double* __restrict__ num, const double* __restrict__ den,
+                                                             double* __restrict__ alpha_out, long long n, long long stride,
+                                                             long long u_stride, double* __restrict__ partial,
+                                                             const int* active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const double alpha = num[b] / den[b];
+  if (blockIdx.x == 0 && threadIdx.x == 0 && alpha_out) alpha_out[b] = alpha;
+  long long lo, hi;
+  chunk_of(n, blockIdx.x, gridDim.x, &lo, &hi);
+  double* u = U + (size_t)b * u_stride;
+  double* r = R + (size_t)b * stride;
+  const double* q = Q + (size_t)b * stride;
+  const double* y = Y + (size_t)b * stride;
+  double s = 0.0;
+  for (long long i = lo + threadIdx.x; i < hi; i += kThreads) {
+    u[i] = fma(alpha, q[i], u[i]);
+    double v = fma(-alpha, y[i], r[i]);
+    r[i] = v;
+    s = fma(v, v, s);
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) partial[(size_t)b * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void direction_kernel(double* __restrict__ Q, const double* __restrict__ Z,
+                                                             const double* __restrict__ beta, long long n,
+                                                             long long stride, const int* active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const double be = beta ? beta[b] : 0.0;
+  long long lo, hi;
+  chunk_of(n, blockIdx.x, gridDim.x, &lo, &hi);
+  double* q = Q + (size_t)b * stride;
+  const double* z = Z + (size_t)b * stride;
+  for (long long i = lo + threadIdx.x; i < hi; i += kThreads) q[i] = fma(be, q[i], z[i]);
+}
+
+__global__ __launch_bounds__(kThreads) void copy_kernel(const double* __restrict__ X, double* __restrict__ Y,
+                                                        long long n, long long xs, long long ys) {
+  const int b = blockIdx.y;
+  long long lo, hi;
+  chunk_of(n, blockIdx.x, gridDim.x, &lo, &hi);
+  for (long long i = lo + threadIdx.x; i < hi; i += kThreads) Y[(size_t)b * ys + i] = X[(size_t)b * xs + i];
+}
+
+__global__ __launch_bounds__(kThreads) void fill_kernel(double* __restrict__ X, double v, long long n,
+                                                        long long stride) {
+  const int b = blockIdx.y;
+  long long lo, hi;
+  chunk_of(n, blockIdx.x, gridDim.x, &lo, &hi);
+  for (long long i = lo + threadIdx.x; i < hi; i += kThreads) X[(size_t)b * stride + i] = v;
+}
+
+__global__ void beta_kernel(const double* __restrict__ rz_new, double* __restrict__ rz_old,
+                            const double* __restrict__ zy, const double* __restrict__ alpha,
+                            double* __restrict__ beta, int flexible, int batch, const int* active) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  if (active && !active[b]) return;
+  double bt = flexible ? (-alpha[b] * zy[b] / rz_old[b]) : (rz_new[b] / rz_old[b]);
+  beta[b] = bt;
+  rz_old[b] = rz_new[b];
+}
+
+__global__ void scale_items_kernel(double* __restrict__ x, const double* __restrict__ f, int batch) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < batch) x[b] *= f[b];
+}
+
+// DIB kinetics, Sec. 7, eqs. (99)-(100); kin = rho, A1, A2, B, C, D, alpha, gamma, k2, k3
+__global__ __launch_bounds__(kThreads) void dib_source_kernel(const double* __restrict__ U, const double* __restrict__ V,
+                                                              double* __restrict__ TU, double* __restrict__ TV,
+                                                              long long n, long long stride, double rho, double A1,
+                                                              double A2, double Bc, double Cc, double Dc,
+                                                              double al, double ga, double k2, double k3,
+                                                              double tau) {
+  const int b = blockIdx.y;
+  long long lo, hi;
+  chunk_of(n, blockIdx.x, gridDim.x, &lo, &hi);
+  const size_t off = (size_t)b * stride;
+  for (long long i = lo + threadIdx.x; i < hi; i += kThreads) {
+    const double e = U[off + i], th = V[off + i];
+    const double f = A1 * (1.0 - th) * e - A2 * e * e * e - Bc * (th - al);
+    const double g = Cc * (1.0 + k2 * e) * (1.0 - th) * (1.0 - ga * (1.0 - th)) -
+                     Dc * th * (1.0 + ga * th) * (1.0 + k3 * e);
+    TU[off + i] = fma(tau * rho, f, e);
+    TV[off + i] = fma(tau * rho, g, th);
+  }
+}
+
+}  // namespace
+
+#define CHECK_LAUNCH() return hipGetLastError() == hipSuccess ? 0 : -1
+
+int launch_reduce(const double* partial, int n_partial, double* out, int batch, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_kernel, dim3(batch), dim3(kThreads), 0, s, partial, n_partial, out);
+  CHECK_LAUNCH();
+}
+int launch_dot_partial(const double* X, const double* Y, long long n, long long stride, int batch,
+                       double* partial, const int* active, hipStream_t s) {
+  hipLaunchKernelGGL(dot_kernel, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, X, Y, n, stride, partial, active);
+  CHECK_LAUNCH();
+}
+int launch_dot2_partial(const double* A, const double* B, const double* C, const double* D, long long n,
+                        long long stride, int batch, double* p1, double* p2, const int* active, hipStream_t s) {
+  hipLaunchKernelGGL(dot2_kernel, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, A, B, C, D, n, stride, p1, p2,
+                     active);
+  CHECK_LAUNCH();
+}
+int launch_residual(const double* Rhs, const double* Y, double* R, long long n, long long stride,
+                    long long rhs_stride, int batch, double* partial, const int* active, hipStream_t s) {
+  hipLaunchKernelGGL(residual_kernel, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, Rhs, Y, R, n, stride,
+                     rhs_stride, partial, active);
+  CHECK_LAUNCH();
+}
+int launch_cg_update(double* U, double* R, const double* Q, const double* Y, const double* num, const double* den,
+                     double* alpha_out, long long n, long long stride, long long u_stride, int batch,
+                     double* partial, const int* active, hipStream_t s) {
+  hipLaunchKernelGGL(cg_update_kernel, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, U, R, Q, Y, num, den,
+                     alpha_out, n, stride, u_stride, partial, active);
+  CHECK_LAUNCH();
+}
+int launch_direction(double* Q, const double* Z, const double* beta, long long n, long long stride, int batch,
+                     const int* active, hipStream_t s) {
+  hipLaunchKernelGGL(direction_kernel, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, Q, Z, beta, n, stride,
+                     active);
+  CHECK_LAUNCH();
+}
+int launch_copy(const double* X, double* Y, long long n, long long xs, long long ys, int batch, hipStream_t s) {
+  hipLaunchKernelGGL(copy_kernel, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, X, Y, n, xs, ys);
+  CHECK_LAUNCH();
+}
+int launch_fill(double* X, double v, long long n, long long stride, int batch, hipStream_t s) {
+  hipLaunchKernelGGL(fill_kernel, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, X, v, n, stride);
+  CHECK_LAUNCH();
+}
+int launch_beta(const double* rz_new, double* rz_old, const double* zy, const double* alpha, double* beta,
+                int flexible, int batch, const int* active, hipStream_t s) {
+  hipLaunchKernelGGL(beta_kernel, dim3((batch + 63) / 64), dim3(64), 0, s, rz_new, rz_old, zy, alpha, beta,
+                     flexible, batch, active);
+  CHECK_LAUNCH();
+}
+int launch_scale_items(double* x, const double* f, int batch, hipStream_t s) {
+  hipLaunchKernelGGL(scale_items_kernel, dim3((batch + 63) / 64), dim3(64), 0, s, x, f, batch);
+  CHECK_LAUNCH();
+}
+int launch_dib_source(const double* U, const double* V, double* TU, double* TV, long long n, long long stride,
+                      int batch, const double* k, double tau, hipStream_t s) {
+  hipLaunchKernelGGL(dib_source_kernel, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, U, V, TU, TV, n, stride,
+                     k[0], k[1], k[2], k[3], k[4], k[5], k[6], k[7], k[8], k[9], tau);
+  CHECK_LAUNCH();
+}
+
+}  // namespace mofem

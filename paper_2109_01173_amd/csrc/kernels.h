@@ -1,0 +1,112 @@
+// Kernel argument blocks and launchers (host-callable, defined in the .hip
+// translation units).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace mofem {
+
+// ---- banded multiterm operator (k_band.hip) --------------------------------
+struct BandArgs {
+  const double* X;         // input items
+  long long in_stride;     // elements between input items
+  int ld_x;                // input row length
+  double* Y;               // output items
+  long long out_stride;
+  int ld_y;
+  int qs, qt;              // output shape
+  int ns_in, nt_in;        // input shape
+  int off_s, off_t;        // input index of output (i, j): (i + off_s, j + off_t)
+  int ph_s;                // node index of output row i is i + ph_s
+  int n_rowblk;            // row blocks per item
+  const double* left;      // [qs][nt][2kb+1] row bands (input row i+off_s+d-kb)
+  const double* right;     // [nt][2kb+1][qt] column bands (input col j+off_t+d-kb)
+  int scaled_mask;         // bit t: term t times item_scale[b]
+  const double* item_scale;  // [batch] or null
+  double* dot_partial;     // [batch][n_partial] or null: <X, Y> per tile
+  int n_partial;           // tiles per item
+  const int* active;       // [batch] or null: skip items with active[b] == 0
+};
+int band_rows_per_block(int kb);
+int band_cols_per_block(int kb);
+int band_supported_terms(int nt);
+int launch_band_apply(const BandArgs& a, int kb, int nt, int batch, bool pattern, hipStream_t s);
+
+// ---- dense transforms on MFMA (k_gemm.hip) ------------------------------------
+// C[m][n] = sum_k A[m][k] B[n][k]   (both operands K-contiguous, "NT").
+// Padded operands: rows and row length rounded up to kPad, zero padding.
+constexpr int kPad = 128;
+__host__ __device__ inline int pad_up(int x) { return (x + kPad - 1) / kPad * kPad; }
+
+enum GemmPrec { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_BF16 = 2, GEMM_BF16X3 = 3 };
+enum GemmAMode { A_F64_RAW = 0, A_PADDED = 1 };          // raw: FP64, ld = K, bounds checked
+enum GemmOMode { O_PAD_T = 0, O_PAD_N = 1, O_F64_RAW = 2 };  // raw: FP64 row-major ld = N
+
+struct GemmArgs {
+  int M, N, K;             // logical sizes
+  // A: raw FP64 (ld = K) or padded (rows pad_up(M), ld pad_up(K))
+  const double* a64;       // FP64 raw or padded FP64
+  const void* a_hi;        // padded low-precision operand (FP32 / BF16 hi)
+  const void* a_lo;        // padded BF16 lo (BF16X3)
+  long long a_stride;      // elements between batch items (0 = shared)
+  // B: always padded (rows pad_up(N), ld pad_up(K))
+  const double* b64;
+  const void* b_hi;
+  const void* b_lo;
+  long long b_stride;
+  // output
+  double* c64;             // FP64 output (raw or padded)
+  void* c_hi;              // low-precision padded output (FP32 / BF16 hi)
+  void* c_lo;              // BF16 lo
+  long long c_stride;
+  // epilogue: divide by D_ij = alpha + s_b (bs lam_i + bt mu_j + d lam_i mu_j)
+  int divide;
+  const double* lam;       // [M]
+  const double* mu;        // [N]
+  double alpha, beta_s, beta_t, delta;
+  const double* item_scale;  // [batch] or null
+  double out_scale;        // multiply the result (before the epilogue division)
+  const int* active;
+};
+int launch_gemm(const GemmArgs& g, int prec, int amode, int omode, int batch, hipStream_t s);
+
+// ---- vector kernels of the PCG recurrence (k_vec.hip) -----------------------
+constexpr int kVecBlocks = 240;   // partial sums per item
+int launch_reduce(const double* partial, int n_partial, double* out, int batch, hipStream_t s);
+// out[b] = sum(X_b * Y_b) partials (X may equal Y)
+int launch_dot_partial(const double* X, const double* Y, long long n, long long stride,
+                       int batch, double* partial, const int* active, hipStream_t s);
+// two dots at once: <A, B> and <C, D>
+int launch_dot2_partial(const double* A, const double* B, const double* C, const double* D,
+                        long long n, long long stride, int batch, double* partial1,
+                        double* partial2, const int* active, hipStream_t s);
+// R = Rhs - Y  (and partial <R, R>)
+int launch_residual(const double* Rhs, const double* Y, double* R, long long n, long long stride,
+                    long long rhs_stride, int batch, double* partial, const int* active, hipStream_t s);
+// alpha_b = num_b / den_b; U += alpha Q; R -= alpha Y; partial <R, R>
+int launch_cg_update(double* U, double* R, const double* Q, const double* Y, const double* num,
+                     const double* den, double* alpha_out, long long n, long long stride,
+                     long long u_stride, int batch, double* partial, const int* active,
+                     hipStream_t s);
+// Q = Z + beta Q with beta_b given
+int launch_direction(double* Q, const double* Z, const double* beta, long long n,
+                     long long stride, int batch, const int* active, hipStream_t s);
+// Y = X copy; X = 0
+int launch_copy(const double* X, double* Y, long long n, long long xs, long long ys, int batch,
+                hipStream_t s);
+int launch_fill(double* X, double v, long long n, long long stride, int batch, hipStream_t s);
+// beta_b from the recurrence: standard  rz_new / rz_old ; flexible
+// -alpha * zy / rz_old ; also rz_old := rz_new
+int launch_beta(const double* rz_new, double* rz_old, const double* zy, const double* alpha,
+                double* beta, int flexible, int batch, const int* active, hipStream_t s);
+// x_b *= f_b for b < batch
+int launch_scale_items(double* x, const double* f, int batch, hipStream_t s);
+// elementwise DIB kinetics: T_u = U + tau rho f(U, V), T_v = V + tau rho g(U, V)
+int launch_dib_source(const double* U, const double* V, double* TU, double* TV, long long n,
+                      long long stride, int batch, const double* kin, double tau,
+                      hipStream_t s);
+
+}  // namespace mofem

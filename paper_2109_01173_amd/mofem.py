@@ -1,0 +1,377 @@
+"""ctypes binding of libmofem (include/mofem.h).
+
+Argument marshalling only: every computation runs in the native library
+(host C++ for assembly and eigen-decomposition, HIP kernels on the GPU for
+everything else).  Device arrays are torch tensors on the current HIP device
+(float64, contiguous); the current torch stream is passed to the library.
+If the shared library is missing this module raises at import time - there
+is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+# torch ships its own HIP runtime (same soname as ROCm's libamdhip64.so.7).
+# Import it first so that libmofem binds to that already-loaded runtime; two
+# HIP runtimes in one process cannot share the device.
+import torch  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("MOFEM_LIB", os.path.join(_HERE, "libmofem.so"))
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libmofem.so not found at %s - build it first "
+                      "(python -m paper_2109_01173_amd.build)" % LIB_PATH)
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ---- constants (mirror include/mofem.h) -------------------------------------
+OK = 0
+E_ARG, E_HIP, E_NOMEM, E_BREAKDOWN, E_MAXIT, E_UNSUPPORTED, E_NOTFINITE, E_NUMERIC = (
+    -1, -2, -3, -4, -5, -6, -7, -8)
+W_ONE, W_POLY, W_PROFILE, W_PROFILE_D, W_PROFILE_INV, W_PROFILE_D2L, W_CALLBACK = range(7)
+PREC_F64, PREC_F32, PREC_BF16, PREC_BF16X3 = range(4)
+PCG_FLEXIBLE, PCG_ZERO_GUESS, PCG_TAU_STOP = 1, 2, 4
+KIN_NONE, KIN_DIB = 0, 1
+TRACE_BAND, TRACE_GEMM_F64, TRACE_GEMM_BF16X3, TRACE_GEMM_BF16, TRACE_VEC = range(5)
+MAX_TERMS = 8
+
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+WeightFn = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.c_double, ctypes.c_void_p)
+
+
+class Weight(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("p", ctypes.c_double * 4), ("fn", WeightFn), ("ctx", _vp)]
+
+
+class OpDesc(ctypes.Structure):
+    _fields_ = [("kb", ctypes.c_int), ("elem_order", ctypes.c_int), ("n_s", ctypes.c_int),
+                ("n_t", ctypes.c_int), ("trim_s", ctypes.c_int), ("trim_t", ctypes.c_int),
+                ("full_input", ctypes.c_int), ("n_terms", ctypes.c_int),
+                ("left", _vp * MAX_TERMS), ("right", _vp * MAX_TERMS),
+                ("left_transpose", ctypes.c_int * MAX_TERMS),
+                ("right_transpose", ctypes.c_int * MAX_TERMS),
+                ("coef", ctypes.c_double * MAX_TERMS), ("scaled", ctypes.c_int * MAX_TERMS)]
+
+
+class PrecDesc(ctypes.Structure):
+    _fields_ = [("kb", ctypes.c_int), ("n_s", ctypes.c_int), ("n_t", ctypes.c_int),
+                ("trim_s", ctypes.c_int), ("trim_t", ctypes.c_int),
+                ("Ks", _vp), ("Ms", _vp), ("Kt", _vp), ("Mt", _vp),
+                ("alpha", ctypes.c_double), ("beta_s", ctypes.c_double),
+                ("beta_t", ctypes.c_double), ("delta", ctypes.c_double),
+                ("precision", ctypes.c_int)]
+
+
+class ImexDesc(ctypes.Structure):
+    _fields_ = [("op", _vp), ("prec", _vp), ("mass", _vp), ("tau", ctypes.c_double),
+                ("d", ctypes.c_double * 2), ("n_species", ctypes.c_int),
+                ("kinetics", ctypes.c_int), ("kin", ctypes.c_double * 10),
+                ("tol", ctypes.c_double), ("maxit", ctypes.c_int), ("flags", ctypes.c_uint)]
+
+
+def _proto(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_ll = ctypes.c_longlong
+_sz = ctypes.c_size_t
+mofem_version = _proto("mofem_version", ctypes.c_int, [])
+mofem_last_error = _proto("mofem_last_error", ctypes.c_char_p, [])
+mofem_assemble_1d = _proto("mofem_assemble_1d", ctypes.c_int,
+                           [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                            ctypes.c_int, ctypes.c_int, ctypes.POINTER(Weight), ctypes.c_int, _vp])
+mofem_geneig_host = _proto("mofem_geneig_host", ctypes.c_int,
+                           [ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp, _vp])
+mofem_op_create = _proto("mofem_op_create", ctypes.c_int, [ctypes.POINTER(OpDesc), ctypes.POINTER(_vp)])
+mofem_op_destroy = _proto("mofem_op_destroy", ctypes.c_int, [_vp])
+mofem_op_shape = _proto("mofem_op_shape", ctypes.c_int, [_vp, _ip, _ip, _ip, _ip])
+mofem_op_apply = _proto("mofem_op_apply", ctypes.c_int,
+                        [_vp, _vp, _ll, _vp, _ll, ctypes.c_int, _vp, _vp, _vp])
+mofem_prec_setup = _proto("mofem_prec_setup", ctypes.c_int, [ctypes.POINTER(PrecDesc), ctypes.POINTER(_vp)])
+mofem_prec_destroy = _proto("mofem_prec_destroy", ctypes.c_int, [_vp])
+mofem_prec_set_coeffs = _proto("mofem_prec_set_coeffs", ctypes.c_int,
+                               [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double])
+mofem_prec_set_precision = _proto("mofem_prec_set_precision", ctypes.c_int, [_vp, ctypes.c_int])
+mofem_prec_eigenvalues = _proto("mofem_prec_eigenvalues", ctypes.c_int, [_vp, _vp, _vp])
+mofem_prec_workspace_size = _proto("mofem_prec_workspace_size", _sz, [_vp, ctypes.c_int])
+mofem_prec_apply = _proto("mofem_prec_apply", ctypes.c_int,
+                          [_vp, _vp, _vp, _ll, ctypes.c_int, _vp, _vp, _sz, _vp])
+mofem_pcg_workspace_size = _proto("mofem_pcg_workspace_size", _sz, [_vp, _vp, ctypes.c_int])
+mofem_pcg_solve = _proto("mofem_pcg_solve", ctypes.c_int,
+                         [_vp, _vp, _vp, _vp, _ll, ctypes.c_int, _vp, ctypes.c_double, ctypes.c_int,
+                          ctypes.c_uint, _vp, _sz, _vp, _vp, _vp])
+mofem_imex_workspace_size = _proto("mofem_imex_workspace_size", _sz, [ctypes.POINTER(ImexDesc), ctypes.c_int])
+mofem_imex_step = _proto("mofem_imex_step", ctypes.c_int,
+                         [ctypes.POINTER(ImexDesc), _vp, _ll, ctypes.c_int, _vp, _sz, _vp, _vp])
+mofem_trace_enable = _proto("mofem_trace_enable", ctypes.c_int, [ctypes.c_int])
+mofem_trace_read = _proto("mofem_trace_read", ctypes.c_int,
+                          [ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_longlong), _dp])
+
+EXPORTS = ["mofem_version", "mofem_last_error", "mofem_assemble_1d", "mofem_geneig_host",
+           "mofem_op_create", "mofem_op_destroy", "mofem_op_shape", "mofem_op_apply",
+           "mofem_prec_setup", "mofem_prec_destroy", "mofem_prec_set_coeffs",
+           "mofem_prec_set_precision", "mofem_prec_eigenvalues", "mofem_prec_workspace_size",
+           "mofem_prec_apply", "mofem_pcg_workspace_size", "mofem_pcg_solve",
+           "mofem_imex_workspace_size", "mofem_imex_step", "mofem_trace_enable", "mofem_trace_read"]
+
+
+class MofemError(RuntimeError):
+    def __init__(self, code, where):
+        msg = mofem_last_error().decode(errors="replace")
+        super().__init__("%s failed (%d): %s" % (where, code, msg))
+        self.code = code
+
+
+def _check(rc, where):
+    if rc != OK:
+        raise MofemError(rc, where)
+
+
+def _hptr(a):
+    return a.ctypes.data_as(_vp)
+
+
+# ---- host entry points ---------------------------------------------------------
+def weight(kind=W_ONE, p=(0.0, 0.0, 0.0, 0.0)):
+    w = Weight()
+    w.kind = kind
+    for i, v in enumerate(p):
+        w.p[i] = float(v)
+    return w
+
+
+def assemble_1d(order, m_elem, di, dj, w=None, x0=0.0, x1=1.0, nq=0):
+    """DIA band (2kb+1, n) of int psi_i^(di) psi_j^(dj) w over [x0, x1]."""
+    kb = max(order, 1)
+    n = kb * m_elem + 1
+    band = np.zeros((2 * kb + 1, n))
+    rc = mofem_assemble_1d(order, m_elem, x0, x1, di, dj, ctypes.byref(w) if w is not None else None,
+                           nq, _hptr(band))
+    _check(rc, "mofem_assemble_1d")
+    return band
+
+
+def geneig_host(K_band, M_band, trim):
+    kb = (K_band.shape[0] - 1) // 2
+    n = K_band.shape[1]
+    q = n - 2 * trim
+    lam = np.zeros(q)
+    V = np.zeros((q, q))
+    K = np.ascontiguousarray(K_band, dtype=np.float64)
+    M = np.ascontiguousarray(M_band, dtype=np.float64)
+    _check(mofem_geneig_host(n, kb, _hptr(K), _hptr(M), trim, _hptr(lam), _hptr(V)), "mofem_geneig_host")
+    return lam, V
+
+
+def band_to_dense(band):
+    """Dense matrix of a DIA band (helper for tests and diagnostics)."""
+    w, n = band.shape
+    kb = (w - 1) // 2
+    D = np.zeros((n, n))
+    for d in range(w):
+        i = np.arange(n)
+        j = i + d - kb
+        ok = (j >= 0) & (j < n)
+        D[i[ok], j[ok]] = band[d, i[ok]]
+    return D
+
+
+# ---- device entry points (torch tensors) -----------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def _dptr(t):
+    if t is None:
+        return None
+    torch = _torch()
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if t.dtype not in (torch.float64, torch.int32, torch.uint8):
+        raise ValueError("expected float64 data")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return _vp(t.data_ptr())
+
+
+def _stream(stream):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return _vp(s.cuda_stream)
+
+
+class Operator:
+    """Y = sum_t c_t op(L_t) X op(R_t) (see mofem_op_desc)."""
+
+    def __init__(self, terms, n_s, n_t, kb, trim_s=0, trim_t=0, full_input=False, elem_order=0):
+        d = OpDesc()
+        d.kb, d.elem_order, d.n_s, d.n_t = kb, elem_order, n_s, n_t
+        d.trim_s, d.trim_t, d.full_input, d.n_terms = trim_s, trim_t, int(full_input), len(terms)
+        self._keep = []
+        for i, t in enumerate(terms):
+            L = np.ascontiguousarray(t["left"], dtype=np.float64)
+            R = np.ascontiguousarray(t["right"], dtype=np.float64)
+            self._keep += [L, R]
+            d.left[i] = L.ctypes.data
+            d.right[i] = R.ctypes.data
+            d.left_transpose[i] = int(t.get("left_T", False))
+            d.right_transpose[i] = int(t.get("right_T", False))
+            d.coef[i] = float(t.get("coef", 1.0))
+            d.scaled[i] = int(t.get("scaled", False))
+        h = _vp()
+        _check(mofem_op_create(ctypes.byref(d), ctypes.byref(h)), "mofem_op_create")
+        self.handle = h
+        self._keep = None
+        qs, qt, i_s, i_t = (ctypes.c_int() for _ in range(4))
+        _check(mofem_op_shape(h, ctypes.byref(qs), ctypes.byref(qt), ctypes.byref(i_s), ctypes.byref(i_t)),
+               "mofem_op_shape")
+        self.shape = (qs.value, qt.value)
+        self.in_shape = (i_s.value, i_t.value)
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            mofem_op_destroy(self.handle)
+            self.handle = None
+
+    def apply(self, X, Y=None, item_scale=None, dot=False, stream=None):
+        torch = _torch()
+        batch = X.shape[0]
+        if tuple(X.shape[1:]) != self.in_shape:
+            raise ValueError("input shape %s, operator expects %s" % (tuple(X.shape[1:]), self.in_shape))
+        if Y is None:
+            Y = torch.empty((batch,) + self.shape, dtype=torch.float64, device=X.device)
+        dots = torch.empty(batch, dtype=torch.float64, device=X.device) if dot else None
+        in_stride = self.in_shape[0] * self.in_shape[1]
+        out_stride = self.shape[0] * self.shape[1]
+        rc = mofem_op_apply(self.handle, _dptr(X), in_stride, _dptr(Y), out_stride, batch,
+                            _dptr(item_scale), _dptr(dots), _stream(stream))
+        _check(rc, "mofem_op_apply")
+        return (Y, dots) if dot else Y
+
+
+class Preconditioner:
+    """Spectral single-term preconditioner (see mofem_prec_desc)."""
+
+    def __init__(self, Ks, Ms, Kt, Mt, coeffs, trim_s=0, trim_t=0, precision=PREC_F64):
+        d = PrecDesc()
+        self._keep = [np.ascontiguousarray(a, dtype=np.float64) for a in (Ks, Ms, Kt, Mt)]
+        d.kb = (self._keep[0].shape[0] - 1) // 2
+        d.n_s, d.n_t = self._keep[0].shape[1], self._keep[2].shape[1]
+        d.trim_s, d.trim_t = trim_s, trim_t
+        d.Ks, d.Ms, d.Kt, d.Mt = (a.ctypes.data for a in self._keep)
+        d.alpha, d.beta_s, d.beta_t, d.delta = (float(c) for c in coeffs)
+        d.precision = precision
+        h = _vp()
+        _check(mofem_prec_setup(ctypes.byref(d), ctypes.byref(h)), "mofem_prec_setup")
+        self.handle = h
+        self._keep = None
+        self.shape = (d.n_s - 2 * trim_s, d.n_t - 2 * trim_t)
+        self.precision = precision
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            mofem_prec_destroy(self.handle)
+            self.handle = None
+
+    def set_coeffs(self, alpha, beta_s, beta_t, delta):
+        _check(mofem_prec_set_coeffs(self.handle, alpha, beta_s, beta_t, delta), "mofem_prec_set_coeffs")
+
+    def set_precision(self, precision):
+        _check(mofem_prec_set_precision(self.handle, precision), "mofem_prec_set_precision")
+        self.precision = precision
+
+    def eigenvalues(self):
+        lam, mu = np.zeros(self.shape[0]), np.zeros(self.shape[1])
+        _check(mofem_prec_eigenvalues(self.handle, _hptr(lam), _hptr(mu)), "mofem_prec_eigenvalues")
+        return lam, mu
+
+    def workspace_size(self, batch):
+        return int(mofem_prec_workspace_size(self.handle, batch))
+
+    def apply(self, R, Z=None, item_scale=None, workspace=None, stream=None):
+        torch = _torch()
+        batch = R.shape[0]
+        if Z is None:
+            Z = torch.empty_like(R)
+        ws = workspace
+        if ws is None:
+            ws = torch.empty(self.workspace_size(batch), dtype=torch.uint8, device=R.device)
+        rc = mofem_prec_apply(self.handle, _dptr(R), _dptr(Z), self.shape[0] * self.shape[1], batch,
+                              _dptr(item_scale),
+                              _dptr(ws), ws.numel(), _stream(stream))
+        _check(rc, "mofem_prec_apply")
+        return Z
+
+
+def pcg_workspace(op, prec, batch, device="cuda"):
+    torch = _torch()
+    n = int(mofem_pcg_workspace_size(op.handle, prec.handle, batch))
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def pcg_solve(op, prec, rhs, U, tol=1e-10, maxit=500, flags=0, item_scale=None, workspace=None,
+              stream=None, raise_on_error=True):
+    """Solve L(U_b) = rhs_b for every item; returns (iters, relres, rc)."""
+    batch = rhs.shape[0]
+    if workspace is None:
+        workspace = pcg_workspace(op, prec, batch, rhs.device)
+    iters = np.zeros(batch, dtype=np.int32)
+    relres = np.zeros(batch)
+    rc = mofem_pcg_solve(op.handle, prec.handle, _dptr(rhs), _dptr(U), op.shape[0] * op.shape[1], batch,
+                         _dptr(item_scale), tol, maxit, flags, _dptr(workspace), workspace.numel(),
+                         _hptr(iters), _hptr(relres), _stream(stream))
+    if raise_on_error:
+        _check(rc, "mofem_pcg_solve")
+    return iters, relres, rc
+
+
+def trace_enable(on=True):
+    _check(mofem_trace_enable(int(on)), "mofem_trace_enable")
+
+
+def trace_read(cls):
+    """(total kernel milliseconds, launches, batch items) for one kernel class."""
+    ms, n, items = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double()
+    _check(mofem_trace_read(cls, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(items)), "mofem_trace_read")
+    return ms.value, n.value, items.value
+
+
+class Imex:
+    """IMEX Euler stepper (see mofem_imex_desc)."""
+
+    def __init__(self, op, prec, mass, tau, d, kinetics=KIN_NONE, kin=None, tol=1e-10, maxit=200, flags=0):
+        self.desc = ImexDesc()
+        self.desc.op, self.desc.prec, self.desc.mass = op.handle, prec.handle, mass.handle
+        self.desc.tau = tau
+        self.desc.n_species = len(d)
+        for i, v in enumerate(d):
+            self.desc.d[i] = v
+        self.desc.kinetics = kinetics
+        if kin is not None:
+            for i, v in enumerate(kin):
+                self.desc.kin[i] = v
+        self.desc.tol, self.desc.maxit, self.desc.flags = tol, maxit, flags
+        self._refs = (op, prec, mass)
+
+    def workspace(self, batch, device="cuda"):
+        torch = _torch()
+        n = int(mofem_imex_workspace_size(ctypes.byref(self.desc), batch))
+        return torch.empty(n, dtype=torch.uint8, device=device)
+
+    def step(self, state, batch, workspace=None, stream=None):
+        """state: tensor (n_species * batch, q_s, q_t), species major."""
+        if workspace is None:
+            workspace = self.workspace(batch, state.device)
+        iters = np.zeros(state.shape[0], dtype=np.int32)
+        q_s, q_t = state.shape[1], state.shape[2]
+        rc = mofem_imex_step(ctypes.byref(self.desc), _dptr(state), q_s * q_t, batch,
+                             _dptr(workspace), workspace.numel(), _hptr(iters), _stream(stream))
+        _check(rc, "mofem_imex_step")
+        return iters

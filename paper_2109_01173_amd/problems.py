@@ -1,0 +1,105 @@
+"""Composition of the MO-FEM operators from the library's 1D matrices.
+
+Only bookkeeping happens here: which assembled 1D matrix goes into which term
+of the multiterm operator.  Assembly (``mofem_assemble_1d``), the
+eigen-decomposition and every apply/solve run in libmofem.  The one piece of
+arithmetic done in Python is the setup-time sum of two assembled bands
+(B1 + gamma M3, the left factor of one elliptic term), O(k n) numbers.
+
+Operators (rows = s, the base coordinate; columns = t):
+* x-normal elliptic, eq. (73) (lumped: eq. (75)):
+    M1 U A + (B1 + g M3) U M + M2 U B2 - C2 U C1 - C2^T U C1^T
+  right-hand side eq. (74): M3 F M with F on all nodes (rows/cols trimmed);
+* x-normal IMEX, eq. (91): M3 U M + c (the five terms with g = 0), with
+  c = d tau passed per batch item;
+* rectangle (eq. (28) on [0, l]^2): elliptic (A + g M) U M + M U A,
+  IMEX  M U M + c (A U M + M U A).
+Preconditioners: the spectral single-term form with the pencils
+(B1, M3) x (A, M) on x-normal domains and (A, M) x (A, M) on the rectangle.
+"""
+import math
+
+import numpy as np
+
+from . import mofem as mf
+
+
+def _assemble(order, m, di, dj, kind=mf.W_ONE, p=(0, 0, 0, 0), x0=0.0, x1=1.0):
+    w = None if kind == mf.W_ONE else mf.weight(kind, p)
+    return mf.assemble_1d(order, m, di, dj, w, x0, x1)
+
+
+class XNormal:
+    """P_k (k = 1..4) or lumped P1 (lumped=True, k = 1) on the x-normal
+    domain {0 <= X <= 1, 0 <= Y <= L(X)}, L(s) = 1 + amp sin(pi s)."""
+
+    def __init__(self, k, m, bc, gamma=0.0, amp=0.3, lumped=False, precision=mf.PREC_F64,
+                 imex=False):
+        self.k, self.m, self.bc, self.gamma, self.lumped = k, m, bc, gamma, lumped
+        order = 0 if lumped else k
+        self.kb = 1 if lumped else k
+        self.n = self.kb * m + 1
+        trim = 1 if bc == "dirichlet" else 0
+        self.trim = trim
+        self.q = self.n - 2 * trim
+        prof = (1.0, amp, math.pi, 0.0)
+        B1 = _assemble(order, m, 1, 1, mf.W_PROFILE, prof)
+        C2 = _assemble(order, m, 1, 0, mf.W_PROFILE_D, prof)
+        M1 = _assemble(order, m, 0, 0, mf.W_PROFILE_INV, prof)
+        M2 = _assemble(order, m, 0, 0, mf.W_PROFILE_D2L, prof)
+        M3 = _assemble(order, m, 0, 0, mf.W_PROFILE, prof)
+        A = _assemble(order, m, 1, 1)
+        M = _assemble(order, m, 0, 0)
+        B2 = _assemble(order, m, 1, 1, mf.W_POLY, (0, 0, 1, 0))
+        C1 = _assemble(order, m, 1, 0, mf.W_POLY, (0, 1, 0, 0))
+        self.bands = dict(B1=B1, C2=C2, M1=M1, M2=M2, M3=M3, A=A, M=M, B2=B2, C1=C1)
+        eo = 0 if lumped else k
+        common = dict(n_s=self.n, n_t=self.n, kb=self.kb, trim_s=trim, trim_t=trim, elem_order=eo)
+        if imex:
+            terms = [dict(left=M3, right=M),
+                     dict(left=M1, right=A, scaled=True),
+                     dict(left=B1, right=M, scaled=True),
+                     dict(left=M2, right=B2, scaled=True),
+                     dict(left=C2, right=C1, coef=-1.0, scaled=True),
+                     dict(left=C2, right=C1, coef=-1.0, left_T=True, right_T=True, scaled=True)]
+            coeffs = (1.0, 1.0, 1.0, 0.0)
+        else:
+            terms = [dict(left=M1, right=A),
+                     dict(left=B1 + gamma * M3, right=M),
+                     dict(left=M2, right=B2),
+                     dict(left=C2, right=C1, coef=-1.0),
+                     dict(left=C2, right=C1, coef=-1.0, left_T=True, right_T=True)]
+            coeffs = (gamma, 1.0, 1.0, 0.0)
+        self.op = mf.Operator(terms, **common)
+        self.rhs_op = mf.Operator([dict(left=M3, right=M)], full_input=True, **common)
+        self.mass = mf.Operator([dict(left=M3, right=M)], **common)
+        self.prec = mf.Preconditioner(B1, M3, A, M, coeffs, trim, trim, precision)
+
+
+class Rect:
+    """Square Kronecker form eq. (28) on [0, length]^2 (P_k or lumped P1)."""
+
+    def __init__(self, k, m, bc, length=1.0, gamma=0.0, lumped=False, precision=mf.PREC_F64,
+                 imex=False):
+        order = 0 if lumped else k
+        self.kb = 1 if lumped else k
+        self.n = self.kb * m + 1
+        trim = 1 if bc == "dirichlet" else 0
+        self.trim = trim
+        self.q = self.n - 2 * trim
+        A = _assemble(order, m, 1, 1, x1=length)
+        M = _assemble(order, m, 0, 0, x1=length)
+        self.bands = dict(A=A, M=M)
+        eo = 0 if lumped else k
+        common = dict(n_s=self.n, n_t=self.n, kb=self.kb, trim_s=trim, trim_t=trim, elem_order=eo)
+        if imex:
+            terms = [dict(left=M, right=M), dict(left=A, right=M, scaled=True),
+                     dict(left=M, right=A, scaled=True)]
+            coeffs = (1.0, 1.0, 1.0, 0.0)
+        else:
+            terms = [dict(left=A + gamma * M, right=M), dict(left=M, right=A)]
+            coeffs = (gamma, 1.0, 1.0, 0.0)
+        self.op = mf.Operator(terms, **common)
+        self.rhs_op = mf.Operator([dict(left=M, right=M)], full_input=True, **common)
+        self.mass = mf.Operator([dict(left=M, right=M)], **common)
+        self.prec = mf.Preconditioner(A, M, A, M, coeffs, trim, trim, precision)

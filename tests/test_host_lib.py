@@ -1,0 +1,118 @@
+"""CPU tests of libmofem's host side: the shared library loads, exports every
+symbol include/mofem.h declares, and its host-only entry points (1D assembly,
+generalised eigen-decomposition, argument checking) agree with the oracle.
+No GPU call is made here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle import fem1d
+from workloads import L_profile, dL_profile
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mofem.h")
+
+mf = pytest.importorskip("paper_2109_01173_amd.mofem",
+                         reason="libmofem.so not built (python -m paper_2109_01173_amd.build)")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mofem_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    lib = ctypes.CDLL(mf.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 19
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(mf.EXPORTS) == set(names)
+
+
+PROF = (1.0, 0.3, np.pi, 0.0)
+
+
+@pytest.mark.parametrize("order", [0, 1, 2, 3, 4])
+def test_assembly_matches_oracle(order):
+    k = max(order, 1)
+    lumped = order == 0
+    m = 7
+    cases = [
+        (1, 1, mf.W_PROFILE, PROF, L_profile),
+        (1, 0, mf.W_PROFILE_D, PROF, dL_profile),
+        (0, 0, mf.W_PROFILE_INV, PROF, lambda s: 1.0 / L_profile(s)),
+        (0, 0, mf.W_PROFILE_D2L, PROF, lambda s: dL_profile(s) ** 2 / L_profile(s)),
+        (0, 0, mf.W_ONE, (0, 0, 0, 0), None),
+        (1, 1, mf.W_POLY, (0, 0, 1, 0), lambda t: t ** 2),
+        (1, 0, mf.W_POLY, (0, 1, 0, 0), lambda t: t),
+    ]
+    for di, dj, kind, p, fw in cases:
+        w = None if kind == mf.W_ONE else mf.weight(kind, p)
+        got = mf.band_to_dense(mf.assemble_1d(order, m, di, dj, w))
+        ref = fem1d.assemble(k, m, di, dj, fw, lumped=lumped)
+        assert np.abs(got - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()), (di, dj, kind)
+
+
+def test_assembly_interval_and_callback():
+    calls = []
+
+    def f(x, ctx):
+        calls.append(x)
+        return 2.0 + x
+
+    cb = mf.WeightFn(f)
+    w = mf.Weight()
+    w.kind = mf.W_CALLBACK
+    w.fn = cb
+    got = mf.band_to_dense(mf.assemble_1d(2, 3, 0, 0, w, x0=0.0, x1=20.0))
+    ref = fem1d.assemble(2, 3, 0, 0, lambda x: 2.0 + x, x0=0.0, x1=20.0)
+    assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
+    assert len(calls) == 3 * 12
+
+
+@pytest.mark.parametrize("k,m,trim", [(1, 40, 1), (2, 30, 1), (3, 20, 0), (4, 15, 1)])
+def test_geneig_matches_scipy(k, m, trim):
+    K = mf.assemble_1d(k, m, 1, 1, mf.weight(mf.W_PROFILE, PROF))
+    M = mf.assemble_1d(k, m, 0, 0, mf.weight(mf.W_PROFILE, PROF))
+    lam, V = mf.geneig_host(K, M, trim)
+    Kd, Md = mf.band_to_dense(K), mf.band_to_dense(M)
+    if trim:
+        Kd, Md = Kd[1:-1, 1:-1], Md[1:-1, 1:-1]
+    lr = sla.eigh(Kd, Md, eigvals_only=True)
+    assert np.abs(lam - lr).max() <= 1e-12 * np.abs(lr).max()
+    assert np.abs(V.T @ Md @ V - np.eye(V.shape[0])).max() < 1e-12
+    res = Kd @ V - Md @ V * lam
+    assert np.linalg.norm(res) <= 1e-13 * np.linalg.norm(Kd, 2) * np.linalg.norm(V)
+
+
+def test_geneig_rejects_indefinite_mass():
+    K = mf.assemble_1d(1, 10, 1, 1)
+    M = -mf.assemble_1d(1, 10, 0, 0)
+    with pytest.raises(mf.MofemError) as e:
+        mf.geneig_host(K, M, 1)
+    assert e.value.code == mf.E_NUMERIC
+
+
+def test_argument_errors_are_reported():
+    band = np.zeros(100)
+    p = band.ctypes.data_as(ctypes.c_void_p)
+    assert mf.mofem_assemble_1d(5, 4, 0.0, 1.0, 0, 0, None, 0, p) == mf.E_ARG
+    assert b"order" in mf.mofem_last_error()
+    assert mf.mofem_assemble_1d(1, 0, 0.0, 1.0, 0, 0, None, 0, p) == mf.E_ARG
+    assert mf.mofem_assemble_1d(1, 4, 1.0, 0.0, 0, 0, None, 0, p) == mf.E_ARG
+    assert mf.mofem_assemble_1d(1, 4, 0.0, 1.0, 2, 0, None, 0, p) == mf.E_ARG
+    assert mf.mofem_assemble_1d(1, 4, 0.0, 1.0, 0, 0, None, 40, p) == mf.E_ARG
+    assert mf.mofem_assemble_1d(1, 4, 0.0, 1.0, 0, 0, None, 0, None) == mf.E_ARG
+    # handle entry points reject NULL before touching the device
+    assert mf.mofem_op_create(None, None) == mf.E_ARG
+    assert mf.mofem_prec_setup(None, None) == mf.E_ARG
+    assert mf.mofem_pcg_solve(None, None, None, None, 0, 1, None, 1e-8, 10, 0, None, 0, None, None,
+                              None) == mf.E_ARG
+    assert mf.mofem_op_apply(None, None, 0, None, 0, 1, None, None, None) == mf.E_ARG
+    assert mf.mofem_version() >= 100
