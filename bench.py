@@ -14,9 +14,9 @@ preconditioner, FP64 recurrence, true-residual check).  The one-off setup
 (1D assembly and the two FP64 eigen-decompositions) runs before timing and
 is reported separately.
 
-value = mixed-path solves/s (split-BF16 MFMA transforms, flexible PCG,
-FP64 recurrence); the FP64 path (FP64 MFMA transforms) is timed on the same
-GPU and reported beside it.  Kernel times come from the library's HIP-event
+value = mixed-path solves/s (split-BF16 MFMA transforms by default, flexible
+PCG, FP64 recurrence); the FP64 path (FP64 MFMA transforms) is timed on the
+same GPU and reported beside it.  Kernel times come from the library's HIP-event
 tracing, recorded on the launch stream inside the timed region.
 """
 import argparse
@@ -73,6 +73,8 @@ def main():
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--n", type=int, default=2049)
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--mixed", default="bf16x3", choices=["bf16x2", "bf16x3", "bf16"],
+                    help="transform precision of the mixed path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -94,7 +96,10 @@ def main():
     B = args.batch
 
     t0 = time.perf_counter()
-    G = XNormal(k, m, "dirichlet", gamma=gamma, precision=mf.PREC_BF16X3)
+    mixed = {"bf16x2": (mf.PREC_BF16X2, mf.TRACE_GEMM_BF16X2, 2, "gemm_bf16_kernel<BF_X2A|BF_X2B,*>"),
+             "bf16x3": (mf.PREC_BF16X3, mf.TRACE_GEMM_BF16X3, 3, "gemm_bf16_kernel<BF_X3,*>"),
+             "bf16": (mf.PREC_BF16, mf.TRACE_GEMM_BF16, 1, "gemm_bf16_kernel<BF_HH,*>")}[args.mixed]
+    G = XNormal(k, m, "dirichlet", gamma=gamma, precision=mixed[0])
     setup_s = time.perf_counter() - t0
     q = G.q
     log("setup (assembly + eigen-decompositions + upload): %.2f s, q = %d" % (setup_s, q))
@@ -119,11 +124,11 @@ def main():
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         mf.trace_enable(False)
-        tr = {c: mf.trace_read(c) for c in range(5)}
+        tr = {c: mf.trace_read(c) for c in range(mf.TRACE_CLASSES)}
         return dt, out, tr
 
     # ---- mixed path (headline) ---------------------------------------------------
-    G.prec.set_precision(mf.PREC_BF16X3)
+    G.prec.set_precision(mixed[0])
     for _ in range(args.warmup):
         step(mf.PCG_FLEXIBLE)
     dt_mx, (it_mx, rr_mx, _), tr_mx = timed(args.steps, mf.PCG_FLEXIBLE)
@@ -141,8 +146,8 @@ def main():
     # ---- roofline of the dominant kernel in the timed region ---------------------
     ms_by_cls = {c: tr_mx[c][0] for c in tr_mx}
     flop_per_item_gemm = 2.0 * q * q * q            # one transform product per item
-    g_ms, g_n, g_items = tr_mx[mf.TRACE_GEMM_BF16X3]
-    mfma_flop = 3.0 * flop_per_item_gemm * g_items   # split BF16: three products
+    g_ms, g_n, g_items = tr_mx[mixed[1]]
+    mfma_flop = mixed[2] * flop_per_item_gemm * g_items   # BF16 products per transform
     achieved_tf = mfma_flop / (g_ms * 1e-3) / 1e12 if g_ms > 0 else 0.0
     b_ms, b_n, b_items = tr_mx[mf.TRACE_BAND]
     op_bytes = 16.0 * q * q * b_items                # read X, write Y (FP64)
@@ -154,9 +159,9 @@ def main():
         % (b_ms, g_ms, tr_mx[mf.TRACE_VEC][0], g_ms / max(g_n, 1), b_ms / max(b_n, 1)))
     roofline = dict(bound="mfma", achieved=round(achieved_tf, 2), peak=BF16_PEAK_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved_tf / BF16_PEAK_TFLOPS, 4), traffic=None,
-                    kernel="gemm_bf16_kernel<3,*,*> (split-BF16 transform product)",
+                    kernel=mixed[3] + " (transform product, %d BF16 MFMA products)" % mixed[2],
                     avg_launch_ms=round(g_ms / max(g_n, 1), 4), launches=g_n,
-                    dominant_class=["band", "gemm_f64", "gemm_bf16x3", "gemm_bf16", "vec"][dominant])
+                    dominant_class=["band", "gemm_f64", "gemm_bf16x3", "gemm_bf16", "vec", "gemm_bf16x2"][dominant])
 
     # ---- CPU baseline (oracle) ----------------------------------------------------------
     cpu = None
@@ -177,7 +182,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64 recurrence + split-bf16 (fp32 accumulate) transforms",
+        "dtype": "f64 recurrence + %s (fp32 accumulate) transforms" % args.mixed,
         "data": "synthetic",
         "config": {"workload": "elliptic P2 x-normal, n=2049 (q=2047), Dirichlet, gamma=1, "
                                "manufactured f + 1e-3 noise, batch %d, rel residual %.0e" % (B, args.tol),

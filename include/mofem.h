@@ -176,8 +176,13 @@ enum {
   MOFEM_PREC_F64 = 0,     /* FP64 MFMA transforms                           */
   MOFEM_PREC_F32 = 1,     /* FP32 MFMA transforms, FP32 intermediates       */
   MOFEM_PREC_BF16 = 2,    /* BF16 operands, FP32 accumulation               */
-  MOFEM_PREC_BF16X3 = 3   /* split BF16 (hi + lo), three products per term,
+  MOFEM_PREC_BF16X3 = 3,  /* split BF16 (hi + lo), three products per term,
                              FP32 accumulation                              */
+  MOFEM_PREC_BF16X2 = 4   /* split BF16 for the data operands, eigenbases
+                             rounded to BF16: the preconditioner is defined
+                             with the rounded (still nonsingular) bases, so
+                             P stays symmetric positive definite and each
+                             transform needs two products; FP32 accumulation */
 };
 typedef struct {
   int kb;                       /* band half-width of the four matrices       */
@@ -291,7 +296,8 @@ enum {
   MOFEM_TRACE_GEMM_BF16X3 = 2,  /* one split-BF16 transform product            */
   MOFEM_TRACE_GEMM_BF16 = 3,    /* one BF16 transform product                  */
   MOFEM_TRACE_VEC = 4,          /* PCG vector kernels and reductions           */
-  MOFEM_TRACE_CLASSES = 5
+  MOFEM_TRACE_GEMM_BF16X2 = 5,  /* one two-product transform (BF16 basis)      */
+  MOFEM_TRACE_CLASSES = 6
 };
 /* on != 0: discard earlier records and start recording; on == 0: stop. */
 int mofem_trace_enable(int on);

@@ -244,7 +244,7 @@ extern "C" int mofem_op_create(const mofem_op_desc* desc, mofem_op_t* out) {
   op->ph_s = D.trim_s;
   op->scaled_mask = mask;
   op->pattern = (D.elem_order >= 2 && D.elem_order == kb && element_structured(left, qs, nt, kb, op->ph_s)) ? 1 : 0;
-  int TI = band_rows_per_block(kb), SW = band_cols_per_block(kb);
+  int TI = band_rows_per_block(kb, nt), SW = band_cols_per_block(kb);
   op->n_rowblk = (qs + op->ph_s + TI - 1) / TI;
   op->n_tiles = ((qt + SW - 1) / SW) * op->n_rowblk;
   int rc = dev_alloc(&op->d_left, left.size());
@@ -319,9 +319,10 @@ int op_launch(mofem_op_t op, const double* X, long long in_stride, double* Y, lo
 extern "C" int mofem_op_apply(mofem_op_t op, const double* X, long long in_stride, double* Y, long long stride,
                               int batch, const double* item_scale, double* dot_xy, void* stream) {
   clear_error();
-  if (!op || !X || !Y) return fail(MOFEM_E_ARG, "op_apply: NULL argument");
+  if (!op) return fail(MOFEM_E_ARG, "op_apply: NULL handle");
   if (batch < 0) return fail(MOFEM_E_ARG, "op_apply: negative batch");
   if (batch == 0) return MOFEM_OK;
+  if (!X || !Y) return fail(MOFEM_E_ARG, "op_apply: NULL argument");
   if (in_stride < (long long)op->ns_in * op->nt_in || stride < (long long)op->qs * op->qt)
     return fail(MOFEM_E_ARG, "op_apply: stride smaller than one item");
   if (dot_xy && op->full_input) return fail(MOFEM_E_ARG, "op_apply: <X, Y> needs a square operator");
@@ -430,7 +431,7 @@ extern "C" int mofem_prec_setup(const mofem_prec_desc* desc, mofem_prec_t* out) 
   if (!D.Ks || !D.Ms || !D.Kt || !D.Mt) return fail(MOFEM_E_ARG, "prec_setup: NULL band");
   if ((D.trim_s != 0 && D.trim_s != 1) || (D.trim_t != 0 && D.trim_t != 1))
     return fail(MOFEM_E_ARG, "prec_setup: trim flags must be 0 or 1");
-  if (D.precision < MOFEM_PREC_F64 || D.precision > MOFEM_PREC_BF16X3)
+  if (D.precision < MOFEM_PREC_F64 || D.precision > MOFEM_PREC_BF16X2)
     return fail(MOFEM_E_ARG, "prec_setup: unknown precision");
   if (D.precision == MOFEM_PREC_F32) return fail(MOFEM_E_UNSUPPORTED, "prec_setup: FP32 transforms are not built");
   const int qs = D.n_s - 2 * D.trim_s, qt = D.n_t - 2 * D.trim_t;
@@ -490,7 +491,7 @@ extern "C" int mofem_prec_set_precision(mofem_prec_t p, int precision) {
   clear_error();
   if (!p) return fail(MOFEM_E_ARG, "prec_set_precision: NULL handle");
   if (precision == MOFEM_PREC_F32) return fail(MOFEM_E_UNSUPPORTED, "FP32 transforms are not built");
-  if (precision < MOFEM_PREC_F64 || precision > MOFEM_PREC_BF16X3) return fail(MOFEM_E_ARG, "unknown precision");
+  if (precision < MOFEM_PREC_F64 || precision > MOFEM_PREC_BF16X2) return fail(MOFEM_E_ARG, "unknown precision");
   p->precision = precision;
   return MOFEM_OK;
 }
@@ -508,7 +509,7 @@ extern "C" size_t mofem_prec_workspace_size(mofem_prec_t p, int batch) {
   // sized for the widest precision (FP64 intermediates), so that a workspace
   // stays valid when mofem_prec_set_precision switches the handle
   size_t items = (size_t)p->ps * p->pt * batch;
-  return 2 * align_up(items * 8, 256) + 1024;
+  return 3 * align_up(items * 8, 256) + 2048;
 }
 
 namespace {
@@ -527,65 +528,86 @@ int prec_launch(mofem_prec_t p, const double* R, double* Z, long long stride, in
   g.item_scale = item_scale;
   g.out_scale = 1.0;
   g.active = active;
-  const int prec = p->precision == MOFEM_PREC_F64 ? GEMM_F64 : p->precision == MOFEM_PREC_BF16 ? GEMM_BF16 : GEMM_BF16X3;
-  const int tcls = prec == GEMM_F64 ? MOFEM_TRACE_GEMM_F64 : prec == GEMM_BF16 ? MOFEM_TRACE_GEMM_BF16
-                                                                                : MOFEM_TRACE_GEMM_BF16X3;
-  auto gemm = [&](int amode, int omode) -> int {
+  const int prec = p->precision == MOFEM_PREC_F64      ? GEMM_F64
+                   : p->precision == MOFEM_PREC_BF16   ? GEMM_BF16
+                   : p->precision == MOFEM_PREC_BF16X2 ? GEMM_BF16X2
+                                                       : GEMM_BF16X3;
+  const int tcls = prec == GEMM_F64      ? MOFEM_TRACE_GEMM_F64
+                   : prec == GEMM_BF16   ? MOFEM_TRACE_GEMM_BF16
+                   : prec == GEMM_BF16X2 ? MOFEM_TRACE_GEMM_BF16X2
+                                         : MOFEM_TRACE_GEMM_BF16X3;
+  auto gemm = [&](int omode) -> int {
     TraceScope trace(tcls, items_done, s);
-    return launch_gemm(g, prec, amode, omode, batch, s);
+    return launch_gemm(g, prec, omode, batch, s);
   };
   Carve c(ws, ws_bytes);
   if (prec == GEMM_F64) {
+    double* T0 = c.take<double>(items * batch);  // padded R
     double* T1 = c.take<double>(items * batch);  // T' then W
     double* T2 = c.take<double>(items * batch);  // S'
-    if (!T1 || !T2) return fail(MOFEM_E_ARG, "prec_apply: workspace too small");
+    if (!T0 || !T1 || !T2) return fail(MOFEM_E_ARG, "prec_apply: workspace too small");
     const long long istr = (long long)items;
+    {
+      TraceScope trace(MOFEM_TRACE_VEC, items_done, s);
+      if (launch_pad_operand(R, stride, p->qs, p->qt, T0, nullptr, nullptr, istr, 0, batch, active, s))
+        return fail(MOFEM_E_HIP, "pad launch");
+    }
     // G1: T' = (R V_t)^T
     g.M = p->qs; g.N = p->qt; g.K = p->qt;
-    g.a64 = R; g.a_stride = stride; g.b64 = p->VtT; g.b_stride = 0;
+    g.a64 = T0; g.a_stride = istr; g.b64 = p->VtT; g.b_stride = 0;
     g.c64 = T1; g.c_stride = istr; g.divide = 0;
-    if (gemm(A_F64_RAW, O_PAD_T)) return fail(MOFEM_E_HIP, "gemm launch");
+    if (gemm(O_PAD_T)) return fail(MOFEM_E_HIP, "gemm launch");
     // G2: S' = (V_s^T T ./ D)^T
     g.M = p->qs; g.N = p->qt; g.K = p->qs;
     g.a64 = p->VsT; g.a_stride = 0; g.b64 = T1; g.b_stride = istr;
     g.c64 = T2; g.c_stride = istr; g.divide = 1;
-    if (gemm(A_PADDED, O_PAD_T)) return fail(MOFEM_E_HIP, "gemm launch");
+    if (gemm(O_PAD_T)) return fail(MOFEM_E_HIP, "gemm launch");
     // G3: W = V_s S
     g.M = p->qs; g.N = p->qt; g.K = p->qs;
     g.a64 = p->Vs; g.a_stride = 0; g.b64 = T2; g.b_stride = istr;
     g.c64 = T1; g.c_stride = istr; g.divide = 0;
-    if (gemm(A_PADDED, O_PAD_N)) return fail(MOFEM_E_HIP, "gemm launch");
+    if (gemm(O_PAD_N)) return fail(MOFEM_E_HIP, "gemm launch");
     // G4: Z = W V_t^T
     g.M = p->qs; g.N = p->qt; g.K = p->qt;
     g.a64 = T1; g.a_stride = istr; g.b64 = p->Vt; g.b_stride = 0;
     g.c64 = Z; g.c_stride = stride; g.divide = 0;
-    if (gemm(A_PADDED, O_F64_RAW)) return fail(MOFEM_E_HIP, "gemm launch");
+    if (gemm(O_F64_RAW)) return fail(MOFEM_E_HIP, "gemm launch");
   } else {
+    unsigned short* T0h = c.take<unsigned short>(items * batch);
+    unsigned short* T0l = c.take<unsigned short>(items * batch);
     unsigned short* T1h = c.take<unsigned short>(items * batch);
     unsigned short* T1l = c.take<unsigned short>(items * batch);
     unsigned short* T2h = c.take<unsigned short>(items * batch);
     unsigned short* T2l = c.take<unsigned short>(items * batch);
-    if (!T1h || !T1l || !T2h || !T2l) return fail(MOFEM_E_ARG, "prec_apply: workspace too small");
+    if (!T0h || !T0l || !T1h || !T1l || !T2h || !T2l) return fail(MOFEM_E_ARG, "prec_apply: workspace too small");
     const long long istr = (long long)items;
+    {
+      TraceScope trace(MOFEM_TRACE_VEC, items_done, s);
+      if (launch_pad_operand(R, stride, p->qs, p->qt, nullptr, T0h, T0l, istr, 1, batch, active, s))
+        return fail(MOFEM_E_HIP, "pad launch");
+    }
     g.M = p->qs; g.N = p->qt; g.K = p->qt;
-    g.a64 = R; g.a_stride = stride; g.b_hi = p->VtT_h; g.b_lo = p->VtT_l; g.b_stride = 0;
+    g.data_is_a = 1;
+    g.a_hi = T0h; g.a_lo = T0l; g.a_stride = istr; g.b_hi = p->VtT_h; g.b_lo = p->VtT_l; g.b_stride = 0;
     g.c_hi = T1h; g.c_lo = T1l; g.c_stride = istr; g.divide = 0;
-    if (gemm(A_F64_RAW, O_PAD_T)) return fail(MOFEM_E_HIP, "gemm launch");
+    if (gemm(O_PAD_T)) return fail(MOFEM_E_HIP, "gemm launch");
     g.M = p->qs; g.N = p->qt; g.K = p->qs;
+    g.data_is_a = 0;
     g.a64 = nullptr; g.a_hi = p->VsT_h; g.a_lo = p->VsT_l; g.a_stride = 0;
     g.b_hi = T1h; g.b_lo = T1l; g.b_stride = istr;
     g.c_hi = T2h; g.c_lo = T2l; g.c_stride = istr; g.divide = 1;
-    if (gemm(A_PADDED, O_PAD_T)) return fail(MOFEM_E_HIP, "gemm launch");
+    if (gemm(O_PAD_T)) return fail(MOFEM_E_HIP, "gemm launch");
     g.M = p->qs; g.N = p->qt; g.K = p->qs;
     g.a_hi = p->Vs_h; g.a_lo = p->Vs_l; g.a_stride = 0;
     g.b_hi = T2h; g.b_lo = T2l; g.b_stride = istr;
     g.c_hi = T1h; g.c_lo = T1l; g.c_stride = istr; g.divide = 0;
-    if (gemm(A_PADDED, O_PAD_N)) return fail(MOFEM_E_HIP, "gemm launch");
+    if (gemm(O_PAD_N)) return fail(MOFEM_E_HIP, "gemm launch");
     g.M = p->qs; g.N = p->qt; g.K = p->qt;
+    g.data_is_a = 1;
     g.a_hi = T1h; g.a_lo = T1l; g.a_stride = istr;
     g.b_hi = p->Vt_h; g.b_lo = p->Vt_l; g.b_stride = 0;
     g.c64 = Z; g.c_stride = stride; g.divide = 0;
-    if (gemm(A_PADDED, O_F64_RAW)) return fail(MOFEM_E_HIP, "gemm launch");
+    if (gemm(O_F64_RAW)) return fail(MOFEM_E_HIP, "gemm launch");
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(MOFEM_E_HIP, std::string("prec_apply launch: ") + hipGetErrorString(e));
@@ -612,9 +634,10 @@ int ensure_internal_ws(void** ws, size_t* have, size_t need, hipStream_t s) {
 extern "C" int mofem_prec_apply(mofem_prec_t p, const double* R, double* Z, long long stride, int batch,
                                 const double* item_scale, void* workspace, size_t ws_bytes, void* stream) {
   clear_error();
-  if (!p || !R || !Z) return fail(MOFEM_E_ARG, "prec_apply: NULL argument");
+  if (!p) return fail(MOFEM_E_ARG, "prec_apply: NULL handle");
   if (batch < 0) return fail(MOFEM_E_ARG, "prec_apply: negative batch");
   if (batch == 0) return MOFEM_OK;
+  if (!R || !Z) return fail(MOFEM_E_ARG, "prec_apply: NULL argument");
   if (stride < (long long)p->qs * p->qt) return fail(MOFEM_E_ARG, "prec_apply: stride smaller than one item");
   hipStream_t s = (hipStream_t)stream;
   size_t need = mofem_prec_workspace_size(p, batch);
@@ -707,9 +730,10 @@ extern "C" int mofem_pcg_solve(mofem_op_t op, mofem_prec_t prec, const double* R
                                void* workspace, size_t ws_bytes, int* iters_out, double* relres_out,
                                void* stream) {
   clear_error();
-  if (!op || !prec || !Rhs || !U) return fail(MOFEM_E_ARG, "pcg_solve: NULL argument");
+  if (!op || !prec) return fail(MOFEM_E_ARG, "pcg_solve: NULL handle");
   if (batch < 0 || maxit < 0 || !(tol >= 0.0)) return fail(MOFEM_E_ARG, "pcg_solve: bad batch/maxit/tol");
   if (batch == 0) return MOFEM_OK;
+  if (!Rhs || !U) return fail(MOFEM_E_ARG, "pcg_solve: NULL argument");
   if (op->full_input) return fail(MOFEM_E_ARG, "pcg_solve: operator must map unknowns to unknowns");
   if (op->qs != prec->qs || op->qt != prec->qt) return fail(MOFEM_E_ARG, "pcg_solve: operator and preconditioner sizes differ");
   const long long n = (long long)op->qs * op->qt;

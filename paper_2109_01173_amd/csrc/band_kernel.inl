@@ -6,24 +6,27 @@
 // half-width KB.  It reads X once and writes Y once: HBM-bound.
 //
 // Design (gfx950, wave64):
-//  * one wave owns a strip of 64 columns (64 - 2 KB outputs) and a block of
-//    TI rows; lanes run along the contiguous t direction, so every row load
-//    and store is one coalesced 512-byte access;
+//  * a block of 4 waves covers 4 adjacent strips of 64 columns (64 - 2 KB
+//    outputs each) and TI rows; lanes run along the contiguous t direction,
+//    so every row load and store is one coalesced 512-byte access;
 //  * the right products W_t = X R_t need the 2 KB neighbouring columns of a
-//    lane: they come from the neighbours' registers through DPP wave shifts,
-//    no LDS and no barriers;
+//    lane: they come from the neighbours' registers through DPP wave shifts;
 //  * the lane's column of every right band (NT x (2KB+1) values) sits in
 //    registers for the whole block; the products W_t of the last 2KB+1 rows
-//    form a register ring; the left products combine the ring with the
-//    row's left coefficients, which are uniform across the wave and come
-//    through the scalar cache;
-//  * the row loop is fully unrolled so every ring slot is a compile-time
-//    register, and, for P_k element matrices (k >= 2), each row's position
-//    inside its element is known at compile time: the left product then
-//    touches only the k + 1 (interior node) or 2k + 1 (element vertex)
-//    structural non-zeros;
+//    form a register ring; the left coefficients of the block's rows are
+//    staged once in LDS (shared by the 4 waves) and read back as
+//    wave-uniform (broadcast) reads;
+//  * rows are processed in groups of U = KB (2KB+1) rows, after which the
+//    ring slot, the row's position inside its element and the prefetch slot
+//    repeat, so inside a group everything is compile-time; for P_k element
+//    matrices (k >= 2) the left product then touches only the k + 1
+//    (interior node) or 2k + 1 (element vertex) structural non-zeros;
+//  * row loads run PF rows ahead in a register queue; they read clamped,
+//    in-range addresses unconditionally (rows and columns outside the
+//    matrix only ever meet zero band coefficients), so the row body has no
+//    branches except the output-row check of the first and last row block;
 //  * an optional fused Frobenius product <X, Y> per item (eq. (77)) is
-//    reduced per wave and written to a partial-sum array (a second, fixed
+//    reduced per block and written to a partial-sum array (a second, fixed
 //    order pass makes it deterministic).
 #pragma once
 
@@ -33,74 +36,104 @@
 
 namespace mofem {
 
-template <int KB>
-struct BandTile {
+constexpr int kBandWaves = 4;
+
+template <int KB, int NT>
+struct BandCfg {
   static constexpr int W = 2 * KB + 1;
-  static constexpr int U = KB * W;  // rows after which ring slot and element phase repeat
-  static constexpr int TI = (KB == 1) ? 48 : (KB == 2) ? 50 : (KB == 3) ? 42 : 36;
-  static constexpr int SW = 64 - 2 * KB;  // output columns per wave
-  static_assert(TI % U == 0, "row block must be a whole number of periods");
+  static constexpr int U = KB * W;   // period of ring slot and element phase
+  static constexpr int RC = NT * W;  // left coefficients per output row
+  // groups per block: about 200 rows, at most 48 KB of staged coefficients
+  static constexpr int G_ROWS = 200 / U;
+  static constexpr int G_LDS = (48 * 1024 / 8) / (RC * U);
+  static constexpr int G_MIN = G_ROWS < G_LDS ? G_ROWS : G_LDS;
+  static constexpr int G = G_MIN < 1 ? 1 : G_MIN;
+  static constexpr int TI = G * U;
+  // prefetch distance: the largest divisor of U not above 12 (about one
+  // period: enough loads in flight to cover HBM latency at 3 waves/SIMD)
+  static constexpr int pf(int d) { return (U % d == 0) ? d : pf(d - 1); }
+  static constexpr int PF = pf(12);
+  static constexpr int SW = 64 - 2 * KB;
 };
 
+// The arrays are separate __restrict__ kernel arguments (not struct members)
+// so that the compiler can order the loads freely around the stores to Y.
 template <int KB, int NT, bool PAT>
-__global__ __launch_bounds__(64) void band_apply_kernel(BandArgs a) {
-  using T = BandTile<KB>;
-  constexpr int W = T::W;
-  constexpr int TI = T::TI;
-  constexpr int NROWS = TI + 2 * KB;
+__global__ __launch_bounds__(256) void band_apply_kernel(BandArgs a, const double* __restrict__ X,
+                                                         double* __restrict__ Y, const double* __restrict__ left,
+                                                         const double* __restrict__ right) {
+  using C = BandCfg<KB, NT>;
+  constexpr int W = C::W, U = C::U, RC = C::RC, TI = C::TI, PF = C::PF;
+  __shared__ double lcoef[TI * RC];
+  __shared__ double dsum[kBandWaves];
 
-  const int lane = threadIdx.x;
-  const int n_strips = (a.qt + T::SW - 1) / T::SW;
-  const int n_tiles = n_strips * a.n_rowblk;
-  const int tile = xcd_tile(blockIdx.x, n_tiles);
-  const int strip = tile / a.n_rowblk;
-  const int rb = tile - strip * a.n_rowblk;
   const int b = blockIdx.y;
   if (a.active && !a.active[b]) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int n_sb = (a.qt + kBandWaves * C::SW - 1) / (kBandWaves * C::SW);
+  const int n_tiles = n_sb * a.n_rowblk;
+  const int tile = xcd_tile(blockIdx.x, n_tiles);
+  const int sb = tile / a.n_rowblk;
+  const int rb = tile - sb * a.n_rowblk;
 
-  const int j = strip * T::SW + lane - KB;  // output column of this lane
+  const int j = (sb * kBandWaves + wave) * C::SW + lane - KB;  // output column of this lane
   const bool own = (lane >= KB) && (lane < 64 - KB) && (j < a.qt);
-  const int bcol = j + a.off_t;             // input column this lane loads
-  const bool in_col = (bcol >= 0) && (bcol < a.nt_in);
+  int bcol = j + a.off_t;                                        // input column this lane loads
+  bcol = bcol < 0 ? 0 : (bcol >= a.nt_in ? a.nt_in - 1 : bcol);  // clamped: meets zero coefficients
 
-  const double scale = a.item_scale ? a.item_scale[b] : 1.0;
+  const int g0 = rb * TI;              // first output node row of this block
+  const int delta = a.off_s - a.ph_s;  // input row = node row + delta
+  const int i0 = g0 - a.ph_s;          // output row of m = 0
+
+  // stage the left coefficients of the block's TI output rows
+  for (int e = threadIdx.x; e < TI * RC; e += 64 * kBandWaves) {
+    const int i = i0 + e / RC;
+    lcoef[e] = (i >= 0 && i < a.qs) ? left[(size_t)i0 * RC + e] : 0.0;
+  }
 
   // right coefficients of column j, with the per-item scale folded in
-  double rc[NT][W];
+  const double scale = a.item_scale ? a.item_scale[b] : 1.0;
   const bool jvalid = (j >= 0) && (j < a.qt);
+  double rc[NT][W];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const double s = ((a.scaled_mask >> t) & 1) ? scale : 1.0;
 #pragma unroll
-    for (int d = 0; d < W; ++d)
-      rc[t][d] = jvalid ? s * a.right[((size_t)t * W + d) * a.qt + j] : 0.0;
+    for (int d = 0; d < W; ++d) rc[t][d] = jvalid ? s * right[((size_t)t * W + d) * a.qt + j] : 0.0;
   }
 
-  const double* __restrict__ Xb = a.X + (size_t)b * a.in_stride + (in_col ? bcol : 0);
-  double* __restrict__ Yb = a.Y + (size_t)b * a.out_stride + (own ? j : 0);
-  const double* __restrict__ Lc = a.left;
+  const double* Xb = X + (size_t)b * a.in_stride + bcol;
+  double* Yb = Y + (size_t)b * a.out_stride + (own ? j : 0);
+  const int last_row = a.ns_in - 1;
+  auto load_row = [&](int p) -> double {
+    int r = g0 - KB + p + delta;
+    r = r < 0 ? 0 : (r > last_row ? last_row : r);
+    return Xb[(size_t)r * a.ld_x];
+  };
 
-  const int g0 = rb * TI;           // first output node row of this block
-  const int delta = a.off_s - a.ph_s;  // input row = node row + delta
-
-  double ring[NT][W];   // W_t of the last W node rows, slot = node mod W
-  double xs[W];         // the lane's own X value of the last W node rows
+  double ring[NT][W];  // W_t of the last W node rows, slot = node mod W
+  double xs[W];        // the lane's own X value of the last W node rows
+  double xq[PF];       // prefetched rows, slot = p mod PF
   double dot = 0.0;
-
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
     for (int d = 0; d < W; ++d) ring[t][d] = 0.0;
-
-  StaticFor<0, NROWS>::run([&](auto pc) {
+#pragma unroll
+  for (int d = 0; d < W; ++d) xs[d] = 0.0;
+  // prologue: rows 0 .. PF-1 in flight
+  StaticFor<0, PF>::run([&](auto pc) {
     constexpr int p = decltype(pc)::value;
-    // node row h = g0 - KB + p ; its ring slot is (p - KB) mod W (g0 = 0 mod W)
-    constexpr int slot = ((p - KB) % W + W) % W;
-    const int h = g0 - KB + p;
-    const int arow = h + delta;
-    double xv = 0.0;
-    if (in_col && arow >= 0 && arow < a.ns_in) xv = Xb[(size_t)arow * a.ld_x];
-    // neighbours: nb[d] = value at lane + d - KB
+    xq[p % PF] = load_row(p);
+  });
+  __syncthreads();  // staged coefficients visible to all four waves
+
+  // consume row p (node row g0 - KB + p): right products into its ring slot
+  auto right_row = [&](int p, auto slot_c, auto q_c) {
+    constexpr int slot = decltype(slot_c)::value;
+    constexpr int qslot = decltype(q_c)::value;
+    const double xv = xq[qslot];
+    xq[qslot] = load_row(p + PF);  // clamped: rows past the end are harmless
     double nb[W];
     nb[KB] = xv;
 #pragma unroll
@@ -115,46 +148,75 @@ __global__ __launch_bounds__(64) void band_apply_kernel(BandArgs a) {
       ring[t][slot] = s;
     }
     xs[slot] = xv;
-    if constexpr (p >= 2 * KB) {
-      // output node row g = h - KB = g0 + m
-      constexpr int m = p - 2 * KB;
-      constexpr int phase = m % KB;
+  };
+
+  // warm-up: node rows g0 - KB .. g0 + KB - 1
+  StaticFor<0, 2 * KB>::run([&](auto pc) {
+    constexpr int p = decltype(pc)::value;
+    right_row(p, std::integral_constant<int, ((p - KB) % W + W) % W>{}, std::integral_constant<int, p % PF>{});
+  });
+
+  // main loop: row p = 2KB + grp U + P completes output node row g = g0 + grp U + P
+  auto group = [&](int grp, auto check_c) {
+    constexpr bool CHECK = decltype(check_c)::value;
+    StaticFor<0, U>::run([&](auto pc) {
+      constexpr int P = decltype(pc)::value;
+      constexpr int slot = (KB + P) % W;
+      constexpr int qslot = (2 * KB + P) % PF;
+      constexpr int phase = P % KB;
       constexpr int dlo = (!PAT || phase == 0) ? 0 : KB - phase;
       constexpr int dhi = (!PAT || phase == 0) ? 2 * KB : 2 * KB - phase;
-      const int g = g0 + m;
-      const int i = g - a.ph_s;
-      if (i >= 0 && i < a.qs) {
-        const double* li = Lc + (size_t)i * (NT * W);
-        double acc = 0.0;
+      const int m = grp * U + P;
+      right_row(2 * KB + m, std::integral_constant<int, slot>{}, std::integral_constant<int, qslot>{});
+      const int i = i0 + m;
+      if (!CHECK || (i >= 0 && i < a.qs)) {
+        const double* li = lcoef + m * RC;
+        // one partial sum per term: short independent FMA chains
+        double part[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
+          part[t] = 0.0;
 #pragma unroll
-          for (int d = dlo; d <= dhi; ++d) {
-            acc = fma(li[t * W + d], ring[t][((m + d - KB) % W + W) % W], acc);
-          }
+          for (int d = dlo; d <= dhi; ++d) part[t] = fma(li[t * W + d], ring[t][(P + d - KB + W) % W], part[t]);
         }
-        if (own) {
-          Yb[(size_t)i * a.ld_y] = acc;
-          dot = fma(acc, xs[(m % W + W) % W], dot);
-        }
+        double acc = part[0];
+#pragma unroll
+        for (int t = 1; t < NT; ++t) acc += part[t];
+        if (own) Yb[(size_t)i * a.ld_y] = acc;
+        dot = fma(own ? acc : 0.0, xs[P % W], dot);
       }
-    }
-  });
+    });
+  };
+  const bool interior = (i0 >= 0) && (i0 + TI <= a.qs);
+  if (interior) {
+    for (int grp = 0; grp < C::G; ++grp) group(grp, std::false_type{});
+  } else {
+    for (int grp = 0; grp < C::G; ++grp) group(grp, std::true_type{});
+  }
 
   if (a.dot_partial) {
     dot = wave_sum(dot);
-    if (lane == 0) a.dot_partial[(size_t)b * a.n_partial + tile] = dot;
+    if (lane == 0) dsum[wave] = dot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < kBandWaves; ++w) t += dsum[w];
+      a.dot_partial[(size_t)b * a.n_partial + tile] = t;
+    }
   }
 }
 
 template <int KB, int NT>
 void launch_kb_nt(const BandArgs& a, int batch, bool pat, hipStream_t s) {
-  int n_strips = (a.qt + BandTile<KB>::SW - 1) / BandTile<KB>::SW;
-  dim3 grid(n_strips * a.n_rowblk, batch);
+  using C = BandCfg<KB, NT>;
+  const int n_sb = (a.qt + kBandWaves * C::SW - 1) / (kBandWaves * C::SW);
+  dim3 grid(n_sb * a.n_rowblk, batch);
   if (pat && KB >= 2)
-    hipLaunchKernelGGL((band_apply_kernel<KB, NT, (KB >= 2)>), grid, dim3(64), 0, s, a);
+    hipLaunchKernelGGL((band_apply_kernel<KB, NT, (KB >= 2)>), grid, dim3(64 * kBandWaves), 0, s, a, a.X, a.Y,
+                       a.left, a.right);
   else
-    hipLaunchKernelGGL((band_apply_kernel<KB, NT, false>), grid, dim3(64), 0, s, a);
+    hipLaunchKernelGGL((band_apply_kernel<KB, NT, false>), grid, dim3(64 * kBandWaves), 0, s, a, a.X, a.Y, a.left,
+                       a.right);
 }
 
 // One translation unit per band width compiles these (k_band_kb*.hip).

@@ -15,15 +15,25 @@ MOFEM_BAND_EXTERN(2)
 MOFEM_BAND_EXTERN(3)
 MOFEM_BAND_EXTERN(4)
 
-int band_rows_per_block(int kb) {
-  switch (kb) {
-    case 1: return BandTile<1>::TI;
-    case 2: return BandTile<2>::TI;
-    case 3: return BandTile<3>::TI;
-    default: return BandTile<4>::TI;
+template <int KB>
+static int rows_kb(int nt) {
+  switch (nt) {
+    case 1: return BandCfg<KB, 1>::TI;
+    case 2: return BandCfg<KB, 2>::TI;
+    case 3: return BandCfg<KB, 3>::TI;
+    case 5: return BandCfg<KB, 5>::TI;
+    default: return BandCfg<KB, 6>::TI;
   }
 }
-int band_cols_per_block(int kb) { return 64 - 2 * kb; }
+int band_rows_per_block(int kb, int nt) {
+  switch (kb) {
+    case 1: return rows_kb<1>(nt);
+    case 2: return rows_kb<2>(nt);
+    case 3: return rows_kb<3>(nt);
+    default: return rows_kb<4>(nt);
+  }
+}
+int band_cols_per_block(int kb) { return kBandWaves * (64 - 2 * kb); }
 int band_supported_terms(int nt) { return nt == 1 || nt == 2 || nt == 3 || nt == 5 || nt == 6; }
 
 template <int KB>

@@ -5,7 +5,7 @@
 //     Z = V_s ((V_s^T R V_t) ./ D) V_t^T,
 // is evaluated as four "NT" products C[m][n] = sum_k A[m][k] B[n][k] whose
 // operands are all contiguous along k:
-//     T' = (R V_t)^T       A = R        B = V_t^T   out transposed
+//     T' = (R V_t)^T       A = R (padded copy)  B = V_t^T   out transposed
 //     S' = (V_s^T T ./ D)^T A = V_s^T   B = T'      out transposed, divide by D
 //     W  = V_s S            A = V_s      B = S'      out row-major
 //     Z  = W V_t^T          A = W        B = V_t     out FP64 (the caller's R/Z layout)
@@ -17,10 +17,16 @@
 //   GEMM_BF16X3  v_mfma_f32_16x16x32_bf16 with split operands x = hi + lo
 //                (hi = bf16(x), lo = bf16(x - hi)); A B ~ Ah Bh + Ah Bl + Al Bh,
 //                FP32 accumulation, FP32-level accuracy.
+//   GEMM_BF16X2  the data operand split, the eigenbasis operand exactly
+//                representable in BF16 (the preconditioner is defined with
+//                the BF16-rounded basis): two products per transform.
 //   GEMM_BF16    the hi * hi product only.
 // Tiling: 256 threads = 4 waves, block tile 128 x 128, each wave 64 x 64
-// (4 x 4 MFMA tiles of 16 x 16).  Global -> register prefetch of the next k
-// tile overlaps the MFMAs of the current one.  Block order is XCD-aware.
+// (4 x 4 MFMA tiles of 16 x 16); k tiles of 16 (FP64) or 64 (BF16).
+// Global -> register prefetch of the next k tile overlaps the MFMAs of the
+// current one; in the split products the three passes run one after the
+// other over all 16 accumulators, so back-to-back MFMAs are independent.
+// Block order is XCD-aware.
 // Intermediates are padded to multiples of 128 in both dimensions and the
 // epilogue writes zeros into the padding, so consumers read whole tiles
 // without bounds checks.
@@ -58,7 +64,7 @@ __device__ __forceinline__ double eval_D(const GemmArgs& g, int row, int col, do
 // ------------------------------------------------------------------------------
 // FP64
 // ------------------------------------------------------------------------------
-template <int AMODE, int OMODE>
+template <int OMODE>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
   constexpr int BK = 16;
   constexpr int LDS_K = BK + 1;
@@ -73,7 +79,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
-  const int lda = (AMODE == A_F64_RAW) ? g.K : pad_up(g.K);
+  const int lda = pad_up(g.K);
   const int ldb = pad_up(g.K);
   const double* __restrict__ A = g.a64 + (size_t)b * g.a_stride;
   const double* __restrict__ B = g.b64 + (size_t)b * g.b_stride;
@@ -86,10 +92,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int kk = k0 + lk + e;
-      if (AMODE == A_F64_RAW)
-        ra[e] = (arow < g.M && kk < g.K) ? A[(size_t)arow * lda + kk] : 0.0;
-      else
-        ra[e] = A[(size_t)arow * lda + kk];
+      ra[e] = A[(size_t)arow * lda + kk];
       rb[e] = B[(size_t)(n0 + lrow) * ldb + kk];
     }
   };
@@ -151,15 +154,22 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
 // ------------------------------------------------------------------------------
 // split BF16 (NPROD = 3) and plain BF16 (NPROD = 1), FP32 accumulation
 // ------------------------------------------------------------------------------
-template <int NPROD, int AMODE, int OMODE>
+// MODE: BF_HH   plain BF16                    A_h B_h
+//       BF_X3   both operands split            A_l B_h + A_h B_l + A_h B_h
+//       BF_X2A  A split, B exact in BF16       A_l B_h + A_h B_h
+//       BF_X2B  B split, A exact in BF16       A_h B_l + A_h B_h
+enum { BF_HH = 0, BF_X3 = 1, BF_X2A = 2, BF_X2B = 3 };
+
+template <int MODE, int OMODE>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
-  constexpr int BK = 32;
-  constexpr int LDS_K = BK + 8;   // 80-byte rows keep 16-byte alignment
-  constexpr bool LO = (NPROD == 3);
+  constexpr int BK = 64;
+  constexpr int LDS_K = BK + 8;   // 144-byte rows keep 16-byte alignment
+  constexpr bool ALO = (MODE == BF_X3 || MODE == BF_X2A);
+  constexpr bool BLO = (MODE == BF_X3 || MODE == BF_X2B);
   __shared__ unsigned short Ah[BM][LDS_K];
   __shared__ unsigned short Bh[BN][LDS_K];
-  __shared__ unsigned short Al[LO ? BM : 1][LDS_K];
-  __shared__ unsigned short Bl[LO ? BN : 1][LDS_K];
+  __shared__ unsigned short Al[ALO ? BM : 1][LDS_K];
+  __shared__ unsigned short Bl[BLO ? BN : 1][LDS_K];
 
   const int b = blockIdx.y;
   if (g.active && !g.active[b]) return;
@@ -170,46 +180,33 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
   const int wm = wave >> 1, wn = wave & 1;
 
   const int Kp = pad_up(g.K);
-  const double* __restrict__ A64 = g.a64 + (size_t)b * g.a_stride;
   const unsigned short* __restrict__ Ahg = (const unsigned short*)g.a_hi + (size_t)b * g.a_stride;
   const unsigned short* __restrict__ Alg = (const unsigned short*)g.a_lo + (size_t)b * g.a_stride;
   const unsigned short* __restrict__ Bhg = (const unsigned short*)g.b_hi + (size_t)b * g.b_stride;
   const unsigned short* __restrict__ Blg = (const unsigned short*)g.b_lo + (size_t)b * g.b_stride;
 
-  // staging: thread owns row tid/2 and k segment (tid%2)*16 (16 values)
-  const int lrow = tid >> 1, lk = (tid & 1) * 16;
-  us8_t ah[2], al[2], bh[2], bl[2];
+  // staging: thread owns row tid/2 and k segment (tid%2)*32 (32 values)
+  constexpr int NV = BK / 16;  // 16-byte vectors per thread and operand
+  const int lrow = tid >> 1, lk = (tid & 1) * (BK / 2);
+  us8_t ah[NV], al[NV], bh[NV], bl[NV];
   auto load_tile = [&](int k0) {
     const int arow = m0 + lrow;
-    if (AMODE == A_F64_RAW) {
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int kk = k0 + lk + h * 8 + e;
-          double x = (arow < g.M && kk < g.K) ? A64[(size_t)arow * g.K + kk] : 0.0;
-          unsigned short hi, lo;
-          split_bf16((float)x, &hi, &lo);
-          ah[h][e] = hi;
-          al[h][e] = lo;
-        }
-    } else {
-      const us8_t* pa = (const us8_t*)(Ahg + (size_t)arow * Kp + k0 + lk);
-      ah[0] = pa[0];
-      ah[1] = pa[1];
-      if (LO) {
-        const us8_t* pl = (const us8_t*)(Alg + (size_t)arow * Kp + k0 + lk);
-        al[0] = pl[0];
-        al[1] = pl[1];
-      }
-    }
+    const us8_t* pa = (const us8_t*)(Ahg + (size_t)arow * Kp + k0 + lk);
     const us8_t* pb = (const us8_t*)(Bhg + (size_t)(n0 + lrow) * Kp + k0 + lk);
-    bh[0] = pb[0];
-    bh[1] = pb[1];
-    if (LO) {
-      const us8_t* pl = (const us8_t*)(Blg + (size_t)(n0 + lrow) * Kp + k0 + lk);
-      bl[0] = pl[0];
-      bl[1] = pl[1];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      ah[v] = pa[v];
+      bh[v] = pb[v];
+    }
+    if (ALO) {
+      const us8_t* pal = (const us8_t*)(Alg + (size_t)arow * Kp + k0 + lk);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) al[v] = pal[v];
+    }
+    if (BLO) {
+      const us8_t* pbl = (const us8_t*)(Blg + (size_t)(n0 + lrow) * Kp + k0 + lk);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) bl[v] = pbl[v];
     }
   };
 
@@ -223,40 +220,50 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
   load_tile(0);
   for (int kt = 0; kt < nk; ++kt) {
     __syncthreads();
-    *(us8_t*)&Ah[lrow][lk] = ah[0];
-    *(us8_t*)&Ah[lrow][lk + 8] = ah[1];
-    *(us8_t*)&Bh[lrow][lk] = bh[0];
-    *(us8_t*)&Bh[lrow][lk + 8] = bh[1];
-    if (LO) {
-      *(us8_t*)&Al[lrow][lk] = al[0];
-      *(us8_t*)&Al[lrow][lk + 8] = al[1];
-      *(us8_t*)&Bl[lrow][lk] = bl[0];
-      *(us8_t*)&Bl[lrow][lk + 8] = bl[1];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      *(us8_t*)&Ah[lrow][lk + 8 * v] = ah[v];
+      *(us8_t*)&Bh[lrow][lk + 8 * v] = bh[v];
+      if (ALO) *(us8_t*)&Al[lrow][lk + 8 * v] = al[v];
+      if (BLO) *(us8_t*)&Bl[lrow][lk + 8 * v] = bl[v];
     }
     __syncthreads();
     if (kt + 1 < nk) load_tile((kt + 1) * BK);
-    bf8_t fa[4], fb[4], fal[4], fbl[4];
-    const int kq = (lane >> 4) * 8;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      fa[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Ah[wm * 64 + i * 16 + (lane & 15)][kq]);
-      if (LO) fal[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Al[wm * 64 + i * 16 + (lane & 15)][kq]);
-    }
+    for (int ks = 0; ks < BK / 32; ++ks) {
+      bf8_t fa[4], fb[4], fal[4], fbl[4];
+      const int kq = ks * 32 + (lane >> 4) * 8;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      fb[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Bh[wn * 64 + j * 16 + (lane & 15)][kq]);
-      if (LO) fbl[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Bl[wn * 64 + j * 16 + (lane & 15)][kq]);
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 4; ++i) {
+        fa[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Ah[wm * 64 + i * 16 + (lane & 15)][kq]);
+        if (ALO) fal[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Al[wm * 64 + i * 16 + (lane & 15)][kq]);
+      }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        if (LO) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fal[i], fb[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fbl[j], acc[i][j], 0, 0, 0);
-        }
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+        fb[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Bh[wn * 64 + j * 16 + (lane & 15)][kq]);
+        if (BLO) fbl[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Bl[wn * 64 + j * 16 + (lane & 15)][kq]);
       }
+      // products outermost: consecutive MFMAs write different accumulators
+      if (ALO) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fal[i], fb[j], acc[i][j], 0, 0, 0);
+      }
+      if (BLO) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fbl[j], acc[i][j], 0, 0, 0);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    }
   }
 
   // epilogue: acc[i][j][r] = C[row][col], row = 4*(lane/16) + r, col = lane%16
@@ -284,31 +291,69 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
           split_bf16((float)v, &hi, &lo);
           size_t idx = (OMODE == O_PAD_T) ? (size_t)col * Mp + row : (size_t)row * Np + col;
           Ch[idx] = hi;
-          if (LO) Cl[idx] = lo;
+          if (MODE != BF_HH) Cl[idx] = lo;   // intermediates keep the split
         }
       }
 }
 
-template <int AMODE, int OMODE>
+template <int OMODE>
 static void launch_mode(const GemmArgs& g, int prec, int batch, hipStream_t s) {
   const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
   dim3 grid(tm * tn, batch);
   if (prec == GEMM_F64)
-    hipLaunchKernelGGL((gemm_f64_kernel<AMODE, OMODE>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_f64_kernel<OMODE>), grid, dim3(256), 0, s, g);
   else if (prec == GEMM_BF16X3)
-    hipLaunchKernelGGL((gemm_bf16_kernel<3, AMODE, OMODE>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_bf16_kernel<BF_X3, OMODE>), grid, dim3(256), 0, s, g);
+  else if (prec == GEMM_BF16X2 && g.data_is_a)
+    hipLaunchKernelGGL((gemm_bf16_kernel<BF_X2A, OMODE>), grid, dim3(256), 0, s, g);
+  else if (prec == GEMM_BF16X2)
+    hipLaunchKernelGGL((gemm_bf16_kernel<BF_X2B, OMODE>), grid, dim3(256), 0, s, g);
   else
-    hipLaunchKernelGGL((gemm_bf16_kernel<1, AMODE, OMODE>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_bf16_kernel<BF_HH, OMODE>), grid, dim3(256), 0, s, g);
 }
 
-int launch_gemm(const GemmArgs& g, int prec, int amode, int omode, int batch, hipStream_t s) {
-  if (prec != GEMM_F64 && prec != GEMM_BF16 && prec != GEMM_BF16X3) return -1;
-  if (amode == A_F64_RAW && omode == O_PAD_T) launch_mode<A_F64_RAW, O_PAD_T>(g, prec, batch, s);
-  else if (amode == A_PADDED && omode == O_PAD_T) launch_mode<A_PADDED, O_PAD_T>(g, prec, batch, s);
-  else if (amode == A_PADDED && omode == O_PAD_N) launch_mode<A_PADDED, O_PAD_N>(g, prec, batch, s);
-  else if (amode == A_PADDED && omode == O_F64_RAW) launch_mode<A_PADDED, O_F64_RAW>(g, prec, batch, s);
+int launch_gemm(const GemmArgs& g, int prec, int omode, int batch, hipStream_t s) {
+  if (prec != GEMM_F64 && prec != GEMM_BF16 && prec != GEMM_BF16X3 && prec != GEMM_BF16X2) return -1;
+  if (omode == O_PAD_T) launch_mode<O_PAD_T>(g, prec, batch, s);
+  else if (omode == O_PAD_N) launch_mode<O_PAD_N>(g, prec, batch, s);
+  else if (omode == O_F64_RAW) launch_mode<O_F64_RAW>(g, prec, batch, s);
   else return -1;
   return 0;
+}
+
+// Raw FP64 items (M x K, row length K) -> padded operand (pad(M) x pad(K)),
+// FP64 or split BF16 (hi, lo), zeros in the padding.  One block per padded
+// row; consecutive threads take consecutive columns (coalesced both ways).
+__global__ __launch_bounds__(256) void pad_operand_kernel(const double* __restrict__ A, long long a_stride, int M,
+                                                          int K, double* __restrict__ o64,
+                                                          unsigned short* __restrict__ ohi,
+                                                          unsigned short* __restrict__ olo, long long o_stride,
+                                                          int split, const int* active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const int row = blockIdx.x;
+  const int Kp = pad_up(K);
+  const double* a = A + (size_t)b * a_stride;
+  const size_t obase = (size_t)b * o_stride + (size_t)row * Kp;
+  for (int c = threadIdx.x; c < Kp; c += 256) {
+    const double x = (row < M && c < K) ? a[(size_t)row * K + c] : 0.0;
+    if (split) {
+      unsigned short hi, lo;
+      split_bf16((float)x, &hi, &lo);
+      ohi[obase + c] = hi;
+      olo[obase + c] = lo;
+    } else {
+      o64[obase + c] = x;
+    }
+  }
+}
+
+int launch_pad_operand(const double* A, long long a_stride, int M, int K, double* o64, unsigned short* ohi,
+                       unsigned short* olo, long long o_stride, int split, int batch, const int* active,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(pad_operand_kernel, dim3(pad_up(M), batch), dim3(256), 0, s, A, a_stride, M, K, o64, ohi, olo,
+                     o_stride, split, active);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 }  // namespace mofem

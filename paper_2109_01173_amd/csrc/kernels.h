@@ -21,7 +21,7 @@ struct BandArgs {
   int ns_in, nt_in;        // input shape
   int off_s, off_t;        // input index of output (i, j): (i + off_s, j + off_t)
   int ph_s;                // node index of output row i is i + ph_s
-  int n_rowblk;            // row blocks per item
+  int n_rowblk;            // row blocks per item (band_rows_per_block rows each)
   const double* left;      // [qs][nt][2kb+1] row bands (input row i+off_s+d-kb)
   const double* right;     // [nt][2kb+1][qt] column bands (input col j+off_t+d-kb)
   int scaled_mask;         // bit t: term t times item_scale[b]
@@ -30,7 +30,7 @@ struct BandArgs {
   int n_partial;           // tiles per item
   const int* active;       // [batch] or null: skip items with active[b] == 0
 };
-int band_rows_per_block(int kb);
+int band_rows_per_block(int kb, int nt);
 int band_cols_per_block(int kb);
 int band_supported_terms(int nt);
 int launch_band_apply(const BandArgs& a, int kb, int nt, int batch, bool pattern, hipStream_t s);
@@ -41,14 +41,13 @@ int launch_band_apply(const BandArgs& a, int kb, int nt, int batch, bool pattern
 constexpr int kPad = 128;
 __host__ __device__ inline int pad_up(int x) { return (x + kPad - 1) / kPad * kPad; }
 
-enum GemmPrec { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_BF16 = 2, GEMM_BF16X3 = 3 };
-enum GemmAMode { A_F64_RAW = 0, A_PADDED = 1 };          // raw: FP64, ld = K, bounds checked
+enum GemmPrec { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_BF16 = 2, GEMM_BF16X3 = 3, GEMM_BF16X2 = 4 };
 enum GemmOMode { O_PAD_T = 0, O_PAD_N = 1, O_F64_RAW = 2 };  // raw: FP64 row-major ld = N
 
 struct GemmArgs {
   int M, N, K;             // logical sizes
-  // A: raw FP64 (ld = K) or padded (rows pad_up(M), ld pad_up(K))
-  const double* a64;       // FP64 raw or padded FP64
+  // A: padded (rows pad_up(M), ld pad_up(K))
+  const double* a64;       // padded FP64
   const void* a_hi;        // padded low-precision operand (FP32 / BF16 hi)
   const void* a_lo;        // padded BF16 lo (BF16X3)
   long long a_stride;      // elements between batch items (0 = shared)
@@ -70,8 +69,13 @@ struct GemmArgs {
   const double* item_scale;  // [batch] or null
   double out_scale;        // multiply the result (before the epilogue division)
   const int* active;
+  int data_is_a;           // GEMM_BF16X2: the split (data) operand is A (else B)
 };
-int launch_gemm(const GemmArgs& g, int prec, int amode, int omode, int batch, hipStream_t s);
+int launch_gemm(const GemmArgs& g, int prec, int omode, int batch, hipStream_t s);
+// raw FP64 items (M x K) -> padded FP64 or split BF16 operand
+int launch_pad_operand(const double* A, long long a_stride, int M, int K, double* o64, unsigned short* ohi,
+                       unsigned short* olo, long long o_stride, int split, int batch, const int* active,
+                       hipStream_t s);
 
 // ---- vector kernels of the PCG recurrence (k_vec.hip) -----------------------
 constexpr int kVecBlocks = 240;   // partial sums per item

@@ -30,10 +30,11 @@ OK = 0
 E_ARG, E_HIP, E_NOMEM, E_BREAKDOWN, E_MAXIT, E_UNSUPPORTED, E_NOTFINITE, E_NUMERIC = (
     -1, -2, -3, -4, -5, -6, -7, -8)
 W_ONE, W_POLY, W_PROFILE, W_PROFILE_D, W_PROFILE_INV, W_PROFILE_D2L, W_CALLBACK = range(7)
-PREC_F64, PREC_F32, PREC_BF16, PREC_BF16X3 = range(4)
+PREC_F64, PREC_F32, PREC_BF16, PREC_BF16X3, PREC_BF16X2 = range(5)
 PCG_FLEXIBLE, PCG_ZERO_GUESS, PCG_TAU_STOP = 1, 2, 4
 KIN_NONE, KIN_DIB = 0, 1
-TRACE_BAND, TRACE_GEMM_F64, TRACE_GEMM_BF16X3, TRACE_GEMM_BF16, TRACE_VEC = range(5)
+TRACE_BAND, TRACE_GEMM_F64, TRACE_GEMM_BF16X3, TRACE_GEMM_BF16, TRACE_VEC, TRACE_GEMM_BF16X2 = range(6)
+TRACE_CLASSES = 6
 MAX_TERMS = 8
 
 _vp = ctypes.c_void_p
@@ -235,9 +236,10 @@ class Operator:
         self.shape = (qs.value, qt.value)
         self.in_shape = (i_s.value, i_t.value)
 
-    def __del__(self):
+    def __del__(self, _destroy=mofem_op_destroy):
+        # the default argument keeps the entry point alive at interpreter exit
         if getattr(self, "handle", None):
-            mofem_op_destroy(self.handle)
+            _destroy(self.handle)
             self.handle = None
 
     def apply(self, X, Y=None, item_scale=None, dot=False, stream=None):
@@ -275,9 +277,9 @@ class Preconditioner:
         self.shape = (d.n_s - 2 * trim_s, d.n_t - 2 * trim_t)
         self.precision = precision
 
-    def __del__(self):
+    def __del__(self, _destroy=mofem_prec_destroy):
         if getattr(self, "handle", None):
-            mofem_prec_destroy(self.handle)
+            _destroy(self.handle)
             self.handle = None
 
     def set_coeffs(self, alpha, beta_s, beta_t, delta):

@@ -45,7 +45,7 @@ def test_prec_fp64(k, m, bc):
     _ = mf
 
 
-@pytest.mark.parametrize("precision,tol", [("BF16X3", 2e-4), ("BF16", 3e-2)])
+@pytest.mark.parametrize("precision,tol", [("BF16X3", 2e-4), ("BF16X2", 5e-2), ("BF16", 3e-2)])
 def test_prec_low_precision(precision, tol):
     from paper_2109_01173_amd import mofem as mf
     p = getattr(mf, "PREC_" + precision)
@@ -59,6 +59,15 @@ def test_prec_low_precision(precision, tol):
         assert rel(Zlo[b], Z64[b]) < tol
         # still a positive definite action: <R, Z> > 0
         assert np.sum(R[b] * Zlo[b]) > 0
+    if precision == "BF16X2":
+        # a fixed symmetric operator (the BF16-rounded basis) applied to
+        # split-BF16 accuracy: <X, P^-1 Y> = <P^-1 X, Y> to ~1e-5
+        G.prec.set_precision(p)
+        Zx = to_host(G.prec.apply(to_dev(R[:1])))[0]
+        Zy = to_host(G.prec.apply(to_dev(R[1:])))[0]
+        G.prec.set_precision(mf.PREC_F64)
+        a1, a2 = np.sum(R[0] * Zy), np.sum(Zx * R[1])
+        assert abs(a1 - a2) <= 1e-4 * np.sqrt(np.sum(R[0] * Zx) * np.sum(R[1] * Zy))
 
 
 def test_prec_tiny_and_errors():
