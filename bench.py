@@ -64,6 +64,44 @@ def cpu_baseline(F0, k, m, gamma, tol, U_gpu0):
                        "eigen-setup excluded; %d iterations in %.1f s" % (info["iters"], dt)), fwd, back
 
 
+# HBM traffic of the transform GEMM, from two rocprofv3 --pmc passes over
+# "bench.py --steps 1 --warmup 0 --no-cpu-baseline --fp64-steps 0" (FETCH_SIZE,
+# then WRITE_SIZE, KiB per dispatch, averaged over that kernel's dispatches),
+# each scaled by the ratio true bytes / counter reading of a plain 512 MiB
+# copy ("bench.py --copy-calibration").  The figures hold for the kernel
+# source they were taken on: if k_gemm.hip changes, traffic is reported null.
+TRAFFIC = {
+    # mixed mode -> (sha256 of k_gemm.hip, (q, batch), bytes per launch)
+    "bf16x3": ("41161e8657ce9d2f0b2053f0ecfc304019f9407cac3497cc5320f5ae4aa2cabf", (2047, 16), 2.852e9),
+}
+FETCH_SCALE = 2.000   # 512 MiB copy: true bytes / FETCH_SIZE reading
+WRITE_SCALE = 1.000   # 512 MiB copy: true bytes / WRITE_SIZE reading
+
+
+def measured_traffic(mode, q, batch):
+    import hashlib
+    rec = TRAFFIC.get(mode)
+    if rec is None:
+        return None
+    src = os.path.join(ROOT, "paper_2109_01173_amd", "csrc", "k_gemm.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if sha != rec[0] or tuple(rec[1]) != (q, batch):
+        return None
+    return rec[2]
+
+
+def copy_calibration(torch):
+    """A plain device copy of known size, for scaling byte counters."""
+    n = 512 * 1024 * 1024 // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "launches": 5}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +114,8 @@ def main():
     ap.add_argument("--mixed", default="bf16x3", choices=["bf16x2", "bf16x3", "bf16"],
                     help="transform precision of the mixed path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 512 MiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs every instance batch on a single "
@@ -84,6 +124,10 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
 
     from paper_2109_01173_amd import mofem as mf
     from paper_2109_01173_amd.problems import XNormal
@@ -137,11 +181,23 @@ def main():
     log("mixed: %.3f s/step, iterations %s, max relres %.2e" % (dt_mx / args.steps, it_mx.tolist(), rr_mx.max()))
 
     # ---- FP64 path -------------------------------------------------------------
-    G.prec.set_precision(mf.PREC_F64)
-    step(0)
-    dt_64, (it_64, rr_64, _), tr_64 = timed(args.fp64_steps, 0)
-    fp64_value = B * args.fp64_steps / dt_64
-    log("fp64: %.3f s/step, iterations %s, max relres %.2e" % (dt_64 / args.fp64_steps, it_64.tolist(), rr_64.max()))
+    fp64 = None
+    if args.fp64_steps > 0:
+        G.prec.set_precision(mf.PREC_F64)
+        step(0)
+        dt_64, (it_64, rr_64, _), tr_64 = timed(args.fp64_steps, 0)
+        fp64_value = B * args.fp64_steps / dt_64
+        log("fp64: %.3f s/step, iterations %s, max relres %.2e"
+            % (dt_64 / args.fp64_steps, it_64.tolist(), rr_64.max()))
+        f_ms, f_n, f_items = tr_64[mf.TRACE_GEMM_F64]
+        f64_tf = 2.0 * q ** 3 * f_items / (f_ms * 1e-3) / 1e12 if f_ms > 0 else 0.0
+        fp64 = {"fp64_solves_per_s": round(fp64_value, 3),
+                "mixed_over_fp64": round(value / fp64_value, 3),
+                "iterations_fp64": int(it_64.max()),
+                "relres_max_fp64": float(rr_64.max()),
+                "gemm_f64": {"bound": "mfma", "achieved": round(f64_tf, 2), "peak": F64_PEAK_TFLOPS,
+                             "unit": "TFLOP/s", "frac": round(f64_tf / F64_PEAK_TFLOPS, 4),
+                             "avg_launch_ms": round(f_ms / max(f_n, 1), 4)}}
 
     # ---- roofline of the dominant kernel in the timed region ---------------------
     ms_by_cls = {c: tr_mx[c][0] for c in tr_mx}
@@ -152,13 +208,14 @@ def main():
     b_ms, b_n, b_items = tr_mx[mf.TRACE_BAND]
     op_bytes = 16.0 * q * q * b_items                # read X, write Y (FP64)
     op_gbs = op_bytes / (b_ms * 1e-3) / 1e9 if b_ms > 0 else 0.0
-    f_ms, f_n, f_items = tr_64[mf.TRACE_GEMM_F64]
-    f64_tf = flop_per_item_gemm * f_items / (f_ms * 1e-3) / 1e12 if f_ms > 0 else 0.0
     dominant = max(ms_by_cls, key=ms_by_cls.get)
     log("trace mixed (ms): band %.1f gemm %.1f vec %.1f | avg gemm launch %.3f ms, avg band launch %.3f ms"
         % (b_ms, g_ms, tr_mx[mf.TRACE_VEC][0], g_ms / max(g_n, 1), b_ms / max(b_n, 1)))
     roofline = dict(bound="mfma", achieved=round(achieved_tf, 2), peak=BF16_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved_tf / BF16_PEAK_TFLOPS, 4), traffic=None,
+                    frac=round(achieved_tf / BF16_PEAK_TFLOPS, 4),
+                    traffic=measured_traffic(args.mixed, q, B),
+                    traffic_unit="HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+                    algorithmic_flop_per_launch=mixed[2] * flop_per_item_gemm * g_items / max(g_n, 1),
                     kernel=mixed[3] + " (transform product, %d BF16 MFMA products)" % mixed[2],
                     avg_launch_ms=round(g_ms / max(g_n, 1), 4), launches=g_n,
                     dominant_class=["band", "gemm_f64", "gemm_bf16x3", "gemm_bf16", "vec", "gemm_bf16x2"][dominant])
@@ -187,23 +244,18 @@ def main():
         "config": {"workload": "elliptic P2 x-normal, n=2049 (q=2047), Dirichlet, gamma=1, "
                                "manufactured f + 1e-3 noise, batch %d, rel residual %.0e" % (B, args.tol),
                    "global_batch": B, "parallelism": "batch on 1 GPU"},
-        "fp64_solves_per_s": round(fp64_value, 3),
-        "mixed_over_fp64": round(value / fp64_value, 3),
         "iterations_mixed": int(it_mx.max()),
-        "iterations_fp64": int(it_64.max()),
         "relres_max_mixed": float(rr_mx.max()),
-        "relres_max_fp64": float(rr_64.max()),
         "setup_s": round(setup_s, 2),
         "op_apply": {"bound": "hbm", "achieved": round(op_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(op_gbs / HBM_PEAK_GBS, 4), "avg_launch_ms": round(b_ms / max(b_n, 1), 4)},
-        "gemm_f64": {"bound": "mfma", "achieved": round(f64_tf, 2), "peak": F64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(f64_tf / F64_PEAK_TFLOPS, 4),
-                     "avg_launch_ms": round(f_ms / max(f_n, 1), 4)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "oracle_forward_err_item0": fwd,
         "oracle_backward_err_item0": back,
     }
+    if fp64:
+        line.update(fp64)
     print(json.dumps(line), flush=True)
 
 
