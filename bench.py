@@ -102,6 +102,63 @@ def copy_calibration(torch):
     print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "launches": 5}), flush=True)
 
 
+def imex_legs(mf, torch, np, nsteps):
+    """Per-step throughput of the IMEX Euler step (eqs. (91)-(96)) on the heat
+    workload (P4, Neumann, n = 2049, d = 0.1, tau = 1e-3, U0 ~ U[0,1) seed 42)
+    and the DIB workload (lumped P1 on [0,20]^2, n = 1025, tau = 1e-2, cap
+    parameters, equilibrium + U[-1e-3,1e-3) seed 7)."""
+    from paper_2109_01173_amd.problems import Rect, XNormal
+    from workloads import dib_initial, dib_params, heat_initial
+    out = {}
+    # heat: split-BF16 transforms, flexible PCG, FP64 residual 1e-10 per step
+    t0 = time.perf_counter()
+    G = XNormal(4, 512, "neumann", gamma=0.0, imex=True, precision=mf.PREC_BF16X3)
+    setup = time.perf_counter() - t0
+    st = torch.from_numpy(heat_initial(G.q, seed=42)[None]).cuda()
+    stepper = mf.Imex(G.op, G.prec, G.mass, 1e-3, [0.1], tol=1e-10, maxit=200, flags=mf.PCG_FLEXIBLE)
+    ws = stepper.workspace(1)
+    mass0 = float(G.mass.apply(st).sum())
+    stepper.step(st, 1, workspace=ws)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    its = [int(stepper.step(st, 1, workspace=ws)[0]) for _ in range(nsteps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    mass1 = float(G.mass.apply(st).sum())
+    out["imex_heat_p4"] = {"workload": "heat P4 x-normal, Neumann, n=2049, d=0.1, tau=1e-3, rel 1e-10 per step",
+                           "steps_per_s": round(nsteps / dt, 3), "steps": nsteps,
+                           "iterations_per_step": round(float(np.mean(its)), 2),
+                           "transforms": "bf16x3", "setup_s": round(setup, 2),
+                           "mass_drift_rel": abs(mass1 - mass0) / abs(mass0)}
+    log("imex heat P4: %.2f steps/s, %.1f iterations/step" % (nsteps / dt, np.mean(its)))
+    del G, st, ws, stepper
+    # DIB: rectangle preset (exact single-term operator), FP64 transforms
+    p = dib_params()
+    t0 = time.perf_counter()
+    G = Rect(1, 1024, "neumann", length=20.0, lumped=True, imex=True)
+    setup = time.perf_counter() - t0
+    eta, theta = dib_initial(G.q, seed=7)
+    st = torch.from_numpy(np.stack([eta, theta])).cuda()
+    kin = [p["rho"], p["A1"], p["A2"], p["B"], p["C"], p["D"], p["alpha"], p["gamma"], p["k2"], p["k3"]]
+    stepper = mf.Imex(G.op, G.prec, G.mass, 1e-2, [1.0, p["d_theta"]], kinetics=mf.KIN_DIB, kin=kin,
+                      tol=1e-10, maxit=50)
+    ws = stepper.workspace(1)
+    stepper.step(st, 1, workspace=ws)
+    torch.cuda.synchronize()
+    n4 = 10 * nsteps
+    t = time.perf_counter()
+    its = [stepper.step(st, 1, workspace=ws).max() for _ in range(n4)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    out["imex_dib_p1"] = {"workload": "DIB lumped P1 rectangle [0,20]^2, Neumann, n=1025, tau=1e-2, "
+                                      "two species, rel 1e-10 per step",
+                          "steps_per_s": round(n4 / dt, 2), "steps": n4,
+                          "iterations_per_step": round(float(np.mean(its)), 2), "transforms": "f64",
+                          "setup_s": round(setup, 2)}
+    log("imex DIB P1: %.1f steps/s, %.1f iterations/step" % (n4 / dt, np.mean(its)))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +171,8 @@ def main():
     ap.add_argument("--mixed", default="bf16x3", choices=["bf16x2", "bf16x3", "bf16"],
                     help="transform precision of the mixed path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--imex-steps", type=int, default=10,
+                    help="IMEX steps timed for the heat (P4) and DIB (lumped P1) legs; 0 skips them")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -220,6 +279,8 @@ def main():
                     avg_launch_ms=round(g_ms / max(g_n, 1), 4), launches=g_n,
                     dominant_class=["band", "gemm_f64", "gemm_bf16x3", "gemm_bf16", "vec", "gemm_bf16x2"][dominant])
 
+    extra = imex_legs(mf, torch, np, args.imex_steps) if args.imex_steps > 0 else {}
+
     # ---- CPU baseline (oracle) ----------------------------------------------------------
     cpu = None
     fwd = back = None
@@ -256,6 +317,7 @@ def main():
     }
     if fp64:
         line.update(fp64)
+    line.update(extra)
     print(json.dumps(line), flush=True)
 
 

@@ -297,7 +297,8 @@ enum {
   MOFEM_TRACE_GEMM_BF16 = 3,    /* one BF16 transform product                  */
   MOFEM_TRACE_VEC = 4,          /* PCG vector kernels and reductions           */
   MOFEM_TRACE_GEMM_BF16X2 = 5,  /* one two-product transform (BF16 basis)      */
-  MOFEM_TRACE_CLASSES = 6
+  MOFEM_TRACE_GEMM_F32 = 6,     /* one FP32 transform product                  */
+  MOFEM_TRACE_CLASSES = 7
 };
 /* on != 0: discard earlier records and start recording; on == 0: stop. */
 int mofem_trace_enable(int on);

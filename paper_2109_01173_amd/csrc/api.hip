@@ -361,6 +361,7 @@ struct mofem_prec_s {
   double *Vs = nullptr, *VsT = nullptr, *Vt = nullptr, *VtT = nullptr;  // FP64 padded
   unsigned short *Vs_h = nullptr, *Vs_l = nullptr, *VsT_h = nullptr, *VsT_l = nullptr;
   unsigned short *Vt_h = nullptr, *Vt_l = nullptr, *VtT_h = nullptr, *VtT_l = nullptr;
+  float *Vs_f = nullptr, *VsT_f = nullptr, *Vt_f = nullptr, *VtT_f = nullptr;  // FP32 padded
   void* ws = nullptr;
   size_t ws_bytes = 0;
 };
@@ -394,6 +395,15 @@ int upload_f64(double** d, const std::vector<double>& h) {
   HIP_TRY(hipMemcpy(*d, h.data(), h.size() * 8, hipMemcpyHostToDevice));
   return MOFEM_OK;
 }
+int upload_f32(float** d, const std::vector<double>& h) {
+  std::vector<float> f(h.size());
+  for (size_t i = 0; i < h.size(); ++i) f[i] = (float)h[i];
+  int rc = dev_alloc(d, f.size());
+  if (rc) return rc;
+  HIP_TRY(hipMemcpy(*d, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+  return MOFEM_OK;
+}
+
 int upload_split(unsigned short** hi, unsigned short** lo, const std::vector<double>& h) {
   std::vector<unsigned short> vh(h.size()), vl(h.size());
   for (size_t i = 0; i < h.size(); ++i) {
@@ -415,7 +425,8 @@ int upload_split(unsigned short** hi, unsigned short** lo, const std::vector<dou
 extern "C" int mofem_prec_destroy(mofem_prec_t p) {
   if (!p) return MOFEM_OK;
   void* ptrs[] = {p->lam, p->mu, p->Vs, p->VsT, p->Vt, p->VtT, p->Vs_h, p->Vs_l, p->VsT_h,
-                  p->VsT_l, p->Vt_h, p->Vt_l, p->VtT_h, p->VtT_l, p->ws};
+                  p->VsT_l, p->Vt_h, p->Vt_l, p->VtT_h, p->VtT_l, p->Vs_f, p->VsT_f, p->Vt_f, p->VtT_f,
+                  p->ws};
   for (void* x : ptrs)
     if (x) (void)hipFree(x);
   delete p;
@@ -433,7 +444,6 @@ extern "C" int mofem_prec_setup(const mofem_prec_desc* desc, mofem_prec_t* out) 
     return fail(MOFEM_E_ARG, "prec_setup: trim flags must be 0 or 1");
   if (D.precision < MOFEM_PREC_F64 || D.precision > MOFEM_PREC_BF16X2)
     return fail(MOFEM_E_ARG, "prec_setup: unknown precision");
-  if (D.precision == MOFEM_PREC_F32) return fail(MOFEM_E_UNSUPPORTED, "prec_setup: FP32 transforms are not built");
   const int qs = D.n_s - 2 * D.trim_s, qt = D.n_t - 2 * D.trim_t;
   if (qs < 1 || qt < 1) return fail(MOFEM_E_ARG, "prec_setup: empty matrices");
 
@@ -469,6 +479,10 @@ extern "C" int mofem_prec_setup(const mofem_prec_desc* desc, mofem_prec_t* out) 
   if (!rc) rc = upload_split(&p->VsT_h, &p->VsT_l, VsT_p);
   if (!rc) rc = upload_split(&p->Vt_h, &p->Vt_l, Vt_p);
   if (!rc) rc = upload_split(&p->VtT_h, &p->VtT_l, VtT_p);
+  if (!rc) rc = upload_f32(&p->Vs_f, Vs_p);
+  if (!rc) rc = upload_f32(&p->VsT_f, VsT_p);
+  if (!rc) rc = upload_f32(&p->Vt_f, Vt_p);
+  if (!rc) rc = upload_f32(&p->VtT_f, VtT_p);
   if (rc) {
     mofem_prec_destroy(p);
     return rc;
@@ -490,7 +504,6 @@ extern "C" int mofem_prec_set_coeffs(mofem_prec_t p, double a, double bs, double
 extern "C" int mofem_prec_set_precision(mofem_prec_t p, int precision) {
   clear_error();
   if (!p) return fail(MOFEM_E_ARG, "prec_set_precision: NULL handle");
-  if (precision == MOFEM_PREC_F32) return fail(MOFEM_E_UNSUPPORTED, "FP32 transforms are not built");
   if (precision < MOFEM_PREC_F64 || precision > MOFEM_PREC_BF16X2) return fail(MOFEM_E_ARG, "unknown precision");
   p->precision = precision;
   return MOFEM_OK;
@@ -513,9 +526,36 @@ extern "C" size_t mofem_prec_workspace_size(mofem_prec_t p, int batch) {
 }
 
 namespace {
+// The padded first-transform operand inside a preconditioner workspace (the
+// first buffer prec_launch carves): FP64, or split BF16 as two halves.
+struct PrecInput {
+  double* f64 = nullptr;
+  float* f32 = nullptr;
+  unsigned short* hi = nullptr;
+  unsigned short* lo = nullptr;
+  long long stride = 0;  // elements between items
+};
+PrecInput prec_input(mofem_prec_t p, void* ws, size_t ws_bytes, int batch) {
+  PrecInput in;
+  const size_t items = (size_t)p->ps * p->pt;
+  Carve c(ws, ws_bytes);
+  if (p->precision == MOFEM_PREC_F64) {
+    in.f64 = c.take<double>(items * batch);
+  } else if (p->precision == MOFEM_PREC_F32) {
+    in.f32 = c.take<float>(items * batch);
+  } else {
+    in.hi = c.take<unsigned short>(items * batch);
+    in.lo = c.take<unsigned short>(items * batch);
+  }
+  in.stride = (long long)items;
+  return in;
+}
+
+// input_ready: the padded operand of R is already in the workspace (written
+// by the fused CG update).
 int prec_launch(mofem_prec_t p, const double* R, double* Z, long long stride, int batch,
                 const double* item_scale, void* ws, size_t ws_bytes, const int* active, hipStream_t s,
-                int n_items = -1) {
+                int n_items = -1, int input_ready = 0) {
   const double items_done = n_items < 0 ? batch : n_items;
   const size_t items = (size_t)p->ps * p->pt;
   GemmArgs g{};
@@ -529,10 +569,12 @@ int prec_launch(mofem_prec_t p, const double* R, double* Z, long long stride, in
   g.out_scale = 1.0;
   g.active = active;
   const int prec = p->precision == MOFEM_PREC_F64      ? GEMM_F64
+                   : p->precision == MOFEM_PREC_F32    ? GEMM_F32
                    : p->precision == MOFEM_PREC_BF16   ? GEMM_BF16
                    : p->precision == MOFEM_PREC_BF16X2 ? GEMM_BF16X2
                                                        : GEMM_BF16X3;
   const int tcls = prec == GEMM_F64      ? MOFEM_TRACE_GEMM_F64
+                   : prec == GEMM_F32    ? MOFEM_TRACE_GEMM_F32
                    : prec == GEMM_BF16   ? MOFEM_TRACE_GEMM_BF16
                    : prec == GEMM_BF16X2 ? MOFEM_TRACE_GEMM_BF16X2
                                          : MOFEM_TRACE_GEMM_BF16X3;
@@ -547,9 +589,9 @@ int prec_launch(mofem_prec_t p, const double* R, double* Z, long long stride, in
     double* T2 = c.take<double>(items * batch);  // S'
     if (!T0 || !T1 || !T2) return fail(MOFEM_E_ARG, "prec_apply: workspace too small");
     const long long istr = (long long)items;
-    {
+    if (!input_ready) {
       TraceScope trace(MOFEM_TRACE_VEC, items_done, s);
-      if (launch_pad_operand(R, stride, p->qs, p->qt, T0, nullptr, nullptr, istr, 0, batch, active, s))
+      if (launch_pad_operand(R, stride, p->qs, p->qt, T0, nullptr, nullptr, nullptr, istr, 0, batch, active, s))
         return fail(MOFEM_E_HIP, "pad launch");
     }
     // G1: T' = (R V_t)^T
@@ -572,6 +614,33 @@ int prec_launch(mofem_prec_t p, const double* R, double* Z, long long stride, in
     g.a64 = T1; g.a_stride = istr; g.b64 = p->Vt; g.b_stride = 0;
     g.c64 = Z; g.c_stride = stride; g.divide = 0;
     if (gemm(O_F64_RAW)) return fail(MOFEM_E_HIP, "gemm launch");
+  } else if (prec == GEMM_F32) {
+    float* T0 = c.take<float>(items * batch);  // padded R
+    float* T1 = c.take<float>(items * batch);  // T' then W
+    float* T2 = c.take<float>(items * batch);  // S'
+    if (!T0 || !T1 || !T2) return fail(MOFEM_E_ARG, "prec_apply: workspace too small");
+    const long long istr = (long long)items;
+    if (!input_ready) {
+      TraceScope trace(MOFEM_TRACE_VEC, items_done, s);
+      if (launch_pad_operand(R, stride, p->qs, p->qt, nullptr, T0, nullptr, nullptr, istr, 0, batch, active, s))
+        return fail(MOFEM_E_HIP, "pad launch");
+    }
+    g.M = p->qs; g.N = p->qt; g.K = p->qt;
+    g.a_hi = T0; g.a_stride = istr; g.b_hi = p->VtT_f; g.b_stride = 0;
+    g.c_hi = T1; g.c_stride = istr; g.divide = 0;
+    if (gemm(O_PAD_T)) return fail(MOFEM_E_HIP, "gemm launch");
+    g.M = p->qs; g.N = p->qt; g.K = p->qs;
+    g.a_hi = p->VsT_f; g.a_stride = 0; g.b_hi = T1; g.b_stride = istr;
+    g.c_hi = T2; g.c_stride = istr; g.divide = 1;
+    if (gemm(O_PAD_T)) return fail(MOFEM_E_HIP, "gemm launch");
+    g.M = p->qs; g.N = p->qt; g.K = p->qs;
+    g.a_hi = p->Vs_f; g.a_stride = 0; g.b_hi = T2; g.b_stride = istr;
+    g.c_hi = T1; g.c_stride = istr; g.divide = 0;
+    if (gemm(O_PAD_N)) return fail(MOFEM_E_HIP, "gemm launch");
+    g.M = p->qs; g.N = p->qt; g.K = p->qt;
+    g.a_hi = T1; g.a_stride = istr; g.b_hi = p->Vt_f; g.b_stride = 0;
+    g.c64 = Z; g.c_stride = stride; g.divide = 0;
+    if (gemm(O_F64_RAW)) return fail(MOFEM_E_HIP, "gemm launch");
   } else {
     unsigned short* T0h = c.take<unsigned short>(items * batch);
     unsigned short* T0l = c.take<unsigned short>(items * batch);
@@ -581,9 +650,9 @@ int prec_launch(mofem_prec_t p, const double* R, double* Z, long long stride, in
     unsigned short* T2l = c.take<unsigned short>(items * batch);
     if (!T0h || !T0l || !T1h || !T1l || !T2h || !T2l) return fail(MOFEM_E_ARG, "prec_apply: workspace too small");
     const long long istr = (long long)items;
-    {
+    if (!input_ready) {
       TraceScope trace(MOFEM_TRACE_VEC, items_done, s);
-      if (launch_pad_operand(R, stride, p->qs, p->qt, nullptr, T0h, T0l, istr, 1, batch, active, s))
+      if (launch_pad_operand(R, stride, p->qs, p->qt, nullptr, nullptr, T0h, T0l, istr, 1, batch, active, s))
         return fail(MOFEM_E_HIP, "pad launch");
     }
     g.M = p->qs; g.N = p->qt; g.K = p->qt;
@@ -757,6 +826,7 @@ extern "C" int mofem_pcg_solve(mofem_op_t op, mofem_prec_t prec, const double* R
   const bool flexible = flags & MOFEM_PCG_FLEXIBLE;
   const bool tau_stop = flags & MOFEM_PCG_TAU_STOP;
   const int nt = op->n_tiles;
+  const PrecInput pin = prec_input(prec, w.prec_ws, w.prec_bytes, batch);
 
   std::vector<int> active(batch, 1), iters(batch, 0), status(batch, MOFEM_OK);
   std::vector<double> target2(batch, 0.0), rhs2(batch, 0.0);
@@ -833,8 +903,11 @@ extern "C" int mofem_pcg_solve(mofem_op_t op, mofem_prec_t prec, const double* R
     // Y = L(Q), <Q, Y>
     TRY(op_launch(op, w.Q, n, w.Y, n, batch, item_scale, w.part_op, w.active, s, n_active));
     LTRY(launch_reduce(w.part_op, nt, w.qy, batch, s));
-    // alpha = <R, Z> / <Q, Y>; U += alpha Q; R -= alpha Y; <R, R>
-    LTRY(launch_cg_update(U, w.R, w.Q, w.Y, w.rz, w.qy, w.alpha, n, n, stride, batch, w.part_a, w.active, s));
+    // alpha = <R, Z> / <Q, Y>; U += alpha Q; R -= alpha Y; <R, R>; R's padded
+    // transform operand for the next preconditioner application
+    LTRY(launch_cg_update_pad(U, w.R, w.Q, w.Y, w.rz, w.qy, w.alpha, op->qs, op->qt, n, stride, batch, w.part_a,
+                              w.active, pin.hi, pin.lo, pin.f64, pin.f32, pin.stride, s));
+    bool r_padded = true;
     LTRY(launch_reduce(w.part_a, kVecBlocks, w.rr, batch, s));
     TRY(fetch(w.qy, qy.data()));
     TRY(fetch(w.rr, rr.data()));
@@ -872,6 +945,7 @@ extern "C" int mofem_pcg_solve(mofem_op_t op, mofem_prec_t prec, const double* R
         } else {
           // recurrence drifted: continue from the true residual with a fresh direction
           restart[b] = 1;
+          r_padded = false;
           LTRY(launch_copy(w.Z + (size_t)b * n, w.R + (size_t)b * n, n, n, n, 1, s));
         }
       }
@@ -880,8 +954,10 @@ extern "C" int mofem_pcg_solve(mofem_op_t op, mofem_prec_t prec, const double* R
     any = false;
     for (int b = 0; b < batch; ++b) any |= active[b] != 0;
     if (!any || it >= maxit) break;
-    // Z = P^{-1}(R); <R, Z>, <Z, Y>
-    TRY(prec_launch(prec, w.R, w.Z, n, batch, item_scale, w.prec_ws, w.prec_bytes, w.active, s, n_active));
+    // Z = P^{-1}(R); <R, Z>, <Z, Y>.  (Fusing the two products into the last
+    // transform's epilogue was measured slower than this separate pass.)
+    TRY(prec_launch(prec, w.R, w.Z, n, batch, item_scale, w.prec_ws, w.prec_bytes, w.active, s, n_active,
+                    r_padded ? 1 : 0));
     LTRY(launch_dot2_partial(w.R, w.Z, w.Z, w.Y, n, n, batch, w.part_a, w.part_b, w.active, s));
     LTRY(launch_reduce(w.part_a, kVecBlocks, w.rz_new, batch, s));
     LTRY(launch_reduce(w.part_b, kVecBlocks, w.zy, batch, s));

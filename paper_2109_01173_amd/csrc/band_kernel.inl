@@ -38,32 +38,41 @@ namespace mofem {
 
 constexpr int kBandWaves = 4;
 
-template <int KB, int NT>
+// Tile configuration.  GG: row groups per block (TI = GG U rows), SS: groups
+// unrolled per loop iteration, PFX: rows in flight per lane (a divisor of
+// SS U, so that every queue slot is a compile-time index).  Zero selects the
+// default.
+template <int KB, int NT, int GG = 0, int SS = 0, int PFX = 0>
 struct BandCfg {
   static constexpr int W = 2 * KB + 1;
   static constexpr int U = KB * W;   // period of ring slot and element phase
   static constexpr int RC = NT * W;  // left coefficients per output row
-  // groups per block: about 200 rows, at most 48 KB of staged coefficients
-  static constexpr int G_ROWS = 200 / U;
+  // default: about 160 rows per block, at most 48 KB of staged coefficients
+  static constexpr int G_ROWS = 160 / U;
   static constexpr int G_LDS = (48 * 1024 / 8) / (RC * U);
   static constexpr int G_MIN = G_ROWS < G_LDS ? G_ROWS : G_LDS;
-  static constexpr int G = G_MIN < 1 ? 1 : G_MIN;
+  static constexpr int G_DEF = G_MIN < 1 ? 1 : G_MIN;
+  static constexpr int S = SS > 0 ? SS : 1;
+  static constexpr int G = GG > 0 ? GG : (G_DEF / S > 0 ? G_DEF / S * S : S);
   static constexpr int TI = G * U;
-  // prefetch distance: the largest divisor of U not above 12 (about one
-  // period: enough loads in flight to cover HBM latency at 3 waves/SIMD)
-  static constexpr int pf(int d) { return (U % d == 0) ? d : pf(d - 1); }
-  static constexpr int PF = pf(12);
+  static constexpr int SU = S * U;
+  // prefetch distance: the largest divisor of S U not above 12 by default
+  static constexpr int pf(int d) { return (SU % d == 0) ? d : pf(d - 1); }
+  static constexpr int PF = PFX > 0 ? PFX : pf(12);
   static constexpr int SW = 64 - 2 * KB;
+  static_assert(G % S == 0, "groups per block must be a multiple of the unroll");
+  static_assert(SU % PF == 0, "prefetch distance must divide the unrolled period");
+  static_assert(TI * RC * 8 <= 64 * 1024, "staged coefficients exceed 64 KB");
 };
 
 // The arrays are separate __restrict__ kernel arguments (not struct members)
 // so that the compiler can order the loads freely around the stores to Y.
-template <int KB, int NT, bool PAT>
+template <int KB, int NT, bool PAT, int GG, int SS, int PFX>
 __global__ __launch_bounds__(256) void band_apply_kernel(BandArgs a, const double* __restrict__ X,
                                                          double* __restrict__ Y, const double* __restrict__ left,
                                                          const double* __restrict__ right) {
-  using C = BandCfg<KB, NT>;
-  constexpr int W = C::W, U = C::U, RC = C::RC, TI = C::TI, PF = C::PF;
+  using C = BandCfg<KB, NT, GG, SS, PFX>;
+  constexpr int W = C::W, RC = C::RC, TI = C::TI, PF = C::PF, SU = C::SU;
   __shared__ double lcoef[TI * RC];
   __shared__ double dsum[kBandWaves];
 
@@ -156,17 +165,17 @@ __global__ __launch_bounds__(256) void band_apply_kernel(BandArgs a, const doubl
     right_row(p, std::integral_constant<int, ((p - KB) % W + W) % W>{}, std::integral_constant<int, p % PF>{});
   });
 
-  // main loop: row p = 2KB + grp U + P completes output node row g = g0 + grp U + P
+  // main loop: row p = 2KB + grp SU + P completes output node row g = g0 + grp SU + P
   auto group = [&](int grp, auto check_c) {
     constexpr bool CHECK = decltype(check_c)::value;
-    StaticFor<0, U>::run([&](auto pc) {
+    StaticFor<0, SU>::run([&](auto pc) {
       constexpr int P = decltype(pc)::value;
       constexpr int slot = (KB + P) % W;
       constexpr int qslot = (2 * KB + P) % PF;
       constexpr int phase = P % KB;
       constexpr int dlo = (!PAT || phase == 0) ? 0 : KB - phase;
       constexpr int dhi = (!PAT || phase == 0) ? 2 * KB : 2 * KB - phase;
-      const int m = grp * U + P;
+      const int m = grp * SU + P;
       right_row(2 * KB + m, std::integral_constant<int, slot>{}, std::integral_constant<int, qslot>{});
       const int i = i0 + m;
       if (!CHECK || (i >= 0 && i < a.qs)) {
@@ -189,9 +198,9 @@ __global__ __launch_bounds__(256) void band_apply_kernel(BandArgs a, const doubl
   };
   const bool interior = (i0 >= 0) && (i0 + TI <= a.qs);
   if (interior) {
-    for (int grp = 0; grp < C::G; ++grp) group(grp, std::false_type{});
+    for (int grp = 0; grp < C::G / C::S; ++grp) group(grp, std::false_type{});
   } else {
-    for (int grp = 0; grp < C::G; ++grp) group(grp, std::true_type{});
+    for (int grp = 0; grp < C::G / C::S; ++grp) group(grp, std::true_type{});
   }
 
   if (a.dot_partial) {
@@ -206,17 +215,17 @@ __global__ __launch_bounds__(256) void band_apply_kernel(BandArgs a, const doubl
   }
 }
 
-template <int KB, int NT>
+template <int KB, int NT, int GG = 0, int SS = 0, int PFX = 0>
 void launch_kb_nt(const BandArgs& a, int batch, bool pat, hipStream_t s) {
-  using C = BandCfg<KB, NT>;
+  using C = BandCfg<KB, NT, GG, SS, PFX>;
   const int n_sb = (a.qt + kBandWaves * C::SW - 1) / (kBandWaves * C::SW);
   dim3 grid(n_sb * a.n_rowblk, batch);
   if (pat && KB >= 2)
-    hipLaunchKernelGGL((band_apply_kernel<KB, NT, (KB >= 2)>), grid, dim3(64 * kBandWaves), 0, s, a, a.X, a.Y,
-                       a.left, a.right);
+    hipLaunchKernelGGL((band_apply_kernel<KB, NT, (KB >= 2), GG, SS, PFX>), grid, dim3(64 * kBandWaves), 0, s, a,
+                       a.X, a.Y, a.left, a.right);
   else
-    hipLaunchKernelGGL((band_apply_kernel<KB, NT, false>), grid, dim3(64 * kBandWaves), 0, s, a, a.X, a.Y, a.left,
-                       a.right);
+    hipLaunchKernelGGL((band_apply_kernel<KB, NT, false, GG, SS, PFX>), grid, dim3(64 * kBandWaves), 0, s, a, a.X,
+                       a.Y, a.left, a.right);
 }
 
 // One translation unit per band width compiles these (k_band_kb*.hip).

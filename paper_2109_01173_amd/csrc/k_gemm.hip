@@ -14,6 +14,7 @@
 //
 // Precisions:
 //   GEMM_F64     v_mfma_f64_16x16x4_f64, FP64 operands and accumulation.
+//   GEMM_F32     v_mfma_f32_16x16x4_f32, FP32 operands and accumulation.
 //   GEMM_BF16X3  v_mfma_f32_16x16x32_bf16 with split operands x = hi + lo
 //                (hi = bf16(x), lo = bf16(x - hi)); A B ~ Ah Bh + Ah Bl + Al Bh,
 //                FP32 accumulation, FP32-level accuracy.
@@ -64,9 +65,8 @@ __device__ __forceinline__ double eval_D(const GemmArgs& g, int row, int col, do
 // ------------------------------------------------------------------------------
 // FP64
 // ------------------------------------------------------------------------------
-template <int OMODE>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
-  constexpr int BK = 16;
+template <int OMODE, int BK = 16>
+__global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmArgs g) {
   constexpr int LDS_K = BK + 1;
   __shared__ double As[BM][LDS_K];
   __shared__ double Bs[BN][LDS_K];
@@ -84,13 +84,14 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
   const double* __restrict__ A = g.a64 + (size_t)b * g.a_stride;
   const double* __restrict__ B = g.b64 + (size_t)b * g.b_stride;
 
-  // global -> register staging: thread owns row tid/2, k segment (tid%2)*8
-  const int lrow = tid >> 1, lk = (tid & 1) * 8;
-  double ra[8], rb[8];
+  // global -> register staging: thread owns row tid/2, k segment (tid%2)*(BK/2)
+  constexpr int HK = BK / 2;
+  const int lrow = tid >> 1, lk = (tid & 1) * HK;
+  double ra[HK], rb[HK];
   auto load_tile = [&](int k0) {
     const int arow = m0 + lrow;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < HK; ++e) {
       const int kk = k0 + lk + e;
       ra[e] = A[(size_t)arow * lda + kk];
       rb[e] = B[(size_t)(n0 + lrow) * ldb + kk];
@@ -108,7 +109,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
   for (int kt = 0; kt < nk; ++kt) {
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < HK; ++e) {
       As[lrow][lk + e] = ra[e];
       Bs[lrow][lk + e] = rb[e];
     }
@@ -152,6 +153,101 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
 }
 
 // ------------------------------------------------------------------------------
+// FP32: v_mfma_f32_16x16x4_f32, FP32 operands and accumulation
+// ------------------------------------------------------------------------------
+template <int OMODE>
+__global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g) {
+  constexpr int BK = 32;
+  constexpr int LDS_K = BK + 1;
+  __shared__ float As[BM][LDS_K];
+  __shared__ float Bs[BN][LDS_K];
+
+  const int b = blockIdx.y;
+  if (g.active && !g.active[b]) return;
+  const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
+  const int tile = xcd_tile(blockIdx.x, tm * tn);
+  const int m0 = (tile / tn) * BM, n0 = (tile % tn) * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  const int Kp = pad_up(g.K);
+  const float* __restrict__ A = (const float*)g.a_hi + (size_t)b * g.a_stride;
+  const float* __restrict__ B = (const float*)g.b_hi + (size_t)b * g.b_stride;
+
+  // global -> register staging: thread owns row tid/2, k segment (tid%2)*16 (four 16-byte loads)
+  const int lrow = tid >> 1, lk = (tid & 1) * 16;
+  f4_t ra[4], rb[4];
+  auto load_tile = [&](int k0) {
+    const f4_t* pa = (const f4_t*)(A + (size_t)(m0 + lrow) * Kp + k0 + lk);
+    const f4_t* pb = (const f4_t*)(B + (size_t)(n0 + lrow) * Kp + k0 + lk);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      ra[v] = pa[v];
+      rb[v] = pb[v];
+    }
+  };
+
+  f4_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = (f4_t){0.f, 0.f, 0.f, 0.f};
+
+  const int nk = (g.K + BK - 1) / BK;
+  load_tile(0);
+  for (int kt = 0; kt < nk; ++kt) {
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        As[lrow][lk + 4 * v + e] = ra[v][e];
+        Bs[lrow][lk + 4 * v + e] = rb[v][e];
+      }
+    __syncthreads();
+    if (kt + 1 < nk) load_tile((kt + 1) * BK);
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      float av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = As[wm * 64 + i * 16 + (lane & 15)][ks * 4 + (lane >> 4)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = Bs[wn * 64 + j * 16 + (lane & 15)][ks * 4 + (lane >> 4)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+  }
+
+  // epilogue: acc[i][j][r] = C[row][col], row = 4*(lane/16) + r, col = lane%16
+  const double s = g.item_scale ? g.item_scale[b] : 1.0;
+  const int Mp = pad_up(g.M), Np = pad_up(g.N);
+  float* __restrict__ C32 = (float*)g.c_hi + (size_t)b * g.c_stride;
+  double* __restrict__ C64 = g.c64 + (size_t)b * g.c_stride;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+        const int col = n0 + wn * 64 + j * 16 + (lane & 15);
+        const bool in = row < g.M && col < g.N;
+        double v = (double)acc[i][j][r] * g.out_scale;
+        if (g.divide && in) v /= eval_D(g, row, col, s);
+        if (!in) v = 0.0;
+        if (OMODE == O_F64_RAW) {
+          if (in) C64[(size_t)row * g.N + col] = v;
+        } else {
+          const size_t idx = (OMODE == O_PAD_T) ? (size_t)col * Mp + row : (size_t)row * Np + col;
+          C32[idx] = (float)v;
+        }
+      }
+}
+
+// ------------------------------------------------------------------------------
 // split BF16 (NPROD = 3) and plain BF16 (NPROD = 1), FP32 accumulation
 // ------------------------------------------------------------------------------
 // MODE: BF_HH   plain BF16                    A_h B_h
@@ -160,10 +256,9 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
 //       BF_X2B  B split, A exact in BF16       A_h B_l + A_h B_h
 enum { BF_HH = 0, BF_X3 = 1, BF_X2A = 2, BF_X2B = 3 };
 
-template <int MODE, int OMODE>
-__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
-  constexpr int BK = 64;
-  constexpr int LDS_K = BK + 8;   // 144-byte rows keep 16-byte alignment
+template <int MODE, int OMODE, int BK = 64, int MINW = 1>
+__global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
+  constexpr int LDS_K = BK + 8;   // padded rows keep 16-byte alignment
   constexpr bool ALO = (MODE == BF_X3 || MODE == BF_X2A);
   constexpr bool BLO = (MODE == BF_X3 || MODE == BF_X2B);
   __shared__ unsigned short Ah[BM][LDS_K];
@@ -302,6 +397,8 @@ static void launch_mode(const GemmArgs& g, int prec, int batch, hipStream_t s) {
   dim3 grid(tm * tn, batch);
   if (prec == GEMM_F64)
     hipLaunchKernelGGL((gemm_f64_kernel<OMODE>), grid, dim3(256), 0, s, g);
+  else if (prec == GEMM_F32)
+    hipLaunchKernelGGL((gemm_f32_kernel<OMODE>), grid, dim3(256), 0, s, g);
   else if (prec == GEMM_BF16X3)
     hipLaunchKernelGGL((gemm_bf16_kernel<BF_X3, OMODE>), grid, dim3(256), 0, s, g);
   else if (prec == GEMM_BF16X2 && g.data_is_a)
@@ -313,7 +410,8 @@ static void launch_mode(const GemmArgs& g, int prec, int batch, hipStream_t s) {
 }
 
 int launch_gemm(const GemmArgs& g, int prec, int omode, int batch, hipStream_t s) {
-  if (prec != GEMM_F64 && prec != GEMM_BF16 && prec != GEMM_BF16X3 && prec != GEMM_BF16X2) return -1;
+  if (prec != GEMM_F64 && prec != GEMM_F32 && prec != GEMM_BF16 && prec != GEMM_BF16X3 && prec != GEMM_BF16X2)
+    return -1;
   if (omode == O_PAD_T) launch_mode<O_PAD_T>(g, prec, batch, s);
   else if (omode == O_PAD_N) launch_mode<O_PAD_N>(g, prec, batch, s);
   else if (omode == O_F64_RAW) launch_mode<O_F64_RAW>(g, prec, batch, s);
@@ -325,7 +423,7 @@ int launch_gemm(const GemmArgs& g, int prec, int omode, int batch, hipStream_t s
 // FP64 or split BF16 (hi, lo), zeros in the padding.  One block per padded
 // row; consecutive threads take consecutive columns (coalesced both ways).
 __global__ __launch_bounds__(256) void pad_operand_kernel(const double* __restrict__ A, long long a_stride, int M,
-                                                          int K, double* __restrict__ o64,
+                                                          int K, double* __restrict__ o64, float* __restrict__ o32,
                                                           unsigned short* __restrict__ ohi,
                                                           unsigned short* __restrict__ olo, long long o_stride,
                                                           int split, const int* active) {
@@ -342,17 +440,19 @@ __global__ __launch_bounds__(256) void pad_operand_kernel(const double* __restri
       split_bf16((float)x, &hi, &lo);
       ohi[obase + c] = hi;
       olo[obase + c] = lo;
+    } else if (o32) {
+      o32[obase + c] = (float)x;
     } else {
       o64[obase + c] = x;
     }
   }
 }
 
-int launch_pad_operand(const double* A, long long a_stride, int M, int K, double* o64, unsigned short* ohi,
-                       unsigned short* olo, long long o_stride, int split, int batch, const int* active,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(pad_operand_kernel, dim3(pad_up(M), batch), dim3(256), 0, s, A, a_stride, M, K, o64, ohi, olo,
-                     o_stride, split, active);
+int launch_pad_operand(const double* A, long long a_stride, int M, int K, double* o64, float* o32,
+                       unsigned short* ohi, unsigned short* olo, long long o_stride, int split, int batch,
+                       const int* active, hipStream_t s) {
+  hipLaunchKernelGGL(pad_operand_kernel, dim3(pad_up(M), batch), dim3(256), 0, s, A, a_stride, M, K, o64, o32, ohi,
+                     olo, o_stride, split, active);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -134,6 +134,57 @@ __global__ __launch_bounds__(kThreads) void cg_update_kernel(double* __restrict_
   if (threadIdx.x == 0) partial[(size_t)b * gridDim.x + blockIdx.x] = s;
 }
 
+// cg_update, also writing R's padded transform operand (row length Kp):
+// FP64, FP32 or split BF16 (hi, lo).  Each thread walks its elements with a
+// running (row, col) so no division sits in the loop.
+__global__ __launch_bounds__(kThreads) void cg_update_pad_kernel(
+    double* __restrict__ U, double* __restrict__ R, const double* __restrict__ Q, const double* __restrict__ Y,
+    const double* __restrict__ num, const double* __restrict__ den, double* __restrict__ alpha_out, int qt,
+    long long n, long long stride, long long u_stride, double* __restrict__ partial, const int* active,
+    unsigned short* __restrict__ ohi, unsigned short* __restrict__ olo, double* __restrict__ o64,
+    float* __restrict__ o32, long long o_stride) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const double alpha = num[b] / den[b];
+  if (blockIdx.x == 0 && threadIdx.x == 0 && alpha_out) alpha_out[b] = alpha;
+  long long lo, hi;
+  chunk_of(n, blockIdx.x, gridDim.x, &lo, &hi);
+  double* u = U + (size_t)b * u_stride;
+  double* r = R + (size_t)b * stride;
+  const double* q = Q + (size_t)b * stride;
+  const double* y = Y + (size_t)b * stride;
+  const int Kp = pad_up(qt);
+  const size_t ob = (size_t)b * o_stride;
+  long long i = lo + threadIdx.x;
+  long long row = i / qt;
+  int col = (int)(i - row * qt);
+  double s = 0.0;
+  for (; i < hi; i += kThreads) {
+    u[i] = fma(alpha, q[i], u[i]);
+    const double v = fma(-alpha, y[i], r[i]);
+    r[i] = v;
+    s = fma(v, v, s);
+    const size_t o = ob + (size_t)row * Kp + col;
+    if (o64) {
+      o64[o] = v;
+    } else if (o32) {
+      o32[o] = (float)v;
+    } else {
+      const float f = (float)v;
+      const __bf16 h = (__bf16)f;
+      ohi[o] = __builtin_bit_cast(unsigned short, h);
+      olo[o] = __builtin_bit_cast(unsigned short, (__bf16)(f - (float)h));
+    }
+    col += kThreads;
+    while (col >= qt) {
+      col -= qt;
+      ++row;
+    }
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) partial[(size_t)b * gridDim.x + blockIdx.x] = s;
+}
+
 __global__ __launch_bounds__(kThreads) void direction_kernel(double* __restrict__ Q, const double* __restrict__ Z,
                                                              const double* __restrict__ beta, long long n,
                                                              long long stride, const int* active) {
@@ -230,6 +281,15 @@ int launch_cg_update(double* U, double* R, const double* Q, const double* Y, con
                      double* partial, const int* active, hipStream_t s) {
   hipLaunchKernelGGL(cg_update_kernel, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, U, R, Q, Y, num, den,
                      alpha_out, n, stride, u_stride, partial, active);
+  CHECK_LAUNCH();
+}
+int launch_cg_update_pad(double* U, double* R, const double* Q, const double* Y, const double* num,
+                         const double* den, double* alpha_out, int qs, int qt, long long stride,
+                         long long u_stride, int batch, double* partial, const int* active, unsigned short* ohi,
+                         unsigned short* olo, double* o64, float* o32, long long o_stride, hipStream_t s) {
+  hipLaunchKernelGGL(cg_update_pad_kernel, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, U, R, Q, Y, num, den,
+                     alpha_out, qt, (long long)qs * qt, stride, u_stride, partial, active, ohi, olo, o64, o32,
+                     o_stride);
   CHECK_LAUNCH();
 }
 int launch_direction(double* Q, const double* Z, const double* beta, long long n, long long stride, int batch,

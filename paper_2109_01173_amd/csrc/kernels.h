@@ -72,10 +72,10 @@ struct GemmArgs {
   int data_is_a;           // GEMM_BF16X2: the split (data) operand is A (else B)
 };
 int launch_gemm(const GemmArgs& g, int prec, int omode, int batch, hipStream_t s);
-// raw FP64 items (M x K) -> padded FP64 or split BF16 operand
-int launch_pad_operand(const double* A, long long a_stride, int M, int K, double* o64, unsigned short* ohi,
-                       unsigned short* olo, long long o_stride, int split, int batch, const int* active,
-                       hipStream_t s);
+// raw FP64 items (M x K) -> padded FP64, FP32 or split BF16 operand
+int launch_pad_operand(const double* A, long long a_stride, int M, int K, double* o64, float* o32,
+                       unsigned short* ohi, unsigned short* olo, long long o_stride, int split, int batch,
+                       const int* active, hipStream_t s);
 
 // ---- vector kernels of the PCG recurrence (k_vec.hip) -----------------------
 constexpr int kVecBlocks = 240;   // partial sums per item
@@ -91,6 +91,12 @@ int launch_dot2_partial(const double* A, const double* B, const double* C, const
 int launch_residual(const double* Rhs, const double* Y, double* R, long long n, long long stride,
                     long long rhs_stride, int batch, double* partial, const int* active, hipStream_t s);
 // alpha_b = num_b / den_b; U += alpha Q; R -= alpha Y; partial <R, R>
+// cg_update that also writes R's padded transform operand (row length
+// pad_up(qt)): FP64 (o64), FP32 (o32) or split BF16 (ohi, olo); padding left untouched
+int launch_cg_update_pad(double* U, double* R, const double* Q, const double* Y, const double* num,
+                         const double* den, double* alpha_out, int qs, int qt, long long stride,
+                         long long u_stride, int batch, double* partial, const int* active, unsigned short* ohi,
+                         unsigned short* olo, double* o64, float* o32, long long o_stride, hipStream_t s);
 int launch_cg_update(double* U, double* R, const double* Q, const double* Y, const double* num,
                      const double* den, double* alpha_out, long long n, long long stride,
                      long long u_stride, int batch, double* partial, const int* active,

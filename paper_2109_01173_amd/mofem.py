@@ -33,8 +33,8 @@ W_ONE, W_POLY, W_PROFILE, W_PROFILE_D, W_PROFILE_INV, W_PROFILE_D2L, W_CALLBACK 
 PREC_F64, PREC_F32, PREC_BF16, PREC_BF16X3, PREC_BF16X2 = range(5)
 PCG_FLEXIBLE, PCG_ZERO_GUESS, PCG_TAU_STOP = 1, 2, 4
 KIN_NONE, KIN_DIB = 0, 1
-TRACE_BAND, TRACE_GEMM_F64, TRACE_GEMM_BF16X3, TRACE_GEMM_BF16, TRACE_VEC, TRACE_GEMM_BF16X2 = range(6)
-TRACE_CLASSES = 6
+TRACE_BAND, TRACE_GEMM_F64, TRACE_GEMM_BF16X3, TRACE_GEMM_BF16, TRACE_VEC, TRACE_GEMM_BF16X2, TRACE_GEMM_F32 = range(7)
+TRACE_CLASSES = 7
 MAX_TERMS = 8
 
 _vp = ctypes.c_void_p
