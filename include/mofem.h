@@ -139,6 +139,11 @@ typedef struct {
   double coef[MOFEM_MAX_TERMS];          /* c_t                               */
   int scaled[MOFEM_MAX_TERMS];           /* 1 = term is also multiplied by the
                                             per-item scale s_b of the apply   */
+  int full_output;      /* 1: X is q_s x q_t and Y is n_s x n_t (all nodes):
+                           the transpose of a full_input operator, e.g. the
+                           gradient M3[:, I] Lambda M[I, :] of a loss with
+                           respect to the full-node load F.  Excludes
+                           full_input.                                        */
 } mofem_op_desc;
 typedef struct mofem_op_s* mofem_op_t;
 
@@ -163,6 +168,14 @@ int mofem_op_shape(mofem_op_t op, int* q_s, int* q_t, int* in_s, int* in_t);
 int mofem_op_apply(mofem_op_t op, const double* X, long long in_stride, double* Y,
                    long long stride, int batch, const double* item_scale,
                    double* dot_xy, void* stream);
+
+/* Batched Frobenius products (eq. (77)'s sum(sum(X o Y)) per item):
+     out[b] = beta * out[b] + alpha * <X_b, Y_b>_F,   b < batch,
+   X_b = X + b * stride (n contiguous doubles), likewise Y_b; out device.
+   Fixed-order two-pass reduction (bitwise reproducible).  Uses a small
+   library-owned device buffer per thread.  Errors: MOFEM_E_ARG. */
+int mofem_dot_accumulate(const double* X, const double* Y, long long n, long long stride,
+                         int batch, double alpha, double beta, double* out, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* a1/a4. Single-term spectral preconditioner                              */
@@ -282,6 +295,30 @@ size_t mofem_imex_workspace_size(const mofem_imex_desc* desc, int batch);
 int mofem_imex_step(const mofem_imex_desc* desc, double* state, long long stride,
                     int batch, void* workspace, size_t ws_bytes, int* iters_out,
                     void* stream);
+
+/* Reverse (adjoint) IMEX Euler step: the exact derivative of
+   mofem_imex_step for a scalar loss J.  With c = d * tau per species,
+     mu  = L_c^{-1}(lam)              (L_c is symmetric: one more MO-PCG solve
+                                       with the same operator, preconditioner,
+                                       tol and flags, zero initial guess),
+     grad_d[item] += -tau <mu, K(U^{n+1})>    (dL_c/dd = tau K),
+     nu  = Mass(mu),
+     lam := nu                                       (no kinetics), or
+     lam_U := nu_U + tau rho (f_U o nu_U + g_U o nu_V),
+     lam_V := nu_V + tau rho (f_V o nu_U + g_V o nu_V)   (DIB, eqs. (99)-(100);
+                                       o = entrywise, partials at U^n, V^n).
+     stiff      operator K (the stiffness part: L_c = Mass + c K), unknowns
+                to unknowns, same shape.
+     state_n    device, the step's input state  (layout of mofem_imex_step).
+     state_np1  device, the step's output state.
+     lam        device, in: dJ/d state_np1, out: dJ/d state_n (same layout).
+     grad_d     device [n_species * batch], accumulated.
+   stride must equal q_s * q_t.  Errors as mofem_pcg_solve. */
+size_t mofem_imex_adjoint_workspace_size(const mofem_imex_desc* desc, int batch);
+int mofem_imex_adjoint_step(const mofem_imex_desc* desc, mofem_op_t stiff, const double* state_n,
+                            const double* state_np1, double* lam, double* grad_d,
+                            long long stride, int batch, void* workspace, size_t ws_bytes,
+                            int* iters_out, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Kernel tracing                                                           */

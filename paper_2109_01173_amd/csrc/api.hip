@@ -158,7 +158,7 @@ extern "C" int mofem_trace_read(int cls, double* total_ms, long long* launches, 
 // ============================================================================
 struct mofem_op_s {
   int kb = 0, nt = 0, qs = 0, qt = 0, ns_in = 0, nt_in = 0;
-  int off_s = 0, off_t = 0, ph_s = 0, full_input = 0, pattern = 0, scaled_mask = 0;
+  int off_s = 0, off_t = 0, ph_s = 0, full_input = 0, full_output = 0, pattern = 0, scaled_mask = 0;
   int n_rowblk = 0, n_tiles = 0;
   double* d_left = nullptr;
   double* d_right = nullptr;
@@ -193,10 +193,13 @@ extern "C" int mofem_op_create(const mofem_op_desc* desc, mofem_op_t* out) {
     return fail(MOFEM_E_ARG, "op_create: matrices too small for the band");
   for (int t = 0; t < D.n_terms; ++t)
     if (!D.left[t] || !D.right[t]) return fail(MOFEM_E_ARG, "op_create: NULL band");
+  if (D.full_input && D.full_output) return fail(MOFEM_E_ARG, "op_create: full_input and full_output exclude each other");
 
   const int kb = D.kb, W = 2 * kb + 1, nt = D.n_terms;
   const int ns = D.n_s, ntt = D.n_t;
-  const int qs = ns - 2 * D.trim_s, qt = ntt - 2 * D.trim_t;
+  // output rows/columns: the unknowns, or all nodes for full_output
+  const int qs = D.full_output ? ns : ns - 2 * D.trim_s, qt = D.full_output ? ntt : ntt - 2 * D.trim_t;
+  const int row0 = D.full_output ? 0 : D.trim_s, col0 = D.full_output ? 0 : D.trim_t;  // node of output 0
   std::vector<double> left((size_t)qs * nt * W, 0.0), right((size_t)nt * W * qt, 0.0);
   int mask = 0;
   for (int t = 0; t < nt; ++t) {
@@ -205,7 +208,7 @@ extern "C" int mofem_op_create(const mofem_op_desc* desc, mofem_op_t* out) {
     const double c = D.coef[t];
     if (D.scaled[t]) mask |= 1 << t;
     for (int i = 0; i < qs; ++i) {
-      int gi = i + D.trim_s;
+      int gi = i + row0;
       for (int d = 0; d < W; ++d) {
         int ga = gi + d - kb;  // node index of the input row
         bool ok = D.full_input ? (ga >= 0 && ga < ns) : (ga >= D.trim_s && ga < ns - D.trim_s);
@@ -215,7 +218,7 @@ extern "C" int mofem_op_create(const mofem_op_desc* desc, mofem_op_t* out) {
       }
     }
     for (int j = 0; j < qt; ++j) {
-      int gj = j + D.trim_t;
+      int gj = j + col0;
       for (int d = 0; d < W; ++d) {
         int gb = gj + d - kb;  // node index of the input column
         bool ok = D.full_input ? (gb >= 0 && gb < ntt) : (gb >= D.trim_t && gb < ntt - D.trim_t);
@@ -237,11 +240,13 @@ extern "C" int mofem_op_create(const mofem_op_desc* desc, mofem_op_t* out) {
   op->qs = qs;
   op->qt = qt;
   op->full_input = D.full_input;
-  op->ns_in = D.full_input ? ns : qs;
-  op->nt_in = D.full_input ? ntt : qt;
-  op->off_s = D.full_input ? D.trim_s : 0;
-  op->off_t = D.full_input ? D.trim_t : 0;
-  op->ph_s = D.trim_s;
+  op->full_output = D.full_output;
+  // input index of output (i, j) is (i + off_s, j + off_t)
+  op->ns_in = D.full_input ? ns : ns - 2 * D.trim_s;
+  op->nt_in = D.full_input ? ntt : ntt - 2 * D.trim_t;
+  op->off_s = D.full_input ? D.trim_s : (D.full_output ? -D.trim_s : 0);
+  op->off_t = D.full_input ? D.trim_t : (D.full_output ? -D.trim_t : 0);
+  op->ph_s = row0;
   op->scaled_mask = mask;
   op->pattern = (D.elem_order >= 2 && D.elem_order == kb && element_structured(left, qs, nt, kb, op->ph_s)) ? 1 : 0;
   int TI = band_rows_per_block(kb, nt), SW = band_cols_per_block(kb);
@@ -325,7 +330,8 @@ extern "C" int mofem_op_apply(mofem_op_t op, const double* X, long long in_strid
   if (!X || !Y) return fail(MOFEM_E_ARG, "op_apply: NULL argument");
   if (in_stride < (long long)op->ns_in * op->nt_in || stride < (long long)op->qs * op->qt)
     return fail(MOFEM_E_ARG, "op_apply: stride smaller than one item");
-  if (dot_xy && op->full_input) return fail(MOFEM_E_ARG, "op_apply: <X, Y> needs a square operator");
+  if (dot_xy && (op->full_input || op->full_output))
+    return fail(MOFEM_E_ARG, "op_apply: <X, Y> needs a square operator");
   hipStream_t s = (hipStream_t)stream;
   double* partial = nullptr;
   if (dot_xy) {
@@ -803,7 +809,8 @@ extern "C" int mofem_pcg_solve(mofem_op_t op, mofem_prec_t prec, const double* R
   if (batch < 0 || maxit < 0 || !(tol >= 0.0)) return fail(MOFEM_E_ARG, "pcg_solve: bad batch/maxit/tol");
   if (batch == 0) return MOFEM_OK;
   if (!Rhs || !U) return fail(MOFEM_E_ARG, "pcg_solve: NULL argument");
-  if (op->full_input) return fail(MOFEM_E_ARG, "pcg_solve: operator must map unknowns to unknowns");
+  if (op->full_input || op->full_output)
+    return fail(MOFEM_E_ARG, "pcg_solve: operator must map unknowns to unknowns");
   if (op->qs != prec->qs || op->qt != prec->qt) return fail(MOFEM_E_ARG, "pcg_solve: operator and preconditioner sizes differ");
   const long long n = (long long)op->qs * op->qt;
   if (stride < n) return fail(MOFEM_E_ARG, "pcg_solve: stride smaller than one item");
@@ -1022,7 +1029,7 @@ extern "C" int mofem_imex_step(const mofem_imex_desc* d, double* state, long lon
   if (d->kinetics != MOFEM_KIN_NONE && d->kinetics != MOFEM_KIN_DIB) return fail(MOFEM_E_ARG, "imex_step: unknown kinetics");
   if (batch < 1) return batch == 0 ? MOFEM_OK : fail(MOFEM_E_ARG, "imex_step: negative batch");
   mofem_op_t op = d->op, mass = d->mass;
-  if (mass->full_input || mass->qs != op->qs || mass->qt != op->qt)
+  if (mass->full_input || mass->full_output || mass->qs != op->qs || mass->qt != op->qt)
     return fail(MOFEM_E_ARG, "imex_step: mass operator must map unknowns to unknowns of the same shape");
   const long long n = (long long)op->qs * op->qt;
   if (stride != n) return fail(MOFEM_E_ARG, "imex_step: items must be contiguous (stride = q_s * q_t)");
@@ -1071,4 +1078,108 @@ extern "C" int mofem_imex_step(const mofem_imex_desc* d, double* state, long lon
   rc = mofem_pcg_solve(op, d->prec, rhs, state, n, items, scale, d->tol, d->maxit, fl, pcg_ws, pcg_need,
                        iters_out, relres.data(), stream);
   return rc;
+}
+
+// ============================================================================
+// Batched Frobenius products and the adjoint IMEX step
+// ============================================================================
+extern "C" int mofem_dot_accumulate(const double* X, const double* Y, long long n, long long stride, int batch,
+                                    double alpha, double beta, double* out, void* stream) {
+  clear_error();
+  if (batch < 0 || n < 0) return fail(MOFEM_E_ARG, "dot_accumulate: negative size");
+  if (batch == 0) return MOFEM_OK;
+  if (!X || !Y || !out) return fail(MOFEM_E_ARG, "dot_accumulate: NULL argument");
+  if (stride < n) return fail(MOFEM_E_ARG, "dot_accumulate: stride smaller than one item");
+  hipStream_t s = (hipStream_t)stream;
+  static thread_local void* part = nullptr;
+  static thread_local size_t have = 0;
+  int rc = ensure_internal_ws(&part, &have, (size_t)batch * kVecBlocks * 8, s);
+  if (rc) return rc;
+  if (launch_dot_partial(X, Y, n, stride, batch, (double*)part, nullptr, s) ||
+      launch_reduce_axpy((const double*)part, kVecBlocks, out, alpha, beta, batch, s))
+    return fail(MOFEM_E_HIP, "dot_accumulate: launch failed");
+  return MOFEM_OK;
+}
+
+extern "C" size_t mofem_imex_adjoint_workspace_size(const mofem_imex_desc* d, int batch) {
+  if (!d || !d->op || !d->prec || !d->mass || batch < 1 || d->n_species < 1 || d->n_species > 2) return 0;
+  size_t items = (size_t)d->n_species * batch;
+  size_t n = (size_t)d->op->qs * d->op->qt;
+  size_t b = 2 * align_up(items * n * 8, 256);               // mu, K(U+) then Mass(mu)
+  b += align_up(items * 8, 256);                             // item scales
+  b += align_up(items * kVecBlocks * 8, 256);                // dot partials
+  return b + pcg_bytes(d->op, d->prec, (int)items, nullptr) + 4096;
+}
+
+extern "C" int mofem_imex_adjoint_step(const mofem_imex_desc* d, mofem_op_t stiff, const double* state_n,
+                                       const double* state_np1, double* lam, double* grad_d, long long stride,
+                                       int batch, void* workspace, size_t ws_bytes, int* iters_out,
+                                       void* stream) {
+  clear_error();
+  if (!d || !d->op || !d->prec || !d->mass || !stiff) return fail(MOFEM_E_ARG, "imex_adjoint_step: NULL argument");
+  if (d->n_species < 1 || d->n_species > 2) return fail(MOFEM_E_ARG, "imex_adjoint_step: n_species must be 1 or 2");
+  if (d->kinetics == MOFEM_KIN_DIB && d->n_species != 2)
+    return fail(MOFEM_E_ARG, "imex_adjoint_step: DIB needs 2 species");
+  if (d->kinetics != MOFEM_KIN_NONE && d->kinetics != MOFEM_KIN_DIB)
+    return fail(MOFEM_E_ARG, "imex_adjoint_step: unknown kinetics");
+  if (batch < 1) return batch == 0 ? MOFEM_OK : fail(MOFEM_E_ARG, "imex_adjoint_step: negative batch");
+  if (!state_n || !state_np1 || !lam || !grad_d) return fail(MOFEM_E_ARG, "imex_adjoint_step: NULL argument");
+  mofem_op_t op = d->op, mass = d->mass;
+  for (mofem_op_t o : {mass, stiff})
+    if (o->full_input || o->full_output || o->qs != op->qs || o->qt != op->qt)
+      return fail(MOFEM_E_ARG, "imex_adjoint_step: mass and stiffness must map unknowns to unknowns of one shape");
+  const long long n = (long long)op->qs * op->qt;
+  if (stride != n) return fail(MOFEM_E_ARG, "imex_adjoint_step: items must be contiguous (stride = q_s * q_t)");
+  const int items = d->n_species * batch;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t need = mofem_imex_adjoint_workspace_size(d, batch);
+  static thread_local void* own_ws = nullptr;
+  static thread_local size_t own_bytes = 0;
+  if (!workspace) {
+    int rc = ensure_internal_ws(&own_ws, &own_bytes, need, s);
+    if (rc) return rc;
+    workspace = own_ws;
+    ws_bytes = own_bytes;
+  } else if (ws_bytes < need) {
+    return fail(MOFEM_E_ARG, "imex_adjoint_step: workspace too small");
+  }
+  Carve c(workspace, ws_bytes);
+  double* mu = c.take<double>((size_t)items * n);
+  double* tmp = c.take<double>((size_t)items * n);
+  double* scale = c.take<double>(items);
+  double* part = c.take<double>((size_t)items * kVecBlocks);
+  const size_t pcg_need = pcg_bytes(op, d->prec, items, nullptr);
+  void* pcg_ws = c.take<char>(pcg_need);
+  if (!mu || !tmp || !scale || !part || !pcg_ws) return fail(MOFEM_E_ARG, "imex_adjoint_step: workspace too small");
+  std::vector<double> hs(items);
+  for (int sp = 0; sp < d->n_species; ++sp)
+    for (int b = 0; b < batch; ++b) hs[(size_t)sp * batch + b] = d->d[sp] * d->tau;
+  HIP_TRY(hipMemcpyAsync(scale, hs.data(), sizeof(double) * items, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));  // hs is a host temporary
+  // mu = L_c^{-1}(lam): the operator is symmetric, so the adjoint solve is a forward solve
+  int rc = mofem_pcg_solve(op, d->prec, lam, mu, n, items, scale, d->tol, d->maxit,
+                           (d->flags & ~MOFEM_PCG_TAU_STOP) | MOFEM_PCG_ZERO_GUESS, pcg_ws, pcg_need, iters_out,
+                           nullptr, stream);
+  if (rc != MOFEM_OK) return rc;
+  // grad_d += -tau <mu, K(U^{n+1})>
+  rc = op_launch(stiff, state_np1, n, tmp, n, items, nullptr, nullptr, nullptr, s);
+  if (rc) return rc;
+  {
+    TraceScope trace(MOFEM_TRACE_VEC, items, s);
+    if (launch_dot_partial(mu, tmp, n, n, items, part, nullptr, s) ||
+        launch_reduce_axpy(part, kVecBlocks, grad_d, -d->tau, 1.0, items, s))
+      return fail(MOFEM_E_HIP, "imex_adjoint_step: launch failed");
+  }
+  // nu = Mass(mu), then the transpose of the explicit kinetics
+  rc = op_launch(mass, mu, n, tmp, n, items, nullptr, nullptr, nullptr, s);
+  if (rc) return rc;
+  TraceScope trace(MOFEM_TRACE_VEC, items, s);
+  int lrc;
+  if (d->kinetics == MOFEM_KIN_DIB)
+    lrc = launch_dib_adjoint(state_n, state_n + (size_t)batch * n, tmp, tmp + (size_t)batch * n, lam,
+                             lam + (size_t)batch * n, n, n, batch, d->kin, d->tau, s);
+  else
+    lrc = launch_copy(tmp, lam, n, n, n, items, s);
+  if (lrc) return fail(MOFEM_E_HIP, "imex_adjoint_step: launch failed");
+  return MOFEM_OK;
 }

@@ -23,7 +23,7 @@
 //                the BF16-rounded basis): two products per transform.
 //   GEMM_BF16    the hi * hi product only.
 // Tiling: 256 threads = 4 waves, block tile 128 x 128, each wave 64 x 64
-// (4 x 4 MFMA tiles of 16 x 16); k tiles of 16 (FP64) or 64 (BF16).
+// (4 x 4 MFMA tiles of 16 x 16); k tiles of 16 (FP64), 32 (FP32, BF16).
 // Global -> register prefetch of the next k tile overlaps the MFMAs of the
 // current one; in the split products the three passes run one after the
 // other over all 16 accumulators, so back-to-back MFMAs are independent.
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g) {
 //       BF_X2B  B split, A exact in BF16       A_h B_l + A_h B_h
 enum { BF_HH = 0, BF_X3 = 1, BF_X2A = 2, BF_X2B = 3 };
 
-template <int MODE, int OMODE, int BK = 64, int MINW = 1>
+template <int MODE, int OMODE, int BK = 32, int MINW = 2>
 __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
   constexpr int LDS_K = BK + 8;   // padded rows keep 16-byte alignment
   constexpr bool ALO = (MODE == BF_X3 || MODE == BF_X2A);

@@ -48,6 +48,17 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const double* __restri
   if (threadIdx.x == 0) out[b] = s;
 }
 
+// out[b] = beta * out[b] + alpha * sum of the item's partials (fixed order)
+__global__ __launch_bounds__(kThreads) void reduce_axpy_kernel(const double* __restrict__ partial, int np,
+                                                               double* __restrict__ out, double alpha,
+                                                               double beta) {
+  const int b = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < np; i += kThreads) s += partial[(size_t)b * np + i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) out[b] = (beta == 0.0 ? 0.0 : beta * out[b]) + alpha * s;
+}
+
 __global__ __launch_bounds__(kThreads) void dot_kernel(const double* __restrict__ X, const double* __restrict__ Y,
                                                        long long n, long long stride,
                                                        double* __restrict__ partial, const int* active) {
@@ -251,12 +262,50 @@ __global__ __launch_bounds__(kThreads) void dib_source_kernel(const double* __re
   }
 }
 
+// Adjoint of the explicit DIB kinetics (eqs. (99)-(100)) in one IMEX step:
+//   LU = NU + tau rho (f_u NU + g_u NV),  LV = NV + tau rho (f_v NU + g_v NV),
+// partial derivatives at the step's input state (U, V).
+__global__ __launch_bounds__(kThreads) void dib_adjoint_kernel(const double* __restrict__ U, const double* __restrict__ V,
+                                                               const double* __restrict__ NU,
+                                                               const double* __restrict__ NV, double* __restrict__ LU,
+                                                               double* __restrict__ LV, long long n, long long stride,
+                                                               double rho, double A1, double A2, double Bc, double Cc,
+                                                               double Dc, double ga, double k2, double k3,
+                                                               double tau) {
+  const int b = blockIdx.y;
+  long long lo, hi;
+  chunk_of(n, blockIdx.x, gridDim.x, &lo, &hi);
+  const size_t off = (size_t)b * stride;
+  const double r = tau * rho;
+  for (long long i = lo + threadIdx.x; i < hi; i += kThreads) {
+    const double e = U[off + i], th = V[off + i];
+    const double nu = NU[off + i], nv = NV[off + i];
+    const double f_e = A1 * (1.0 - th) - 3.0 * A2 * e * e;
+    const double f_t = -A1 * e - Bc;
+    const double g_e = Cc * k2 * (1.0 - th) * (1.0 - ga * (1.0 - th)) - Dc * k3 * th * (1.0 + ga * th);
+    const double g_t = Cc * (1.0 + k2 * e) * (2.0 * ga * (1.0 - th) - 1.0) - Dc * (1.0 + k3 * e) * (1.0 + 2.0 * ga * th);
+    LU[off + i] = nu + r * (f_e * nu + g_e * nv);
+    LV[off + i] = nv + r * (f_t * nu + g_t * nv);
+  }
+}
+
 }  // namespace
 
 #define CHECK_LAUNCH() return hipGetLastError() == hipSuccess ? 0 : -1
 
 int launch_reduce(const double* partial, int n_partial, double* out, int batch, hipStream_t s) {
   hipLaunchKernelGGL(reduce_kernel, dim3(batch), dim3(kThreads), 0, s, partial, n_partial, out);
+  CHECK_LAUNCH();
+}
+int launch_reduce_axpy(const double* partial, int n_partial, double* out, double alpha, double beta, int batch,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(reduce_axpy_kernel, dim3(batch), dim3(kThreads), 0, s, partial, n_partial, out, alpha, beta);
+  CHECK_LAUNCH();
+}
+int launch_dib_adjoint(const double* U, const double* V, const double* NU, const double* NV, double* LU, double* LV,
+                       long long n, long long stride, int batch, const double* k, double tau, hipStream_t s) {
+  hipLaunchKernelGGL(dib_adjoint_kernel, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, U, V, NU, NV, LU, LV, n,
+                     stride, k[0], k[1], k[2], k[3], k[4], k[5], k[7], k[8], k[9], tau);
   CHECK_LAUNCH();
 }
 int launch_dot_partial(const double* X, const double* Y, long long n, long long stride, int batch,

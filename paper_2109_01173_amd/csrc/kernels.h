@@ -80,6 +80,12 @@ int launch_pad_operand(const double* A, long long a_stride, int M, int K, double
 // ---- vector kernels of the PCG recurrence (k_vec.hip) -----------------------
 constexpr int kVecBlocks = 240;   // partial sums per item
 int launch_reduce(const double* partial, int n_partial, double* out, int batch, hipStream_t s);
+// out[b] = beta out[b] + alpha (sum of partials)
+int launch_reduce_axpy(const double* partial, int n_partial, double* out, double alpha, double beta, int batch,
+                       hipStream_t s);
+// adjoint of the DIB kinetics in one IMEX step (kin = rho, A1, A2, B, C, D, alpha, gamma, k2, k3)
+int launch_dib_adjoint(const double* U, const double* V, const double* NU, const double* NV, double* LU, double* LV,
+                       long long n, long long stride, int batch, const double* kin, double tau, hipStream_t s);
 // out[b] = sum(X_b * Y_b) partials (X may equal Y)
 int launch_dot_partial(const double* X, const double* Y, long long n, long long stride,
                        int batch, double* partial, const int* active, hipStream_t s);

@@ -54,7 +54,8 @@ class OpDesc(ctypes.Structure):
                 ("left", _vp * MAX_TERMS), ("right", _vp * MAX_TERMS),
                 ("left_transpose", ctypes.c_int * MAX_TERMS),
                 ("right_transpose", ctypes.c_int * MAX_TERMS),
-                ("coef", ctypes.c_double * MAX_TERMS), ("scaled", ctypes.c_int * MAX_TERMS)]
+                ("coef", ctypes.c_double * MAX_TERMS), ("scaled", ctypes.c_int * MAX_TERMS),
+                ("full_output", ctypes.c_int)]
 
 
 class PrecDesc(ctypes.Structure):
@@ -110,6 +111,13 @@ mofem_pcg_solve = _proto("mofem_pcg_solve", ctypes.c_int,
 mofem_imex_workspace_size = _proto("mofem_imex_workspace_size", _sz, [ctypes.POINTER(ImexDesc), ctypes.c_int])
 mofem_imex_step = _proto("mofem_imex_step", ctypes.c_int,
                          [ctypes.POINTER(ImexDesc), _vp, _ll, ctypes.c_int, _vp, _sz, _vp, _vp])
+mofem_dot_accumulate = _proto("mofem_dot_accumulate", ctypes.c_int,
+                              [_vp, _vp, _ll, _ll, ctypes.c_int, ctypes.c_double, ctypes.c_double, _vp, _vp])
+mofem_imex_adjoint_workspace_size = _proto("mofem_imex_adjoint_workspace_size", _sz,
+                                           [ctypes.POINTER(ImexDesc), ctypes.c_int])
+mofem_imex_adjoint_step = _proto("mofem_imex_adjoint_step", ctypes.c_int,
+                                 [ctypes.POINTER(ImexDesc), _vp, _vp, _vp, _vp, _vp, _ll, ctypes.c_int, _vp, _sz,
+                                  _vp, _vp])
 mofem_trace_enable = _proto("mofem_trace_enable", ctypes.c_int, [ctypes.c_int])
 mofem_trace_read = _proto("mofem_trace_read", ctypes.c_int,
                           [ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_longlong), _dp])
@@ -119,7 +127,9 @@ EXPORTS = ["mofem_version", "mofem_last_error", "mofem_assemble_1d", "mofem_gene
            "mofem_prec_setup", "mofem_prec_destroy", "mofem_prec_set_coeffs",
            "mofem_prec_set_precision", "mofem_prec_eigenvalues", "mofem_prec_workspace_size",
            "mofem_prec_apply", "mofem_pcg_workspace_size", "mofem_pcg_solve",
-           "mofem_imex_workspace_size", "mofem_imex_step", "mofem_trace_enable", "mofem_trace_read"]
+           "mofem_imex_workspace_size", "mofem_imex_step", "mofem_dot_accumulate",
+           "mofem_imex_adjoint_workspace_size", "mofem_imex_adjoint_step", "mofem_trace_enable",
+           "mofem_trace_read"]
 
 
 class MofemError(RuntimeError):
@@ -211,10 +221,12 @@ def _stream(stream):
 class Operator:
     """Y = sum_t c_t op(L_t) X op(R_t) (see mofem_op_desc)."""
 
-    def __init__(self, terms, n_s, n_t, kb, trim_s=0, trim_t=0, full_input=False, elem_order=0):
+    def __init__(self, terms, n_s, n_t, kb, trim_s=0, trim_t=0, full_input=False, elem_order=0,
+                 full_output=False):
         d = OpDesc()
         d.kb, d.elem_order, d.n_s, d.n_t = kb, elem_order, n_s, n_t
         d.trim_s, d.trim_t, d.full_input, d.n_terms = trim_s, trim_t, int(full_input), len(terms)
+        d.full_output = int(full_output)
         self._keep = []
         for i, t in enumerate(terms):
             L = np.ascontiguousarray(t["left"], dtype=np.float64)
@@ -334,6 +346,17 @@ def pcg_solve(op, prec, rhs, U, tol=1e-10, maxit=500, flags=0, item_scale=None, 
     return iters, relres, rc
 
 
+def dot_accumulate(X, Y, out, alpha=1.0, beta=0.0, stream=None):
+    """out[b] = beta out[b] + alpha <X_b, Y_b>_F for the leading batch dimension."""
+    batch = X.shape[0]
+    if Y.shape != X.shape or out.numel() < batch:
+        raise ValueError("dot_accumulate: shapes")
+    n = X[0].numel() if batch else 0
+    _check(mofem_dot_accumulate(_dptr(X), _dptr(Y), n, n, batch, alpha, beta, _dptr(out), _stream(stream)),
+           "mofem_dot_accumulate")
+    return out
+
+
 def trace_enable(on=True):
     _check(mofem_trace_enable(int(on)), "mofem_trace_enable")
 
@@ -376,4 +399,22 @@ class Imex:
         rc = mofem_imex_step(ctypes.byref(self.desc), _dptr(state), q_s * q_t, batch,
                              _dptr(workspace), workspace.numel(), _hptr(iters), _stream(stream))
         _check(rc, "mofem_imex_step")
+        return iters
+
+    def adjoint_workspace(self, batch, device="cuda"):
+        torch = _torch()
+        n = int(mofem_imex_adjoint_workspace_size(ctypes.byref(self.desc), batch))
+        return torch.empty(n, dtype=torch.uint8, device=device)
+
+    def adjoint_step(self, stiff, state_n, state_np1, lam, grad_d, batch, workspace=None, stream=None):
+        """Reverse step: lam (in dJ/dU^{n+1}, out dJ/dU^n) and grad_d
+        (device [n_species * batch], accumulated) - see mofem_imex_adjoint_step."""
+        if workspace is None:
+            workspace = self.adjoint_workspace(batch, lam.device)
+        iters = np.zeros(lam.shape[0], dtype=np.int32)
+        q_s, q_t = lam.shape[1], lam.shape[2]
+        rc = mofem_imex_adjoint_step(ctypes.byref(self.desc), stiff.handle, _dptr(state_n), _dptr(state_np1),
+                                     _dptr(lam), _dptr(grad_d), q_s * q_t, batch, _dptr(workspace),
+                                     workspace.numel(), _hptr(iters), _stream(stream))
+        _check(rc, "mofem_imex_adjoint_step")
         return iters

@@ -72,7 +72,11 @@ class XNormal:
             coeffs = (gamma, 1.0, 1.0, 0.0)
         self.op = mf.Operator(terms, **common)
         self.rhs_op = mf.Operator([dict(left=M3, right=M)], full_input=True, **common)
+        # transpose of the full-node load: dJ/dF = M3[:, I] Lambda M[I, :]
+        self.rhs_adjoint_op = mf.Operator([dict(left=M3, right=M)], full_output=True, **common)
         self.mass = mf.Operator([dict(left=M3, right=M)], **common)
+        # stiffness part K of L_c = Mass + c K (for the gradient in d)
+        self.stiff = mf.Operator([dict(t, scaled=False) for t in terms[1:]], **common) if imex else None
         self.prec = mf.Preconditioner(B1, M3, A, M, coeffs, trim, trim, precision)
 
 
@@ -101,5 +105,7 @@ class Rect:
             coeffs = (gamma, 1.0, 1.0, 0.0)
         self.op = mf.Operator(terms, **common)
         self.rhs_op = mf.Operator([dict(left=M, right=M)], full_input=True, **common)
+        self.rhs_adjoint_op = mf.Operator([dict(left=M, right=M)], full_output=True, **common)
         self.mass = mf.Operator([dict(left=M, right=M)], **common)
+        self.stiff = mf.Operator([dict(t, scaled=False) for t in terms[1:]], **common) if imex else None
         self.prec = mf.Preconditioner(A, M, A, M, coeffs, trim, trim, precision)
