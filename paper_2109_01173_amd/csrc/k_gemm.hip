@@ -23,7 +23,7 @@
 //                the BF16-rounded basis): two products per transform.
 //   GEMM_BF16    the hi * hi product only.
 // Tiling: 256 threads = 4 waves, block tile 128 x 128, each wave 64 x 64
-// (4 x 4 MFMA tiles of 16 x 16); k tiles of 16 (FP64), 32 (FP32, BF16).
+// (4 x 4 MFMA tiles of 16 x 16); k tiles of 16 (FP64), 32 (FP32), 64 (BF16).
 // Global -> register prefetch of the next k tile overlaps the MFMAs of the
 // current one; in the split products the three passes run one after the
 // other over all 16 accumulators, so back-to-back MFMAs are independent.
@@ -256,15 +256,22 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g) {
 //       BF_X2B  B split, A exact in BF16       A_h B_l + A_h B_h
 enum { BF_HH = 0, BF_X3 = 1, BF_X2A = 2, BF_X2B = 3 };
 
-template <int MODE, int OMODE, int BK = 32, int MINW = 2>
+template <int MODE, int OMODE, int BK = 64, int MINW = 2>
 __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
   constexpr int LDS_K = BK + 8;   // padded rows keep 16-byte alignment
   constexpr bool ALO = (MODE == BF_X3 || MODE == BF_X2A);
   constexpr bool BLO = (MODE == BF_X3 || MODE == BF_X2B);
-  __shared__ unsigned short Ah[BM][LDS_K];
-  __shared__ unsigned short Bh[BN][LDS_K];
-  __shared__ unsigned short Al[ALO ? BM : 1][LDS_K];
-  __shared__ unsigned short Bl[BLO ? BN : 1][LDS_K];
+  // One LDS buffer: the operand tiles of the main loop, then (padded output)
+  // the staging tile of the epilogue, so the output leaves in whole rows.
+  constexpr int SLD = BN + 8;  // staging row length (272 bytes: 16-byte aligned)
+  constexpr int MAIN = (2 + (ALO ? 1 : 0) + (BLO ? 1 : 0)) * BM * LDS_K;
+  constexpr int STAGE = (OMODE == O_F64_RAW) ? 0 : BM * SLD;
+  __shared__ __attribute__((aligned(16))) unsigned short lds[MAIN > STAGE ? MAIN : STAGE];
+  typedef unsigned short Row[LDS_K];
+  Row* Ah = reinterpret_cast<Row*>(lds);
+  Row* Bh = Ah + BM;
+  Row* Al = Bh + BN;                 // used when ALO
+  Row* Bl = Al + (ALO ? BM : 0);     // used when BLO
 
   const int b = blockIdx.y;
   if (g.active && !g.active[b]) return;
@@ -363,9 +370,6 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
 
   // epilogue: acc[i][j][r] = C[row][col], row = 4*(lane/16) + r, col = lane%16
   const double s = g.item_scale ? g.item_scale[b] : 1.0;
-  const int Mp = pad_up(g.M), Np = pad_up(g.N);
-  unsigned short* __restrict__ Ch = (unsigned short*)g.c_hi + (size_t)b * g.c_stride;
-  unsigned short* __restrict__ Cl = (unsigned short*)g.c_lo + (size_t)b * g.c_stride;
   double* __restrict__ C64 = g.c64 + (size_t)b * g.c_stride;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -382,13 +386,55 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
         if (OMODE == O_F64_RAW) {
           if (in) C64[(size_t)row * g.N + col] = v;
         } else {
-          unsigned short hi, lo;
-          split_bf16((float)v, &hi, &lo);
-          size_t idx = (OMODE == O_PAD_T) ? (size_t)col * Mp + row : (size_t)row * Np + col;
-          Ch[idx] = hi;
-          if (MODE != BF_HH) Cl[idx] = lo;   // intermediates keep the split
+          acc[i][j][r] = (float)v;  // the FP32 value to split
         }
       }
+  if constexpr (OMODE != O_F64_RAW) {
+    // Padded split output through LDS: pass 0 writes hi, pass 1 lo.  In
+    // LDS the tile is laid out as the output rows (C^T rows for O_PAD_T),
+    // then every thread stores whole 16-byte pieces of those rows.
+    const int Mp = pad_up(g.M), Np = pad_up(g.N);
+    unsigned short* __restrict__ Cg[2] = {(unsigned short*)g.c_hi + (size_t)b * g.c_stride,
+                                          (unsigned short*)g.c_lo + (size_t)b * g.c_stride};
+    __syncthreads();  // every wave is done with the operand tiles
+    for (int pass = 0; pass < (MODE == BF_HH ? 1 : 2); ++pass) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int rl = wm * 64 + i * 16 + 4 * (lane >> 4);  // first of 4 consecutive tile rows
+          const int cl = wn * 64 + j * 16 + (lane & 15);
+          unsigned short u[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const float f = acc[i][j][r];
+            const unsigned short h = bf16_bits(f);
+            u[r] = pass == 0 ? h : bf16_bits(f - bf16_to_f(h));
+          }
+          if (OMODE == O_PAD_T) {
+            // C^T row cl holds C[rl .. rl+3][cl] contiguously: one 8-byte write
+            const unsigned long long packed = (unsigned long long)u[0] | ((unsigned long long)u[1] << 16) |
+                                              ((unsigned long long)u[2] << 32) | ((unsigned long long)u[3] << 48);
+            *reinterpret_cast<unsigned long long*>(&lds[cl * SLD + rl]) = packed;
+          } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) lds[(rl + r) * SLD + cl] = u[r];
+          }
+        }
+      __syncthreads();
+      // 128 rows of 128 values = 2048 pieces of 16 bytes, 8 per thread
+      unsigned short* __restrict__ C = Cg[pass];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const int idx = tid + 256 * v;
+        const int sr = idx >> 4, ch = (idx & 15) * 8;
+        const us8_t val = *reinterpret_cast<const us8_t*>(&lds[sr * SLD + ch]);
+        const size_t o = (OMODE == O_PAD_T) ? (size_t)(n0 + sr) * Mp + m0 + ch : (size_t)(m0 + sr) * Np + n0 + ch;
+        *reinterpret_cast<us8_t*>(C + o) = val;
+      }
+      __syncthreads();  // before the next pass overwrites the staging tile
+    }
+  }
 }
 
 template <int OMODE>
