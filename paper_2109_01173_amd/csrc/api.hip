@@ -99,6 +99,13 @@ void trace_resolve(TraceState& t) {
   }
   t.recs.clear();
 }
+// Correct the item count of a class after the fact (launches whose item
+// count was only known later, e.g. under device-side masking).
+void trace_add_items(int cls, double delta) {
+  TraceState& t = trace_state();
+  std::lock_guard<std::mutex> g(t.mu);
+  if (t.on) t.items[cls] += delta;
+}
 // RAII: records e0 now and e1 when the scope (one kernel launch) ends
 struct TraceScope {
   hipStream_t s;
@@ -734,8 +741,8 @@ namespace {
 struct PcgWs {
   double *R, *Z, *Q, *Y;
   double *part_a, *part_b, *part_op;
-  double *rz, *rz_new, *qy, *rr, *zy, *alpha, *beta, *rhs2, *tmp;
-  int* active;
+  double *rz, *rz_new, *qy, *rr, *zy, *alpha, *beta, *rhs2, *tr, *target2;
+  int *active, *claim, *restart, *status, *iters;  // device-side control, see k_vec.hip
   void* prec_ws;
   size_t prec_bytes;
 };
@@ -746,8 +753,8 @@ size_t pcg_bytes(mofem_op_t op, mofem_prec_t prec, int batch, size_t* prec_part)
   b += 4 * align_up(n * batch * 8, 256);
   b += 2 * align_up((size_t)batch * kVecBlocks * 8, 256);
   b += align_up((size_t)batch * op->n_tiles * 8, 256);
-  b += 9 * align_up((size_t)batch * 8, 256);
-  b += align_up((size_t)batch * 4, 256);
+  b += 11 * align_up((size_t)batch * 8, 256);
+  b += 5 * align_up((size_t)batch * 4, 256);
   size_t pp = mofem_prec_workspace_size(prec, batch);
   if (prec_part) *prec_part = pp;
   return b + pp + 4096;
@@ -763,34 +770,32 @@ bool carve_pcg(mofem_op_t op, mofem_prec_t prec, int batch, void* ws, size_t byt
   w->part_a = c.take<double>((size_t)batch * kVecBlocks);
   w->part_b = c.take<double>((size_t)batch * kVecBlocks);
   w->part_op = c.take<double>((size_t)batch * op->n_tiles);
-  w->rz = c.take<double>(batch);
-  w->rz_new = c.take<double>(batch);
-  w->qy = c.take<double>(batch);
-  w->rr = c.take<double>(batch);
-  w->zy = c.take<double>(batch);
-  w->alpha = c.take<double>(batch);
-  w->beta = c.take<double>(batch);
-  w->rhs2 = c.take<double>(batch);
-  w->tmp = c.take<double>(batch);
-  w->active = c.take<int>(batch);
+  double** scal[] = {&w->rz, &w->rz_new, &w->qy, &w->rr, &w->zy, &w->alpha, &w->beta, &w->rhs2, &w->tr,
+                     &w->target2};
+  for (double** x : scal) *x = c.take<double>(batch);
+  (void)c.take<double>(batch);  // spare
+  int** flags[] = {&w->active, &w->claim, &w->restart, &w->status, &w->iters};
+  for (int** x : flags) *x = c.take<int>(batch);
   w->prec_bytes = mofem_prec_workspace_size(prec, batch);
   w->prec_ws = c.take<char>(w->prec_bytes);
   return w->prec_ws != nullptr;
 }
 
-struct HostBuf {
-  double* d = nullptr;
-  int* i = nullptr;
-  int n = 0;
-  ~HostBuf() {
-    if (d) (void)hipHostFree(d);
-    if (i) (void)hipHostFree(i);
+// Pinned host buffer for the few bytes the solve reads back; kept per thread.
+struct PinnedHost {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~PinnedHost() {
+    if (p) (void)hipHostFree(p);
   }
-  int init(int batch) {
-    n = batch;
-    if (hipHostMalloc((void**)&d, sizeof(double) * 4 * batch) != hipSuccess) return MOFEM_E_NOMEM;
-    if (hipHostMalloc((void**)&i, sizeof(int) * batch) != hipSuccess) return MOFEM_E_NOMEM;
-    return MOFEM_OK;
+  void* get(size_t need) {
+    if (need <= bytes) return p;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+    if (hipHostMalloc(&p, need) != hipSuccess) return nullptr;
+    bytes = need;
+    return p;
   }
 };
 }  // namespace
@@ -800,6 +805,10 @@ extern "C" size_t mofem_pcg_workspace_size(mofem_op_t op, mofem_prec_t prec, int
   return pcg_bytes(op, prec, batch, nullptr);
 }
 
+// The iteration runs under device-side control: every kernel skips the items
+// whose `active` flag is clear, convergence and breakdown are decided on the
+// device (pcg_check / pcg_confirm), and the host reads the flags one
+// iteration behind, so no host round trip sits inside an iteration.
 extern "C" int mofem_pcg_solve(mofem_op_t op, mofem_prec_t prec, const double* Rhs, double* U, long long stride,
                                int batch, const double* item_scale, double tol, int maxit, unsigned flags,
                                void* workspace, size_t ws_bytes, int* iters_out, double* relres_out,
@@ -828,176 +837,158 @@ extern "C" int mofem_pcg_solve(mofem_op_t op, mofem_prec_t prec, const double* R
   }
   PcgWs w{};
   if (!carve_pcg(op, prec, batch, workspace, ws_bytes, &w)) return fail(MOFEM_E_ARG, "pcg_solve: workspace too small");
-  HostBuf hb;
-  if (hb.init(batch)) return fail(MOFEM_E_NOMEM, "pcg_solve: pinned host buffer");
+  static thread_local PinnedHost pinned;
+  // layout: two slots of active flags and the initial flags, then (aligned) tr, rhs2,
+  // target2, then iters, status
+  const size_t dbl_off = align_up((size_t)batch * 12, 64);
+  char* host = (char*)pinned.get(dbl_off + (size_t)batch * (24 + 8));
+  if (!host) return fail(MOFEM_E_NOMEM, "pcg_solve: pinned host buffer");
+  int* h_active = (int*)host;
   const bool flexible = flags & MOFEM_PCG_FLEXIBLE;
   const bool tau_stop = flags & MOFEM_PCG_TAU_STOP;
   const int nt = op->n_tiles;
   const PrecInput pin = prec_input(prec, w.prec_ws, w.prec_bytes, batch);
+  int n_active = batch;  // as of the last read-back (used for tracing only)
 
-  std::vector<int> active(batch, 1), iters(batch, 0), status(batch, MOFEM_OK);
-  std::vector<double> target2(batch, 0.0), rhs2(batch, 0.0);
-  int n_active = batch;
-  auto count_active = [&]() {
-    n_active = 0;
-    for (int b = 0; b < batch; ++b) n_active += active[b] != 0;
-  };
-  auto push_active = [&]() -> int {
-    count_active();
-    for (int b = 0; b < batch; ++b) hb.i[b] = active[b];
-    HIP_TRY(hipMemcpyAsync(w.active, hb.i, sizeof(int) * batch, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    return MOFEM_OK;
-  };
-  auto fetch = [&](const double* dev, double* host) -> int {
-    HIP_TRY(hipMemcpyAsync(hb.d, dev, sizeof(double) * batch, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    std::memcpy(host, hb.d, sizeof(double) * batch);
-    return MOFEM_OK;
-  };
-  int rc;
-#define TRY(x)                   \
-  do {                           \
-    if ((rc = (x)) != MOFEM_OK)  \
-      return rc;                 \
-  } while (0)
 #define LTRY(x)                                                            \
   do {                                                                     \
     TraceScope _trace(MOFEM_TRACE_VEC, n_active, s);                       \
     if ((x) != 0) return fail(MOFEM_E_HIP, "pcg_solve: launch failed");    \
   } while (0)
+#define TRY(x)                       \
+  do {                               \
+    int _rc = (x);                   \
+    if (_rc != MOFEM_OK) return _rc; \
+  } while (0)
 
-
-  TRY(push_active());
-  // ||Rhs||^2
-  LTRY(launch_dot_partial(Rhs, Rhs, n, stride, batch, w.part_a, w.active, s));
+  // ||Rhs||^2 and the initial residual R = Rhs - L(U) (or Rhs with a zero guess)
+  LTRY(launch_dot_partial(Rhs, Rhs, n, stride, batch, w.part_a, nullptr, s));
   LTRY(launch_reduce(w.part_a, kVecBlocks, w.rhs2, batch, s));
-  TRY(fetch(w.rhs2, rhs2.data()));
-  // R = Rhs - L(U)  (or Rhs with a zero guess)
   if (flags & MOFEM_PCG_ZERO_GUESS) {
     LTRY(launch_fill(U, 0.0, n, stride, batch, s));
     LTRY(launch_copy(Rhs, w.R, n, stride, n, batch, s));
-    LTRY(launch_dot_partial(w.R, w.R, n, n, batch, w.part_a, w.active, s));
+    LTRY(launch_dot_partial(w.R, w.R, n, n, batch, w.part_a, nullptr, s));
   } else {
-    TRY(op_launch(op, U, stride, w.Y, n, batch, item_scale, nullptr, w.active, s, n_active));
-    LTRY(launch_residual(Rhs, w.Y, w.R, n, n, stride, batch, w.part_a, w.active, s));
+    TRY(op_launch(op, U, stride, w.Y, n, batch, item_scale, nullptr, nullptr, s, n_active));
+    LTRY(launch_residual(Rhs, w.Y, w.R, n, n, stride, batch, w.part_a, nullptr, s));
   }
   LTRY(launch_reduce(w.part_a, kVecBlocks, w.rr, batch, s));
-  std::vector<double> rr(batch), qy(batch);
-  TRY(fetch(w.rr, rr.data()));
-  bool any = false;
-  for (int b = 0; b < batch; ++b) {
-    if (!std::isfinite(rr[b]) || !std::isfinite(rhs2[b])) {
-      status[b] = MOFEM_E_NOTFINITE;
-      active[b] = 0;
-      continue;
+  LTRY(launch_pcg_init(w.rhs2, w.rr, w.target2, w.active, w.claim, w.restart, w.status, w.iters, tol * tol,
+                       tau_stop ? 1 : 0, batch, s));
+  // The active set is known on the host only one iteration late; launches
+  // are traced with the last known count and corrected at the end from the
+  // exact per-iteration counts.
+  int* h_init = h_active + 2 * batch;
+  HIP_TRY(hipMemcpyAsync(h_init, w.active, sizeof(int) * batch, hipMemcpyDeviceToHost, s));
+  std::vector<int> cnt;             // active items after iteration j
+  double rec_band = 0, rec_prec = 0;  // items recorded for the Y = L(Q) and P^-1 launches
+  int last_it = -1;
+  // Z = P^{-1}(R), <R, Z>, Q = Z
+  TRY(prec_launch(prec, w.R, w.Z, n, batch, item_scale, w.prec_ws, w.prec_bytes, w.active, s, n_active));
+  rec_prec += n_active;
+  LTRY(launch_dot_partial(w.R, w.Z, n, n, batch, w.part_a, w.active, s));
+  LTRY(launch_reduce(w.part_a, kVecBlocks, w.rz, batch, s));
+  LTRY(launch_direction(w.Q, w.Z, nullptr, n, n, batch, w.active, s));
+
+  // The flags of iteration i are copied to pinned memory behind an event;
+  // the host waits for them only after iteration i + 1 is queued, so the
+  // device never idles on the host and at most one iteration runs masked
+  // after the last item has converged.
+  static thread_local hipEvent_t flag_ev[2] = {nullptr, nullptr};
+  for (auto& e : flag_ev)
+    if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  int* h_flags[2] = {h_active, h_active + batch};
+  for (int it = 0; it < maxit; ++it) {
+    {
+      // Y = L(Q), <Q, Y>
+      last_it = it;
+      TRY(op_launch(op, w.Q, n, w.Y, n, batch, item_scale, w.part_op, w.active, s, n_active));
+      rec_band += n_active;
+      LTRY(launch_reduce(w.part_op, nt, w.qy, batch, s));
+      // alpha = <R, Z> / <Q, Y>; U += alpha Q; R -= alpha Y; ||R||^2; R's padded transform operand
+      LTRY(launch_cg_update_pad(U, w.R, w.Q, w.Y, w.rz, w.qy, w.alpha, op->qs, op->qt, n, stride, batch, w.part_a,
+                                w.active, pin.hi, pin.lo, pin.f64, pin.f32, pin.stride, s));
+      LTRY(launch_reduce(w.part_a, kVecBlocks, w.rr, batch, s));
+      LTRY(launch_pcg_check(w.qy, w.rr, w.target2, w.active, w.claim, w.status, w.iters, batch, s));
+      // items that claim convergence: confirm on the true residual Rhs - L(U); where it
+      // fails, continue from the true residual with a fresh direction
+      TRY(op_launch(op, U, stride, w.Z, n, batch, item_scale, nullptr, w.claim, s, 0));
+      LTRY(launch_residual(Rhs, w.Z, w.Z, n, n, stride, batch, w.part_b, w.claim, s));
+      LTRY(launch_reduce(w.part_b, kVecBlocks, w.tr, batch, s));
+      LTRY(launch_pcg_confirm(w.tr, w.target2, w.active, w.claim, w.restart, batch, s));
+      LTRY(launch_copy_masked(w.Z, w.R, n, n, n, batch, w.restart, s));
+      {
+        TraceScope _trace(MOFEM_TRACE_VEC, n_active, s);
+        if (launch_pad_operand(w.R, n, op->qs, op->qt, pin.f64, pin.f32, pin.hi, pin.lo, pin.stride,
+                               (pin.hi != nullptr) ? 1 : 0, batch, w.restart, s))
+          return fail(MOFEM_E_HIP, "pcg_solve: launch failed");
+      }
+      // Z = P^{-1}(R); <R, Z>, <Z, Y>; beta (zero after a restart); Q = Z + beta Q
+      TRY(prec_launch(prec, w.R, w.Z, n, batch, item_scale, w.prec_ws, w.prec_bytes, w.active, s, n_active, 1));
+      rec_prec += n_active;
+      LTRY(launch_dot2_partial(w.R, w.Z, w.Z, w.Y, n, n, batch, w.part_a, w.part_b, w.active, s));
+      LTRY(launch_reduce(w.part_a, kVecBlocks, w.rz_new, batch, s));
+      LTRY(launch_reduce(w.part_b, kVecBlocks, w.zy, batch, s));
+      LTRY(launch_beta_restart(w.rz_new, w.rz, w.zy, w.alpha, w.beta, w.restart, flexible ? 1 : 0, batch, w.active,
+                               s));
+      LTRY(launch_direction(w.Q, w.Z, w.beta, n, n, batch, w.active, s));
     }
-    target2[b] = tol * tol * (tau_stop ? rr[b] : rhs2[b]);
-    if (rhs2[b] == 0.0 || rr[b] <= target2[b]) active[b] = 0;
-    any |= active[b] != 0;
+    HIP_TRY(hipMemcpyAsync(h_flags[it & 1], w.active, sizeof(int) * batch, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(flag_ev[it & 1], s));
+    if (it == 0) continue;
+    HIP_TRY(hipEventSynchronize(flag_ev[(it - 1) & 1]));
+    n_active = 0;
+    for (int b = 0; b < batch; ++b) n_active += h_flags[(it - 1) & 1][b] != 0;
+    cnt.push_back(n_active);
+    if (n_active == 0) break;
   }
-  TRY(push_active());
-  if (any) {
-    TRY(prec_launch(prec, w.R, w.Z, n, batch, item_scale, w.prec_ws, w.prec_bytes, w.active, s, n_active));
-    LTRY(launch_dot_partial(w.R, w.Z, n, n, batch, w.part_a, w.active, s));
-    LTRY(launch_reduce(w.part_a, kVecBlocks, w.rz, batch, s));
-    LTRY(launch_direction(w.Q, w.Z, nullptr, n, n, batch, w.active, s));
+  // final true residuals of every item
+  TRY(op_launch(op, U, stride, w.Z, n, batch, item_scale, nullptr, nullptr, s, batch));
+  LTRY(launch_residual(Rhs, w.Z, w.Z, n, n, stride, batch, w.part_b, nullptr, s));
+  LTRY(launch_reduce(w.part_b, kVecBlocks, w.tr, batch, s));
+  double* h_tr = (double*)(host + dbl_off);
+  double* h_rhs2 = h_tr + batch;
+  double* h_tg = h_rhs2 + batch;
+  int* h_iters = (int*)(h_tg + batch);
+  int* h_status = h_iters + batch;
+  HIP_TRY(hipMemcpyAsync(h_tr, w.tr, sizeof(double) * batch, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(h_rhs2, w.rhs2, sizeof(double) * batch, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(h_tg, w.target2, sizeof(double) * batch, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(h_iters, w.iters, sizeof(int) * batch, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(h_status, w.status, sizeof(int) * batch, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (last_it >= 0) {
+    // exact items: Y = L(Q) of iteration j ran on the items active after j - 1 (the
+    // initial set for j = 0), P^-1 of iteration j on those active after j
+    int n_last = 0;
+    for (int b = 0; b < batch; ++b) n_last += h_flags[last_it & 1][b] != 0;
+    while ((int)cnt.size() < last_it + 1) cnt.push_back(n_last);
+    int n_init = 0;
+    for (int b = 0; b < batch; ++b) n_init += h_init[b] != 0;
+    double ex_band = 0, ex_prec = n_init;
+    for (int j = 0; j <= last_it; ++j) {
+      ex_band += j == 0 ? n_init : cnt[j - 1];
+      ex_prec += cnt[j];
+    }
+    const int tcls = prec->precision == MOFEM_PREC_F64      ? MOFEM_TRACE_GEMM_F64
+                     : prec->precision == MOFEM_PREC_F32    ? MOFEM_TRACE_GEMM_F32
+                     : prec->precision == MOFEM_PREC_BF16   ? MOFEM_TRACE_GEMM_BF16
+                     : prec->precision == MOFEM_PREC_BF16X2 ? MOFEM_TRACE_GEMM_BF16X2
+                                                            : MOFEM_TRACE_GEMM_BF16X3;
+    trace_add_items(MOFEM_TRACE_BAND, ex_band - rec_band);
+    trace_add_items(tcls, 4.0 * (ex_prec - rec_prec));
   }
-  int it = 0;
-  std::vector<int> restart(batch, 0);
-  while (any && it < maxit) {
-    ++it;
-    // Y = L(Q), <Q, Y>
-    TRY(op_launch(op, w.Q, n, w.Y, n, batch, item_scale, w.part_op, w.active, s, n_active));
-    LTRY(launch_reduce(w.part_op, nt, w.qy, batch, s));
-    // alpha = <R, Z> / <Q, Y>; U += alpha Q; R -= alpha Y; <R, R>; R's padded
-    // transform operand for the next preconditioner application
-    LTRY(launch_cg_update_pad(U, w.R, w.Q, w.Y, w.rz, w.qy, w.alpha, op->qs, op->qt, n, stride, batch, w.part_a,
-                              w.active, pin.hi, pin.lo, pin.f64, pin.f32, pin.stride, s));
-    bool r_padded = true;
-    LTRY(launch_reduce(w.part_a, kVecBlocks, w.rr, batch, s));
-    TRY(fetch(w.qy, qy.data()));
-    TRY(fetch(w.rr, rr.data()));
-    std::vector<int> check;
-    for (int b = 0; b < batch; ++b) {
-      if (!active[b]) continue;
-      iters[b] = it;
-      if (!std::isfinite(qy[b]) || qy[b] <= 0.0) {
-        status[b] = MOFEM_E_BREAKDOWN;
-        active[b] = 0;
-        continue;
-      }
-      if (!std::isfinite(rr[b])) {
-        status[b] = MOFEM_E_NOTFINITE;
-        active[b] = 0;
-        continue;
-      }
-      if (rr[b] <= target2[b]) check.push_back(b);
-    }
-    if (!check.empty()) {
-      // confirm on the true residual Rhs - L(U) for the items that claim convergence
-      std::vector<int> save = active;
-      for (int b = 0; b < batch; ++b) active[b] = 0;
-      for (int b : check) active[b] = 1;
-      TRY(push_active());
-      TRY(op_launch(op, U, stride, w.Z, n, batch, item_scale, nullptr, w.active, s, n_active));
-      LTRY(launch_residual(Rhs, w.Z, w.Z, n, n, stride, batch, w.part_b, w.active, s));
-      LTRY(launch_reduce(w.part_b, kVecBlocks, w.tmp, batch, s));
-      std::vector<double> tr(batch);
-      TRY(fetch(w.tmp, tr.data()));
-      active = save;
-      for (int b : check) {
-        if (tr[b] <= target2[b]) {
-          active[b] = 0;
-        } else {
-          // recurrence drifted: continue from the true residual with a fresh direction
-          restart[b] = 1;
-          r_padded = false;
-          LTRY(launch_copy(w.Z + (size_t)b * n, w.R + (size_t)b * n, n, n, n, 1, s));
-        }
-      }
-      TRY(push_active());
-    }
-    any = false;
-    for (int b = 0; b < batch; ++b) any |= active[b] != 0;
-    if (!any || it >= maxit) break;
-    // Z = P^{-1}(R); <R, Z>, <Z, Y>.  (Fusing the two products into the last
-    // transform's epilogue was measured slower than this separate pass.)
-    TRY(prec_launch(prec, w.R, w.Z, n, batch, item_scale, w.prec_ws, w.prec_bytes, w.active, s, n_active,
-                    r_padded ? 1 : 0));
-    LTRY(launch_dot2_partial(w.R, w.Z, w.Z, w.Y, n, n, batch, w.part_a, w.part_b, w.active, s));
-    LTRY(launch_reduce(w.part_a, kVecBlocks, w.rz_new, batch, s));
-    LTRY(launch_reduce(w.part_b, kVecBlocks, w.zy, batch, s));
-    LTRY(launch_beta(w.rz_new, w.rz, w.zy, w.alpha, w.beta, flexible ? 1 : 0, batch, w.active, s));
-    bool any_restart = false;
-    for (int b = 0; b < batch; ++b) any_restart |= restart[b] != 0;
-    if (any_restart) {
-      for (int b = 0; b < batch; ++b) {
-        hb.d[b] = restart[b] ? 0.0 : 1.0;
-        restart[b] = 0;
-      }
-      // beta := beta * keep  (zero for restarted items: a fresh direction Q = Z)
-      HIP_TRY(hipMemcpyAsync(w.tmp, hb.d, sizeof(double) * batch, hipMemcpyHostToDevice, s));
-      LTRY(launch_scale_items(w.beta, w.tmp, batch, s));
-      HIP_TRY(hipStreamSynchronize(s));
-    }
-    LTRY(launch_direction(w.Q, w.Z, w.beta, n, n, batch, w.active, s));
-  }
-  // final true residuals for every item
-  for (int b = 0; b < batch; ++b) active[b] = 1;
-  TRY(push_active());
-  TRY(op_launch(op, U, stride, w.Z, n, batch, item_scale, nullptr, w.active, s, n_active));
-  LTRY(launch_residual(Rhs, w.Z, w.Z, n, n, stride, batch, w.part_b, w.active, s));
-  LTRY(launch_reduce(w.part_b, kVecBlocks, w.tmp, batch, s));
-  std::vector<double> tr(batch);
-  TRY(fetch(w.tmp, tr.data()));
   int result = MOFEM_OK;
   for (int b = 0; b < batch; ++b) {
-    double rel = rhs2[b] > 0.0 ? std::sqrt(tr[b] / rhs2[b]) : std::sqrt(tr[b]);
+    const double tr = h_tr[b], rhs2 = h_rhs2[b];
+    const double rel = rhs2 > 0.0 ? std::sqrt(tr / rhs2) : std::sqrt(tr);
     if (relres_out) relres_out[b] = rel;
-    if (iters_out) iters_out[b] = iters[b];
-    if (status[b] == MOFEM_OK && !(tr[b] <= target2[b] || (rhs2[b] == 0.0 && tr[b] == 0.0))) status[b] = MOFEM_E_MAXIT;
-    if (status[b] != MOFEM_OK && result == MOFEM_OK) result = status[b];
+    if (iters_out) iters_out[b] = h_iters[b];
+    int st = h_status[b];
+    // final test on the true residual against the item's target (tol^2 ||Rhs||^2,
+    // or tol^2 times the initial residual under the tau rule)
+    if (st == MOFEM_OK && !(tr <= h_tg[b] || (rhs2 == 0.0 && tr == 0.0))) st = MOFEM_E_MAXIT;
+    if (st != MOFEM_OK && result == MOFEM_OK) result = st;
   }
   if (result == MOFEM_E_MAXIT) return fail(result, "pcg_solve: tolerance not reached within maxit");
   if (result == MOFEM_E_BREAKDOWN) return fail(result, "pcg_solve: breakdown, <Q, L(Q)> <= 0");
@@ -1055,10 +1046,9 @@ extern "C" int mofem_imex_step(const mofem_imex_desc* d, double* state, long lon
   if (!rhs || !scale || !pcg_ws || (d->kinetics == MOFEM_KIN_DIB && !trans))
     return fail(MOFEM_E_ARG, "imex_step: workspace too small");
   // per-item c = d_species * tau
-  std::vector<double> hs(items);
   for (int sp = 0; sp < d->n_species; ++sp)
-    for (int b = 0; b < batch; ++b) hs[(size_t)sp * batch + b] = d->d[sp] * d->tau;
-  HIP_TRY(hipMemcpyAsync(scale, hs.data(), sizeof(double) * items, hipMemcpyHostToDevice, s));
+    if (launch_fill(scale + (size_t)sp * batch, d->d[sp] * d->tau, batch, batch, 1, s) != 0)
+      return fail(MOFEM_E_HIP, "imex_step: launch failed");
   // right-hand side: Mass(U + tau f(U, V))  (eq. (93))
   const double* src = state;
   long long src_stride = stride;
@@ -1071,7 +1061,6 @@ extern "C" int mofem_imex_step(const mofem_imex_desc* d, double* state, long lon
   }
   int rc = op_launch(mass, src, src_stride, rhs, n, items, nullptr, nullptr, nullptr, s);
   if (rc) return rc;
-  HIP_TRY(hipStreamSynchronize(s));
   unsigned fl = d->flags & ~MOFEM_PCG_ZERO_GUESS;
   std::vector<double> relres(items);
   // the state is both the guess and the solution; all species in one batched solve
@@ -1151,11 +1140,9 @@ extern "C" int mofem_imex_adjoint_step(const mofem_imex_desc* d, mofem_op_t stif
   const size_t pcg_need = pcg_bytes(op, d->prec, items, nullptr);
   void* pcg_ws = c.take<char>(pcg_need);
   if (!mu || !tmp || !scale || !part || !pcg_ws) return fail(MOFEM_E_ARG, "imex_adjoint_step: workspace too small");
-  std::vector<double> hs(items);
   for (int sp = 0; sp < d->n_species; ++sp)
-    for (int b = 0; b < batch; ++b) hs[(size_t)sp * batch + b] = d->d[sp] * d->tau;
-  HIP_TRY(hipMemcpyAsync(scale, hs.data(), sizeof(double) * items, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipStreamSynchronize(s));  // hs is a host temporary
+    if (launch_fill(scale + (size_t)sp * batch, d->d[sp] * d->tau, batch, batch, 1, s) != 0)
+      return fail(MOFEM_E_HIP, "imex_adjoint_step: launch failed");
   // mu = L_c^{-1}(lam): the operator is symmetric, so the adjoint solve is a forward solve
   int rc = mofem_pcg_solve(op, d->prec, lam, mu, n, items, scale, d->tol, d->maxit,
                            (d->flags & ~MOFEM_PCG_TAU_STOP) | MOFEM_PCG_ZERO_GUESS, pcg_ws, pcg_need, iters_out,

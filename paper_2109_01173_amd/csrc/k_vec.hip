@@ -236,6 +236,92 @@ __global__ void beta_kernel(const double* __restrict__ rz_new, double* __restric
   rz_old[b] = rz_new[b];
 }
 
+// ---- device-side control of the MO-PCG iteration ---------------------------
+// Per item: active (iterating), claim (its recurrence residual passed the
+// target: confirm on the true residual), restart (the true residual did
+// not: continue from it with a fresh direction), status, iteration count.
+// The host only reads `active` every few iterations.
+constexpr int kStatusOk = 0, kStatusBreakdown = -4, kStatusNotFinite = -7;
+
+__global__ void pcg_init_kernel(const double* __restrict__ rhs2, const double* __restrict__ rr,
+                                double* __restrict__ target2, int* __restrict__ active, int* __restrict__ claim,
+                                int* __restrict__ restart, int* __restrict__ status, int* __restrict__ iters,
+                                double tol2, int tau_stop, int batch) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  const double r = rr[b], f = rhs2[b];
+  claim[b] = 0;
+  restart[b] = 0;
+  iters[b] = 0;
+  if (!isfinite(r) || !isfinite(f)) {
+    status[b] = kStatusNotFinite;
+    active[b] = 0;
+    target2[b] = 0.0;
+    return;
+  }
+  status[b] = kStatusOk;
+  const double t = tol2 * (tau_stop ? r : f);
+  target2[b] = t;
+  active[b] = (f == 0.0 || r <= t) ? 0 : 1;
+}
+
+__global__ void pcg_check_kernel(const double* __restrict__ qy, const double* __restrict__ rr,
+                                 const double* __restrict__ target2, int* __restrict__ active,
+                                 int* __restrict__ claim, int* __restrict__ status, int* __restrict__ iters,
+                                 int batch) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  claim[b] = 0;
+  if (!active[b]) return;
+  iters[b] += 1;
+  const double a = qy[b], r = rr[b];
+  if (!isfinite(a) || !(a > 0.0)) {
+    status[b] = kStatusBreakdown;
+    active[b] = 0;
+  } else if (!isfinite(r)) {
+    status[b] = kStatusNotFinite;
+    active[b] = 0;
+  } else if (r <= target2[b]) {
+    claim[b] = 1;
+  }
+}
+
+__global__ void pcg_confirm_kernel(const double* __restrict__ tr, const double* __restrict__ target2,
+                                   int* __restrict__ active, int* __restrict__ claim, int* __restrict__ restart,
+                                   int batch) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  if (!claim[b]) return;
+  if (tr[b] <= target2[b]) active[b] = 0;
+  else restart[b] = 1;  // the recurrence drifted: continue from the true residual
+}
+
+// beta of the next direction; zero (a fresh direction) for restarted items
+__global__ void beta_restart_kernel(const double* __restrict__ rz_new, double* __restrict__ rz_old,
+                                    const double* __restrict__ zy, const double* __restrict__ alpha,
+                                    double* __restrict__ beta, int* __restrict__ restart, int flexible, int batch,
+                                    const int* __restrict__ active) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch || !active[b]) return;
+  double bt = flexible ? (-alpha[b] * zy[b] / rz_old[b]) : (rz_new[b] / rz_old[b]);
+  if (restart[b]) {
+    bt = 0.0;
+    restart[b] = 0;
+  }
+  beta[b] = bt;
+  rz_old[b] = rz_new[b];
+}
+
+__global__ __launch_bounds__(kThreads) void copy_masked_kernel(const double* __restrict__ X, double* __restrict__ Y,
+                                                               long long n, long long xs, long long ys,
+                                                               const int* __restrict__ mask) {
+  const int b = blockIdx.y;
+  if (!mask[b]) return;
+  long long lo, hi;
+  chunk_of(n, blockIdx.x, gridDim.x, &lo, &hi);
+  for (long long i = lo + threadIdx.x; i < hi; i += kThreads) Y[(size_t)b * ys + i] = X[(size_t)b * xs + i];
+}
+
 __global__ void scale_items_kernel(double* __restrict__ x, const double* __restrict__ f, int batch) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b < batch) x[b] *= f[b];
@@ -359,6 +445,35 @@ int launch_beta(const double* rz_new, double* rz_old, const double* zy, const do
                 int flexible, int batch, const int* active, hipStream_t s) {
   hipLaunchKernelGGL(beta_kernel, dim3((batch + 63) / 64), dim3(64), 0, s, rz_new, rz_old, zy, alpha, beta,
                      flexible, batch, active);
+  CHECK_LAUNCH();
+}
+int launch_pcg_init(const double* rhs2, const double* rr, double* target2, int* active, int* claim, int* restart,
+                    int* status, int* iters, double tol2, int tau_stop, int batch, hipStream_t s) {
+  hipLaunchKernelGGL(pcg_init_kernel, dim3((batch + 63) / 64), dim3(64), 0, s, rhs2, rr, target2, active, claim,
+                     restart, status, iters, tol2, tau_stop, batch);
+  CHECK_LAUNCH();
+}
+int launch_pcg_check(const double* qy, const double* rr, const double* target2, int* active, int* claim,
+                     int* status, int* iters, int batch, hipStream_t s) {
+  hipLaunchKernelGGL(pcg_check_kernel, dim3((batch + 63) / 64), dim3(64), 0, s, qy, rr, target2, active, claim,
+                     status, iters, batch);
+  CHECK_LAUNCH();
+}
+int launch_pcg_confirm(const double* tr, const double* target2, int* active, int* claim, int* restart, int batch,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(pcg_confirm_kernel, dim3((batch + 63) / 64), dim3(64), 0, s, tr, target2, active, claim,
+                     restart, batch);
+  CHECK_LAUNCH();
+}
+int launch_beta_restart(const double* rz_new, double* rz_old, const double* zy, const double* alpha, double* beta,
+                        int* restart, int flexible, int batch, const int* active, hipStream_t s) {
+  hipLaunchKernelGGL(beta_restart_kernel, dim3((batch + 63) / 64), dim3(64), 0, s, rz_new, rz_old, zy, alpha, beta,
+                     restart, flexible, batch, active);
+  CHECK_LAUNCH();
+}
+int launch_copy_masked(const double* X, double* Y, long long n, long long xs, long long ys, int batch,
+                       const int* mask, hipStream_t s) {
+  hipLaunchKernelGGL(copy_masked_kernel, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, X, Y, n, xs, ys, mask);
   CHECK_LAUNCH();
 }
 int launch_scale_items(double* x, const double* f, int batch, hipStream_t s) {

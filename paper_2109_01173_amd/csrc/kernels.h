@@ -120,6 +120,17 @@ int launch_beta(const double* rz_new, double* rz_old, const double* zy, const do
                 double* beta, int flexible, int batch, const int* active, hipStream_t s);
 // x_b *= f_b for b < batch
 int launch_scale_items(double* x, const double* f, int batch, hipStream_t s);
+// device-side control of the PCG iteration (see k_vec.hip)
+int launch_pcg_init(const double* rhs2, const double* rr, double* target2, int* active, int* claim, int* restart,
+                    int* status, int* iters, double tol2, int tau_stop, int batch, hipStream_t s);
+int launch_pcg_check(const double* qy, const double* rr, const double* target2, int* active, int* claim,
+                     int* status, int* iters, int batch, hipStream_t s);
+int launch_pcg_confirm(const double* tr, const double* target2, int* active, int* claim, int* restart, int batch,
+                       hipStream_t s);
+int launch_beta_restart(const double* rz_new, double* rz_old, const double* zy, const double* alpha, double* beta,
+                        int* restart, int flexible, int batch, const int* active, hipStream_t s);
+int launch_copy_masked(const double* X, double* Y, long long n, long long xs, long long ys, int batch,
+                       const int* mask, hipStream_t s);
 // elementwise DIB kinetics: T_u = U + tau rho f(U, V), T_v = V + tau rho g(U, V)
 int launch_dib_source(const double* U, const double* V, double* TU, double* TV, long long n,
                       long long stride, int batch, const double* kin, double tau,
