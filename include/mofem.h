@@ -258,11 +258,30 @@ size_t mofem_pcg_workspace_size(mofem_op_t op, mofem_prec_t prec, int batch);
      iters_out, relres_out  host [batch] or NULL.
    Errors: MOFEM_E_MAXIT (U holds the last iterate, relres_out its true
    relative residual), MOFEM_E_BREAKDOWN, MOFEM_E_NOTFINITE, MOFEM_E_ARG,
-   MOFEM_E_NOMEM.  Synchronises `stream` once per iteration (a few bytes). */
+   MOFEM_E_NOMEM.  The iteration runs under device-side control; the host
+   reads a few bytes of flags one iteration behind and synchronises once at
+   the end. */
 int mofem_pcg_solve(mofem_op_t op, mofem_prec_t prec, const double* Rhs, double* U,
                     long long stride, int batch, const double* item_scale,
                     double tol, int maxit, unsigned flags, void* workspace,
                     size_t ws_bytes, int* iters_out, double* relres_out, void* stream);
+
+/* The same solve without any host synchronisation (capturable in a HIP
+   graph; several solves on several streams overlap): exactly `maxit`
+   iterations are queued, the items that converged run masked (their
+   kernels exit at once), and the per-item results stay on the device.
+     workspace  required (mofem_pcg_workspace_size bytes), device.
+     iters_dev, status_dev  device [batch] int: iterations and MOFEM_OK or the
+                error code of mofem_pcg_solve for that item (E_MAXIT,
+                E_BREAKDOWN, E_NOTFINITE).
+     relres_dev device [batch]: final true relative residual.
+   Returns MOFEM_OK once everything is queued; errors only for invalid
+   arguments or failed launches. */
+int mofem_pcg_solve_async(mofem_op_t op, mofem_prec_t prec, const double* Rhs, double* U,
+                          long long stride, int batch, const double* item_scale,
+                          double tol, int maxit, unsigned flags, void* workspace,
+                          size_t ws_bytes, int* iters_dev, int* status_dev,
+                          double* relres_dev, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* a7. IMEX Euler step (Sec. 6, eqs. (87)-(96); DIB kinetics Sec. 7)        */
@@ -295,6 +314,27 @@ size_t mofem_imex_workspace_size(const mofem_imex_desc* desc, int batch);
 int mofem_imex_step(const mofem_imex_desc* desc, double* state, long long stride,
                     int batch, void* workspace, size_t ws_bytes, int* iters_out,
                     void* stream);
+
+/* One IMEX step as a HIP graph over fixed buffers: the right-hand side and
+   exactly `iters_per_step` PCG iterations per solve (items that converged
+   run masked, so the result equals mofem_imex_step's when iters_per_step
+   covers its iteration count), with no host synchronisation.  Each replay
+   advances `state` (the buffer given at creation) by one step; replays on
+   one stream run back to back without host involvement.
+     workspace   device, mofem_imex_workspace_size bytes, owned by the caller
+                 and kept alive (and unused elsewhere) while the graph lives.
+   The graph owns small device result arrays; mofem_imex_graph_result reads,
+   for every item since the previous read, the largest iteration count and
+   the first non-OK status (MOFEM_E_MAXIT when iters_per_step was too few),
+   plus the last step's relative residual, and returns the first error. */
+typedef struct mofem_imex_graph_s* mofem_imex_graph_t;
+int mofem_imex_graph_create(const mofem_imex_desc* desc, double* state, long long stride,
+                            int batch, void* workspace, size_t ws_bytes, int iters_per_step,
+                            mofem_imex_graph_t* graph, void* stream);
+int mofem_imex_graph_launch(mofem_imex_graph_t graph, int nsteps, void* stream);
+int mofem_imex_graph_result(mofem_imex_graph_t graph, int* max_iters, int* status,
+                            double* relres, void* stream);
+int mofem_imex_graph_destroy(mofem_imex_graph_t graph);
 
 /* Reverse (adjoint) IMEX Euler step: the exact derivative of
    mofem_imex_step for a scalar loss J.  With c = d * tau per species,

@@ -99,9 +99,17 @@ void trace_resolve(TraceState& t) {
   }
   t.recs.clear();
 }
+// Tracing is suspended on a thread while it captures a HIP graph (event
+// records inside a graph would not describe individual replays).
+thread_local int g_trace_suspended = 0;
+struct TraceCapture {
+  TraceCapture() { ++g_trace_suspended; }
+  ~TraceCapture() { --g_trace_suspended; }
+};
 // Correct the item count of a class after the fact (launches whose item
 // count was only known later, e.g. under device-side masking).
 void trace_add_items(int cls, double delta) {
+  if (g_trace_suspended) return;
   TraceState& t = trace_state();
   std::lock_guard<std::mutex> g(t.mu);
   if (t.on) t.items[cls] += delta;
@@ -113,6 +121,7 @@ struct TraceScope {
   int cls;
   double items;
   TraceScope(int c, double n, hipStream_t st) : s(st), cls(c), items(n) {
+    if (g_trace_suspended) return;
     TraceState& t = trace_state();
     std::lock_guard<std::mutex> g(t.mu);
     if (!t.on) return;
@@ -805,197 +814,262 @@ extern "C" size_t mofem_pcg_workspace_size(mofem_op_t op, mofem_prec_t prec, int
   return pcg_bytes(op, prec, batch, nullptr);
 }
 
-// The iteration runs under device-side control: every kernel skips the items
-// whose `active` flag is clear, convergence and breakdown are decided on the
-// device (pcg_check / pcg_confirm), and the host reads the flags one
-// iteration behind, so no host round trip sits inside an iteration.
-extern "C" int mofem_pcg_solve(mofem_op_t op, mofem_prec_t prec, const double* Rhs, double* U, long long stride,
-                               int batch, const double* item_scale, double tol, int maxit, unsigned flags,
-                               void* workspace, size_t ws_bytes, int* iters_out, double* relres_out,
-                               void* stream) {
-  clear_error();
-  if (!op || !prec) return fail(MOFEM_E_ARG, "pcg_solve: NULL handle");
-  if (batch < 0 || maxit < 0 || !(tol >= 0.0)) return fail(MOFEM_E_ARG, "pcg_solve: bad batch/maxit/tol");
-  if (batch == 0) return MOFEM_OK;
-  if (!Rhs || !U) return fail(MOFEM_E_ARG, "pcg_solve: NULL argument");
-  if (op->full_input || op->full_output)
-    return fail(MOFEM_E_ARG, "pcg_solve: operator must map unknowns to unknowns");
-  if (op->qs != prec->qs || op->qt != prec->qt) return fail(MOFEM_E_ARG, "pcg_solve: operator and preconditioner sizes differ");
-  const long long n = (long long)op->qs * op->qt;
-  if (stride < n) return fail(MOFEM_E_ARG, "pcg_solve: stride smaller than one item");
-  hipStream_t s = (hipStream_t)stream;
-  const size_t need = pcg_bytes(op, prec, batch, nullptr);
-  static thread_local void* own_ws = nullptr;
-  static thread_local size_t own_bytes = 0;
-  if (!workspace) {
-    int rc = ensure_internal_ws(&own_ws, &own_bytes, need, s);
-    if (rc) return rc;
-    workspace = own_ws;
-    ws_bytes = own_bytes;
-  } else if (ws_bytes < need) {
-    return fail(MOFEM_E_ARG, "pcg_solve: workspace too small");
-  }
+namespace {
+// One MO-PCG solve under device-side control: every kernel skips the items
+// whose `active` flag is clear, and convergence, breakdown and the
+// true-residual confirmation (with a restart on drift) are decided on the
+// device (pcg_init / pcg_check / pcg_confirm), so the launches of an
+// iteration never depend on the host.
+struct PcgRun {
+  mofem_op_t op;
+  mofem_prec_t prec;
+  const double* Rhs;
+  double* U;
+  long long stride, n;
+  int batch;
+  const double* item_scale;
+  double tol;
+  unsigned flags;
+  hipStream_t s;
   PcgWs w{};
-  if (!carve_pcg(op, prec, batch, workspace, ws_bytes, &w)) return fail(MOFEM_E_ARG, "pcg_solve: workspace too small");
-  static thread_local PinnedHost pinned;
-  // layout: two slots of active flags and the initial flags, then (aligned) tr, rhs2,
-  // target2, then iters, status
-  const size_t dbl_off = align_up((size_t)batch * 12, 64);
-  char* host = (char*)pinned.get(dbl_off + (size_t)batch * (24 + 8));
-  if (!host) return fail(MOFEM_E_NOMEM, "pcg_solve: pinned host buffer");
-  int* h_active = (int*)host;
-  const bool flexible = flags & MOFEM_PCG_FLEXIBLE;
-  const bool tau_stop = flags & MOFEM_PCG_TAU_STOP;
-  const int nt = op->n_tiles;
-  const PrecInput pin = prec_input(prec, w.prec_ws, w.prec_bytes, batch);
-  int n_active = batch;  // as of the last read-back (used for tracing only)
+  PrecInput pin;
+  int n_trace;  // item count recorded with traced launches
+  double rec_band = 0, rec_prec = 0;
 
-#define LTRY(x)                                                            \
-  do {                                                                     \
-    TraceScope _trace(MOFEM_TRACE_VEC, n_active, s);                       \
-    if ((x) != 0) return fail(MOFEM_E_HIP, "pcg_solve: launch failed");    \
+  int launch_fail() { return fail(MOFEM_E_HIP, "pcg_solve: launch failed"); }
+#define PCG_LTRY(x)                                       \
+  do {                                                    \
+    TraceScope _trace(MOFEM_TRACE_VEC, n_trace, s);       \
+    if ((x) != 0) return launch_fail();                   \
   } while (0)
-#define TRY(x)                       \
+#define PCG_TRY(x)                   \
   do {                               \
     int _rc = (x);                   \
     if (_rc != MOFEM_OK) return _rc; \
   } while (0)
 
-  // ||Rhs||^2 and the initial residual R = Rhs - L(U) (or Rhs with a zero guess)
-  LTRY(launch_dot_partial(Rhs, Rhs, n, stride, batch, w.part_a, nullptr, s));
-  LTRY(launch_reduce(w.part_a, kVecBlocks, w.rhs2, batch, s));
-  if (flags & MOFEM_PCG_ZERO_GUESS) {
-    LTRY(launch_fill(U, 0.0, n, stride, batch, s));
-    LTRY(launch_copy(Rhs, w.R, n, stride, n, batch, s));
-    LTRY(launch_dot_partial(w.R, w.R, n, n, batch, w.part_a, nullptr, s));
-  } else {
-    TRY(op_launch(op, U, stride, w.Y, n, batch, item_scale, nullptr, nullptr, s, n_active));
-    LTRY(launch_residual(Rhs, w.Y, w.R, n, n, stride, batch, w.part_a, nullptr, s));
+  // ||Rhs||^2, R = Rhs - L(U) (or Rhs with a zero guess), targets, Z = P^-1(R), Q = Z
+  int begin() {
+    PCG_LTRY(launch_dot_partial(Rhs, Rhs, n, stride, batch, w.part_a, nullptr, s));
+    PCG_LTRY(launch_reduce(w.part_a, kVecBlocks, w.rhs2, batch, s));
+    if (flags & MOFEM_PCG_ZERO_GUESS) {
+      PCG_LTRY(launch_fill(U, 0.0, n, stride, batch, s));
+      PCG_LTRY(launch_copy(Rhs, w.R, n, stride, n, batch, s));
+      PCG_LTRY(launch_dot_partial(w.R, w.R, n, n, batch, w.part_a, nullptr, s));
+    } else {
+      PCG_TRY(op_launch(op, U, stride, w.Y, n, batch, item_scale, nullptr, nullptr, s, n_trace));
+      PCG_LTRY(launch_residual(Rhs, w.Y, w.R, n, n, stride, batch, w.part_a, nullptr, s));
+    }
+    PCG_LTRY(launch_reduce(w.part_a, kVecBlocks, w.rr, batch, s));
+    PCG_LTRY(launch_pcg_init(w.rhs2, w.rr, w.target2, w.active, w.claim, w.restart, w.status, w.iters, tol * tol,
+                             (flags & MOFEM_PCG_TAU_STOP) ? 1 : 0, batch, s));
+    PCG_TRY(prec_launch(prec, w.R, w.Z, n, batch, item_scale, w.prec_ws, w.prec_bytes, w.active, s, n_trace));
+    rec_prec += n_trace;
+    PCG_LTRY(launch_dot_partial(w.R, w.Z, n, n, batch, w.part_a, w.active, s));
+    PCG_LTRY(launch_reduce(w.part_a, kVecBlocks, w.rz, batch, s));
+    PCG_LTRY(launch_direction(w.Q, w.Z, nullptr, n, n, batch, w.active, s));
+    return MOFEM_OK;
   }
-  LTRY(launch_reduce(w.part_a, kVecBlocks, w.rr, batch, s));
-  LTRY(launch_pcg_init(w.rhs2, w.rr, w.target2, w.active, w.claim, w.restart, w.status, w.iters, tol * tol,
-                       tau_stop ? 1 : 0, batch, s));
-  // The active set is known on the host only one iteration late; launches
-  // are traced with the last known count and corrected at the end from the
-  // exact per-iteration counts.
-  int* h_init = h_active + 2 * batch;
-  HIP_TRY(hipMemcpyAsync(h_init, w.active, sizeof(int) * batch, hipMemcpyDeviceToHost, s));
-  std::vector<int> cnt;             // active items after iteration j
-  double rec_band = 0, rec_prec = 0;  // items recorded for the Y = L(Q) and P^-1 launches
-  int last_it = -1;
-  // Z = P^{-1}(R), <R, Z>, Q = Z
-  TRY(prec_launch(prec, w.R, w.Z, n, batch, item_scale, w.prec_ws, w.prec_bytes, w.active, s, n_active));
-  rec_prec += n_active;
-  LTRY(launch_dot_partial(w.R, w.Z, n, n, batch, w.part_a, w.active, s));
-  LTRY(launch_reduce(w.part_a, kVecBlocks, w.rz, batch, s));
-  LTRY(launch_direction(w.Q, w.Z, nullptr, n, n, batch, w.active, s));
 
-  // The flags of iteration i are copied to pinned memory behind an event;
-  // the host waits for them only after iteration i + 1 is queued, so the
-  // device never idles on the host and at most one iteration runs masked
-  // after the last item has converged.
+  int iteration() {
+    // Y = L(Q), <Q, Y>
+    PCG_TRY(op_launch(op, w.Q, n, w.Y, n, batch, item_scale, w.part_op, w.active, s, n_trace));
+    rec_band += n_trace;
+    PCG_LTRY(launch_reduce(w.part_op, op->n_tiles, w.qy, batch, s));
+    // alpha = <R, Z> / <Q, Y>; U += alpha Q; R -= alpha Y; ||R||^2; R's padded transform operand
+    PCG_LTRY(launch_cg_update_pad(U, w.R, w.Q, w.Y, w.rz, w.qy, w.alpha, op->qs, op->qt, n, stride, batch, w.part_a,
+                                  w.active, pin.hi, pin.lo, pin.f64, pin.f32, pin.stride, s));
+    PCG_LTRY(launch_reduce(w.part_a, kVecBlocks, w.rr, batch, s));
+    PCG_LTRY(launch_pcg_check(w.qy, w.rr, w.target2, w.active, w.claim, w.status, w.iters, batch, s));
+    // items that claim convergence: confirm on the true residual Rhs - L(U); where it
+    // fails, continue from the true residual with a fresh direction
+    PCG_TRY(op_launch(op, U, stride, w.Z, n, batch, item_scale, nullptr, w.claim, s, 0));
+    PCG_LTRY(launch_residual(Rhs, w.Z, w.Z, n, n, stride, batch, w.part_b, w.claim, s));
+    PCG_LTRY(launch_reduce(w.part_b, kVecBlocks, w.tr, batch, s));
+    PCG_LTRY(launch_pcg_confirm(w.tr, w.target2, w.active, w.claim, w.restart, batch, s));
+    PCG_LTRY(launch_copy_masked(w.Z, w.R, n, n, n, batch, w.restart, s));
+    PCG_LTRY(launch_pad_operand(w.R, n, op->qs, op->qt, pin.f64, pin.f32, pin.hi, pin.lo, pin.stride,
+                                (pin.hi != nullptr) ? 1 : 0, batch, w.restart, s));
+    // Z = P^{-1}(R); <R, Z>, <Z, Y>; beta (zero after a restart); Q = Z + beta Q
+    PCG_TRY(prec_launch(prec, w.R, w.Z, n, batch, item_scale, w.prec_ws, w.prec_bytes, w.active, s, n_trace, 1));
+    rec_prec += n_trace;
+    PCG_LTRY(launch_dot2_partial(w.R, w.Z, w.Z, w.Y, n, n, batch, w.part_a, w.part_b, w.active, s));
+    PCG_LTRY(launch_reduce(w.part_a, kVecBlocks, w.rz_new, batch, s));
+    PCG_LTRY(launch_reduce(w.part_b, kVecBlocks, w.zy, batch, s));
+    PCG_LTRY(launch_beta_restart(w.rz_new, w.rz, w.zy, w.alpha, w.beta, w.restart,
+                                 (flags & MOFEM_PCG_FLEXIBLE) ? 1 : 0, batch, w.active, s));
+    PCG_LTRY(launch_direction(w.Q, w.Z, w.beta, n, n, batch, w.active, s));
+    return MOFEM_OK;
+  }
+
+  // final true residuals of every item and the per-item result on the device
+  int finish(int* iters_dev, int* status_dev, double* relres_dev) {
+    PCG_TRY(op_launch(op, U, stride, w.Z, n, batch, item_scale, nullptr, nullptr, s, batch));
+    PCG_LTRY(launch_residual(Rhs, w.Z, w.Z, n, n, stride, batch, w.part_b, nullptr, s));
+    PCG_LTRY(launch_reduce(w.part_b, kVecBlocks, w.tr, batch, s));
+    PCG_LTRY(launch_pcg_final(w.tr, w.rhs2, w.target2, w.status, w.iters, iters_dev, status_dev, relres_dev, batch,
+                              s));
+    return MOFEM_OK;
+  }
+#undef PCG_LTRY
+#undef PCG_TRY
+};
+
+int pcg_prepare(PcgRun& r, mofem_op_t op, mofem_prec_t prec, const double* Rhs, double* U, long long stride,
+                int batch, const double* item_scale, double tol, int maxit, unsigned flags, void* workspace,
+                size_t ws_bytes, hipStream_t s) {
+  if (!op || !prec) return fail(MOFEM_E_ARG, "pcg_solve: NULL handle");
+  if (batch < 0 || maxit < 0 || !(tol >= 0.0)) return fail(MOFEM_E_ARG, "pcg_solve: bad batch/maxit/tol");
+  if (batch > 0 && (!Rhs || !U)) return fail(MOFEM_E_ARG, "pcg_solve: NULL argument");
+  if (op->full_input || op->full_output)
+    return fail(MOFEM_E_ARG, "pcg_solve: operator must map unknowns to unknowns");
+  if (op->qs != prec->qs || op->qt != prec->qt)
+    return fail(MOFEM_E_ARG, "pcg_solve: operator and preconditioner sizes differ");
+  const long long n = (long long)op->qs * op->qt;
+  if (stride < n) return fail(MOFEM_E_ARG, "pcg_solve: stride smaller than one item");
+  if (batch == 0) return MOFEM_OK;
+  if (!workspace || ws_bytes < pcg_bytes(op, prec, batch, nullptr))
+    return fail(MOFEM_E_ARG, "pcg_solve: workspace too small");
+  r.op = op;
+  r.prec = prec;
+  r.Rhs = Rhs;
+  r.U = U;
+  r.stride = stride;
+  r.n = n;
+  r.batch = batch;
+  r.item_scale = item_scale;
+  r.tol = tol;
+  r.flags = flags;
+  r.s = s;
+  r.n_trace = batch;
+  if (!carve_pcg(op, prec, batch, workspace, ws_bytes, &r.w)) return fail(MOFEM_E_ARG, "pcg_solve: workspace too small");
+  r.pin = prec_input(prec, r.w.prec_ws, r.w.prec_bytes, batch);
+  return MOFEM_OK;
+}
+
+int trace_class_of(mofem_prec_t p) {
+  return p->precision == MOFEM_PREC_F64      ? MOFEM_TRACE_GEMM_F64
+         : p->precision == MOFEM_PREC_F32    ? MOFEM_TRACE_GEMM_F32
+         : p->precision == MOFEM_PREC_BF16   ? MOFEM_TRACE_GEMM_BF16
+         : p->precision == MOFEM_PREC_BF16X2 ? MOFEM_TRACE_GEMM_BF16X2
+                                             : MOFEM_TRACE_GEMM_BF16X3;
+}
+
+int status_error(int result) {
+  if (result == MOFEM_E_MAXIT) return fail(result, "pcg_solve: tolerance not reached within maxit");
+  if (result == MOFEM_E_BREAKDOWN) return fail(result, "pcg_solve: breakdown, <Q, L(Q)> <= 0");
+  if (result == MOFEM_E_NOTFINITE) return fail(result, "pcg_solve: non-finite residual");
+  return result;
+}
+}  // namespace
+
+// The host reads the active flags one iteration behind (the next iteration
+// is already queued), so the device never waits on the host inside the
+// loop; at most one masked iteration runs after the last item converged.
+extern "C" int mofem_pcg_solve(mofem_op_t op, mofem_prec_t prec, const double* Rhs, double* U, long long stride,
+                               int batch, const double* item_scale, double tol, int maxit, unsigned flags,
+                               void* workspace, size_t ws_bytes, int* iters_out, double* relres_out,
+                               void* stream) {
+  clear_error();
+  hipStream_t s = (hipStream_t)stream;
+  if (op && prec && batch > 0 && !workspace) {
+    static thread_local void* own_ws = nullptr;
+    static thread_local size_t own_bytes = 0;
+    int rc = ensure_internal_ws(&own_ws, &own_bytes, pcg_bytes(op, prec, batch, nullptr), s);
+    if (rc) return rc;
+    workspace = own_ws;
+    ws_bytes = own_bytes;
+  }
+  PcgRun r;
+  int rc = pcg_prepare(r, op, prec, Rhs, U, stride, batch, item_scale, tol, maxit, flags, workspace, ws_bytes, s);
+  if (rc != MOFEM_OK || batch == 0) return rc;
+  static thread_local PinnedHost pinned;
+  // layout: two slots of active flags, the initial flags, then (aligned) relres, iters, status
+  const size_t dbl_off = align_up((size_t)batch * 12, 64);
+  char* host = (char*)pinned.get(dbl_off + (size_t)batch * 16);
+  if (!host) return fail(MOFEM_E_NOMEM, "pcg_solve: pinned host buffer");
+  int* h_flags[2] = {(int*)host, (int*)host + batch};
+  int* h_init = (int*)host + 2 * batch;
+  double* h_relres = (double*)(host + dbl_off);
+  int* h_iters = (int*)(h_relres + batch);
+  int* h_status = h_iters + batch;
+
+  rc = r.begin();
+  if (rc) return rc;
+  // The active set is known on the host one iteration late; launches are traced
+  // with the last known count and corrected at the end from the exact counts.
+  HIP_TRY(hipMemcpyAsync(h_init, r.w.active, sizeof(int) * batch, hipMemcpyDeviceToHost, s));
   static thread_local hipEvent_t flag_ev[2] = {nullptr, nullptr};
   for (auto& e : flag_ev)
     if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  int* h_flags[2] = {h_active, h_active + batch};
+  std::vector<int> cnt;  // active items after iteration j
+  int last_it = -1;
   for (int it = 0; it < maxit; ++it) {
-    {
-      // Y = L(Q), <Q, Y>
-      last_it = it;
-      TRY(op_launch(op, w.Q, n, w.Y, n, batch, item_scale, w.part_op, w.active, s, n_active));
-      rec_band += n_active;
-      LTRY(launch_reduce(w.part_op, nt, w.qy, batch, s));
-      // alpha = <R, Z> / <Q, Y>; U += alpha Q; R -= alpha Y; ||R||^2; R's padded transform operand
-      LTRY(launch_cg_update_pad(U, w.R, w.Q, w.Y, w.rz, w.qy, w.alpha, op->qs, op->qt, n, stride, batch, w.part_a,
-                                w.active, pin.hi, pin.lo, pin.f64, pin.f32, pin.stride, s));
-      LTRY(launch_reduce(w.part_a, kVecBlocks, w.rr, batch, s));
-      LTRY(launch_pcg_check(w.qy, w.rr, w.target2, w.active, w.claim, w.status, w.iters, batch, s));
-      // items that claim convergence: confirm on the true residual Rhs - L(U); where it
-      // fails, continue from the true residual with a fresh direction
-      TRY(op_launch(op, U, stride, w.Z, n, batch, item_scale, nullptr, w.claim, s, 0));
-      LTRY(launch_residual(Rhs, w.Z, w.Z, n, n, stride, batch, w.part_b, w.claim, s));
-      LTRY(launch_reduce(w.part_b, kVecBlocks, w.tr, batch, s));
-      LTRY(launch_pcg_confirm(w.tr, w.target2, w.active, w.claim, w.restart, batch, s));
-      LTRY(launch_copy_masked(w.Z, w.R, n, n, n, batch, w.restart, s));
-      {
-        TraceScope _trace(MOFEM_TRACE_VEC, n_active, s);
-        if (launch_pad_operand(w.R, n, op->qs, op->qt, pin.f64, pin.f32, pin.hi, pin.lo, pin.stride,
-                               (pin.hi != nullptr) ? 1 : 0, batch, w.restart, s))
-          return fail(MOFEM_E_HIP, "pcg_solve: launch failed");
-      }
-      // Z = P^{-1}(R); <R, Z>, <Z, Y>; beta (zero after a restart); Q = Z + beta Q
-      TRY(prec_launch(prec, w.R, w.Z, n, batch, item_scale, w.prec_ws, w.prec_bytes, w.active, s, n_active, 1));
-      rec_prec += n_active;
-      LTRY(launch_dot2_partial(w.R, w.Z, w.Z, w.Y, n, n, batch, w.part_a, w.part_b, w.active, s));
-      LTRY(launch_reduce(w.part_a, kVecBlocks, w.rz_new, batch, s));
-      LTRY(launch_reduce(w.part_b, kVecBlocks, w.zy, batch, s));
-      LTRY(launch_beta_restart(w.rz_new, w.rz, w.zy, w.alpha, w.beta, w.restart, flexible ? 1 : 0, batch, w.active,
-                               s));
-      LTRY(launch_direction(w.Q, w.Z, w.beta, n, n, batch, w.active, s));
-    }
-    HIP_TRY(hipMemcpyAsync(h_flags[it & 1], w.active, sizeof(int) * batch, hipMemcpyDeviceToHost, s));
+    last_it = it;
+    rc = r.iteration();
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(h_flags[it & 1], r.w.active, sizeof(int) * batch, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipEventRecord(flag_ev[it & 1], s));
     if (it == 0) continue;
     HIP_TRY(hipEventSynchronize(flag_ev[(it - 1) & 1]));
-    n_active = 0;
-    for (int b = 0; b < batch; ++b) n_active += h_flags[(it - 1) & 1][b] != 0;
-    cnt.push_back(n_active);
-    if (n_active == 0) break;
+    int na = 0;
+    for (int b = 0; b < batch; ++b) na += h_flags[(it - 1) & 1][b] != 0;
+    cnt.push_back(na);
+    r.n_trace = na;
+    if (na == 0) break;
   }
-  // final true residuals of every item
-  TRY(op_launch(op, U, stride, w.Z, n, batch, item_scale, nullptr, nullptr, s, batch));
-  LTRY(launch_residual(Rhs, w.Z, w.Z, n, n, stride, batch, w.part_b, nullptr, s));
-  LTRY(launch_reduce(w.part_b, kVecBlocks, w.tr, batch, s));
-  double* h_tr = (double*)(host + dbl_off);
-  double* h_rhs2 = h_tr + batch;
-  double* h_tg = h_rhs2 + batch;
-  int* h_iters = (int*)(h_tg + batch);
-  int* h_status = h_iters + batch;
-  HIP_TRY(hipMemcpyAsync(h_tr, w.tr, sizeof(double) * batch, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(h_rhs2, w.rhs2, sizeof(double) * batch, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(h_tg, w.target2, sizeof(double) * batch, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(h_iters, w.iters, sizeof(int) * batch, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(h_status, w.status, sizeof(int) * batch, hipMemcpyDeviceToHost, s));
+  // per-item results (iterations, status, relative residual) into scratch arrays
+  // of this solve that the iteration no longer needs, then to the host
+  rc = r.finish(r.w.claim, r.w.restart, r.w.rr);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(h_relres, r.w.rr, sizeof(double) * batch, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(h_iters, r.w.claim, sizeof(int) * batch, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(h_status, r.w.restart, sizeof(int) * batch, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (last_it >= 0) {
     // exact items: Y = L(Q) of iteration j ran on the items active after j - 1 (the
     // initial set for j = 0), P^-1 of iteration j on those active after j
-    int n_last = 0;
-    for (int b = 0; b < batch; ++b) n_last += h_flags[last_it & 1][b] != 0;
+    int n_last = 0, n_init = 0;
+    for (int b = 0; b < batch; ++b) {
+      n_last += h_flags[last_it & 1][b] != 0;
+      n_init += h_init[b] != 0;
+    }
     while ((int)cnt.size() < last_it + 1) cnt.push_back(n_last);
-    int n_init = 0;
-    for (int b = 0; b < batch; ++b) n_init += h_init[b] != 0;
     double ex_band = 0, ex_prec = n_init;
     for (int j = 0; j <= last_it; ++j) {
       ex_band += j == 0 ? n_init : cnt[j - 1];
       ex_prec += cnt[j];
     }
-    const int tcls = prec->precision == MOFEM_PREC_F64      ? MOFEM_TRACE_GEMM_F64
-                     : prec->precision == MOFEM_PREC_F32    ? MOFEM_TRACE_GEMM_F32
-                     : prec->precision == MOFEM_PREC_BF16   ? MOFEM_TRACE_GEMM_BF16
-                     : prec->precision == MOFEM_PREC_BF16X2 ? MOFEM_TRACE_GEMM_BF16X2
-                                                            : MOFEM_TRACE_GEMM_BF16X3;
-    trace_add_items(MOFEM_TRACE_BAND, ex_band - rec_band);
-    trace_add_items(tcls, 4.0 * (ex_prec - rec_prec));
+    trace_add_items(MOFEM_TRACE_BAND, ex_band - r.rec_band);
+    trace_add_items(trace_class_of(prec), 4.0 * (ex_prec - r.rec_prec));
   }
   int result = MOFEM_OK;
   for (int b = 0; b < batch; ++b) {
-    const double tr = h_tr[b], rhs2 = h_rhs2[b];
-    const double rel = rhs2 > 0.0 ? std::sqrt(tr / rhs2) : std::sqrt(tr);
-    if (relres_out) relres_out[b] = rel;
+    if (relres_out) relres_out[b] = h_relres[b];
     if (iters_out) iters_out[b] = h_iters[b];
-    int st = h_status[b];
-    // final test on the true residual against the item's target (tol^2 ||Rhs||^2,
-    // or tol^2 times the initial residual under the tau rule)
-    if (st == MOFEM_OK && !(tr <= h_tg[b] || (rhs2 == 0.0 && tr == 0.0))) st = MOFEM_E_MAXIT;
-    if (st != MOFEM_OK && result == MOFEM_OK) result = st;
+    if (h_status[b] != MOFEM_OK && result == MOFEM_OK) result = h_status[b];
   }
-  if (result == MOFEM_E_MAXIT) return fail(result, "pcg_solve: tolerance not reached within maxit");
-  if (result == MOFEM_E_BREAKDOWN) return fail(result, "pcg_solve: breakdown, <Q, L(Q)> <= 0");
-  if (result == MOFEM_E_NOTFINITE) return fail(result, "pcg_solve: non-finite residual");
-  return result;
-#undef TRY
-#undef LTRY
+  return status_error(result);
+}
+
+extern "C" int mofem_pcg_solve_async(mofem_op_t op, mofem_prec_t prec, const double* Rhs, double* U,
+                                     long long stride, int batch, const double* item_scale, double tol, int maxit,
+                                     unsigned flags, void* workspace, size_t ws_bytes, int* iters_dev,
+                                     int* status_dev, double* relres_dev, void* stream) {
+  clear_error();
+  if (batch > 0 && (!workspace || !iters_dev || !status_dev || !relres_dev))
+    return fail(MOFEM_E_ARG, "pcg_solve_async: NULL workspace or result array");
+  PcgRun r;
+  hipStream_t s = (hipStream_t)stream;
+  int rc = pcg_prepare(r, op, prec, Rhs, U, stride, batch, item_scale, tol, maxit, flags, workspace, ws_bytes, s);
+  if (rc != MOFEM_OK || batch == 0) return rc;
+  rc = r.begin();
+  if (rc) return rc;
+  for (int it = 0; it < maxit; ++it) {
+    rc = r.iteration();
+    if (rc) return rc;
+  }
+  return r.finish(iters_dev, status_dev, relres_dev);
 }
 
 // ============================================================================
@@ -1011,62 +1085,205 @@ extern "C" size_t mofem_imex_workspace_size(const mofem_imex_desc* d, int batch)
   return b + pcg_bytes(d->op, d->prec, (int)items, nullptr) + 4096;
 }
 
-extern "C" int mofem_imex_step(const mofem_imex_desc* d, double* state, long long stride, int batch,
-                               void* workspace, size_t ws_bytes, int* iters_out, void* stream) {
-  clear_error();
+namespace {
+int imex_check(const mofem_imex_desc* d, const double* state, long long stride, int batch) {
   if (!d || !state || !d->op || !d->prec || !d->mass) return fail(MOFEM_E_ARG, "imex_step: NULL argument");
   if (d->n_species < 1 || d->n_species > 2) return fail(MOFEM_E_ARG, "imex_step: n_species must be 1 or 2");
   if (d->kinetics == MOFEM_KIN_DIB && d->n_species != 2) return fail(MOFEM_E_ARG, "imex_step: DIB needs 2 species");
-  if (d->kinetics != MOFEM_KIN_NONE && d->kinetics != MOFEM_KIN_DIB) return fail(MOFEM_E_ARG, "imex_step: unknown kinetics");
-  if (batch < 1) return batch == 0 ? MOFEM_OK : fail(MOFEM_E_ARG, "imex_step: negative batch");
+  if (d->kinetics != MOFEM_KIN_NONE && d->kinetics != MOFEM_KIN_DIB)
+    return fail(MOFEM_E_ARG, "imex_step: unknown kinetics");
+  if (batch < 0) return fail(MOFEM_E_ARG, "imex_step: negative batch");
   mofem_op_t op = d->op, mass = d->mass;
   if (mass->full_input || mass->full_output || mass->qs != op->qs || mass->qt != op->qt)
     return fail(MOFEM_E_ARG, "imex_step: mass operator must map unknowns to unknowns of the same shape");
-  const long long n = (long long)op->qs * op->qt;
-  if (stride != n) return fail(MOFEM_E_ARG, "imex_step: items must be contiguous (stride = q_s * q_t)");
+  if (stride != (long long)op->qs * op->qt)
+    return fail(MOFEM_E_ARG, "imex_step: items must be contiguous (stride = q_s * q_t)");
+  return MOFEM_OK;
+}
+
+struct ImexParts {
+  double *rhs, *trans, *scale;
+  void* pcg_ws;
+  size_t pcg_need;
+};
+int imex_carve(const mofem_imex_desc* d, int batch, void* workspace, size_t ws_bytes, ImexParts* p) {
   const int items = d->n_species * batch;
+  const size_t n = (size_t)d->op->qs * d->op->qt;
+  Carve c(workspace, ws_bytes);
+  p->rhs = c.take<double>((size_t)items * n);
+  p->trans = d->kinetics == MOFEM_KIN_DIB ? c.take<double>((size_t)items * n) : nullptr;
+  p->scale = c.take<double>(items);
+  p->pcg_need = pcg_bytes(d->op, d->prec, items, nullptr);
+  p->pcg_ws = c.take<char>(p->pcg_need);
+  if (!p->rhs || !p->scale || !p->pcg_ws || (d->kinetics == MOFEM_KIN_DIB && !p->trans))
+    return fail(MOFEM_E_ARG, "imex_step: workspace too small");
+  return MOFEM_OK;
+}
+
+// per-item c = d_species * tau and the right-hand side Mass(U + tau f(U, V)) (eq. (93))
+int imex_rhs(const mofem_imex_desc* d, const double* state, int batch, const ImexParts& p, hipStream_t s) {
+  const long long n = (long long)d->op->qs * d->op->qt;
+  const int items = d->n_species * batch;
+  for (int sp = 0; sp < d->n_species; ++sp)
+    if (launch_fill(p.scale + (size_t)sp * batch, d->d[sp] * d->tau, batch, batch, 1, s) != 0)
+      return fail(MOFEM_E_HIP, "imex_step: launch failed");
+  const double* src = state;
+  if (d->kinetics == MOFEM_KIN_DIB) {
+    if (launch_dib_source(state, state + (size_t)batch * n, p.trans, p.trans + (size_t)batch * n, n, n, batch,
+                          d->kin, d->tau, s) != 0)
+      return fail(MOFEM_E_HIP, "imex_step: kinetics launch failed");
+    src = p.trans;
+  }
+  return op_launch(d->mass, src, n, p.rhs, n, items, nullptr, nullptr, nullptr, s);
+}
+}  // namespace
+
+extern "C" int mofem_imex_step(const mofem_imex_desc* d, double* state, long long stride, int batch,
+                               void* workspace, size_t ws_bytes, int* iters_out, void* stream) {
+  clear_error();
+  int rc = imex_check(d, state, stride, batch);
+  if (rc != MOFEM_OK || batch == 0) return rc;
   hipStream_t s = (hipStream_t)stream;
-  size_t need = mofem_imex_workspace_size(d, batch);
+  const size_t need = mofem_imex_workspace_size(d, batch);
   static thread_local void* own_ws = nullptr;
   static thread_local size_t own_bytes = 0;
   if (!workspace) {
-    int rc = ensure_internal_ws(&own_ws, &own_bytes, need, s);
+    rc = ensure_internal_ws(&own_ws, &own_bytes, need, s);
     if (rc) return rc;
     workspace = own_ws;
     ws_bytes = own_bytes;
   } else if (ws_bytes < need) {
     return fail(MOFEM_E_ARG, "imex_step: workspace too small");
   }
-  Carve c(workspace, ws_bytes);
-  double* rhs = c.take<double>((size_t)items * n);
-  double* trans = d->kinetics == MOFEM_KIN_DIB ? c.take<double>((size_t)items * n) : nullptr;
-  double* scale = c.take<double>(items);
-  size_t pcg_need = pcg_bytes(op, d->prec, items, nullptr);
-  void* pcg_ws = c.take<char>(pcg_need);
-  if (!rhs || !scale || !pcg_ws || (d->kinetics == MOFEM_KIN_DIB && !trans))
-    return fail(MOFEM_E_ARG, "imex_step: workspace too small");
-  // per-item c = d_species * tau
-  for (int sp = 0; sp < d->n_species; ++sp)
-    if (launch_fill(scale + (size_t)sp * batch, d->d[sp] * d->tau, batch, batch, 1, s) != 0)
-      return fail(MOFEM_E_HIP, "imex_step: launch failed");
-  // right-hand side: Mass(U + tau f(U, V))  (eq. (93))
-  const double* src = state;
-  long long src_stride = stride;
-  if (d->kinetics == MOFEM_KIN_DIB) {
-    if (launch_dib_source(state, state + (size_t)batch * n, trans, trans + (size_t)batch * n, n, n, batch,
-                          d->kin, d->tau, s) != 0)
-      return fail(MOFEM_E_HIP, "imex_step: kinetics launch failed");
-    src = trans;
-    src_stride = n;
-  }
-  int rc = op_launch(mass, src, src_stride, rhs, n, items, nullptr, nullptr, nullptr, s);
+  ImexParts p;
+  rc = imex_carve(d, batch, workspace, ws_bytes, &p);
   if (rc) return rc;
-  unsigned fl = d->flags & ~MOFEM_PCG_ZERO_GUESS;
+  rc = imex_rhs(d, state, batch, p, s);
+  if (rc) return rc;
+  const int items = d->n_species * batch;
   std::vector<double> relres(items);
   // the state is both the guess and the solution; all species in one batched solve
-  rc = mofem_pcg_solve(op, d->prec, rhs, state, n, items, scale, d->tol, d->maxit, fl, pcg_ws, pcg_need,
-                       iters_out, relres.data(), stream);
-  return rc;
+  return mofem_pcg_solve(d->op, d->prec, p.rhs, state, stride, items, p.scale, d->tol, d->maxit,
+                         d->flags & ~MOFEM_PCG_ZERO_GUESS, p.pcg_ws, p.pcg_need, iters_out, relres.data(), stream);
+}
+
+// ---- the IMEX step as a replayable HIP graph ---------------------------------
+struct mofem_imex_graph_s {
+  hipGraphExec_t exec = nullptr;
+  int items = 0;
+  int* d_int = nullptr;        // [4][items]: last iters, last status, max iters, first error
+  double* d_relres = nullptr;  // [items]: relative residual of the last step
+};
+
+namespace {
+// accumulate a step's per-item results over replays: max iterations, first error
+__global__ void imex_accum_kernel(const int* __restrict__ iters, const int* __restrict__ status,
+                                  int* __restrict__ max_iters, int* __restrict__ first_err, int items) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= items) return;
+  if (iters[b] > max_iters[b]) max_iters[b] = iters[b];
+  if (first_err[b] == 0 && status[b] != 0) first_err[b] = status[b];
+}
+__global__ void fill_int_kernel(int* __restrict__ x, int v, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+}  // namespace
+
+extern "C" int mofem_imex_graph_create(const mofem_imex_desc* d, double* state, long long stride, int batch,
+                                       void* workspace, size_t ws_bytes, int iters_per_step,
+                                       mofem_imex_graph_t* out, void* stream) {
+  clear_error();
+  if (!out) return fail(MOFEM_E_ARG, "imex_graph_create: NULL output");
+  *out = nullptr;
+  int rc = imex_check(d, state, stride, batch);
+  if (rc != MOFEM_OK) return rc;
+  if (batch < 1 || iters_per_step < 1) return fail(MOFEM_E_ARG, "imex_graph_create: batch and iters_per_step >= 1");
+  if (!workspace || ws_bytes < mofem_imex_workspace_size(d, batch))
+    return fail(MOFEM_E_ARG, "imex_graph_create: workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  if (!s) return fail(MOFEM_E_ARG, "imex_graph_create: capture needs a created (non-default) stream");
+  ImexParts p;
+  rc = imex_carve(d, batch, workspace, ws_bytes, &p);
+  if (rc) return rc;
+  auto* g = new mofem_imex_graph_s();
+  g->items = d->n_species * batch;
+  if (dev_alloc(&g->d_int, (size_t)4 * g->items) != MOFEM_OK || dev_alloc(&g->d_relres, (size_t)g->items) != MOFEM_OK) {
+    mofem_imex_graph_destroy(g);
+    return fail(MOFEM_E_NOMEM, "imex_graph_create: result arrays");
+  }
+  hipLaunchKernelGGL(fill_int_kernel, dim3((4 * g->items + 255) / 256), dim3(256), 0, s, g->d_int, 0, 4 * g->items);
+  HIP_TRY(hipStreamSynchronize(s));
+  // capture one step: right-hand side, then exactly iters_per_step masked PCG
+  // iterations (no host synchronisation anywhere), then the result accumulation
+  TraceCapture no_trace;
+  hipGraph_t graph = nullptr;
+  HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  int* it_last = g->d_int;
+  int* st_last = g->d_int + g->items;
+  rc = imex_rhs(d, state, batch, p, s);
+  if (rc == MOFEM_OK)
+    rc = mofem_pcg_solve_async(d->op, d->prec, p.rhs, state, stride, g->items, p.scale, d->tol, iters_per_step,
+                               d->flags & ~MOFEM_PCG_ZERO_GUESS, p.pcg_ws, p.pcg_need, it_last, st_last, g->d_relres,
+                               stream);
+  if (rc == MOFEM_OK)
+    hipLaunchKernelGGL(imex_accum_kernel, dim3((g->items + 63) / 64), dim3(64), 0, s, it_last, st_last,
+                       g->d_int + 2 * g->items, g->d_int + 3 * g->items, g->items);
+  hipError_t e = hipStreamEndCapture(s, &graph);
+  if (rc != MOFEM_OK || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    mofem_imex_graph_destroy(g);
+    return rc != MOFEM_OK ? rc : fail(MOFEM_E_HIP, std::string("imex_graph_create: capture: ") + hipGetErrorString(e));
+  }
+  e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    mofem_imex_graph_destroy(g);
+    return fail(MOFEM_E_HIP, std::string("imex_graph_create: instantiate: ") + hipGetErrorString(e));
+  }
+  *out = g;
+  return MOFEM_OK;
+}
+
+extern "C" int mofem_imex_graph_launch(mofem_imex_graph_t g, int nsteps, void* stream) {
+  clear_error();
+  if (!g || nsteps < 0) return fail(MOFEM_E_ARG, "imex_graph_launch: bad argument");
+  for (int i = 0; i < nsteps; ++i) HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return MOFEM_OK;
+}
+
+extern "C" int mofem_imex_graph_result(mofem_imex_graph_t g, int* max_iters, int* status, double* relres,
+                                       void* stream) {
+  clear_error();
+  if (!g) return fail(MOFEM_E_ARG, "imex_graph_result: NULL handle");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<int> h((size_t)4 * g->items);
+  std::vector<double> r(g->items);
+  HIP_TRY(hipMemcpyAsync(h.data(), g->d_int, h.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(r.data(), g->d_relres, r.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  int result = MOFEM_OK;
+  for (int b = 0; b < g->items; ++b) {
+    if (max_iters) max_iters[b] = h[(size_t)2 * g->items + b];
+    const int st = h[(size_t)3 * g->items + b];
+    if (status) status[b] = st;
+    if (relres) relres[b] = r[b];
+    if (st != MOFEM_OK && result == MOFEM_OK) result = st;
+  }
+  // start a new accumulation
+  hipLaunchKernelGGL(fill_int_kernel, dim3((2 * g->items + 255) / 256), dim3(256), 0, s, g->d_int + 2 * g->items, 0,
+                     2 * g->items);
+  HIP_TRY(hipGetLastError());
+  return result;
+}
+
+extern "C" int mofem_imex_graph_destroy(mofem_imex_graph_t g) {
+  if (!g) return MOFEM_OK;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->d_int) (void)hipFree(g->d_int);
+  if (g->d_relres) (void)hipFree(g->d_relres);
+  delete g;
+  return MOFEM_OK;
 }
 
 // ============================================================================

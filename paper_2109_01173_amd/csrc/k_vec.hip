@@ -241,7 +241,7 @@ __global__ void beta_kernel(const double* __restrict__ rz_new, double* __restric
 // target: confirm on the true residual), restart (the true residual did
 // not: continue from it with a fresh direction), status, iteration count.
 // The host only reads `active` every few iterations.
-constexpr int kStatusOk = 0, kStatusBreakdown = -4, kStatusNotFinite = -7;
+constexpr int kStatusOk = 0, kStatusBreakdown = -4, kStatusMaxit = -5, kStatusNotFinite = -7;
 
 __global__ void pcg_init_kernel(const double* __restrict__ rhs2, const double* __restrict__ rr,
                                 double* __restrict__ target2, int* __restrict__ active, int* __restrict__ claim,
@@ -294,6 +294,23 @@ __global__ void pcg_confirm_kernel(const double* __restrict__ tr, const double* 
   if (!claim[b]) return;
   if (tr[b] <= target2[b]) active[b] = 0;
   else restart[b] = 1;  // the recurrence drifted: continue from the true residual
+}
+
+// per-item result of a solve: iterations, status (MAXIT if the final true
+// residual misses the item's target), relative true residual
+__global__ void pcg_final_kernel(const double* __restrict__ tr, const double* __restrict__ rhs2,
+                                 const double* __restrict__ target2, const int* __restrict__ status,
+                                 const int* __restrict__ iters, int* __restrict__ iters_out,
+                                 int* __restrict__ status_out, double* __restrict__ relres_out, int batch) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  const double t = tr[b], f = rhs2[b];
+  int st = status[b];
+  if (st == kStatusOk && !(t <= target2[b] || (f == 0.0 && t == 0.0))) st = kStatusMaxit;
+  const int it = iters[b];
+  iters_out[b] = it;
+  status_out[b] = st;
+  relres_out[b] = f > 0.0 ? sqrt(t / f) : sqrt(t);
 }
 
 // beta of the next direction; zero (a fresh direction) for restarted items
@@ -463,6 +480,13 @@ int launch_pcg_confirm(const double* tr, const double* target2, int* active, int
                        hipStream_t s) {
   hipLaunchKernelGGL(pcg_confirm_kernel, dim3((batch + 63) / 64), dim3(64), 0, s, tr, target2, active, claim,
                      restart, batch);
+  CHECK_LAUNCH();
+}
+int launch_pcg_final(const double* tr, const double* rhs2, const double* target2, const int* status,
+                     const int* iters, int* iters_out, int* status_out, double* relres_out, int batch,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(pcg_final_kernel, dim3((batch + 63) / 64), dim3(64), 0, s, tr, rhs2, target2, status, iters,
+                     iters_out, status_out, relres_out, batch);
   CHECK_LAUNCH();
 }
 int launch_beta_restart(const double* rz_new, double* rz_old, const double* zy, const double* alpha, double* beta,

@@ -127,6 +127,9 @@ int launch_pcg_check(const double* qy, const double* rr, const double* target2, 
                      int* status, int* iters, int batch, hipStream_t s);
 int launch_pcg_confirm(const double* tr, const double* target2, int* active, int* claim, int* restart, int batch,
                        hipStream_t s);
+int launch_pcg_final(const double* tr, const double* rhs2, const double* target2, const int* status,
+                     const int* iters, int* iters_out, int* status_out, double* relres_out, int batch,
+                     hipStream_t s);
 int launch_beta_restart(const double* rz_new, double* rz_old, const double* zy, const double* alpha, double* beta,
                         int* restart, int flexible, int batch, const int* active, hipStream_t s);
 int launch_copy_masked(const double* X, double* Y, long long n, long long xs, long long ys, int batch,

@@ -118,6 +118,15 @@ mofem_imex_adjoint_workspace_size = _proto("mofem_imex_adjoint_workspace_size", 
 mofem_imex_adjoint_step = _proto("mofem_imex_adjoint_step", ctypes.c_int,
                                  [ctypes.POINTER(ImexDesc), _vp, _vp, _vp, _vp, _vp, _ll, ctypes.c_int, _vp, _sz,
                                   _vp, _vp])
+mofem_pcg_solve_async = _proto("mofem_pcg_solve_async", ctypes.c_int,
+                               [_vp, _vp, _vp, _vp, _ll, ctypes.c_int, _vp, ctypes.c_double, ctypes.c_int,
+                                ctypes.c_uint, _vp, _sz, _vp, _vp, _vp, _vp])
+mofem_imex_graph_create = _proto("mofem_imex_graph_create", ctypes.c_int,
+                                 [ctypes.POINTER(ImexDesc), _vp, _ll, ctypes.c_int, _vp, _sz, ctypes.c_int,
+                                  ctypes.POINTER(_vp), _vp])
+mofem_imex_graph_launch = _proto("mofem_imex_graph_launch", ctypes.c_int, [_vp, ctypes.c_int, _vp])
+mofem_imex_graph_result = _proto("mofem_imex_graph_result", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp])
+mofem_imex_graph_destroy = _proto("mofem_imex_graph_destroy", ctypes.c_int, [_vp])
 mofem_trace_enable = _proto("mofem_trace_enable", ctypes.c_int, [ctypes.c_int])
 mofem_trace_read = _proto("mofem_trace_read", ctypes.c_int,
                           [ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_longlong), _dp])
@@ -128,8 +137,9 @@ EXPORTS = ["mofem_version", "mofem_last_error", "mofem_assemble_1d", "mofem_gene
            "mofem_prec_set_precision", "mofem_prec_eigenvalues", "mofem_prec_workspace_size",
            "mofem_prec_apply", "mofem_pcg_workspace_size", "mofem_pcg_solve",
            "mofem_imex_workspace_size", "mofem_imex_step", "mofem_dot_accumulate",
-           "mofem_imex_adjoint_workspace_size", "mofem_imex_adjoint_step", "mofem_trace_enable",
-           "mofem_trace_read"]
+           "mofem_imex_adjoint_workspace_size", "mofem_imex_adjoint_step", "mofem_pcg_solve_async",
+           "mofem_imex_graph_create", "mofem_imex_graph_launch", "mofem_imex_graph_result",
+           "mofem_imex_graph_destroy", "mofem_trace_enable", "mofem_trace_read"]
 
 
 class MofemError(RuntimeError):
@@ -344,6 +354,66 @@ def pcg_solve(op, prec, rhs, U, tol=1e-10, maxit=500, flags=0, item_scale=None, 
     if raise_on_error:
         _check(rc, "mofem_pcg_solve")
     return iters, relres, rc
+
+
+def pcg_solve_async(op, prec, rhs, U, workspace, iters, status, relres, tol=1e-10, maxit=100, flags=0,
+                    item_scale=None, stream=None):
+    """Queue a solve of exactly `maxit` masked iterations with no host
+    synchronisation; iters/status (int32) and relres (float64) are device
+    tensors [batch] that receive the per-item results."""
+    batch = rhs.shape[0]
+    rc = mofem_pcg_solve_async(op.handle, prec.handle, _dptr(rhs), _dptr(U), op.shape[0] * op.shape[1], batch,
+                               _dptr(item_scale), tol, maxit, flags, _dptr(workspace), workspace.numel(),
+                               _dptr(iters), _dptr(status), _dptr(relres), _stream(stream))
+    _check(rc, "mofem_pcg_solve_async")
+
+
+class ImexGraph:
+    """One IMEX step captured as a HIP graph over a fixed state tensor
+    (see mofem_imex_graph_create).  Runs on its own stream, ordered after
+    and before the caller's current stream."""
+
+    def __init__(self, stepper, state, batch, iters_per_step):
+        torch = _torch()
+        self.state, self.batch = state, batch
+        self.workspace = stepper.workspace(batch, state.device)
+        self.stream = torch.cuda.Stream(device=state.device)
+        self._refs = stepper
+        h = _vp()
+        cur = torch.cuda.current_stream(state.device)
+        self.stream.wait_stream(cur)
+        q_s, q_t = state.shape[1], state.shape[2]
+        rc = mofem_imex_graph_create(ctypes.byref(stepper.desc), _dptr(state), q_s * q_t, batch,
+                                     _dptr(self.workspace), self.workspace.numel(), iters_per_step,
+                                     ctypes.byref(h), ctypes.c_void_p(self.stream.cuda_stream))
+        _check(rc, "mofem_imex_graph_create")
+        self.handle = h
+        cur.wait_stream(self.stream)
+
+    def launch(self, nsteps=1):
+        torch = _torch()
+        cur = torch.cuda.current_stream(self.state.device)
+        self.stream.wait_stream(cur)
+        _check(mofem_imex_graph_launch(self.handle, nsteps, ctypes.c_void_p(self.stream.cuda_stream)),
+               "mofem_imex_graph_launch")
+        cur.wait_stream(self.stream)
+
+    def result(self, raise_on_error=True):
+        n = self.state.shape[0]
+        iters = np.zeros(n, dtype=np.int32)
+        status = np.zeros(n, dtype=np.int32)
+        relres = np.zeros(n)
+        rc = mofem_imex_graph_result(self.handle, _hptr(iters), _hptr(status), _hptr(relres),
+                                     ctypes.c_void_p(self.stream.cuda_stream))
+        if raise_on_error:
+            _check(rc, "mofem_imex_graph_result")
+        return iters, status, relres
+
+    def __del__(self, _destroy=mofem_imex_graph_destroy):
+        if getattr(self, "handle", None):
+            self.stream.synchronize()
+            _destroy(self.handle)
+            self.handle = None
 
 
 def dot_accumulate(X, Y, out, alpha=1.0, beta=0.0, stream=None):

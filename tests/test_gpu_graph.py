@@ -1,0 +1,102 @@
+"""GPU tests of the host-synchronisation-free paths: MO-PCG queued with a
+fixed iteration budget (mofem_pcg_solve_async) on several streams, and the
+IMEX step captured as a HIP graph and replayed (mofem_imex_graph_*).
+
+The masked iterations after convergence change nothing, so both must
+reproduce the synchronous path's states and iteration counts (the kernels
+and their order are the same).  Graph replays are checked one by one, with
+unrelated eager work and synchronisations between them."""
+import numpy as np
+import pytest
+
+from gpu_cases import gpu_xnormal, rel, to_dev, to_host
+from workloads import dib_initial, dib_params, heat_initial
+
+pytestmark = pytest.mark.gpu
+
+
+def _kin(p):
+    return [p["rho"], p["A1"], p["A2"], p["B"], p["C"], p["D"], p["alpha"], p["gamma"], p["k2"], p["k3"]]
+
+
+def test_imex_graph_replays_match_eager_dib():
+    import torch
+    from paper_2109_01173_amd import mofem as mf
+    from paper_2109_01173_amd.problems import Rect
+    p = dib_params()
+    G = Rect(1, 24, "neumann", length=20.0, lumped=True, imex=True)
+    eta, theta = dib_initial(G.q, seed=7, amp=1e-2)
+    s_eager = to_dev(np.stack([eta, theta]))
+    s_graph = s_eager.clone()
+    mk = lambda: mf.Imex(G.op, G.prec, G.mass, 1e-2, [1.0, p["d_theta"]], kinetics=mf.KIN_DIB, kin=_kin(p),
+                         tol=1e-12, maxit=20)
+    eager, graphed = mk(), mk()
+    g = mf.ImexGraph(graphed, s_graph, 1, iters_per_step=4)
+    noise = to_dev(np.random.default_rng(0).standard_normal((2, G.q, G.q)))
+    for step in range(5):
+        its = eager.step(s_eager, 1)
+        g.launch(1)
+        _ = G.op.apply(noise)          # unrelated eager work between replays
+        torch.cuda.synchronize()
+        assert rel(to_host(s_graph), to_host(s_eager)) <= 1e-14, step
+        max_its, status, relres = g.result()
+        assert np.all(status == 0) and np.all(max_its == its) and np.all(relres < 1e-12)
+
+
+def test_imex_graph_heat_and_budget_too_small():
+    import torch
+    from paper_2109_01173_amd import mofem as mf
+    G = gpu_xnormal(2, 16, "neumann", 0.0, imex=True)
+    U0 = heat_initial(G.q, seed=42)
+    s_eager, s_graph = to_dev(U0[None]), to_dev(U0[None])
+    eager = mf.Imex(G.op, G.prec, G.mass, 1e-3, [0.1], tol=1e-12, maxit=60)
+    g = mf.ImexGraph(mf.Imex(G.op, G.prec, G.mass, 1e-3, [0.1], tol=1e-12, maxit=60), s_graph, 1, iters_per_step=40)
+    its = []
+    for _ in range(3):
+        its.append(int(eager.step(s_eager, 1)[0]))
+    g.launch(3)
+    torch.cuda.synchronize()
+    assert rel(to_host(s_graph), to_host(s_eager)) <= 1e-14
+    max_its, status, _ = g.result()
+    assert status[0] == 0 and max_its[0] == max(its)
+    # a budget below the iteration count is reported as MAXIT for that step
+    g2 = mf.ImexGraph(mf.Imex(G.op, G.prec, G.mass, 1e-3, [0.1], tol=1e-12, maxit=60), to_dev(U0[None]), 1,
+                      iters_per_step=2)
+    g2.launch(1)
+    with pytest.raises(mf.MofemError):
+        g2.result()
+    _, status, _ = g2.result(raise_on_error=False)  # the accumulation restarted: nothing since
+    assert status[0] == 0
+
+
+def test_pcg_async_uneven_shapes_on_two_streams():
+    import torch
+    from paper_2109_01173_amd import mofem as mf
+    cases = [gpu_xnormal(2, 20, "dirichlet", 1.0), gpu_xnormal(3, 11, "neumann", 1.0)]
+    rng = np.random.default_rng(12)
+    runs = []
+    for G in cases:
+        B = 3
+        R = to_dev(rng.standard_normal((B, G.q, G.q)))
+        U_sync = torch.empty_like(R)
+        its_sync, rr_sync, _ = mf.pcg_solve(G.op, G.prec, R, U_sync, tol=1e-11, maxit=80, flags=mf.PCG_ZERO_GUESS)
+        runs.append((G, R, U_sync, its_sync, rr_sync))
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = []
+    for (G, R, _, its_sync, _), st in zip(runs, streams):
+        B = R.shape[0]
+        U = torch.empty_like(R)
+        ws = mf.pcg_workspace(G.op, G.prec, B)
+        iters = torch.empty(B, dtype=torch.int32, device="cuda")
+        status = torch.empty(B, dtype=torch.int32, device="cuda")
+        relres = torch.empty(B, dtype=torch.float64, device="cuda")
+        st.wait_stream(torch.cuda.current_stream())
+        mf.pcg_solve_async(G.op, G.prec, R, U, ws, iters, status, relres, tol=1e-11, maxit=int(its_sync.max()) + 3,
+                           flags=mf.PCG_ZERO_GUESS, stream=st)
+        outs.append((U, iters, status, relres, ws))
+    torch.cuda.synchronize()
+    for (G, R, U_sync, its_sync, rr_sync), (U, iters, status, relres, _) in zip(runs, outs):
+        assert np.all(to_host(status) == 0)
+        assert np.array_equal(to_host(iters), its_sync)
+        assert rel(to_host(U), to_host(U_sync)) <= 1e-14
+        assert np.allclose(to_host(relres), rr_sync, rtol=1e-12, atol=0)
