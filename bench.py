@@ -125,12 +125,28 @@ def imex_legs(mf, torch, np, nsteps):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
     mass1 = float(G.mass.apply(st).sum())
+    # the same steps replayed from a HIP graph (iteration budget: the most seen + 2)
+    budget = max(its) + 2
+    g = mf.ImexGraph(mf.Imex(G.op, G.prec, G.mass, 1e-3, [0.1], tol=1e-10, maxit=200, flags=mf.PCG_FLEXIBLE),
+                     st, 1, iters_per_step=budget)
+    g.launch(1)
+    g.result()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    g.launch(nsteps)
+    torch.cuda.synchronize()
+    dtg = time.perf_counter() - t
+    gi, _, _ = g.result()
     out["imex_heat_p4"] = {"workload": "heat P4 x-normal, Neumann, n=2049, d=0.1, tau=1e-3, rel 1e-10 per step",
                            "steps_per_s": round(nsteps / dt, 3), "steps": nsteps,
                            "iterations_per_step": round(float(np.mean(its)), 2),
+                           "graph_steps_per_s": round(nsteps / dtg, 3), "graph_iteration_budget": budget,
+                           "graph_max_iterations": int(gi.max()),
                            "transforms": "bf16x3", "setup_s": round(setup, 2),
                            "mass_drift_rel": abs(mass1 - mass0) / abs(mass0)}
-    log("imex heat P4: %.2f steps/s, %.1f iterations/step" % (nsteps / dt, np.mean(its)))
+    log("imex heat P4: %.2f steps/s, %.1f iterations/step; graph replay %.2f steps/s"
+        % (nsteps / dt, np.mean(its), nsteps / dtg))
+    del g
     del G, st, ws, stepper
     # DIB: rectangle preset (exact single-term operator), FP64 transforms
     p = dib_params()
@@ -150,12 +166,26 @@ def imex_legs(mf, torch, np, nsteps):
     its = [stepper.step(st, 1, workspace=ws).max() for _ in range(n4)]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
+    g = mf.ImexGraph(mf.Imex(G.op, G.prec, G.mass, 1e-2, [1.0, p["d_theta"]], kinetics=mf.KIN_DIB, kin=kin,
+                             tol=1e-10, maxit=50), st, 1, iters_per_step=2)
+    g.launch(1)
+    g.result()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    g.launch(n4)
+    torch.cuda.synchronize()
+    dtg = time.perf_counter() - t
+    gi, _, _ = g.result()
     out["imex_dib_p1"] = {"workload": "DIB lumped P1 rectangle [0,20]^2, Neumann, n=1025, tau=1e-2, "
                                       "two species, rel 1e-10 per step",
                           "steps_per_s": round(n4 / dt, 2), "steps": n4,
-                          "iterations_per_step": round(float(np.mean(its)), 2), "transforms": "f64",
+                          "iterations_per_step": round(float(np.mean(its)), 2),
+                          "graph_steps_per_s": round(n4 / dtg, 2), "graph_iteration_budget": 2,
+                          "graph_max_iterations": int(gi.max()), "transforms": "f64",
                           "setup_s": round(setup, 2)}
-    log("imex DIB P1: %.1f steps/s, %.1f iterations/step" % (n4 / dt, np.mean(its)))
+    log("imex DIB P1: %.1f steps/s, %.1f iterations/step; graph replay %.1f steps/s"
+        % (n4 / dt, np.mean(its), n4 / dtg))
+    del g
     return out
 
 

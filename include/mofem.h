@@ -235,6 +235,18 @@ int mofem_prec_apply(mofem_prec_t prec, const double* R, double* Z, long long st
                      int batch, const double* item_scale, void* workspace,
                      size_t ws_bytes, void* stream);
 
+/* Autotuner of the transforms' block tile (128 x 128 or 64 x 64) for this
+   handle's shapes, its current precision and `batch`: times one application
+   with each (on scratch buffers it allocates and frees) and keeps the faster
+   choice in the handle for later applications with that precision and batch
+   size (otherwise: 128 unless its grid gives fewer than two blocks per
+   compute unit).  Synchronises `stream`.  tile_out: host, may be NULL.
+   Errors: MOFEM_E_ARG, MOFEM_E_NOMEM, MOFEM_E_HIP. */
+int mofem_prec_tune(mofem_prec_t prec, int batch, int* tile_out, void* stream);
+/* Set that choice directly (tile 64 or 128) for the current precision and
+   `batch`.  Errors: MOFEM_E_ARG. */
+int mofem_prec_set_tile(mofem_prec_t prec, int batch, int tile);
+
 /* ------------------------------------------------------------------------ */
 /* a5/a6/a8. MO-PCG (Sec. 5, eqs. (77)-(78)) on a batch of equations        */
 /*           L_b(U_b) = Rhs_b                                               */

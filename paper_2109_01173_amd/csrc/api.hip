@@ -384,6 +384,7 @@ struct mofem_prec_s {
   unsigned short *Vs_h = nullptr, *Vs_l = nullptr, *VsT_h = nullptr, *VsT_l = nullptr;
   unsigned short *Vt_h = nullptr, *Vt_l = nullptr, *VtT_h = nullptr, *VtT_l = nullptr;
   float *Vs_f = nullptr, *VsT_f = nullptr, *Vt_f = nullptr, *VtT_f = nullptr;  // FP32 padded
+  std::vector<std::pair<long long, int>> tuned;  // (precision << 32 | batch) -> block tile
   void* ws = nullptr;
   size_t ws_bytes = 0;
 };
@@ -573,6 +574,17 @@ PrecInput prec_input(mofem_prec_t p, void* ws, size_t ws_bytes, int batch) {
   return in;
 }
 
+// Block tile of the transforms for this batch: the tuned choice if
+// mofem_prec_tune measured one, else 128 unless the 128-tile grid would not
+// give every CU two blocks.
+int prec_tile(mofem_prec_t p, int batch) {
+  const long long key = ((long long)p->precision << 32) | (unsigned)batch;
+  for (auto& kv : p->tuned)
+    if (kv.first == key) return kv.second;
+  const long long blocks128 = (long long)(p->ps / 128) * (p->pt / 128) * batch;
+  return blocks128 < 2 * 256 ? 64 : 128;
+}
+
 // input_ready: the padded operand of R is already in the workspace (written
 // by the fused CG update).
 int prec_launch(mofem_prec_t p, const double* R, double* Z, long long stride, int batch,
@@ -600,9 +612,10 @@ int prec_launch(mofem_prec_t p, const double* R, double* Z, long long stride, in
                    : prec == GEMM_BF16   ? MOFEM_TRACE_GEMM_BF16
                    : prec == GEMM_BF16X2 ? MOFEM_TRACE_GEMM_BF16X2
                                          : MOFEM_TRACE_GEMM_BF16X3;
+  const int tile = prec_tile(p, batch);
   auto gemm = [&](int omode) -> int {
     TraceScope trace(tcls, items_done, s);
-    return launch_gemm(g, prec, omode, batch, s);
+    return launch_gemm(g, prec, omode, batch, tile, s);
   };
   Carve c(ws, ws_bytes);
   if (prec == GEMM_F64) {
@@ -741,6 +754,69 @@ extern "C" int mofem_prec_apply(mofem_prec_t p, const double* R, double* Z, long
     return fail(MOFEM_E_ARG, "prec_apply: workspace too small");
   }
   return prec_launch(p, R, Z, stride, batch, item_scale, workspace, ws_bytes, nullptr, s);
+}
+
+extern "C" int mofem_prec_set_tile(mofem_prec_t p, int batch, int tile) {
+  clear_error();
+  if (!p || batch < 1 || (tile != 64 && tile != 128)) return fail(MOFEM_E_ARG, "prec_set_tile: bad argument");
+  const long long key = ((long long)p->precision << 32) | (unsigned)batch;
+  auto it = std::find_if(p->tuned.begin(), p->tuned.end(), [&](auto& kv) { return kv.first == key; });
+  if (it == p->tuned.end()) p->tuned.push_back({key, tile});
+  else it->second = tile;
+  return MOFEM_OK;
+}
+
+// Autotuner: time one preconditioner application per block tile on the
+// handle's shapes and this batch (zero input; the cost does not depend on
+// the values) and keep the faster for (precision, batch).
+extern "C" int mofem_prec_tune(mofem_prec_t p, int batch, int* tile_out, void* stream) {
+  clear_error();
+  if (!p || batch < 1) return fail(MOFEM_E_ARG, "prec_tune: bad argument");
+  hipStream_t s = (hipStream_t)stream;
+  const long long n = (long long)p->qs * p->qt;
+  double *R = nullptr, *Z = nullptr;
+  char* ws = nullptr;
+  const size_t wsb = mofem_prec_workspace_size(p, batch);
+  int rc = dev_alloc(&R, (size_t)n * batch);
+  if (!rc) rc = dev_alloc(&Z, (size_t)n * batch);
+  if (!rc) rc = dev_alloc(&ws, wsb);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  float best = 1e30f;
+  int best_tile = 128;
+  const long long key = ((long long)p->precision << 32) | (unsigned)batch;
+  if (!rc && launch_fill(R, 0.0, n, n, batch, s)) rc = fail(MOFEM_E_HIP, "prec_tune: launch failed");
+  if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    rc = fail(MOFEM_E_HIP, "prec_tune: events");
+  for (int tile : {128, 64}) {
+    if (rc) break;
+    auto it = std::find_if(p->tuned.begin(), p->tuned.end(), [&](auto& kv) { return kv.first == key; });
+    if (it == p->tuned.end()) p->tuned.push_back({key, tile});
+    else it->second = tile;
+    rc = prec_launch(p, R, Z, n, batch, nullptr, ws, wsb, nullptr, s);  // warm-up
+    if (rc) break;
+    if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(MOFEM_E_HIP, "prec_tune: event"); break; }
+    for (int r = 0; r < 3 && !rc; ++r) rc = prec_launch(p, R, Z, n, batch, nullptr, ws, wsb, nullptr, s);
+    float ms = 0.f;
+    if (!rc && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      rc = fail(MOFEM_E_HIP, "prec_tune: timing");
+    if (!rc && ms < best) {
+      best = ms;
+      best_tile = tile;
+    }
+  }
+  if (!rc) {
+    auto it = std::find_if(p->tuned.begin(), p->tuned.end(), [&](auto& kv) { return kv.first == key; });
+    it->second = best_tile;
+    if (tile_out) *tile_out = best_tile;
+  }
+  (void)hipStreamSynchronize(s);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (R) (void)hipFree(R);
+  if (Z) (void)hipFree(Z);
+  if (ws) (void)hipFree(ws);
+  return rc;
 }
 
 // ============================================================================

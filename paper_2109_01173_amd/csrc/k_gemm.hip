@@ -23,7 +23,9 @@
 //                the BF16-rounded basis): two products per transform.
 //   GEMM_BF16    the hi * hi product only.
 // Tiling: 256 threads = 4 waves, block tile 128 x 128, each wave 64 x 64
-// (4 x 4 MFMA tiles of 16 x 16); k tiles of 16 (FP64), 32 (FP32), 64 (BF16).
+// (4 x 4 MFMA tiles of 16 x 16), or 64 x 64 blocks of 32 x 32 wave tiles for
+// grids too small to fill the chip (picked per shape, see mofem_prec_tune);
+// k tiles of 16 (FP64), 32 (FP32), 64 (BF16).
 // Global -> register prefetch of the next k tile overlaps the MFMAs of the
 // current one; in the split products the three passes run one after the
 // other over all 16 accumulators, so back-to-back MFMAs are independent.
@@ -42,7 +44,6 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 typedef unsigned short us8_t __attribute__((ext_vector_type(8)));
 
-constexpr int BM = 128, BN = 128;
 
 __device__ __forceinline__ unsigned short bf16_bits(float x) {
   __bf16 h = (__bf16)x;   // round to nearest even
@@ -65,17 +66,19 @@ __device__ __forceinline__ double eval_D(const GemmArgs& g, int row, int col, do
 // ------------------------------------------------------------------------------
 // FP64
 // ------------------------------------------------------------------------------
-template <int OMODE, int BK = 16>
+template <int OMODE, int BK = 16, int WT = 4>
 __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmArgs g) {
+  constexpr int TB = 32 * WT;  // block tile TB x TB: 4 waves of WT x WT MFMA tiles
   constexpr int LDS_K = BK + 1;
-  __shared__ double As[BM][LDS_K];
-  __shared__ double Bs[BN][LDS_K];
+  __shared__ double As[TB][LDS_K];
+  __shared__ double Bs[TB][LDS_K];
 
   const int b = blockIdx.y;
   if (g.active && !g.active[b]) return;
-  const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
+  // tiles cover the padded extent, so every padded output entry is written
+  const int tm = pad_up(g.M) / TB, tn = pad_up(g.N) / TB;
   const int tile = xcd_tile(blockIdx.x, tm * tn);
-  const int m0 = (tile / tn) * BM, n0 = (tile % tn) * BN;
+  const int m0 = (tile / tn) * TB, n0 = (tile % tn) * TB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
@@ -84,9 +87,10 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmArgs g) {
   const double* __restrict__ A = g.a64 + (size_t)b * g.a_stride;
   const double* __restrict__ B = g.b64 + (size_t)b * g.b_stride;
 
-  // global -> register staging: thread owns row tid/2, k segment (tid%2)*(BK/2)
-  constexpr int HK = BK / 2;
-  const int lrow = tid >> 1, lk = (tid & 1) * HK;
+  // global -> register staging: TPR threads per tile row, HK values each
+  constexpr int TPR = 256 / TB;
+  constexpr int HK = BK / TPR;
+  const int lrow = tid / TPR, lk = (tid % TPR) * HK;
   double ra[HK], rb[HK];
   auto load_tile = [&](int k0) {
     const int arow = m0 + lrow;
@@ -98,11 +102,11 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmArgs g) {
     }
   };
 
-  d4_t acc[4][4];
+  d4_t acc[WT][WT];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < WT; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = (d4_t){0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < WT; ++j) acc[i][j] = (d4_t){0.0, 0.0, 0.0, 0.0};
 
   const int nk = (g.K + BK - 1) / BK;
   load_tile(0);
@@ -117,15 +121,15 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmArgs g) {
     if (kt + 1 < nk) load_tile((kt + 1) * BK);
 #pragma unroll
     for (int ks = 0; ks < BK / 4; ++ks) {
-      double av[4], bv[4];
+      double av[WT], bv[WT];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = As[wm * 64 + i * 16 + (lane & 15)][ks * 4 + (lane >> 4)];
+      for (int i = 0; i < WT; ++i) av[i] = As[wm * (16 * WT) + i * 16 + (lane & 15)][ks * 4 + (lane >> 4)];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = Bs[wn * 64 + j * 16 + (lane & 15)][ks * 4 + (lane >> 4)];
+      for (int j = 0; j < WT; ++j) bv[j] = Bs[wn * (16 * WT) + j * 16 + (lane & 15)][ks * 4 + (lane >> 4)];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < WT; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < WT; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
   }
@@ -135,13 +139,13 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmArgs g) {
   double* __restrict__ C = g.c64 + (size_t)b * g.c_stride;
   const int Mp = pad_up(g.M), Np = pad_up(g.N);
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < WT; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < WT; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * 64 + i * 16 + 4 * r + (lane >> 4);
-        const int col = n0 + wn * 64 + j * 16 + (lane & 15);
+        const int row = m0 + wm * (16 * WT) + i * 16 + 4 * r + (lane >> 4);
+        const int col = n0 + wn * (16 * WT) + j * 16 + (lane & 15);
         const bool in = row < g.M && col < g.N;
         double v = acc[i][j][r] * g.out_scale;
         if (g.divide && in) v /= eval_D(g, row, col, s);
@@ -155,18 +159,20 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmArgs g) {
 // ------------------------------------------------------------------------------
 // FP32: v_mfma_f32_16x16x4_f32, FP32 operands and accumulation
 // ------------------------------------------------------------------------------
-template <int OMODE>
+template <int OMODE, int WT = 4>
 __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g) {
+  constexpr int TB = 32 * WT;  // block tile TB x TB: 4 waves of WT x WT MFMA tiles
   constexpr int BK = 32;
   constexpr int LDS_K = BK + 1;
-  __shared__ float As[BM][LDS_K];
-  __shared__ float Bs[BN][LDS_K];
+  __shared__ float As[TB][LDS_K];
+  __shared__ float Bs[TB][LDS_K];
 
   const int b = blockIdx.y;
   if (g.active && !g.active[b]) return;
-  const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
+  // tiles cover the padded extent, so every padded output entry is written
+  const int tm = pad_up(g.M) / TB, tn = pad_up(g.N) / TB;
   const int tile = xcd_tile(blockIdx.x, tm * tn);
-  const int m0 = (tile / tn) * BM, n0 = (tile % tn) * BN;
+  const int m0 = (tile / tn) * TB, n0 = (tile % tn) * TB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
@@ -174,31 +180,33 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g) {
   const float* __restrict__ A = (const float*)g.a_hi + (size_t)b * g.a_stride;
   const float* __restrict__ B = (const float*)g.b_hi + (size_t)b * g.b_stride;
 
-  // global -> register staging: thread owns row tid/2, k segment (tid%2)*16 (four 16-byte loads)
-  const int lrow = tid >> 1, lk = (tid & 1) * 16;
-  f4_t ra[4], rb[4];
+  // global -> register staging: TPR threads per tile row, NV 16-byte loads each
+  constexpr int TPR = 256 / TB;
+  constexpr int NV = BK / TPR / 4;
+  const int lrow = tid / TPR, lk = (tid % TPR) * (BK / TPR);
+  f4_t ra[NV], rb[NV];
   auto load_tile = [&](int k0) {
     const f4_t* pa = (const f4_t*)(A + (size_t)(m0 + lrow) * Kp + k0 + lk);
     const f4_t* pb = (const f4_t*)(B + (size_t)(n0 + lrow) * Kp + k0 + lk);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
+    for (int v = 0; v < NV; ++v) {
       ra[v] = pa[v];
       rb[v] = pb[v];
     }
   };
 
-  f4_t acc[4][4];
+  f4_t acc[WT][WT];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < WT; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = (f4_t){0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < WT; ++j) acc[i][j] = (f4_t){0.f, 0.f, 0.f, 0.f};
 
   const int nk = (g.K + BK - 1) / BK;
   load_tile(0);
   for (int kt = 0; kt < nk; ++kt) {
     __syncthreads();
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
+    for (int v = 0; v < NV; ++v)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         As[lrow][lk + 4 * v + e] = ra[v][e];
@@ -208,15 +216,15 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g) {
     if (kt + 1 < nk) load_tile((kt + 1) * BK);
 #pragma unroll
     for (int ks = 0; ks < BK / 4; ++ks) {
-      float av[4], bv[4];
+      float av[WT], bv[WT];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = As[wm * 64 + i * 16 + (lane & 15)][ks * 4 + (lane >> 4)];
+      for (int i = 0; i < WT; ++i) av[i] = As[wm * (16 * WT) + i * 16 + (lane & 15)][ks * 4 + (lane >> 4)];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = Bs[wn * 64 + j * 16 + (lane & 15)][ks * 4 + (lane >> 4)];
+      for (int j = 0; j < WT; ++j) bv[j] = Bs[wn * (16 * WT) + j * 16 + (lane & 15)][ks * 4 + (lane >> 4)];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < WT; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < WT; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
   }
@@ -227,13 +235,13 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g) {
   float* __restrict__ C32 = (float*)g.c_hi + (size_t)b * g.c_stride;
   double* __restrict__ C64 = g.c64 + (size_t)b * g.c_stride;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < WT; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < WT; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
-        const int col = n0 + wn * 64 + j * 16 + (lane & 15);
+        const int row = m0 + wm * (16 * WT) + i * 16 + 4 * (lane >> 4) + r;
+        const int col = n0 + wn * (16 * WT) + j * 16 + (lane & 15);
         const bool in = row < g.M && col < g.N;
         double v = (double)acc[i][j][r] * g.out_scale;
         if (g.divide && in) v /= eval_D(g, row, col, s);
@@ -256,28 +264,31 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g) {
 //       BF_X2B  B split, A exact in BF16       A_h B_l + A_h B_h
 enum { BF_HH = 0, BF_X3 = 1, BF_X2A = 2, BF_X2B = 3 };
 
-template <int MODE, int OMODE, int BK = 64, int MINW = 2>
+template <int MODE, int OMODE, int BK = 64, int MINW = 2, int WT = 4>
 __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
+  // block tile TB x TB: 4 waves in 2 x 2, each WT x WT MFMA tiles of 16 x 16
+  constexpr int TB = 32 * WT;
   constexpr int LDS_K = BK + 8;   // padded rows keep 16-byte alignment
   constexpr bool ALO = (MODE == BF_X3 || MODE == BF_X2A);
   constexpr bool BLO = (MODE == BF_X3 || MODE == BF_X2B);
   // One LDS buffer: the operand tiles of the main loop, then (padded output)
   // the staging tile of the epilogue, so the output leaves in whole rows.
-  constexpr int SLD = BN + 8;  // staging row length (272 bytes: 16-byte aligned)
-  constexpr int MAIN = (2 + (ALO ? 1 : 0) + (BLO ? 1 : 0)) * BM * LDS_K;
-  constexpr int STAGE = (OMODE == O_F64_RAW) ? 0 : BM * SLD;
+  constexpr int SLD = TB + 8;  // staging row length (16-byte aligned)
+  constexpr int MAIN = (2 + (ALO ? 1 : 0) + (BLO ? 1 : 0)) * TB * LDS_K;
+  constexpr int STAGE = (OMODE == O_F64_RAW) ? 0 : TB * SLD;
   __shared__ __attribute__((aligned(16))) unsigned short lds[MAIN > STAGE ? MAIN : STAGE];
   typedef unsigned short Row[LDS_K];
   Row* Ah = reinterpret_cast<Row*>(lds);
-  Row* Bh = Ah + BM;
-  Row* Al = Bh + BN;                 // used when ALO
-  Row* Bl = Al + (ALO ? BM : 0);     // used when BLO
+  Row* Bh = Ah + TB;
+  Row* Al = Bh + TB;                 // used when ALO
+  Row* Bl = Al + (ALO ? TB : 0);     // used when BLO
 
   const int b = blockIdx.y;
   if (g.active && !g.active[b]) return;
-  const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
+  // tiles cover the padded extent, so every padded output entry is written
+  const int tm = pad_up(g.M) / TB, tn = pad_up(g.N) / TB;
   const int tile = xcd_tile(blockIdx.x, tm * tn);
-  const int m0 = (tile / tn) * BM, n0 = (tile % tn) * BN;
+  const int m0 = (tile / tn) * TB, n0 = (tile % tn) * TB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
@@ -287,9 +298,10 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
   const unsigned short* __restrict__ Bhg = (const unsigned short*)g.b_hi + (size_t)b * g.b_stride;
   const unsigned short* __restrict__ Blg = (const unsigned short*)g.b_lo + (size_t)b * g.b_stride;
 
-  // staging: thread owns row tid/2 and k segment (tid%2)*32 (32 values)
-  constexpr int NV = BK / 16;  // 16-byte vectors per thread and operand
-  const int lrow = tid >> 1, lk = (tid & 1) * (BK / 2);
+  // staging: TPR threads per tile row, each a k segment of BK / TPR values
+  constexpr int TPR = 256 / TB;
+  constexpr int NV = BK / TPR / 8;  // 16-byte vectors per thread and operand
+  const int lrow = tid / TPR, lk = (tid % TPR) * (BK / TPR);
   us8_t ah[NV], al[NV], bh[NV], bl[NV];
   auto load_tile = [&](int k0) {
     const int arow = m0 + lrow;
@@ -312,11 +324,11 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
     }
   };
 
-  f4_t acc[4][4];
+  f4_t acc[WT][WT];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < WT; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = (f4_t){0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < WT; ++j) acc[i][j] = (f4_t){0.f, 0.f, 0.f, 0.f};
 
   const int nk = (g.K + BK - 1) / BK;
   load_tile(0);
@@ -333,37 +345,37 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
     if (kt + 1 < nk) load_tile((kt + 1) * BK);
 #pragma unroll
     for (int ks = 0; ks < BK / 32; ++ks) {
-      bf8_t fa[4], fb[4], fal[4], fbl[4];
+      bf8_t fa[WT], fb[WT], fal[WT], fbl[WT];
       const int kq = ks * 32 + (lane >> 4) * 8;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        fa[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Ah[wm * 64 + i * 16 + (lane & 15)][kq]);
-        if (ALO) fal[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Al[wm * 64 + i * 16 + (lane & 15)][kq]);
+      for (int i = 0; i < WT; ++i) {
+        fa[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Ah[wm * (16 * WT) + i * 16 + (lane & 15)][kq]);
+        if (ALO) fal[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Al[wm * (16 * WT) + i * 16 + (lane & 15)][kq]);
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        fb[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Bh[wn * 64 + j * 16 + (lane & 15)][kq]);
-        if (BLO) fbl[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Bl[wn * 64 + j * 16 + (lane & 15)][kq]);
+      for (int j = 0; j < WT; ++j) {
+        fb[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Bh[wn * (16 * WT) + j * 16 + (lane & 15)][kq]);
+        if (BLO) fbl[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Bl[wn * (16 * WT) + j * 16 + (lane & 15)][kq]);
       }
       // products outermost: consecutive MFMAs write different accumulators
       if (ALO) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < WT; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
+          for (int j = 0; j < WT; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fal[i], fb[j], acc[i][j], 0, 0, 0);
       }
       if (BLO) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < WT; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
+          for (int j = 0; j < WT; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fbl[j], acc[i][j], 0, 0, 0);
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < WT; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < WT; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
     }
   }
@@ -372,13 +384,13 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
   const double s = g.item_scale ? g.item_scale[b] : 1.0;
   double* __restrict__ C64 = g.c64 + (size_t)b * g.c_stride;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < WT; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < WT; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
-        const int col = n0 + wn * 64 + j * 16 + (lane & 15);
+        const int row = m0 + wm * (16 * WT) + i * 16 + 4 * (lane >> 4) + r;
+        const int col = n0 + wn * (16 * WT) + j * 16 + (lane & 15);
         const bool in = row < g.M && col < g.N;
         double v = (double)acc[i][j][r] * g.out_scale;
         if (g.divide && in) v /= eval_D(g, row, col, s);
@@ -399,11 +411,11 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
     __syncthreads();  // every wave is done with the operand tiles
     for (int pass = 0; pass < (MODE == BF_HH ? 1 : 2); ++pass) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < WT; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int rl = wm * 64 + i * 16 + 4 * (lane >> 4);  // first of 4 consecutive tile rows
-          const int cl = wn * 64 + j * 16 + (lane & 15);
+        for (int j = 0; j < WT; ++j) {
+          const int rl = wm * (16 * WT) + i * 16 + 4 * (lane >> 4);  // first of 4 consecutive tile rows
+          const int cl = wn * (16 * WT) + j * 16 + (lane & 15);
           unsigned short u[4];
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
@@ -422,12 +434,12 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
           }
         }
       __syncthreads();
-      // 128 rows of 128 values = 2048 pieces of 16 bytes, 8 per thread
+      // TB rows of TB values in 16-byte pieces, TB * TB / 2048 per thread
       unsigned short* __restrict__ C = Cg[pass];
 #pragma unroll
-      for (int v = 0; v < 8; ++v) {
+      for (int v = 0; v < TB * TB / 2048; ++v) {
         const int idx = tid + 256 * v;
-        const int sr = idx >> 4, ch = (idx & 15) * 8;
+        const int sr = idx / (TB / 8), ch = (idx % (TB / 8)) * 8;
         const us8_t val = *reinterpret_cast<const us8_t*>(&lds[sr * SLD + ch]);
         const size_t o = (OMODE == O_PAD_T) ? (size_t)(n0 + sr) * Mp + m0 + ch : (size_t)(m0 + sr) * Np + n0 + ch;
         *reinterpret_cast<us8_t*>(C + o) = val;
@@ -437,30 +449,32 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
   }
 }
 
-template <int OMODE>
+template <int OMODE, int WT>
 static void launch_mode(const GemmArgs& g, int prec, int batch, hipStream_t s) {
-  const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
-  dim3 grid(tm * tn, batch);
+  constexpr int TB = 32 * WT;
+  dim3 grid((pad_up(g.M) / TB) * (pad_up(g.N) / TB), batch);
   if (prec == GEMM_F64)
-    hipLaunchKernelGGL((gemm_f64_kernel<OMODE>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_f64_kernel<OMODE, 16, WT>), grid, dim3(256), 0, s, g);
   else if (prec == GEMM_F32)
-    hipLaunchKernelGGL((gemm_f32_kernel<OMODE>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_f32_kernel<OMODE, WT>), grid, dim3(256), 0, s, g);
   else if (prec == GEMM_BF16X3)
-    hipLaunchKernelGGL((gemm_bf16_kernel<BF_X3, OMODE>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_bf16_kernel<BF_X3, OMODE, 64, 2, WT>), grid, dim3(256), 0, s, g);
   else if (prec == GEMM_BF16X2 && g.data_is_a)
-    hipLaunchKernelGGL((gemm_bf16_kernel<BF_X2A, OMODE>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_bf16_kernel<BF_X2A, OMODE, 64, 2, WT>), grid, dim3(256), 0, s, g);
   else if (prec == GEMM_BF16X2)
-    hipLaunchKernelGGL((gemm_bf16_kernel<BF_X2B, OMODE>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_bf16_kernel<BF_X2B, OMODE, 64, 2, WT>), grid, dim3(256), 0, s, g);
   else
-    hipLaunchKernelGGL((gemm_bf16_kernel<BF_HH, OMODE>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_bf16_kernel<BF_HH, OMODE, 64, 2, WT>), grid, dim3(256), 0, s, g);
 }
 
-int launch_gemm(const GemmArgs& g, int prec, int omode, int batch, hipStream_t s) {
+int launch_gemm(const GemmArgs& g, int prec, int omode, int batch, int tile, hipStream_t s) {
   if (prec != GEMM_F64 && prec != GEMM_F32 && prec != GEMM_BF16 && prec != GEMM_BF16X3 && prec != GEMM_BF16X2)
     return -1;
-  if (omode == O_PAD_T) launch_mode<O_PAD_T>(g, prec, batch, s);
-  else if (omode == O_PAD_N) launch_mode<O_PAD_N>(g, prec, batch, s);
-  else if (omode == O_F64_RAW) launch_mode<O_F64_RAW>(g, prec, batch, s);
+  if (tile != 64 && tile != 128) return -1;
+  const bool big = tile == 128;
+  if (omode == O_PAD_T) big ? launch_mode<O_PAD_T, 4>(g, prec, batch, s) : launch_mode<O_PAD_T, 2>(g, prec, batch, s);
+  else if (omode == O_PAD_N) big ? launch_mode<O_PAD_N, 4>(g, prec, batch, s) : launch_mode<O_PAD_N, 2>(g, prec, batch, s);
+  else if (omode == O_F64_RAW) big ? launch_mode<O_F64_RAW, 4>(g, prec, batch, s) : launch_mode<O_F64_RAW, 2>(g, prec, batch, s);
   else return -1;
   return 0;
 }

@@ -71,7 +71,8 @@ struct GemmArgs {
   const int* active;
   int data_is_a;           // GEMM_BF16X2: the split (data) operand is A (else B)
 };
-int launch_gemm(const GemmArgs& g, int prec, int omode, int batch, hipStream_t s);
+// tile: block tile edge, 128 (4 waves of 64 x 64) or 64 (4 waves of 32 x 32)
+int launch_gemm(const GemmArgs& g, int prec, int omode, int batch, int tile, hipStream_t s);
 // raw FP64 items (M x K) -> padded FP64, FP32 or split BF16 operand
 int launch_pad_operand(const double* A, long long a_stride, int M, int K, double* o64, float* o32,
                        unsigned short* ohi, unsigned short* olo, long long o_stride, int split, int batch,

@@ -104,6 +104,8 @@ mofem_prec_eigenvalues = _proto("mofem_prec_eigenvalues", ctypes.c_int, [_vp, _v
 mofem_prec_workspace_size = _proto("mofem_prec_workspace_size", _sz, [_vp, ctypes.c_int])
 mofem_prec_apply = _proto("mofem_prec_apply", ctypes.c_int,
                           [_vp, _vp, _vp, _ll, ctypes.c_int, _vp, _vp, _sz, _vp])
+mofem_prec_tune = _proto("mofem_prec_tune", ctypes.c_int, [_vp, ctypes.c_int, _ip, _vp])
+mofem_prec_set_tile = _proto("mofem_prec_set_tile", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int])
 mofem_pcg_workspace_size = _proto("mofem_pcg_workspace_size", _sz, [_vp, _vp, ctypes.c_int])
 mofem_pcg_solve = _proto("mofem_pcg_solve", ctypes.c_int,
                          [_vp, _vp, _vp, _vp, _ll, ctypes.c_int, _vp, ctypes.c_double, ctypes.c_int,
@@ -135,7 +137,8 @@ EXPORTS = ["mofem_version", "mofem_last_error", "mofem_assemble_1d", "mofem_gene
            "mofem_op_create", "mofem_op_destroy", "mofem_op_shape", "mofem_op_apply",
            "mofem_prec_setup", "mofem_prec_destroy", "mofem_prec_set_coeffs",
            "mofem_prec_set_precision", "mofem_prec_eigenvalues", "mofem_prec_workspace_size",
-           "mofem_prec_apply", "mofem_pcg_workspace_size", "mofem_pcg_solve",
+           "mofem_prec_apply", "mofem_prec_tune", "mofem_prec_set_tile", "mofem_pcg_workspace_size",
+           "mofem_pcg_solve",
            "mofem_imex_workspace_size", "mofem_imex_step", "mofem_dot_accumulate",
            "mofem_imex_adjoint_workspace_size", "mofem_imex_adjoint_step", "mofem_pcg_solve_async",
            "mofem_imex_graph_create", "mofem_imex_graph_launch", "mofem_imex_graph_result",
@@ -306,6 +309,15 @@ class Preconditioner:
 
     def set_coeffs(self, alpha, beta_s, beta_t, delta):
         _check(mofem_prec_set_coeffs(self.handle, alpha, beta_s, beta_t, delta), "mofem_prec_set_coeffs")
+
+    def tune(self, batch, stream=None):
+        """Pick the transforms' block tile for this batch by timing (mofem_prec_tune)."""
+        tile = ctypes.c_int()
+        _check(mofem_prec_tune(self.handle, batch, ctypes.byref(tile), _stream(stream)), "mofem_prec_tune")
+        return tile.value
+
+    def set_tile(self, batch, tile):
+        _check(mofem_prec_set_tile(self.handle, batch, tile), "mofem_prec_set_tile")
 
     def set_precision(self, precision):
         _check(mofem_prec_set_precision(self.handle, precision), "mofem_prec_set_precision")

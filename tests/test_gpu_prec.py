@@ -80,3 +80,21 @@ def test_prec_tiny_and_errors():
     assert rel(to_host(G.prec.apply(to_dev(R)))[0], S.apply(R[0])) < 1e-13
     with pytest.raises(mf.MofemError):
         G.prec.set_precision(99)
+
+
+@pytest.mark.parametrize("precision", ["F64", "F32", "BF16X3", "BF16"])
+def test_block_tiles_agree_and_tuner(precision):
+    """Both block tiles of the transforms compute the same products in the same
+    k order: the results agree to the last bits; the tuner picks one of them."""
+    from paper_2109_01173_amd import mofem as mf
+    G = gpu_xnormal(2, 150, "dirichlet", 1.0)   # q = 299: ragged against 64 and 128
+    G.prec.set_precision(getattr(mf, "PREC_" + precision))
+    R = to_dev(np.random.default_rng(5).standard_normal((2, G.q, G.q)))
+    out = {}
+    for tile in (64, 128):
+        G.prec.set_tile(2, tile)
+        out[tile] = to_host(G.prec.apply(R))
+    assert rel(out[64], out[128]) <= 1e-15
+    assert G.prec.tune(2) in (64, 128)
+    assert rel(to_host(G.prec.apply(R)), out[128]) <= 1e-15
+    G.prec.set_precision(mf.PREC_F64)
