@@ -295,6 +295,34 @@ int mofem_pcg_solve_async(mofem_op_t op, mofem_prec_t prec, const double* Rhs, d
                           size_t ws_bytes, int* iters_dev, int* status_dev,
                           double* relres_dev, void* stream);
 
+/* Independent batched solves of uneven shapes (one group per operator /
+   preconditioner pair), advanced together on one stream each so that the
+   groups overlap on the device; each group stops as in mofem_pcg_solve.
+   Arguments of a group as in mofem_pcg_solve (workspace required). */
+typedef struct {
+  mofem_op_t op;
+  mofem_prec_t prec;
+  const double* rhs;
+  double* u;
+  long long stride;
+  int batch;
+  const double* item_scale;
+  double tol;
+  int maxit;
+  unsigned flags;
+  void* workspace;
+  size_t ws_bytes;
+  int* iters_out;       /* host [batch] or NULL */
+  double* relres_out;   /* host [batch] or NULL */
+} mofem_pcg_group;
+/*   streams     [n_groups] created streams (may repeat; groups on one stream
+                 serialise).
+     status_out  host [n_groups] or NULL: the first error of each group.
+   Returns the first error over all groups (as mofem_pcg_solve).
+   Synchronises every stream once at the end. */
+int mofem_pcg_solve_many(int n_groups, const mofem_pcg_group* groups, void* const* streams,
+                         int* status_out);
+
 /* ------------------------------------------------------------------------ */
 /* a7. IMEX Euler step (Sec. 6, eqs. (87)-(96); DIB kinetics Sec. 7)        */
 /* ------------------------------------------------------------------------ */

@@ -1128,6 +1128,128 @@ extern "C" int mofem_pcg_solve(mofem_op_t op, mofem_prec_t prec, const double* R
   return status_error(result);
 }
 
+// Several independent batched solves (uneven shapes, each its own operator,
+// preconditioner and stream) advanced together: each group's iteration is
+// queued on its stream in turn, so the groups overlap on the device, and
+// each group's flags are read one iteration behind, as in mofem_pcg_solve.
+extern "C" int mofem_pcg_solve_many(int n_groups, const mofem_pcg_group* groups, void* const* streams,
+                                    int* status_out) {
+  clear_error();
+  if (n_groups < 0 || (n_groups > 0 && (!groups || !streams))) return fail(MOFEM_E_ARG, "pcg_solve_many: bad argument");
+  std::vector<PcgRun> runs(n_groups);
+  std::vector<int> live(n_groups, 0);
+  std::vector<hipEvent_t> ev(2 * (size_t)n_groups, nullptr);
+  struct Res {
+    int *it = nullptr, *st = nullptr;
+    double* rr = nullptr;
+  };
+  std::vector<Res> res(n_groups);
+  int rc = MOFEM_OK;
+  auto cleanup = [&]() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    for (auto& r : res) {
+      if (r.it) (void)hipHostFree(r.it);
+      if (r.rr) (void)hipHostFree(r.rr);
+    }
+  };
+  for (int gi = 0; gi < n_groups && !rc; ++gi) {
+    const mofem_pcg_group& G = groups[gi];
+    hipStream_t s = (hipStream_t)streams[gi];
+    rc = pcg_prepare(runs[gi], G.op, G.prec, G.rhs, G.u, G.stride, G.batch, G.item_scale, G.tol, G.maxit, G.flags,
+                     G.workspace, G.ws_bytes, s);
+    if (rc || G.batch == 0) continue;
+    if (hipHostMalloc((void**)&res[gi].it, sizeof(int) * 2 * (size_t)G.batch) != hipSuccess ||
+        hipHostMalloc((void**)&res[gi].rr, sizeof(double) * (size_t)G.batch) != hipSuccess ||
+        hipEventCreateWithFlags(&ev[2 * gi], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ev[2 * gi + 1], hipEventDisableTiming) != hipSuccess) {
+      rc = fail(MOFEM_E_NOMEM, "pcg_solve_many: host buffers");
+      break;
+    }
+    res[gi].st = res[gi].it + G.batch;
+    rc = runs[gi].begin();
+    live[gi] = G.maxit > 0 ? 1 : 0;
+  }
+  if (rc) {
+    cleanup();
+    return rc;
+  }
+  // flags in pinned memory: two slots (alternate iterations) per group
+  std::vector<int*> hflag(2 * (size_t)n_groups, nullptr);
+  for (int gi = 0; gi < n_groups; ++gi)
+    if (groups[gi].batch > 0 && hipHostMalloc((void**)&hflag[2 * gi], sizeof(int) * 2 * (size_t)groups[gi].batch) != hipSuccess)
+      rc = fail(MOFEM_E_NOMEM, "pcg_solve_many: host buffers");
+  for (int it = 0; !rc; ++it) {
+    int any = 0;
+    for (int gi = 0; gi < n_groups && !rc; ++gi) {
+      if (!live[gi]) continue;
+      const mofem_pcg_group& G = groups[gi];
+      hipStream_t s = runs[gi].s;
+      int* slot = hflag[2 * gi] + (it & 1) * G.batch;
+      rc = runs[gi].iteration();
+      if (!rc && (hipMemcpyAsync(slot, runs[gi].w.active, sizeof(int) * G.batch, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                  hipEventRecord(ev[2 * gi + (it & 1)], s) != hipSuccess))
+        rc = fail(MOFEM_E_HIP, "pcg_solve_many: flags");
+      any = 1;
+    }
+    if (rc || !any) break;
+    for (int gi = 0; gi < n_groups && !rc; ++gi) {
+      if (!live[gi]) continue;
+      const mofem_pcg_group& G = groups[gi];
+      if (it + 1 >= G.maxit) {
+        live[gi] = 0;
+        continue;
+      }
+      if (it == 0) continue;
+      if (hipEventSynchronize(ev[2 * gi + ((it - 1) & 1)]) != hipSuccess) {
+        rc = fail(MOFEM_E_HIP, "pcg_solve_many: event");
+        break;
+      }
+      const int* slot = hflag[2 * gi] + ((it - 1) & 1) * G.batch;
+      int na = 0;
+      for (int b = 0; b < G.batch; ++b) na += slot[b] != 0;
+      runs[gi].n_trace = na;
+      if (na == 0) live[gi] = 0;
+    }
+  }
+  // results: device scratch of each run, then to the host
+  for (int gi = 0; gi < n_groups && !rc; ++gi) {
+    const mofem_pcg_group& G = groups[gi];
+    if (G.batch == 0) continue;
+    PcgRun& r = runs[gi];
+    rc = r.finish(r.w.claim, r.w.restart, r.w.rr);
+    if (!rc && (hipMemcpyAsync(res[gi].it, r.w.claim, sizeof(int) * G.batch, hipMemcpyDeviceToHost, r.s) != hipSuccess ||
+                hipMemcpyAsync(res[gi].st, r.w.restart, sizeof(int) * G.batch, hipMemcpyDeviceToHost, r.s) != hipSuccess ||
+                hipMemcpyAsync(res[gi].rr, r.w.rr, sizeof(double) * G.batch, hipMemcpyDeviceToHost, r.s) != hipSuccess))
+      rc = fail(MOFEM_E_HIP, "pcg_solve_many: results");
+  }
+  int result = MOFEM_OK;
+  for (int gi = 0; gi < n_groups && !rc; ++gi) {
+    const mofem_pcg_group& G = groups[gi];
+    if (G.batch == 0) {
+      if (status_out) status_out[gi] = MOFEM_OK;
+      continue;
+    }
+    if (hipStreamSynchronize(runs[gi].s) != hipSuccess) {
+      rc = fail(MOFEM_E_HIP, "pcg_solve_many: synchronise");
+      break;
+    }
+    int gst = MOFEM_OK;
+    for (int b = 0; b < G.batch; ++b) {
+      if (G.iters_out) G.iters_out[b] = res[gi].it[b];
+      if (G.relres_out) G.relres_out[b] = res[gi].rr[b];
+      if (res[gi].st[b] != MOFEM_OK && gst == MOFEM_OK) gst = res[gi].st[b];
+    }
+    if (status_out) status_out[gi] = gst;
+    if (gst != MOFEM_OK && result == MOFEM_OK) result = gst;
+  }
+  for (int* h : hflag)
+    if (h) (void)hipHostFree(h);
+  cleanup();
+  if (rc) return rc;
+  return status_error(result);
+}
+
 extern "C" int mofem_pcg_solve_async(mofem_op_t op, mofem_prec_t prec, const double* Rhs, double* U,
                                      long long stride, int batch, const double* item_scale, double tol, int maxit,
                                      unsigned flags, void* workspace, size_t ws_bytes, int* iters_dev,

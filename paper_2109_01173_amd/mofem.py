@@ -67,6 +67,14 @@ class PrecDesc(ctypes.Structure):
                 ("precision", ctypes.c_int)]
 
 
+class PcgGroup(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_void_p), ("prec", ctypes.c_void_p), ("rhs", ctypes.c_void_p),
+                ("u", ctypes.c_void_p), ("stride", ctypes.c_longlong), ("batch", ctypes.c_int),
+                ("item_scale", ctypes.c_void_p), ("tol", ctypes.c_double), ("maxit", ctypes.c_int),
+                ("flags", ctypes.c_uint), ("workspace", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t),
+                ("iters_out", ctypes.c_void_p), ("relres_out", ctypes.c_void_p)]
+
+
 class ImexDesc(ctypes.Structure):
     _fields_ = [("op", _vp), ("prec", _vp), ("mass", _vp), ("tau", ctypes.c_double),
                 ("d", ctypes.c_double * 2), ("n_species", ctypes.c_int),
@@ -129,6 +137,8 @@ mofem_imex_graph_create = _proto("mofem_imex_graph_create", ctypes.c_int,
 mofem_imex_graph_launch = _proto("mofem_imex_graph_launch", ctypes.c_int, [_vp, ctypes.c_int, _vp])
 mofem_imex_graph_result = _proto("mofem_imex_graph_result", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp])
 mofem_imex_graph_destroy = _proto("mofem_imex_graph_destroy", ctypes.c_int, [_vp])
+mofem_pcg_solve_many = _proto("mofem_pcg_solve_many", ctypes.c_int,
+                              [ctypes.c_int, ctypes.POINTER(PcgGroup), ctypes.POINTER(_vp), _vp])
 mofem_trace_enable = _proto("mofem_trace_enable", ctypes.c_int, [ctypes.c_int])
 mofem_trace_read = _proto("mofem_trace_read", ctypes.c_int,
                           [ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_longlong), _dp])
@@ -141,6 +151,7 @@ EXPORTS = ["mofem_version", "mofem_last_error", "mofem_assemble_1d", "mofem_gene
            "mofem_pcg_solve",
            "mofem_imex_workspace_size", "mofem_imex_step", "mofem_dot_accumulate",
            "mofem_imex_adjoint_workspace_size", "mofem_imex_adjoint_step", "mofem_pcg_solve_async",
+           "mofem_pcg_solve_many",
            "mofem_imex_graph_create", "mofem_imex_graph_launch", "mofem_imex_graph_result",
            "mofem_imex_graph_destroy", "mofem_trace_enable", "mofem_trace_read"]
 
@@ -378,6 +389,46 @@ def pcg_solve_async(op, prec, rhs, U, workspace, iters, status, relres, tol=1e-1
                                _dptr(item_scale), tol, maxit, flags, _dptr(workspace), workspace.numel(),
                                _dptr(iters), _dptr(status), _dptr(relres), _stream(stream))
     _check(rc, "mofem_pcg_solve_async")
+
+
+def pcg_solve_many(groups, streams, raise_on_error=True):
+    """Solve several batched systems of uneven shapes together (mofem_pcg_solve_many).
+
+    groups: list of dicts with op, prec, rhs, U and optionally tol, maxit,
+    flags, item_scale, workspace; streams: one torch.cuda.Stream per group
+    (ordered after the current stream here).  Returns per group (iters,
+    relres) and the per-group status list."""
+    torch = _torch()
+    n = len(groups)
+    arr = (PcgGroup * n)()
+    keep, outs = [], []
+    cur = torch.cuda.current_stream()
+    for i, g in enumerate(groups):
+        op, prec, rhs, U = g["op"], g["prec"], g["rhs"], g["U"]
+        batch = rhs.shape[0]
+        ws = g.get("workspace")
+        if ws is None:
+            ws = pcg_workspace(op, prec, batch, rhs.device)
+        its = np.zeros(batch, dtype=np.int32)
+        rr = np.zeros(batch)
+        keep.append(ws)
+        outs.append((its, rr))
+        streams[i].wait_stream(cur)
+        a = arr[i]
+        a.op, a.prec, a.rhs, a.u = op.handle.value, prec.handle.value, rhs.data_ptr(), U.data_ptr()
+        a.stride, a.batch = op.shape[0] * op.shape[1], batch
+        a.item_scale = g["item_scale"].data_ptr() if g.get("item_scale") is not None else None
+        a.tol, a.maxit, a.flags = g.get("tol", 1e-10), g.get("maxit", 500), g.get("flags", 0)
+        a.workspace, a.ws_bytes = ws.data_ptr(), ws.numel()
+        a.iters_out, a.relres_out = its.ctypes.data, rr.ctypes.data
+    sarr = (_vp * max(n, 1))(*[_vp(st.cuda_stream) for st in streams])
+    status = np.zeros(max(n, 1), dtype=np.int32)
+    rc = mofem_pcg_solve_many(n, arr, sarr, _hptr(status))
+    if raise_on_error:
+        _check(rc, "mofem_pcg_solve_many")
+    for st in streams:
+        cur.wait_stream(st)
+    return outs, status[:n].tolist()
 
 
 class ImexGraph:

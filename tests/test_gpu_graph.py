@@ -100,3 +100,31 @@ def test_pcg_async_uneven_shapes_on_two_streams():
         assert np.array_equal(to_host(iters), its_sync)
         assert rel(to_host(U), to_host(U_sync)) <= 1e-14
         assert np.allclose(to_host(relres), rr_sync, rtol=1e-12, atol=0)
+
+
+def test_pcg_solve_many_uneven_groups():
+    """Uneven instances (orders 1-4 and lumped P1, several node counts, both
+    boundary conditions) solved together on three streams equal the
+    one-at-a-time solves."""
+    import torch
+    from paper_2109_01173_amd import mofem as mf
+    specs = [(1, 64, "dirichlet", False, 3), (2, 64, "dirichlet", False, 2), (3, 21, "neumann", False, 1),
+             (4, 16, "dirichlet", False, 2), (2, 16, "neumann", False, 4), (1, 128, "dirichlet", True, 1)]
+    rng = np.random.default_rng(33)
+    groups, ref = [], []
+    for k, m, bc, lumped, B in specs:
+        G = gpu_xnormal(k, m, bc, 1.0, lumped=lumped)
+        R = to_dev(rng.standard_normal((B, G.q, G.q)))
+        U1 = torch.empty_like(R)
+        its, rr, _ = mf.pcg_solve(G.op, G.prec, R, U1, tol=1e-11, maxit=100, flags=mf.PCG_ZERO_GUESS)
+        ref.append((U1, its, rr))
+        groups.append(dict(op=G.op, prec=G.prec, rhs=R, U=torch.empty_like(R), tol=1e-11, maxit=100,
+                           flags=mf.PCG_ZERO_GUESS, _keep=G))
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    outs, status = mf.pcg_solve_many(groups, [streams[i % 3] for i in range(len(groups))])
+    torch.cuda.synchronize()
+    assert status == [0] * len(groups)
+    for g, (its, rr), (U1, its1, rr1) in zip(groups, outs, ref):
+        assert np.array_equal(its, its1)
+        assert np.allclose(rr, rr1, rtol=1e-12, atol=0)
+        assert rel(to_host(g["U"]), to_host(U1)) <= 1e-14
