@@ -102,6 +102,58 @@ def copy_calibration(torch):
     print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "launches": 5}), flush=True)
 
 
+def uneven_leg(mf, torch, np, n_inst):
+    """Uneven batch: n_inst elliptic instances with n drawn from {257, 513,
+    1025, 2049} and k from 1..4 (seed 5; k = 3 uses m = round((n-1)/3)),
+    gamma = 1, manufactured f + 1e-3 noise, rel 1e-8, split-BF16 transforms.
+    Same-shape instances form one batched group; the groups are solved
+    one after another (pcg_solve) and together on four streams
+    (pcg_solve_many)."""
+    from paper_2109_01173_amd.problems import XNormal
+    from workloads import elliptic_batch
+    rng = np.random.default_rng(5)
+    ns = rng.choice([257, 513, 1025, 2049], size=n_inst)
+    ks = rng.integers(1, 5, size=n_inst)
+    shapes = {}
+    for n, k in zip(ns.tolist(), ks.tolist()):
+        shapes[(n, k)] = shapes.get((n, k), 0) + 1
+    t0 = time.perf_counter()
+    groups = []
+    for gi, ((n, k), cnt) in enumerate(sorted(shapes.items())):
+        m = int(round((n - 1) / k))
+        G = XNormal(k, m, "dirichlet", gamma=1.0, precision=mf.PREC_BF16X3)
+        F = torch.from_numpy(elliptic_batch(G.n, 1.0, cnt, sigma=1e-3, seed0=5000 + 100 * gi)).cuda()
+        rhs = G.rhs_op.apply(F)
+        groups.append(dict(op=G.op, prec=G.prec, rhs=rhs, U=torch.empty_like(rhs), tol=1e-8, maxit=300,
+                           flags=mf.PCG_FLEXIBLE | mf.PCG_ZERO_GUESS, _keep=G))
+        groups[-1]["workspace"] = mf.pcg_workspace(G.op, G.prec, cnt)
+    setup = time.perf_counter() - t0
+    for g in groups:  # warm-up (also the kernels' first use)
+        mf.pcg_solve(g["op"], g["prec"], g["rhs"], g["U"], tol=1e-8, maxit=300, flags=g["flags"],
+                     workspace=g["workspace"])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for g in groups:
+        mf.pcg_solve(g["op"], g["prec"], g["rhs"], g["U"], tol=1e-8, maxit=300, flags=g["flags"],
+                     workspace=g["workspace"])
+    torch.cuda.synchronize()
+    dt_seq = time.perf_counter() - t
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    t = time.perf_counter()
+    outs, status = mf.pcg_solve_many(groups, [streams[i % 4] for i in range(len(groups))])
+    torch.cuda.synchronize()
+    dt_many = time.perf_counter() - t
+    its = np.concatenate([o[0] for o in outs])
+    log("uneven batch: %d instances in %d shape groups: %.1f solves/s one group at a time, %.1f together"
+        % (n_inst, len(groups), n_inst / dt_seq, n_inst / dt_many))
+    return {"uneven_batch": {"workload": "%d elliptic instances, n in {257,513,1025,2049}, k in 1..4 (seed 5), "
+                                         "Dirichlet, gamma=1, rel 1e-8, split-BF16 transforms" % n_inst,
+                             "groups": len(groups), "solves_per_s_sequential": round(n_inst / dt_seq, 2),
+                             "solves_per_s_streams": round(n_inst / dt_many, 2), "streams": 4,
+                             "iterations_max": int(its.max()), "status_ok": all(st == 0 for st in status),
+                             "setup_s": round(setup, 2)}}
+
+
 def imex_legs(mf, torch, np, nsteps):
     """Per-step throughput of the IMEX Euler step (eqs. (91)-(96)) on the heat
     workload (P4, Neumann, n = 2049, d = 0.1, tau = 1e-3, U0 ~ U[0,1) seed 42)
@@ -203,6 +255,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--imex-steps", type=int, default=10,
                     help="IMEX steps timed for the heat (P4) and DIB (lumped P1) legs; 0 skips them")
+    ap.add_argument("--uneven", type=int, default=64,
+                    help="instances of the uneven-batch leg (0 skips it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -310,6 +364,8 @@ def main():
                     dominant_class=["band", "gemm_f64", "gemm_bf16x3", "gemm_bf16", "vec", "gemm_bf16x2"][dominant])
 
     extra = imex_legs(mf, torch, np, args.imex_steps) if args.imex_steps > 0 else {}
+    if args.uneven > 0:
+        extra.update(uneven_leg(mf, torch, np, args.uneven))
 
     # ---- CPU baseline (oracle) ----------------------------------------------------------
     cpu = None
