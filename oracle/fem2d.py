@@ -23,27 +23,34 @@ import numpy as np
 from .fem1d import gauss_legendre, lagrange_ref
 
 
-def assemble_2d(k, m, L, dL, gamma=0.0, lumped=False, nq=12):
-    """Dense (n^2 x n^2) matrix  A_2D + gamma M_2D  and  M_2D  (full nodes)."""
+def assemble_2d(k, m, L, dL, gamma=0.0, lumped=False, nq=12, m_t=None, t_interval=(0.0, 1.0)):
+    """Dense (n_s n_t x n_s n_t) matrices  A_2D + gamma M_2D  and  M_2D (full
+    nodes).  m elements along s, m_t (default m) along t; t runs over
+    t_interval ([-1/2, 1/2] with L = 2 S for the symmetric domains of the
+    remark after eq. (19))."""
     kk = 1 if lumped else k
+    m_t = m if m_t is None else m_t
     n = kk * m + 1
+    n_t = kk * m_t + 1
     h = 1.0 / m
+    t0, t1 = t_interval
+    ht = (t1 - t0) / m_t
     if lumped:
         xq, wq = np.array([0.0, 1.0]), np.array([0.5, 0.5])
     else:
         xq, wq = gauss_legendre(nq)
     phi, dphi = lagrange_ref(kk, xq)
     nl = kk + 1
-    A2 = np.zeros((n * n, n * n))
-    M2 = np.zeros((n * n, n * n))
+    A2 = np.zeros((n * n_t, n * n_t))
+    M2 = np.zeros((n * n_t, n * n_t))
     for es in range(m):
-        for et in range(m):
+        for et in range(m_t):
             for qa in range(xq.size):
                 s = h * (es + xq[qa])
                 Ls, dLs = L(s), dL(s)
                 for qb in range(xq.size):
-                    t = h * (et + xq[qb])
-                    w = wq[qa] * wq[qb] * h * h
+                    t = t0 + ht * (et + xq[qb])
+                    w = wq[qa] * wq[qb] * h * ht
                     # Jacobian of (s, t) -> (X, Y) = (s, t L(s))
                     J = np.array([[1.0, 0.0], [t * dLs, Ls]])
                     detJ = np.linalg.det(J)
@@ -57,8 +64,8 @@ def assemble_2d(k, m, L, dL, gamma=0.0, lumped=False, nq=12):
                         for b in range(nl):
                             vals[c] = phi[a, qa] * phi[b, qb]
                             grads[c, 0] = dphi[a, qa] / h * phi[b, qb]
-                            grads[c, 1] = phi[a, qa] * dphi[b, qb] / h
-                            glob[c] = (es * kk + a) * n + (et * kk + b)
+                            grads[c, 1] = phi[a, qa] * dphi[b, qb] / ht
+                            glob[c] = (es * kk + a) * n_t + (et * kk + b)
                             c += 1
                     pg = grads @ Jinv_T.T          # physical gradients
                     A2[np.ix_(glob, glob)] += w * abs(detJ) * (pg @ pg.T)
@@ -66,9 +73,10 @@ def assemble_2d(k, m, L, dL, gamma=0.0, lumped=False, nq=12):
     return A2 + gamma * M2, M2
 
 
-def trim(Mat, n, bc):
+def trim(Mat, n, bc, n_t=None):
     """Restrict a full-node 2D matrix to the unknowns of the boundary rule."""
     if bc == "neumann":
         return Mat
-    idx = np.array([i * n + j for i in range(1, n - 1) for j in range(1, n - 1)])
+    n_t = n if n_t is None else n_t
+    idx = np.array([i * n_t + j for i in range(1, n - 1) for j in range(1, n_t - 1)])
     return Mat[np.ix_(idx, idx)]

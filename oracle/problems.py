@@ -55,18 +55,23 @@ class XNormalProblem:
     gamma  : reaction coefficient of -Lap u + gamma u = f.
     """
 
-    def __init__(self, k, m, bc, L, dL, gamma=0.0, lumped=False, nq=12):
+    def __init__(self, k, m, bc, L, dL, gamma=0.0, lumped=False, nq=12, m_t=None, t_interval=(0.0, 1.0)):
         self.k, self.m, self.bc, self.gamma, self.lumped = k, m, bc, gamma, lumped
+        self.m_t = m if m_t is None else m_t
         self.n = fem1d.n_nodes(1 if lumped else k, m)
+        self.n_t = fem1d.n_nodes(1 if lumped else k, self.m_t)
         self.I = interior(self.n, bc)
+        self.J = interior(self.n_t, bc)
         self.q = self.I.size
-        full = fem1d.xnormal_matrices(k, m, m, L, dL, lumped=lumped, nq=nq)
+        self.q_t = self.J.size
+        full = fem1d.xnormal_matrices(k, m, self.m_t, L, dL, lumped=lumped, nq=nq, t_interval=t_interval)
         self.full = full
-        ix = np.ix_(self.I, self.I)
-        self.mat = {key: val[ix] for key, val in full.items()}
+        s_keys, t_keys = ("B1", "C2", "M1", "M2", "M3"), ("A", "M", "B2", "C1")
+        self.mat = {key: full[key][np.ix_(self.I, self.I)] for key in s_keys}
+        self.mat.update({key: full[key][np.ix_(self.J, self.J)] for key in t_keys})
         # row-trimmed (q x n) mass matrices for the full-node load vector
         self.M3_rows = full["M3"][self.I, :]
-        self.M_rows = full["M"][self.I, :]
+        self.M_rows = full["M"][self.J, :]
 
     # -- operators -----------------------------------------------------------
     def apply(self, U, gamma=None):
@@ -126,11 +131,11 @@ class XNormalProblem:
         IMEX presets (``imex_prec_pairs``) add the coefficient c.
         """
         T = self.mat
-        I = np.eye(self.q)
+        Is, It = np.eye(self.q), np.eye(self.q_t)
         if preset == "sylv":
             return (T["B1"], T["M3"]), (T["A"], T["M"]), (self.gamma, 1.0, 1.0, 0.0)
         if preset == "paper-product":
-            return (T["B1"], I), (T["A"] + T["B2"], I), (0.0, 0.0, 0.0, 1.0)
+            return (T["B1"], Is), (T["A"] + T["B2"], It), (0.0, 0.0, 0.0, 1.0)
         raise ValueError(preset)
 
     def imex_prec_pairs(self, preset, c):
@@ -139,8 +144,7 @@ class XNormalProblem:
             return (T["B1"], T["M3"]), (T["A"], T["M"]), (1.0, c, c, 0.0)
         if preset == "paper-imex":
             # eq. (95): (M3 + c B1)^-1 U (M + c (A + B2))^-1
-            I = np.eye(self.q)
-            return ((T["M3"] + c * T["B1"], I), (T["M"] + c * (T["A"] + T["B2"]), I),
+            return ((T["M3"] + c * T["B1"], np.eye(self.q)), (T["M"] + c * (T["A"] + T["B2"]), np.eye(self.q_t)),
                     (0.0, 0.0, 0.0, 1.0))
         raise ValueError(preset)
 

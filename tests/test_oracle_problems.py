@@ -36,6 +36,36 @@ def test_kronecker_equals_bruteforce_2d(k, m, lumped, bc):
     assert math.isclose(M2.sum(), 1.0 + 0.6 / math.pi, rel_tol=1e-12 if not lumped else 1e-2)
 
 
+def cap_L(s):
+    """L = 2 S for the cap-shaped symmetric domain |X| <= S(Y) = 1 - Y^2 / 2."""
+    return 2.0 - s ** 2
+
+
+def cap_dL(s):
+    return -2.0 * s
+
+
+@pytest.mark.parametrize("k,m,m_t,lumped,bc", [(1, 4, 6, False, "dirichlet"), (2, 3, 2, False, "neumann"),
+                                               (3, 2, 3, False, "dirichlet"), (4, 2, 1, False, "neumann"),
+                                               (1, 5, 3, True, "neumann")])
+def test_cap_domain_and_uneven_mesh_equal_bruteforce_2d(k, m, m_t, lumped, bc):
+    """Symmetric x-normal domain (remark after eq. (19): t in [-1/2, 1/2],
+    L = 2 S) with the cap profile, different element counts along s and t."""
+    gamma = 0.7
+    P = XNormalProblem(k, m, bc, cap_L, cap_dL, gamma=gamma, lumped=lumped, m_t=m_t, t_interval=(-0.5, 0.5))
+    assert (P.q, P.q_t) != (P.q_t, P.q) or m == m_t
+    K = P.kron().toarray()
+    A2, M2 = fem2d.assemble_2d(k, m, cap_L, cap_dL, gamma=gamma, lumped=lumped, m_t=m_t, t_interval=(-0.5, 0.5))
+    K2 = fem2d.trim(A2, P.n, bc, P.n_t)
+    assert K.shape == K2.shape == (P.q * P.q_t, P.q * P.q_t)
+    assert np.abs(K - K2).max() <= 1e-13 * np.abs(K2).max()
+    rng = np.random.default_rng(1)
+    U = rng.standard_normal((P.q, P.q_t))
+    assert np.allclose(vec_r(P.apply(U)), K @ vec_r(U), atol=1e-13 * np.abs(K).max() * P.q)
+    # area of the cap: int_0^1 2 (1 - y^2 / 2) dy = 5 / 3
+    assert math.isclose(M2.sum(), 5.0 / 3.0, rel_tol=1e-12 if not lumped else 5e-2)
+
+
 @pytest.mark.parametrize("k,m,lumped", CASES)
 @pytest.mark.parametrize("bc", ["dirichlet", "neumann"])
 def test_operator_symmetric_positive(k, m, lumped, bc):
