@@ -77,7 +77,12 @@ enum {
   MOFEM_W_PROFILE_D = 3,    /* w = L'(x)                                     */
   MOFEM_W_PROFILE_INV = 4,  /* w = 1 / L(x)                                  */
   MOFEM_W_PROFILE_D2L = 5,  /* w = L'(x)^2 / L(x)                            */
-  MOFEM_W_CALLBACK = 6      /* w = fn(x, ctx)                                */
+  MOFEM_W_CALLBACK = 6,     /* w = fn(x, ctx)                                */
+  /* polynomial profile L(x) = p0 + p1 x + p2 x^2 + p3 x^3 (w = L is
+     MOFEM_W_POLY), e.g. L = 2 S for the cap-shaped symmetric domain       */
+  MOFEM_W_PPROFILE_D = 7,   /* w = L'(x)                                     */
+  MOFEM_W_PPROFILE_INV = 8, /* w = 1 / L(x)                                  */
+  MOFEM_W_PPROFILE_D2L = 9  /* w = L'(x)^2 / L(x)                            */
 };
 typedef double (*mofem_weight_fn)(double x, void* ctx);
 typedef struct {

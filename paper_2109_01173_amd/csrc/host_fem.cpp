@@ -137,6 +137,13 @@ double eval_weight(const mofem_weight* w, double x) {
       return dL * dL / L;
     }
     case MOFEM_W_CALLBACK: return w->fn(x, w->ctx);
+    case MOFEM_W_PPROFILE_D: return p[1] + x * (2.0 * p[2] + x * 3.0 * p[3]);
+    case MOFEM_W_PPROFILE_INV: return 1.0 / (p[0] + x * (p[1] + x * (p[2] + x * p[3])));
+    case MOFEM_W_PPROFILE_D2L: {
+      double L = p[0] + x * (p[1] + x * (p[2] + x * p[3]));
+      double dL = p[1] + x * (2.0 * p[2] + x * 3.0 * p[3]);
+      return dL * dL / L;
+    }
     default: return NAN;
   }
 }
@@ -174,7 +181,7 @@ extern "C" int mofem_assemble_1d(int order, int m_elem, double x0, double x1, in
   if (!(x1 > x0)) return fail(MOFEM_E_ARG, "assemble_1d: need x1 > x0");
   if (nq == 0) nq = 12;
   if (nq < 1 || nq > 32) return fail(MOFEM_E_ARG, "assemble_1d: nq must be 1..32");
-  if (w && (w->kind < MOFEM_W_ONE || w->kind > MOFEM_W_CALLBACK))
+  if (w && (w->kind < MOFEM_W_ONE || w->kind > MOFEM_W_PPROFILE_D2L))
     return fail(MOFEM_E_ARG, "assemble_1d: unknown weight kind");
   if (w && w->kind == MOFEM_W_CALLBACK && !w->fn)
     return fail(MOFEM_E_ARG, "assemble_1d: callback weight without function");

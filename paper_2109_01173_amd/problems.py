@@ -19,8 +19,6 @@ Preconditioners: the spectral single-term form with the pencils
 """
 import math
 
-import numpy as np
-
 from . import mofem as mf
 
 
@@ -30,31 +28,51 @@ def _assemble(order, m, di, dj, kind=mf.W_ONE, p=(0, 0, 0, 0), x0=0.0, x1=1.0):
 
 
 class XNormal:
-    """P_k (k = 1..4) or lumped P1 (lumped=True, k = 1) on the x-normal
-    domain {0 <= X <= 1, 0 <= Y <= L(X)}, L(s) = 1 + amp sin(pi s)."""
+    """P_k (k = 1..4) or lumped P1 (lumped=True, k = 1) on an x-normal domain
+    mapped from [0, 1] x [t0, t1] by (s, t) -> (s, t L(s)).
+
+    profile: ("sine", amp): L(s) = 1 + amp sin(pi s) on t in [0, 1] (the
+             domain {0 <= Y <= L(X)}); ("poly", (p0, p1, p2, p3)): a cubic
+             L(s); the symmetric domains {|X| <= S(Y)} of the remark after
+             eq. (19) use t_interval = (-1/2, 1/2) and L = 2 S, e.g. the
+             cap-shaped domain S = 1 - s^2 / 2: ("poly", (2, 0, -1, 0)).
+    m_t:     elements along t (default m), so q_s and q_t may differ."""
 
     def __init__(self, k, m, bc, gamma=0.0, amp=0.3, lumped=False, precision=mf.PREC_F64,
-                 imex=False):
+                 imex=False, m_t=None, profile=None, t_interval=(0.0, 1.0)):
         self.k, self.m, self.bc, self.gamma, self.lumped = k, m, bc, gamma, lumped
+        m_t = m if m_t is None else m_t
+        self.m_t = m_t
         order = 0 if lumped else k
         self.kb = 1 if lumped else k
         self.n = self.kb * m + 1
+        self.n_t = self.kb * m_t + 1
         trim = 1 if bc == "dirichlet" else 0
         self.trim = trim
         self.q = self.n - 2 * trim
-        prof = (1.0, amp, math.pi, 0.0)
-        B1 = _assemble(order, m, 1, 1, mf.W_PROFILE, prof)
-        C2 = _assemble(order, m, 1, 0, mf.W_PROFILE_D, prof)
-        M1 = _assemble(order, m, 0, 0, mf.W_PROFILE_INV, prof)
-        M2 = _assemble(order, m, 0, 0, mf.W_PROFILE_D2L, prof)
-        M3 = _assemble(order, m, 0, 0, mf.W_PROFILE, prof)
-        A = _assemble(order, m, 1, 1)
-        M = _assemble(order, m, 0, 0)
-        B2 = _assemble(order, m, 1, 1, mf.W_POLY, (0, 0, 1, 0))
-        C1 = _assemble(order, m, 1, 0, mf.W_POLY, (0, 1, 0, 0))
+        self.q_t = self.n_t - 2 * trim
+        kind, prof = profile if profile is not None else ("sine", amp)
+        if kind == "sine":
+            p = (1.0, prof, math.pi, 0.0)
+            wL, wD, wI, wD2 = mf.W_PROFILE, mf.W_PROFILE_D, mf.W_PROFILE_INV, mf.W_PROFILE_D2L
+        elif kind == "poly":
+            p = tuple(float(c) for c in prof)
+            wL, wD, wI, wD2 = mf.W_POLY, mf.W_PPROFILE_D, mf.W_PPROFILE_INV, mf.W_PPROFILE_D2L
+        else:
+            raise ValueError("profile kind must be 'sine' or 'poly'")
+        t0, t1 = t_interval
+        B1 = _assemble(order, m, 1, 1, wL, p)
+        C2 = _assemble(order, m, 1, 0, wD, p)
+        M1 = _assemble(order, m, 0, 0, wI, p)
+        M2 = _assemble(order, m, 0, 0, wD2, p)
+        M3 = _assemble(order, m, 0, 0, wL, p)
+        A = _assemble(order, m_t, 1, 1, x0=t0, x1=t1)
+        M = _assemble(order, m_t, 0, 0, x0=t0, x1=t1)
+        B2 = _assemble(order, m_t, 1, 1, mf.W_POLY, (0, 0, 1, 0), x0=t0, x1=t1)
+        C1 = _assemble(order, m_t, 1, 0, mf.W_POLY, (0, 1, 0, 0), x0=t0, x1=t1)
         self.bands = dict(B1=B1, C2=C2, M1=M1, M2=M2, M3=M3, A=A, M=M, B2=B2, C1=C1)
         eo = 0 if lumped else k
-        common = dict(n_s=self.n, n_t=self.n, kb=self.kb, trim_s=trim, trim_t=trim, elem_order=eo)
+        common = dict(n_s=self.n, n_t=self.n_t, kb=self.kb, trim_s=trim, trim_t=trim, elem_order=eo)
         if imex:
             terms = [dict(left=M3, right=M),
                      dict(left=M1, right=A, scaled=True),

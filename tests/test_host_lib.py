@@ -51,6 +51,12 @@ def test_assembly_matches_oracle(order):
         (0, 0, mf.W_ONE, (0, 0, 0, 0), None),
         (1, 1, mf.W_POLY, (0, 0, 1, 0), lambda t: t ** 2),
         (1, 0, mf.W_POLY, (0, 1, 0, 0), lambda t: t),
+        # the cap profile L = 2 - s^2 (cubic-polynomial profile kinds)
+        (1, 1, mf.W_POLY, (2, 0, -1, 0), lambda s: 2.0 - s ** 2),
+        (1, 0, mf.W_PPROFILE_D, (2, 0, -1, 0), lambda s: -2.0 * s),
+        (0, 0, mf.W_PPROFILE_INV, (2, 0, -1, 0), lambda s: 1.0 / (2.0 - s ** 2)),
+        (0, 0, mf.W_PPROFILE_D2L, (2, 0, -1, 0), lambda s: 4.0 * s ** 2 / (2.0 - s ** 2)),
+        (0, 0, mf.W_PPROFILE_D, (0.5, 1.0, -2.0, 3.0), lambda s: 1.0 - 4.0 * s + 9.0 * s ** 2),
     ]
     for di, dj, kind, p, fw in cases:
         w = None if kind == mf.W_ONE else mf.weight(kind, p)
