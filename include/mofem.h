@@ -196,11 +196,15 @@ enum {
   MOFEM_PREC_BF16 = 2,    /* BF16 operands, FP32 accumulation               */
   MOFEM_PREC_BF16X3 = 3,  /* split BF16 (hi + lo), three products per term,
                              FP32 accumulation                              */
-  MOFEM_PREC_BF16X2 = 4   /* split BF16 for the data operands, eigenbases
+  MOFEM_PREC_BF16X2 = 4,  /* split BF16 for the data operands, eigenbases
                              rounded to BF16: the preconditioner is defined
                              with the rounded (still nonsingular) bases, so
                              P stays symmetric positive definite and each
                              transform needs two products; FP32 accumulation */
+  MOFEM_PREC_BF16_FWD = 5 /* forward transforms (V_s^T R V_t) in BF16 (one
+                             product), back transforms (V_s (.) V_t^T) in
+                             split BF16 (three); FP32 accumulation.  Not
+                             symmetric: use the flexible PCG.               */
 };
 typedef struct {
   int kb;                       /* band half-width of the four matrices       */

@@ -465,7 +465,7 @@ extern "C" int mofem_prec_setup(const mofem_prec_desc* desc, mofem_prec_t* out) 
   if (!D.Ks || !D.Ms || !D.Kt || !D.Mt) return fail(MOFEM_E_ARG, "prec_setup: NULL band");
   if ((D.trim_s != 0 && D.trim_s != 1) || (D.trim_t != 0 && D.trim_t != 1))
     return fail(MOFEM_E_ARG, "prec_setup: trim flags must be 0 or 1");
-  if (D.precision < MOFEM_PREC_F64 || D.precision > MOFEM_PREC_BF16X2)
+  if (D.precision < MOFEM_PREC_F64 || D.precision > MOFEM_PREC_BF16_FWD)
     return fail(MOFEM_E_ARG, "prec_setup: unknown precision");
   const int qs = D.n_s - 2 * D.trim_s, qt = D.n_t - 2 * D.trim_t;
   if (qs < 1 || qt < 1) return fail(MOFEM_E_ARG, "prec_setup: empty matrices");
@@ -527,7 +527,7 @@ extern "C" int mofem_prec_set_coeffs(mofem_prec_t p, double a, double bs, double
 extern "C" int mofem_prec_set_precision(mofem_prec_t p, int precision) {
   clear_error();
   if (!p) return fail(MOFEM_E_ARG, "prec_set_precision: NULL handle");
-  if (precision < MOFEM_PREC_F64 || precision > MOFEM_PREC_BF16X2) return fail(MOFEM_E_ARG, "unknown precision");
+  if (precision < MOFEM_PREC_F64 || precision > MOFEM_PREC_BF16_FWD) return fail(MOFEM_E_ARG, "unknown precision");
   p->precision = precision;
   return MOFEM_OK;
 }
@@ -549,6 +549,20 @@ extern "C" size_t mofem_prec_workspace_size(mofem_prec_t p, int batch) {
 }
 
 namespace {
+// Product mode of the four transforms of a split-BF16 family precision.
+void split_modes(int precision, int* mode) {
+  const int m = precision == MOFEM_PREC_BF16     ? GEMM_BF16
+                : precision == MOFEM_PREC_BF16X2 ? GEMM_BF16X2
+                                                 : GEMM_BF16X3;
+  for (int i = 0; i < 4; ++i) mode[i] = m;
+  if (precision == MOFEM_PREC_BF16_FWD) mode[0] = mode[1] = GEMM_BF16;  // forward in BF16
+}
+int split_trace_class(int gemm_mode) {
+  return gemm_mode == GEMM_BF16 ? MOFEM_TRACE_GEMM_BF16
+         : gemm_mode == GEMM_BF16X2 ? MOFEM_TRACE_GEMM_BF16X2
+                                    : MOFEM_TRACE_GEMM_BF16X3;
+}
+
 // The padded first-transform operand inside a preconditioner workspace (the
 // first buffer prec_launch carves): FP64, or split BF16 as two halves.
 struct PrecInput {
@@ -569,6 +583,9 @@ PrecInput prec_input(mofem_prec_t p, void* ws, size_t ws_bytes, int batch) {
   } else {
     in.hi = c.take<unsigned short>(items * batch);
     in.lo = c.take<unsigned short>(items * batch);
+    int mode[4];
+    split_modes(p->precision, mode);
+    if (mode[0] == GEMM_BF16) in.lo = nullptr;  // the first transform reads hi only
   }
   in.stride = (long long)items;
   return in;
@@ -606,7 +623,7 @@ int prec_launch(mofem_prec_t p, const double* R, double* Z, long long stride, in
                    : p->precision == MOFEM_PREC_F32    ? GEMM_F32
                    : p->precision == MOFEM_PREC_BF16   ? GEMM_BF16
                    : p->precision == MOFEM_PREC_BF16X2 ? GEMM_BF16X2
-                                                       : GEMM_BF16X3;
+                                                       : GEMM_BF16X3;  // BF16X3, BF16_FWD: split branch
   const int tcls = prec == GEMM_F64      ? MOFEM_TRACE_GEMM_F64
                    : prec == GEMM_F32    ? MOFEM_TRACE_GEMM_F32
                    : prec == GEMM_BF16   ? MOFEM_TRACE_GEMM_BF16
@@ -685,33 +702,46 @@ int prec_launch(mofem_prec_t p, const double* R, double* Z, long long stride, in
     unsigned short* T2l = c.take<unsigned short>(items * batch);
     if (!T0h || !T0l || !T1h || !T1l || !T2h || !T2l) return fail(MOFEM_E_ARG, "prec_apply: workspace too small");
     const long long istr = (long long)items;
+    // product mode of each transform G1..G4 and whether it reads its operands' lo halves
+    int mode[4];
+    split_modes(p->precision, mode);
+    const int data_is_a[4] = {1, 0, 0, 1};
+    auto a_lo = [&](int i) { return mode[i] == GEMM_BF16X3 || (mode[i] == GEMM_BF16X2 && data_is_a[i]); };
+    auto b_lo = [&](int i) { return mode[i] == GEMM_BF16X3 || (mode[i] == GEMM_BF16X2 && !data_is_a[i]); };
+    auto run = [&](int i, int omode) -> int {
+      g.data_is_a = data_is_a[i];
+      TraceScope trace(split_trace_class(mode[i]), items_done, s);
+      return launch_gemm(g, mode[i], omode, batch, tile, s);
+    };
     if (!input_ready) {
       TraceScope trace(MOFEM_TRACE_VEC, items_done, s);
-      if (launch_pad_operand(R, stride, p->qs, p->qt, nullptr, nullptr, T0h, T0l, istr, 1, batch, active, s))
+      if (launch_pad_operand(R, stride, p->qs, p->qt, nullptr, nullptr, T0h, a_lo(0) ? T0l : nullptr, istr, 1, batch,
+                             active, s))
         return fail(MOFEM_E_HIP, "pad launch");
     }
+    // G1: T' = (R V_t)^T
     g.M = p->qs; g.N = p->qt; g.K = p->qt;
-    g.data_is_a = 1;
     g.a_hi = T0h; g.a_lo = T0l; g.a_stride = istr; g.b_hi = p->VtT_h; g.b_lo = p->VtT_l; g.b_stride = 0;
-    g.c_hi = T1h; g.c_lo = T1l; g.c_stride = istr; g.divide = 0;
-    if (gemm(O_PAD_T)) return fail(MOFEM_E_HIP, "gemm launch");
+    g.c_hi = T1h; g.c_lo = b_lo(1) ? T1l : nullptr; g.c_stride = istr; g.divide = 0;
+    if (run(0, O_PAD_T)) return fail(MOFEM_E_HIP, "gemm launch");
+    // G2: S' = (V_s^T T ./ D)^T
     g.M = p->qs; g.N = p->qt; g.K = p->qs;
-    g.data_is_a = 0;
     g.a64 = nullptr; g.a_hi = p->VsT_h; g.a_lo = p->VsT_l; g.a_stride = 0;
     g.b_hi = T1h; g.b_lo = T1l; g.b_stride = istr;
-    g.c_hi = T2h; g.c_lo = T2l; g.c_stride = istr; g.divide = 1;
-    if (gemm(O_PAD_T)) return fail(MOFEM_E_HIP, "gemm launch");
+    g.c_hi = T2h; g.c_lo = b_lo(2) ? T2l : nullptr; g.c_stride = istr; g.divide = 1;
+    if (run(1, O_PAD_T)) return fail(MOFEM_E_HIP, "gemm launch");
+    // G3: W = V_s S
     g.M = p->qs; g.N = p->qt; g.K = p->qs;
     g.a_hi = p->Vs_h; g.a_lo = p->Vs_l; g.a_stride = 0;
     g.b_hi = T2h; g.b_lo = T2l; g.b_stride = istr;
-    g.c_hi = T1h; g.c_lo = T1l; g.c_stride = istr; g.divide = 0;
-    if (gemm(O_PAD_N)) return fail(MOFEM_E_HIP, "gemm launch");
+    g.c_hi = T1h; g.c_lo = a_lo(3) ? T1l : nullptr; g.c_stride = istr; g.divide = 0;
+    if (run(2, O_PAD_N)) return fail(MOFEM_E_HIP, "gemm launch");
+    // G4: Z = W V_t^T
     g.M = p->qs; g.N = p->qt; g.K = p->qt;
-    g.data_is_a = 1;
     g.a_hi = T1h; g.a_lo = T1l; g.a_stride = istr;
     g.b_hi = p->Vt_h; g.b_lo = p->Vt_l; g.b_stride = 0;
-    g.c64 = Z; g.c_stride = stride; g.divide = 0;
-    if (gemm(O_F64_RAW)) return fail(MOFEM_E_HIP, "gemm launch");
+    g.c64 = Z; g.c_hi = nullptr; g.c_lo = nullptr; g.c_stride = stride; g.divide = 0;
+    if (run(3, O_F64_RAW)) return fail(MOFEM_E_HIP, "gemm launch");
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(MOFEM_E_HIP, std::string("prec_apply launch: ") + hipGetErrorString(e));
@@ -1117,7 +1147,12 @@ extern "C" int mofem_pcg_solve(mofem_op_t op, mofem_prec_t prec, const double* R
       ex_prec += cnt[j];
     }
     trace_add_items(MOFEM_TRACE_BAND, ex_band - r.rec_band);
-    trace_add_items(trace_class_of(prec), 4.0 * (ex_prec - r.rec_prec));
+    if (prec->precision == MOFEM_PREC_BF16_FWD) {
+      trace_add_items(MOFEM_TRACE_GEMM_BF16, 2.0 * (ex_prec - r.rec_prec));
+      trace_add_items(MOFEM_TRACE_GEMM_BF16X3, 2.0 * (ex_prec - r.rec_prec));
+    } else {
+      trace_add_items(trace_class_of(prec), 4.0 * (ex_prec - r.rec_prec));
+    }
   }
   int result = MOFEM_OK;
   for (int b = 0; b < batch; ++b) {

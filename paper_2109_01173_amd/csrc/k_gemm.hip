@@ -22,6 +22,8 @@
 //                representable in BF16 (the preconditioner is defined with
 //                the BF16-rounded basis): two products per transform.
 //   GEMM_BF16    the hi * hi product only.
+// A transform writes the lo half of a split output only when its consumer
+// reads it (c_lo set).
 // Tiling: 256 threads = 4 waves, block tile 128 x 128, each wave 64 x 64
 // (4 x 4 MFMA tiles of 16 x 16), or 64 x 64 blocks of 32 x 32 wave tiles for
 // grids too small to fill the chip (picked per shape, see mofem_prec_tune);
@@ -409,7 +411,9 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
     unsigned short* __restrict__ Cg[2] = {(unsigned short*)g.c_hi + (size_t)b * g.c_stride,
                                           (unsigned short*)g.c_lo + (size_t)b * g.c_stride};
     __syncthreads();  // every wave is done with the operand tiles
-    for (int pass = 0; pass < (MODE == BF_HH ? 1 : 2); ++pass) {
+    // the lo half is written when the consumer reads it (c_lo set)
+    const int passes = g.c_lo ? 2 : 1;
+    for (int pass = 0; pass < passes; ++pass) {
 #pragma unroll
       for (int i = 0; i < WT; ++i)
 #pragma unroll
@@ -480,7 +484,7 @@ int launch_gemm(const GemmArgs& g, int prec, int omode, int batch, int tile, hip
 }
 
 // Raw FP64 items (M x K, row length K) -> padded operand (pad(M) x pad(K)),
-// FP64 or split BF16 (hi, lo), zeros in the padding.  One block per padded
+// FP64, FP32 or split BF16 (hi, and lo unless olo is null), zeros in the padding.  One block per padded
 // row; consecutive threads take consecutive columns (coalesced both ways).
 __global__ __launch_bounds__(256) void pad_operand_kernel(const double* __restrict__ A, long long a_stride, int M,
                                                           int K, double* __restrict__ o64, float* __restrict__ o32,
@@ -499,7 +503,7 @@ __global__ __launch_bounds__(256) void pad_operand_kernel(const double* __restri
       unsigned short hi, lo;
       split_bf16((float)x, &hi, &lo);
       ohi[obase + c] = hi;
-      olo[obase + c] = lo;
+      if (olo) olo[obase + c] = lo;
     } else if (o32) {
       o32[obase + c] = (float)x;
     } else {

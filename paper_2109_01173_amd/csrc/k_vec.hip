@@ -184,7 +184,7 @@ __global__ __launch_bounds__(kThreads) void cg_update_pad_kernel(
       const float f = (float)v;
       const __bf16 h = (__bf16)f;
       ohi[o] = __builtin_bit_cast(unsigned short, h);
-      olo[o] = __builtin_bit_cast(unsigned short, (__bf16)(f - (float)h));
+      if (olo) olo[o] = __builtin_bit_cast(unsigned short, (__bf16)(f - (float)h));
     }
     col += kThreads;
     while (col >= qt) {

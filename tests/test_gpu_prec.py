@@ -46,7 +46,8 @@ def test_prec_fp64(k, m, bc):
     _ = mf
 
 
-@pytest.mark.parametrize("precision,tol", [("F32", 2e-5), ("BF16X3", 2e-4), ("BF16X2", 5e-2), ("BF16", 3e-2)])
+@pytest.mark.parametrize("precision,tol", [("F32", 2e-5), ("BF16X3", 2e-4), ("BF16X2", 5e-2), ("BF16", 3e-2),
+                                           ("BF16_FWD", 3e-2)])
 def test_prec_low_precision(precision, tol):
     from paper_2109_01173_amd import mofem as mf
     p = getattr(mf, "PREC_" + precision)
@@ -82,7 +83,7 @@ def test_prec_tiny_and_errors():
         G.prec.set_precision(99)
 
 
-@pytest.mark.parametrize("precision", ["F64", "F32", "BF16X3", "BF16"])
+@pytest.mark.parametrize("precision", ["F64", "F32", "BF16X3", "BF16", "BF16_FWD"])
 def test_block_tiles_agree_and_tuner(precision):
     """Both block tiles of the transforms compute the same products in the same
     k order: the results agree to the last bits; the tuner picks one of them."""
