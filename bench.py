@@ -66,14 +66,14 @@ def cpu_baseline(F0, k, m, gamma, tol, U_gpu0):
 
 
 # HBM traffic of the transform GEMM, from two rocprofv3 --pmc passes over
-# "bench.py --steps 1 --warmup 0 --no-cpu-baseline --fp64-steps 0 --imex-steps 0" (FETCH_SIZE,
+# "bench.py --steps 1 --warmup 0 --no-cpu-baseline --fp64-steps 0 --imex-steps 0 --uneven 0" (FETCH_SIZE,
 # then WRITE_SIZE, KiB per dispatch, averaged over that kernel's dispatches),
 # each scaled by the ratio true bytes / counter reading of a plain 512 MiB
 # copy ("bench.py --copy-calibration").  The figures hold for the kernel
 # source they were taken on: if k_gemm.hip changes, traffic is reported null.
 TRAFFIC = {
     # mixed mode -> (sha256 of k_gemm.hip, (q, batch), bytes per launch)
-    "bf16x3": ("2170ba076ffd466b31cbf073b9053dfd791ed1179e4aea708c80c3add5c1d94e", (2047, 16), 2.513e9),
+    "bf16fwd": ("1523b925ce7195b7cc5a9d49474cc57379364cef8179edc58bee508e28a6b4d1", (2047, 16), 2.576e9),
 }
 FETCH_SCALE = 2.000   # 512 MiB copy: true bytes / FETCH_SIZE reading
 WRITE_SCALE = 1.000   # 512 MiB copy: true bytes / WRITE_SIZE reading
