@@ -103,7 +103,7 @@ def copy_calibration(torch):
     print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "launches": 5}), flush=True)
 
 
-def uneven_leg(mf, torch, np, n_inst):
+def uneven_leg(mf, torch, np, n_inst, prec, prec_name):
     """Uneven batch: n_inst elliptic instances with n drawn from {257, 513,
     1025, 2049} and k from 1..4 (seed 5; k = 3 uses m = round((n-1)/3)),
     gamma = 1, manufactured f + 1e-3 noise, rel 1e-8, split-BF16 transforms.
@@ -122,7 +122,7 @@ def uneven_leg(mf, torch, np, n_inst):
     groups = []
     for gi, ((n, k), cnt) in enumerate(sorted(shapes.items())):
         m = int(round((n - 1) / k))
-        G = XNormal(k, m, "dirichlet", gamma=1.0, precision=mf.PREC_BF16X3)
+        G = XNormal(k, m, "dirichlet", gamma=1.0, precision=prec)
         F = torch.from_numpy(elliptic_batch(G.n, 1.0, cnt, sigma=1e-3, seed0=5000 + 100 * gi)).cuda()
         rhs = G.rhs_op.apply(F)
         groups.append(dict(op=G.op, prec=G.prec, rhs=rhs, U=torch.empty_like(rhs), tol=1e-8, maxit=300,
@@ -148,14 +148,14 @@ def uneven_leg(mf, torch, np, n_inst):
     log("uneven batch: %d instances in %d shape groups: %.1f solves/s one group at a time, %.1f together"
         % (n_inst, len(groups), n_inst / dt_seq, n_inst / dt_many))
     return {"uneven_batch": {"workload": "%d elliptic instances, n in {257,513,1025,2049}, k in 1..4 (seed 5), "
-                                         "Dirichlet, gamma=1, rel 1e-8, split-BF16 transforms" % n_inst,
+                                         "Dirichlet, gamma=1, rel 1e-8, %s transforms" % (n_inst, prec_name),
                              "groups": len(groups), "solves_per_s_sequential": round(n_inst / dt_seq, 2),
                              "solves_per_s_streams": round(n_inst / dt_many, 2), "streams": 4,
                              "iterations_max": int(its.max()), "status_ok": all(st == 0 for st in status),
                              "setup_s": round(setup, 2)}}
 
 
-def imex_legs(mf, torch, np, nsteps):
+def imex_legs(mf, torch, np, nsteps, prec, prec_name):
     """Per-step throughput of the IMEX Euler step (eqs. (91)-(96)) on the heat
     workload (P4, Neumann, n = 2049, d = 0.1, tau = 1e-3, U0 ~ U[0,1) seed 42)
     and the DIB workload (lumped P1 on [0,20]^2, n = 1025, tau = 1e-2, cap
@@ -163,9 +163,9 @@ def imex_legs(mf, torch, np, nsteps):
     from paper_2109_01173_amd.problems import Rect, XNormal
     from workloads import dib_initial, dib_params, heat_initial
     out = {}
-    # heat: split-BF16 transforms, flexible PCG, FP64 residual 1e-10 per step
+    # heat: the mixed path's transforms, flexible PCG, FP64 residual 1e-10 per step
     t0 = time.perf_counter()
-    G = XNormal(4, 512, "neumann", gamma=0.0, imex=True, precision=mf.PREC_BF16X3)
+    G = XNormal(4, 512, "neumann", gamma=0.0, imex=True, precision=prec)
     setup = time.perf_counter() - t0
     st = torch.from_numpy(heat_initial(G.q, seed=42)[None]).cuda()
     stepper = mf.Imex(G.op, G.prec, G.mass, 1e-3, [0.1], tol=1e-10, maxit=200, flags=mf.PCG_FLEXIBLE)
@@ -195,7 +195,7 @@ def imex_legs(mf, torch, np, nsteps):
                            "iterations_per_step": round(float(np.mean(its)), 2),
                            "graph_steps_per_s": round(nsteps / dtg, 3), "graph_iteration_budget": budget,
                            "graph_max_iterations": int(gi.max()),
-                           "transforms": "bf16x3", "setup_s": round(setup, 2),
+                           "transforms": prec_name, "setup_s": round(setup, 2),
                            "mass_drift_rel": abs(mass1 - mass0) / abs(mass0)}
     log("imex heat P4: %.2f steps/s, %.1f iterations/step; graph replay %.2f steps/s"
         % (nsteps / dt, np.mean(its), nsteps / dtg))
@@ -367,9 +367,9 @@ def main():
                     avg_launch_ms=round(g_ms / max(g_n, 1), 4), launches=g_n,
                     dominant_class=["band", "gemm_f64", "gemm_bf16x3", "gemm_bf16", "vec", "gemm_bf16x2"][dominant])
 
-    extra = imex_legs(mf, torch, np, args.imex_steps) if args.imex_steps > 0 else {}
+    extra = imex_legs(mf, torch, np, args.imex_steps, mixed[0], args.mixed) if args.imex_steps > 0 else {}
     if args.uneven > 0:
-        extra.update(uneven_leg(mf, torch, np, args.uneven))
+        extra.update(uneven_leg(mf, torch, np, args.uneven, mixed[0], args.mixed))
 
     # ---- CPU baseline (oracle) ----------------------------------------------------------
     cpu = None
