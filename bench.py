@@ -242,6 +242,84 @@ def imex_legs(mf, torch, np, nsteps, prec, prec_name):
     return out
 
 
+def paper_prec_leg(mf, torch, np, G_head, batch, nsteps):
+    """The paper's own product preconditioners, applied by banded Cholesky
+    solves, beside the spectral one: (1) the banded apply on the headline
+    shape (HBM-bound: each of its two launches reads the input and its
+    scratch and writes both, 32 B per entry); (2) eq. (80) on a smaller
+    elliptic P2 case (its iteration count grows with q; the spectral count
+    does not); (3) heat steps (P4, n = 2049) preconditioned by eq. (95)."""
+    from paper_2109_01173_amd.problems import XNormal
+    from workloads import heat_initial
+    out = {}
+    q = G_head.q
+    prec = G_head.product_prec()
+    R = torch.randn(batch, q, q, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(3))
+    Z = torch.empty_like(R)
+    ws = torch.empty(prec.workspace_size(batch), dtype=torch.uint8, device="cuda")
+    prec.apply(R, Z, workspace=ws)
+    torch.cuda.synchronize()
+    mf.trace_enable(True)
+    for _ in range(5):
+        prec.apply(R, Z, workspace=ws)
+    torch.cuda.synchronize()
+    mf.trace_enable(False)
+    c_ms, c_n, c_items = mf.trace_read(mf.TRACE_BCHOL)
+    gbs = 32.0 * q * q * c_items / (c_ms * 1e-3) / 1e9 if c_ms > 0 else 0.0
+    out["banded_apply"] = {"workload": "eq. (80) B1^-1 R (A+B2)^-1, P2 q=%d, batch %d" % (q, batch),
+                           "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(gbs / HBM_PEAK_GBS, 4), "avg_launch_ms": round(c_ms / max(c_n, 1), 4),
+                           "apply_ms": round(2 * c_ms / max(c_n, 1), 4)}
+    del R, Z, ws, prec
+    # elliptic eq. (80) vs spectral (FP64 both) at q = 255
+    G = XNormal(2, 128, "dirichlet", gamma=1.0)
+    from workloads import elliptic_batch
+    F = torch.from_numpy(elliptic_batch(G.n, 1.0, batch, sigma=1e-3, seed0=1234)).cuda()
+    rhs = G.rhs_op.apply(F)
+    U = torch.empty_like(rhs)
+    res = {}
+    for name, pr in (("eq80", G.product_prec()), ("spectral", G.prec)):
+        mf.pcg_solve(G.op, pr, rhs, U, tol=1e-8, maxit=20000, flags=mf.PCG_ZERO_GUESS)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        its, rr, _ = mf.pcg_solve(G.op, pr, rhs, U, tol=1e-8, maxit=20000, flags=mf.PCG_ZERO_GUESS)
+        torch.cuda.synchronize()
+        res[name] = (batch / (time.perf_counter() - t), int(its.max()))
+    out["paper_eq80_elliptic"] = {"workload": "elliptic P2 x-normal, n=257 (q=255), Dirichlet, gamma=1, batch %d, "
+                                              "rel 1e-8, FP64" % batch,
+                                  "solves_per_s": round(res["eq80"][0], 2), "iterations": res["eq80"][1],
+                                  "spectral_solves_per_s": round(res["spectral"][0], 2),
+                                  "spectral_iterations": res["spectral"][1]}
+    log("paper eq. (80) at q=255: %d iterations, %.1f solves/s (spectral: %d iterations, %.1f solves/s)"
+        % (res["eq80"][1], res["eq80"][0], res["spectral"][1], res["spectral"][0]))
+    del G, F, rhs, U
+    # heat with eq. (95) against the spectral preconditioner, both with the
+    # stopping rule of Sec. 6 (||R_s|| <= tau ||R_0||), FP64
+    tau, d = 1e-3, 0.1
+    G = XNormal(4, 512, "neumann", gamma=0.0, imex=True)
+    U0 = torch.from_numpy(heat_initial(G.q, seed=42)[None]).cuda()
+    res = {}
+    for name, pr in (("eq95", G.product_prec(scales=(d * tau,))), ("spectral", G.prec)):
+        st = U0.clone()
+        stepper = mf.Imex(G.op, pr, G.mass, tau, [d], tol=tau, maxit=5000, flags=mf.PCG_TAU_STOP)
+        ws = stepper.workspace(1)
+        stepper.step(st, 1, workspace=ws)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        its = [int(stepper.step(st, 1, workspace=ws)[0]) for _ in range(nsteps)]
+        torch.cuda.synchronize()
+        res[name] = (nsteps / (time.perf_counter() - t), float(np.mean(its)))
+    out["paper_eq95_heat_p4"] = {"workload": "heat P4 x-normal, Neumann, n=2049, d=0.1, tau=1e-3, stop at "
+                                             "||R_s|| <= tau ||R_0|| (Sec. 6), FP64",
+                                 "steps_per_s": round(res["eq95"][0], 3),
+                                 "iterations_per_step": round(res["eq95"][1], 2),
+                                 "spectral_steps_per_s": round(res["spectral"][0], 3),
+                                 "spectral_iterations_per_step": round(res["spectral"][1], 2)}
+    log("paper eq. (95) heat P4, tau stop: %.2f steps/s, %.1f iterations/step (spectral FP64: %.2f steps/s, "
+        "%.1f iterations/step)" % (res["eq95"][0], res["eq95"][1], res["spectral"][0], res["spectral"][1]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -258,6 +336,8 @@ def main():
                     help="IMEX steps timed for the heat (P4) and DIB (lumped P1) legs; 0 skips them")
     ap.add_argument("--uneven", type=int, default=64,
                     help="instances of the uneven-batch leg (0 skips it)")
+    ap.add_argument("--paper-prec", type=int, default=1,
+                    help="run the leg of the paper's product preconditioners (eqs. (80), (95)); 0 skips it")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -365,11 +445,14 @@ def main():
                     algorithmic_flop_per_launch=mixed[2] * flop_per_item_gemm * g_items / max(g_n, 1),
                     kernel=mixed[3] + " (transform product, %d BF16 MFMA products)" % mixed[2],
                     avg_launch_ms=round(g_ms / max(g_n, 1), 4), launches=g_n,
-                    dominant_class=["band", "gemm_f64", "gemm_bf16x3", "gemm_bf16", "vec", "gemm_bf16x2"][dominant])
+                    dominant_class=["band", "gemm_f64", "gemm_bf16x3", "gemm_bf16", "vec", "gemm_bf16x2", "gemm_f32",
+                                    "bchol"][dominant])
 
     extra = imex_legs(mf, torch, np, args.imex_steps, mixed[0], args.mixed) if args.imex_steps > 0 else {}
     if args.uneven > 0:
         extra.update(uneven_leg(mf, torch, np, args.uneven, mixed[0], args.mixed))
+    if args.paper_prec > 0:
+        extra.update(paper_prec_leg(mf, torch, np, G, B, max(args.imex_steps, 3)))
 
     # ---- CPU baseline (oracle) ----------------------------------------------------------
     cpu = None

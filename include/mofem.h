@@ -257,6 +257,43 @@ int mofem_prec_tune(mofem_prec_t prec, int batch, int* tile_out, void* stream);
 int mofem_prec_set_tile(mofem_prec_t prec, int batch, int tile);
 
 /* ------------------------------------------------------------------------ */
+/* The paper's product preconditioners by banded Cholesky solves             */
+/*   P_j(U) = S_j U T_j,  S_j = a Ms + c_j bs Ks,  T_j = a Mt + c_j bt Kt    */
+/*   P_j^{-1}(R) = S_j^{-1} R T_j^{-1}                                        */
+/* (Sec. 5, eq. (80): Ks = B1, Kt = A + B2, a = 0, bs = bt = 1, scale 1;     */
+/*  Sec. 6, eq. (95): Ms = M3, Ks = B1, Mt = M, Kt = A + B2, a = 1,           */
+/*  bs = bt = 1, one scale c = d tau per species).                           */
+/* ------------------------------------------------------------------------ */
+#define MOFEM_MAX_SCALES 8
+typedef struct {
+  int kb;                       /* band half-width of the four matrices, 1..4 */
+  int n_s, n_t, trim_s, trim_t; /* as in mofem_prec_desc                      */
+  const double* Ks;             /* host DIA bands, symmetric                  */
+  const double* Ms;             /* host DIA bands; may be NULL when a == 0    */
+  const double* Kt;
+  const double* Mt;
+  double a, bs, bt;             /* S_j = a Ms + c_j bs Ks, T_j likewise        */
+  int n_scales;                 /* 1 .. MOFEM_MAX_SCALES                      */
+  double scales[MOFEM_MAX_SCALES];  /* c_j                                    */
+} mofem_bprec_desc;
+/* Factorise every S_j and T_j (interior rows and columns when trimmed) by
+   banded Cholesky on the host in FP64 (the factors keep half-width kb) and
+   upload the factors.  The returned handle is used like a spectral one
+   (mofem_prec_apply, mofem_prec_workspace_size, mofem_pcg_*, mofem_imex_*):
+   one application is a forward and a back substitution along each dimension,
+   O(kb q_s q_t) work per item and about 64 bytes of HBM traffic per entry.
+   Item b uses the factor pair j whose scale c_j equals its item scale s_b
+   exactly (s_b = 1 when item_scale is NULL), and pair 0 when none does (the
+   preconditioner is then still symmetric positive definite).  Arithmetic is
+   FP64 only: mofem_prec_set_precision accepts MOFEM_PREC_F64 alone, and
+   mofem_prec_set_coeffs, mofem_prec_eigenvalues, mofem_prec_tune and
+   mofem_prec_set_tile return MOFEM_E_UNSUPPORTED for this handle.
+   Errors: MOFEM_E_ARG (kb, sizes, trim flags, NULL bands, n_scales),
+   MOFEM_E_NUMERIC (a factor is not positive definite, e.g. eq. (80) under
+   Neumann conditions, where B1 is singular), MOFEM_E_NOMEM, MOFEM_E_HIP. */
+int mofem_prec_setup_banded(const mofem_bprec_desc* desc, mofem_prec_t* prec);
+
+/* ------------------------------------------------------------------------ */
 /* a5/a6/a8. MO-PCG (Sec. 5, eqs. (77)-(78)) on a batch of equations        */
 /*           L_b(U_b) = Rhs_b                                               */
 /* ------------------------------------------------------------------------ */
@@ -424,7 +461,9 @@ enum {
   MOFEM_TRACE_VEC = 4,          /* PCG vector kernels and reductions           */
   MOFEM_TRACE_GEMM_BF16X2 = 5,  /* one two-product transform (BF16 basis)      */
   MOFEM_TRACE_GEMM_F32 = 6,     /* one FP32 transform product                  */
-  MOFEM_TRACE_CLASSES = 7
+  MOFEM_TRACE_BCHOL = 7,        /* one banded Cholesky solve (two per product-
+                                   preconditioner application)               */
+  MOFEM_TRACE_CLASSES = 8
 };
 /* on != 0: discard earlier records and start recording; on == 0: stop. */
 int mofem_trace_enable(int on);

@@ -387,6 +387,9 @@ struct mofem_prec_s {
   std::vector<std::pair<long long, int>> tuned;  // (precision << 32 | batch) -> block tile
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  // product preconditioner by banded Cholesky (mofem_prec_setup_banded)
+  int banded = 0, kb = 0, n_sets = 0;
+  double *Lf_s = nullptr, *Lb_s = nullptr, *Lf_t = nullptr, *Lb_t = nullptr, *scales = nullptr;
 };
 
 namespace {
@@ -449,7 +452,7 @@ extern "C" int mofem_prec_destroy(mofem_prec_t p) {
   if (!p) return MOFEM_OK;
   void* ptrs[] = {p->lam, p->mu, p->Vs, p->VsT, p->Vt, p->VtT, p->Vs_h, p->Vs_l, p->VsT_h,
                   p->VsT_l, p->Vt_h, p->Vt_l, p->VtT_h, p->VtT_l, p->Vs_f, p->VsT_f, p->Vt_f, p->VtT_f,
-                  p->ws};
+                  p->ws, p->Lf_s, p->Lb_s, p->Lf_t, p->Lb_t, p->scales};
   for (void* x : ptrs)
     if (x) (void)hipFree(x);
   delete p;
@@ -514,9 +517,70 @@ extern "C" int mofem_prec_setup(const mofem_prec_desc* desc, mofem_prec_t* out) 
   return MOFEM_OK;
 }
 
+// Product preconditioner S U T by banded Cholesky: factor S_j = a Ms + c_j bs Ks
+// and T_j = a Mt + c_j bt Kt (interior rows and columns) for every scale c_j.
+extern "C" int mofem_prec_setup_banded(const mofem_bprec_desc* desc, mofem_prec_t* out) {
+  clear_error();
+  if (!desc || !out) return fail(MOFEM_E_ARG, "prec_setup_banded: NULL argument");
+  *out = nullptr;
+  const mofem_bprec_desc& D = *desc;
+  if (D.kb < 1 || D.kb > 4) return fail(MOFEM_E_ARG, "prec_setup_banded: kb must be 1..4");
+  if (!D.Ks || !D.Kt || (D.a != 0.0 && (!D.Ms || !D.Mt))) return fail(MOFEM_E_ARG, "prec_setup_banded: NULL band");
+  if ((D.trim_s != 0 && D.trim_s != 1) || (D.trim_t != 0 && D.trim_t != 1))
+    return fail(MOFEM_E_ARG, "prec_setup_banded: trim flags must be 0 or 1");
+  if (D.n_scales < 1 || D.n_scales > MOFEM_MAX_SCALES) return fail(MOFEM_E_ARG, "prec_setup_banded: n_scales 1..8");
+  const int qs = D.n_s - 2 * D.trim_s, qt = D.n_t - 2 * D.trim_t;
+  if (qs < 1 || qt < 1) return fail(MOFEM_E_ARG, "prec_setup_banded: empty matrices");
+  const int kb = D.kb, w = 2 * kb + 1, c = kb + 1;
+  // interior band rows of a Ms + sc b Ks (DIA input: band[d * n + i] = K[i][i + d - kb])
+  auto combine = [&](int n, int trim, const double* K, const double* M, double b, double sc) {
+    const int q = n - 2 * trim;
+    std::vector<double> S((size_t)q * w, 0.0);
+    for (int i = 0; i < q; ++i)
+      for (int d = 0; d < w; ++d) {
+        const int j = i + d - kb;
+        if (j < 0 || j >= q) continue;
+        const size_t at = (size_t)d * n + i + trim;
+        S[(size_t)i * w + d] = (D.a != 0.0 ? D.a * M[at] : 0.0) + sc * b * K[at];
+      }
+    return S;
+  };
+  std::vector<double> Lf_s((size_t)D.n_scales * qs * c), Lb_s(Lf_s.size());
+  std::vector<double> Lf_t((size_t)D.n_scales * qt * c), Lb_t(Lf_t.size());
+  std::vector<double> sc(D.scales, D.scales + D.n_scales);
+  for (int j = 0; j < D.n_scales; ++j) {
+    auto S = combine(D.n_s, D.trim_s, D.Ks, D.Ms, D.bs, sc[j]);
+    auto T = combine(D.n_t, D.trim_t, D.Kt, D.Mt, D.bt, sc[j]);
+    if (band_cholesky(qs, kb, S.data(), &Lf_s[(size_t)j * qs * c], &Lb_s[(size_t)j * qs * c]) != MOFEM_OK ||
+        band_cholesky(qt, kb, T.data(), &Lf_t[(size_t)j * qt * c], &Lb_t[(size_t)j * qt * c]) != MOFEM_OK)
+      return fail(MOFEM_E_NUMERIC, "prec_setup_banded: a factor is not positive definite");
+  }
+  auto* p = new mofem_prec_s();
+  p->qs = qs;
+  p->qt = qt;
+  p->ps = qs;
+  p->pt = qt;
+  p->precision = MOFEM_PREC_F64;
+  p->banded = 1;
+  p->kb = kb;
+  p->n_sets = D.n_scales;
+  int rc = upload_f64(&p->Lf_s, Lf_s);
+  if (!rc) rc = upload_f64(&p->Lb_s, Lb_s);
+  if (!rc) rc = upload_f64(&p->Lf_t, Lf_t);
+  if (!rc) rc = upload_f64(&p->Lb_t, Lb_t);
+  if (!rc) rc = upload_f64(&p->scales, sc);
+  if (rc) {
+    mofem_prec_destroy(p);
+    return rc;
+  }
+  *out = p;
+  return MOFEM_OK;
+}
+
 extern "C" int mofem_prec_set_coeffs(mofem_prec_t p, double a, double bs, double bt, double d) {
   clear_error();
   if (!p) return fail(MOFEM_E_ARG, "prec_set_coeffs: NULL handle");
+  if (p->banded) return fail(MOFEM_E_UNSUPPORTED, "prec_set_coeffs: banded product preconditioner");
   p->alpha = a;
   p->bs = bs;
   p->bt = bt;
@@ -528,6 +592,8 @@ extern "C" int mofem_prec_set_precision(mofem_prec_t p, int precision) {
   clear_error();
   if (!p) return fail(MOFEM_E_ARG, "prec_set_precision: NULL handle");
   if (precision < MOFEM_PREC_F64 || precision > MOFEM_PREC_BF16_FWD) return fail(MOFEM_E_ARG, "unknown precision");
+  if (p->banded && precision != MOFEM_PREC_F64)
+    return fail(MOFEM_E_UNSUPPORTED, "prec_set_precision: the banded product preconditioner is FP64 only");
   p->precision = precision;
   return MOFEM_OK;
 }
@@ -535,6 +601,7 @@ extern "C" int mofem_prec_set_precision(mofem_prec_t p, int precision) {
 extern "C" int mofem_prec_eigenvalues(mofem_prec_t p, double* lam, double* mu) {
   clear_error();
   if (!p) return fail(MOFEM_E_ARG, "prec_eigenvalues: NULL handle");
+  if (p->banded) return fail(MOFEM_E_UNSUPPORTED, "prec_eigenvalues: banded product preconditioner");
   if (lam) std::memcpy(lam, p->h_lam.data(), sizeof(double) * p->qs);
   if (mu) std::memcpy(mu, p->h_mu.data(), sizeof(double) * p->qt);
   return MOFEM_OK;
@@ -545,6 +612,7 @@ extern "C" size_t mofem_prec_workspace_size(mofem_prec_t p, int batch) {
   // sized for the widest precision (FP64 intermediates), so that a workspace
   // stays valid when mofem_prec_set_precision switches the handle
   size_t items = (size_t)p->ps * p->pt * batch;
+  if (p->banded) return 2 * align_up(items * 8, 256) + 2048;  // substitution scratch, S^-1 R
   return 3 * align_up(items * 8, 256) + 2048;
 }
 
@@ -574,6 +642,7 @@ struct PrecInput {
 };
 PrecInput prec_input(mofem_prec_t p, void* ws, size_t ws_bytes, int batch) {
   PrecInput in;
+  if (p->banded) return in;  // the solves read R itself
   const size_t items = (size_t)p->ps * p->pt;
   Carve c(ws, ws_bytes);
   if (p->precision == MOFEM_PREC_F64) {
@@ -609,6 +678,35 @@ int prec_launch(mofem_prec_t p, const double* R, double* Z, long long stride, in
                 int n_items = -1, int input_ready = 0) {
   const double items_done = n_items < 0 ? batch : n_items;
   const size_t items = (size_t)p->ps * p->pt;
+  if (p->banded) {
+    // Z = S^-1 R T^-1: two transposing banded solves
+    Carve c(ws, ws_bytes);
+    double* W = c.take<double>(items * batch);
+    double* Yt = c.take<double>(items * batch);
+    if (!W || !Yt) return fail(MOFEM_E_ARG, "prec_apply: workspace too small");
+    BcholArgs a{};
+    a.W = W;
+    a.w_stride = (long long)items;
+    a.scales = p->scales;
+    a.n_sets = p->n_sets;
+    a.item_scale = item_scale;
+    a.active = active;
+    a.X = R; a.x_stride = stride; a.ld_x = p->qt;
+    a.Out = Yt; a.o_stride = (long long)items; a.ld_o = p->qs;
+    a.n_rows = p->qs; a.n_cols = p->qt; a.Lf = p->Lf_s; a.Lb = p->Lb_s;
+    {
+      TraceScope trace(MOFEM_TRACE_BCHOL, items_done, s);
+      if (launch_bchol(a, p->kb, batch, s)) return fail(MOFEM_E_HIP, "banded solve launch");
+    }
+    a.X = Yt; a.x_stride = (long long)items; a.ld_x = p->qs;
+    a.Out = Z; a.o_stride = stride; a.ld_o = p->qt;
+    a.n_rows = p->qt; a.n_cols = p->qs; a.Lf = p->Lf_t; a.Lb = p->Lb_t;
+    {
+      TraceScope trace(MOFEM_TRACE_BCHOL, items_done, s);
+      if (launch_bchol(a, p->kb, batch, s)) return fail(MOFEM_E_HIP, "banded solve launch");
+    }
+    return MOFEM_OK;
+  }
   GemmArgs g{};
   g.lam = p->lam;
   g.mu = p->mu;
@@ -789,6 +887,7 @@ extern "C" int mofem_prec_apply(mofem_prec_t p, const double* R, double* Z, long
 extern "C" int mofem_prec_set_tile(mofem_prec_t p, int batch, int tile) {
   clear_error();
   if (!p || batch < 1 || (tile != 64 && tile != 128)) return fail(MOFEM_E_ARG, "prec_set_tile: bad argument");
+  if (p->banded) return fail(MOFEM_E_UNSUPPORTED, "prec_set_tile: banded product preconditioner");
   const long long key = ((long long)p->precision << 32) | (unsigned)batch;
   auto it = std::find_if(p->tuned.begin(), p->tuned.end(), [&](auto& kv) { return kv.first == key; });
   if (it == p->tuned.end()) p->tuned.push_back({key, tile});
@@ -802,6 +901,7 @@ extern "C" int mofem_prec_set_tile(mofem_prec_t p, int batch, int tile) {
 extern "C" int mofem_prec_tune(mofem_prec_t p, int batch, int* tile_out, void* stream) {
   clear_error();
   if (!p || batch < 1) return fail(MOFEM_E_ARG, "prec_tune: bad argument");
+  if (p->banded) return fail(MOFEM_E_UNSUPPORTED, "prec_tune: banded product preconditioner");
   hipStream_t s = (hipStream_t)stream;
   const long long n = (long long)p->qs * p->qt;
   double *R = nullptr, *Z = nullptr;
@@ -994,8 +1094,9 @@ struct PcgRun {
     PCG_LTRY(launch_reduce(w.part_b, kVecBlocks, w.tr, batch, s));
     PCG_LTRY(launch_pcg_confirm(w.tr, w.target2, w.active, w.claim, w.restart, batch, s));
     PCG_LTRY(launch_copy_masked(w.Z, w.R, n, n, n, batch, w.restart, s));
-    PCG_LTRY(launch_pad_operand(w.R, n, op->qs, op->qt, pin.f64, pin.f32, pin.hi, pin.lo, pin.stride,
-                                (pin.hi != nullptr) ? 1 : 0, batch, w.restart, s));
+    if (pin.f64 || pin.f32 || pin.hi)
+      PCG_LTRY(launch_pad_operand(w.R, n, op->qs, op->qt, pin.f64, pin.f32, pin.hi, pin.lo, pin.stride,
+                                  (pin.hi != nullptr) ? 1 : 0, batch, w.restart, s));
     // Z = P^{-1}(R); <R, Z>, <Z, Y>; beta (zero after a restart); Q = Z + beta Q
     PCG_TRY(prec_launch(prec, w.R, w.Z, n, batch, item_scale, w.prec_ws, w.prec_bytes, w.active, s, n_trace, 1));
     rec_prec += n_trace;
@@ -1054,6 +1155,7 @@ int pcg_prepare(PcgRun& r, mofem_op_t op, mofem_prec_t prec, const double* Rhs, 
 }
 
 int trace_class_of(mofem_prec_t p) {
+  if (p->banded) return MOFEM_TRACE_BCHOL;
   return p->precision == MOFEM_PREC_F64      ? MOFEM_TRACE_GEMM_F64
          : p->precision == MOFEM_PREC_F32    ? MOFEM_TRACE_GEMM_F32
          : p->precision == MOFEM_PREC_BF16   ? MOFEM_TRACE_GEMM_BF16
@@ -1151,7 +1253,7 @@ extern "C" int mofem_pcg_solve(mofem_op_t op, mofem_prec_t prec, const double* R
       trace_add_items(MOFEM_TRACE_GEMM_BF16, 2.0 * (ex_prec - r.rec_prec));
       trace_add_items(MOFEM_TRACE_GEMM_BF16X3, 2.0 * (ex_prec - r.rec_prec));
     } else {
-      trace_add_items(trace_class_of(prec), 4.0 * (ex_prec - r.rec_prec));
+      trace_add_items(trace_class_of(prec), (prec->banded ? 2.0 : 4.0) * (ex_prec - r.rec_prec));
     }
   }
   int result = MOFEM_OK;

@@ -439,6 +439,9 @@ int launch_cg_update_pad(double* U, double* R, const double* Q, const double* Y,
                          const double* den, double* alpha_out, int qs, int qt, long long stride,
                          long long u_stride, int batch, double* partial, const int* active, unsigned short* ohi,
                          unsigned short* olo, double* o64, float* o32, long long o_stride, hipStream_t s) {
+  if (!ohi && !o64 && !o32)  // no transform operand wanted
+    return launch_cg_update(U, R, Q, Y, num, den, alpha_out, (long long)qs * qt, stride, u_stride, batch, partial,
+                            active, s);
   hipLaunchKernelGGL(cg_update_pad_kernel, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, U, R, Q, Y, num, den,
                      alpha_out, qt, (long long)qs * qt, stride, u_stride, partial, active, ohi, olo, o64, o32,
                      o_stride);

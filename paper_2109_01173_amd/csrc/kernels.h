@@ -35,6 +35,28 @@ int band_cols_per_block(int kb);
 int band_supported_terms(int nt);
 int launch_band_apply(const BandArgs& a, int kb, int nt, int batch, bool pattern, hipStream_t s);
 
+// ---- banded Cholesky solves of the product preconditioners (k_bchol.hip) -----
+// Out^T = S^{-1} X per item: X is n_rows x n_cols (row length ld_x), S = L L^T
+// of order n_rows with half-width kb; Out is n_cols x n_rows (row length ld_o).
+struct BcholArgs {
+  const double* X;
+  long long x_stride;
+  int ld_x;
+  double* W;               // scratch items, n_rows x n_cols (row length n_cols)
+  long long w_stride;
+  double* Out;
+  long long o_stride;
+  int ld_o;
+  int n_rows, n_cols;
+  const double* Lf;        // [n_sets][n_rows][kb+1]: 1/L[i][i], L[i][i-1], .., L[i][i-kb]
+  const double* Lb;        // [n_sets][n_rows][kb+1]: 1/L[i][i], L[i+1][i], .., L[i+kb][i]
+  const double* scales;    // [n_sets]: item b uses the set whose scale equals item_scale[b]
+  int n_sets;              //           (1.0 when item_scale is null; set 0 if none matches)
+  const double* item_scale;
+  const int* active;
+};
+int launch_bchol(const BcholArgs& a, int kb, int batch, hipStream_t s);
+
 // ---- dense transforms on MFMA (k_gemm.hip) ------------------------------------
 // C[m][n] = sum_k A[m][k] B[n][k]   (both operands K-contiguous, "NT").
 // Padded operands: rows and row length rounded up to kPad, zero padding.

@@ -37,4 +37,11 @@ int geneig_dense(int q, int kb, const double* K, const double* M, double* lam, d
 // restricted to indices [t, n - t).
 void band_to_dense(int n, int kb, const double* band, int trim, double* dense);
 
+// ---- banded Cholesky (host_chol.cpp) ------------------------------------------
+// S: q rows of 2 kb + 1 entries, S[i * (2 kb + 1) + kb + (j - i)] = S_ij, symmetric
+// positive definite.  Writes Lf[i * (kb + 1) + l] = L[i][i - l] and
+// Lb[i * (kb + 1) + l] = L[i + l][i] for l = 1..kb (0 outside the matrix), and
+// 1 / L[i][i] at l = 0, where S = L L^T.  MOFEM_E_NUMERIC if S is not SPD.
+int band_cholesky(int q, int kb, const double* S, double* Lf, double* Lb);
+
 }  // namespace mofem

@@ -34,9 +34,11 @@ W_PPROFILE_D, W_PPROFILE_INV, W_PPROFILE_D2L = 7, 8, 9
 PREC_F64, PREC_F32, PREC_BF16, PREC_BF16X3, PREC_BF16X2, PREC_BF16_FWD = range(6)
 PCG_FLEXIBLE, PCG_ZERO_GUESS, PCG_TAU_STOP = 1, 2, 4
 KIN_NONE, KIN_DIB = 0, 1
-TRACE_BAND, TRACE_GEMM_F64, TRACE_GEMM_BF16X3, TRACE_GEMM_BF16, TRACE_VEC, TRACE_GEMM_BF16X2, TRACE_GEMM_F32 = range(7)
-TRACE_CLASSES = 7
+(TRACE_BAND, TRACE_GEMM_F64, TRACE_GEMM_BF16X3, TRACE_GEMM_BF16, TRACE_VEC, TRACE_GEMM_BF16X2, TRACE_GEMM_F32,
+ TRACE_BCHOL) = range(8)
+TRACE_CLASSES = 8
 MAX_TERMS = 8
+MAX_SCALES = 8
 
 _vp = ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -66,6 +68,14 @@ class PrecDesc(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("beta_s", ctypes.c_double),
                 ("beta_t", ctypes.c_double), ("delta", ctypes.c_double),
                 ("precision", ctypes.c_int)]
+
+
+class BPrecDesc(ctypes.Structure):
+    _fields_ = [("kb", ctypes.c_int), ("n_s", ctypes.c_int), ("n_t", ctypes.c_int),
+                ("trim_s", ctypes.c_int), ("trim_t", ctypes.c_int),
+                ("Ks", _vp), ("Ms", _vp), ("Kt", _vp), ("Mt", _vp),
+                ("a", ctypes.c_double), ("bs", ctypes.c_double), ("bt", ctypes.c_double),
+                ("n_scales", ctypes.c_int), ("scales", ctypes.c_double * MAX_SCALES)]
 
 
 class PcgGroup(ctypes.Structure):
@@ -106,6 +116,8 @@ mofem_op_apply = _proto("mofem_op_apply", ctypes.c_int,
                         [_vp, _vp, _ll, _vp, _ll, ctypes.c_int, _vp, _vp, _vp])
 mofem_prec_setup = _proto("mofem_prec_setup", ctypes.c_int, [ctypes.POINTER(PrecDesc), ctypes.POINTER(_vp)])
 mofem_prec_destroy = _proto("mofem_prec_destroy", ctypes.c_int, [_vp])
+mofem_prec_setup_banded = _proto("mofem_prec_setup_banded", ctypes.c_int,
+                                 [ctypes.POINTER(BPrecDesc), ctypes.POINTER(_vp)])
 mofem_prec_set_coeffs = _proto("mofem_prec_set_coeffs", ctypes.c_int,
                                [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double])
 mofem_prec_set_precision = _proto("mofem_prec_set_precision", ctypes.c_int, [_vp, ctypes.c_int])
@@ -148,7 +160,8 @@ EXPORTS = ["mofem_version", "mofem_last_error", "mofem_assemble_1d", "mofem_gene
            "mofem_op_create", "mofem_op_destroy", "mofem_op_shape", "mofem_op_apply",
            "mofem_prec_setup", "mofem_prec_destroy", "mofem_prec_set_coeffs",
            "mofem_prec_set_precision", "mofem_prec_eigenvalues", "mofem_prec_workspace_size",
-           "mofem_prec_apply", "mofem_prec_tune", "mofem_prec_set_tile", "mofem_pcg_workspace_size",
+           "mofem_prec_apply", "mofem_prec_tune", "mofem_prec_set_tile", "mofem_prec_setup_banded",
+           "mofem_pcg_workspace_size",
            "mofem_pcg_solve",
            "mofem_imex_workspace_size", "mofem_imex_step", "mofem_dot_accumulate",
            "mofem_imex_adjoint_workspace_size", "mofem_imex_adjoint_step", "mofem_pcg_solve_async",
@@ -356,6 +369,32 @@ class Preconditioner:
                               _dptr(ws), ws.numel(), _stream(stream))
         _check(rc, "mofem_prec_apply")
         return Z
+
+
+class BandedPreconditioner(Preconditioner):
+    """Product preconditioner P_j(U) = S_j U T_j with S_j = a Ms + c_j bs Ks and
+    T_j = a Mt + c_j bt Kt, applied by banded Cholesky solves
+    (mofem_prec_setup_banded); FP64 only.  Ms, Mt may be None when a == 0."""
+
+    def __init__(self, Ks, Ms, Kt, Mt, a=0.0, bs=1.0, bt=1.0, scales=(1.0,), trim_s=0, trim_t=0):
+        if not 1 <= len(scales) <= MAX_SCALES:
+            raise ValueError("1..%d scales" % MAX_SCALES)
+        d = BPrecDesc()
+        keep = [None if x is None else np.ascontiguousarray(x, dtype=np.float64) for x in (Ks, Ms, Kt, Mt)]
+        d.kb = (keep[0].shape[0] - 1) // 2
+        d.n_s, d.n_t = keep[0].shape[1], keep[2].shape[1]
+        d.trim_s, d.trim_t = trim_s, trim_t
+        d.Ks, d.Ms, d.Kt, d.Mt = (None if x is None else x.ctypes.data for x in keep)
+        d.a, d.bs, d.bt = float(a), float(bs), float(bt)
+        d.n_scales = len(scales)
+        for j, c in enumerate(scales):
+            d.scales[j] = float(c)
+        h = _vp()
+        _check(mofem_prec_setup_banded(ctypes.byref(d), ctypes.byref(h)), "mofem_prec_setup_banded")
+        self.handle = h
+        self.shape = (d.n_s - 2 * trim_s, d.n_t - 2 * trim_t)
+        self.precision = PREC_F64
+        self.scales = tuple(float(c) for c in scales)
 
 
 def pcg_workspace(op, prec, batch, device="cuda"):

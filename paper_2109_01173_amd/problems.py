@@ -2,9 +2,10 @@
 
 Only bookkeeping happens here: which assembled 1D matrix goes into which term
 of the multiterm operator.  Assembly (``mofem_assemble_1d``), the
-eigen-decomposition and every apply/solve run in libmofem.  The one piece of
-arithmetic done in Python is the setup-time sum of two assembled bands
-(B1 + gamma M3, the left factor of one elliptic term), O(k n) numbers.
+eigen-decomposition and every apply/solve run in libmofem.  The only
+arithmetic done in Python is setup-time sums of assembled bands (B1 + gamma M3,
+the left factor of one elliptic term, and A + B2 of the product
+preconditioner), O(k n) numbers.
 
 Operators (rows = s, the base coordinate; columns = t):
 * x-normal elliptic, eq. (73) (lumped: eq. (75)):
@@ -15,7 +16,9 @@ Operators (rows = s, the base coordinate; columns = t):
 * rectangle (eq. (28) on [0, l]^2): elliptic (A + g M) U M + M U A,
   IMEX  M U M + c (A U M + M U A).
 Preconditioners: the spectral single-term form with the pencils
-(B1, M3) x (A, M) on x-normal domains and (A, M) x (A, M) on the rectangle.
+(B1, M3) x (A, M) on x-normal domains and (A, M) x (A, M) on the rectangle;
+the paper's product preconditioners eqs. (80), (95), (96) by banded Cholesky
+solves (XNormal.product_prec).
 """
 import math
 
@@ -96,6 +99,21 @@ class XNormal:
         # stiffness part K of L_c = Mass + c K (for the gradient in d)
         self.stiff = mf.Operator([dict(t, scaled=False) for t in terms[1:]], **common) if imex else None
         self.prec = mf.Preconditioner(B1, M3, A, M, coeffs, trim, trim, precision)
+        self.imex = imex
+
+    def product_prec(self, scales=(1.0,)):
+        """The paper's own product preconditioner by banded Cholesky solves:
+        elliptic eq. (80), B1 U (A + B2) (lumped: A1 U (A + A2));
+        IMEX eq. (95), (M3 + c B1) U (M + c (A + B2)) (lumped eq. (96):
+        M0 D1 and M0 in place of M3 and M), one factor pair per c = d tau in
+        `scales` (the item scale of each item selects its pair)."""
+        b = self.bands
+        AB2 = b["A"] + b["B2"]
+        if self.imex:
+            return mf.BandedPreconditioner(b["B1"], b["M3"], AB2, b["M"], a=1.0, bs=1.0, bt=1.0, scales=scales,
+                                           trim_s=self.trim, trim_t=self.trim)
+        return mf.BandedPreconditioner(b["B1"], None, AB2, None, a=0.0, bs=1.0, bt=1.0, scales=(1.0,),
+                                       trim_s=self.trim, trim_t=self.trim)
 
 
 class Rect:

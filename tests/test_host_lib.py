@@ -122,3 +122,26 @@ def test_argument_errors_are_reported():
                               None) == mf.E_ARG
     assert mf.mofem_op_apply(None, None, 0, None, 0, 1, None, None, None) == mf.E_ARG
     assert mf.mofem_version() >= 100
+
+
+def test_banded_product_setup_errors_on_the_host():
+    """mofem_prec_setup_banded factorises on the host before any device call:
+    an indefinite factor (here -B1) is MOFEM_E_NUMERIC, bad counts E_ARG."""
+    B1 = mf.assemble_1d(2, 8, 1, 1)
+    A = mf.assemble_1d(2, 8, 1, 1)
+    with pytest.raises(mf.MofemError) as e:
+        mf.BandedPreconditioner(-B1, None, A, None, a=0.0, trim_s=1, trim_t=1)
+    assert e.value.code == mf.E_NUMERIC
+    d = mf.BPrecDesc()
+    keep = [np.ascontiguousarray(B1), np.ascontiguousarray(A)]
+    d.kb, d.n_s, d.n_t, d.trim_s, d.trim_t = 2, B1.shape[1], A.shape[1], 1, 1
+    d.Ks, d.Kt = keep[0].ctypes.data, keep[1].ctypes.data
+    d.a, d.bs, d.bt = 0.0, 1.0, 1.0
+    h = ctypes.c_void_p()
+    for n_scales in (0, mf.MAX_SCALES + 1):
+        d.n_scales = n_scales
+        assert mf.mofem_prec_setup_banded(ctypes.byref(d), ctypes.byref(h)) == mf.E_ARG
+    d.n_scales, d.scales[0] = 1, 1.0
+    d.a = 1.0  # a != 0 needs the mass bands
+    assert mf.mofem_prec_setup_banded(ctypes.byref(d), ctypes.byref(h)) == mf.E_ARG
+    assert mf.mofem_prec_setup_banded(None, None) == mf.E_ARG
