@@ -467,6 +467,11 @@ enum {
 };
 /* on != 0: discard earlier records and start recording; on == 0: stop. */
 int mofem_trace_enable(int on);
+/* Record only the classes whose bit (1 << class) is set in `mask` (default:
+   all).  Every recorded launch adds two timing events (without system-scope
+   fences) to its stream; a selection keeps a traced run closer still to an
+   untraced one.  Never fails. */
+int mofem_trace_select(unsigned mask);
 /* Synchronise the recorded events and return, for one class, the summed
    kernel time in milliseconds, the number of launches and the summed batch
    items processed (any pointer may be NULL).  Errors: MOFEM_E_ARG (class). */

@@ -65,6 +65,7 @@ struct TraceRec {
 struct TraceState {
   std::mutex mu;
   bool on = false;
+  unsigned mask = ~0u;  // classes that record events (mofem_trace_select)
   std::vector<TraceRec> recs;
   std::vector<hipEvent_t> pool;
   double total_ms[MOFEM_TRACE_CLASSES] = {};
@@ -81,7 +82,11 @@ hipEvent_t trace_event(TraceState& t) {
     t.pool.pop_back();
     return e;
   }
+  // timing-only events: no system-scope fence, so a record does not write back
+  // and invalidate the caches between the traced kernels
   hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) == hipSuccess) return e;
+  (void)hipGetLastError();
   if (hipEventCreate(&e) != hipSuccess) return nullptr;
   return e;
 }
@@ -112,7 +117,7 @@ void trace_add_items(int cls, double delta) {
   if (g_trace_suspended) return;
   TraceState& t = trace_state();
   std::lock_guard<std::mutex> g(t.mu);
-  if (t.on) t.items[cls] += delta;
+  if (t.on && ((t.mask >> cls) & 1u)) t.items[cls] += delta;
 }
 // RAII: records e0 now and e1 when the scope (one kernel launch) ends
 struct TraceScope {
@@ -124,7 +129,7 @@ struct TraceScope {
     if (g_trace_suspended) return;
     TraceState& t = trace_state();
     std::lock_guard<std::mutex> g(t.mu);
-    if (!t.on) return;
+    if (!t.on || !((t.mask >> c) & 1u)) return;
     e0 = trace_event(t);
     e1 = trace_event(t);
     if (e0 && e1) (void)hipEventRecord(e0, s);
@@ -154,6 +159,14 @@ extern "C" int mofem_trace_enable(int on) {
     }
   }
   t.on = on != 0;
+  return MOFEM_OK;
+}
+
+extern "C" int mofem_trace_select(unsigned mask) {
+  clear_error();
+  TraceState& t = trace_state();
+  std::lock_guard<std::mutex> g(t.mu);
+  t.mask = mask;
   return MOFEM_OK;
 }
 

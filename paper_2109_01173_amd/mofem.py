@@ -153,6 +153,7 @@ mofem_imex_graph_destroy = _proto("mofem_imex_graph_destroy", ctypes.c_int, [_vp
 mofem_pcg_solve_many = _proto("mofem_pcg_solve_many", ctypes.c_int,
                               [ctypes.c_int, ctypes.POINTER(PcgGroup), ctypes.POINTER(_vp), _vp])
 mofem_trace_enable = _proto("mofem_trace_enable", ctypes.c_int, [ctypes.c_int])
+mofem_trace_select = _proto("mofem_trace_select", ctypes.c_int, [ctypes.c_uint])
 mofem_trace_read = _proto("mofem_trace_read", ctypes.c_int,
                           [ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_longlong), _dp])
 
@@ -167,7 +168,7 @@ EXPORTS = ["mofem_version", "mofem_last_error", "mofem_assemble_1d", "mofem_gene
            "mofem_imex_adjoint_workspace_size", "mofem_imex_adjoint_step", "mofem_pcg_solve_async",
            "mofem_pcg_solve_many",
            "mofem_imex_graph_create", "mofem_imex_graph_launch", "mofem_imex_graph_result",
-           "mofem_imex_graph_destroy", "mofem_trace_enable", "mofem_trace_read"]
+           "mofem_imex_graph_destroy", "mofem_trace_enable", "mofem_trace_select", "mofem_trace_read"]
 
 
 class MofemError(RuntimeError):
@@ -532,6 +533,12 @@ def dot_accumulate(X, Y, out, alpha=1.0, beta=0.0, stream=None):
 
 def trace_enable(on=True):
     _check(mofem_trace_enable(int(on)), "mofem_trace_enable")
+
+
+def trace_select(classes=None):
+    """Record only these trace classes (None: all)."""
+    mask = 0xFFFFFFFF if classes is None else sum(1 << c for c in classes)
+    _check(mofem_trace_select(mask), "mofem_trace_select")
 
 
 def trace_read(cls):
