@@ -685,10 +685,11 @@ int prec_tile(mofem_prec_t p, int batch) {
 }
 
 // input_ready: the padded operand of R is already in the workspace (written
-// by the fused CG update).
+// by the fused CG update).  z32: if set (FP32 and BF16 transforms only), the
+// last transform writes Z in FP32 there (same item stride) instead of Z.
 int prec_launch(mofem_prec_t p, const double* R, double* Z, long long stride, int batch,
                 const double* item_scale, void* ws, size_t ws_bytes, const int* active, hipStream_t s,
-                int n_items = -1, int input_ready = 0) {
+                int n_items = -1, int input_ready = 0, float* z32 = nullptr) {
   const double items_done = n_items < 0 ? batch : n_items;
   const size_t items = (size_t)p->ps * p->pt;
   if (p->banded) {
@@ -802,8 +803,8 @@ int prec_launch(mofem_prec_t p, const double* R, double* Z, long long stride, in
     if (gemm(O_PAD_N)) return fail(MOFEM_E_HIP, "gemm launch");
     g.M = p->qs; g.N = p->qt; g.K = p->qt;
     g.a_hi = T1; g.a_stride = istr; g.b_hi = p->Vt_f; g.b_stride = 0;
-    g.c64 = Z; g.c_stride = stride; g.divide = 0;
-    if (gemm(O_F64_RAW)) return fail(MOFEM_E_HIP, "gemm launch");
+    g.c64 = Z; g.c_hi = z32; g.c_stride = stride; g.divide = 0;
+    if (gemm(z32 ? O_F32_RAW : O_F64_RAW)) return fail(MOFEM_E_HIP, "gemm launch");
   } else {
     unsigned short* T0h = c.take<unsigned short>(items * batch);
     unsigned short* T0l = c.take<unsigned short>(items * batch);
@@ -851,8 +852,8 @@ int prec_launch(mofem_prec_t p, const double* R, double* Z, long long stride, in
     g.M = p->qs; g.N = p->qt; g.K = p->qt;
     g.a_hi = T1h; g.a_lo = T1l; g.a_stride = istr;
     g.b_hi = p->Vt_h; g.b_lo = p->Vt_l; g.b_stride = 0;
-    g.c64 = Z; g.c_hi = nullptr; g.c_lo = nullptr; g.c_stride = stride; g.divide = 0;
-    if (run(3, O_F64_RAW)) return fail(MOFEM_E_HIP, "gemm launch");
+    g.c64 = Z; g.c_hi = z32; g.c_lo = nullptr; g.c_stride = stride; g.divide = 0;
+    if (run(3, z32 ? O_F32_RAW : O_F64_RAW)) return fail(MOFEM_E_HIP, "gemm launch");
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(MOFEM_E_HIP, std::string("prec_apply launch: ") + hipGetErrorString(e));
@@ -1052,6 +1053,7 @@ struct PcgRun {
   hipStream_t s;
   PcgWs w{};
   PrecInput pin;
+  float* z32 = nullptr;  // FP32 Z (in w.Z's memory) for FP32 / BF16 preconditioners
   int n_trace;  // item count recorded with traced launches
   double rec_band = 0, rec_prec = 0;
 
@@ -1082,11 +1084,20 @@ struct PcgRun {
     PCG_LTRY(launch_reduce(w.part_a, kVecBlocks, w.rr, batch, s));
     PCG_LTRY(launch_pcg_init(w.rhs2, w.rr, w.target2, w.active, w.claim, w.restart, w.status, w.iters, tol * tol,
                              (flags & MOFEM_PCG_TAU_STOP) ? 1 : 0, batch, s));
-    PCG_TRY(prec_launch(prec, w.R, w.Z, n, batch, item_scale, w.prec_ws, w.prec_bytes, w.active, s, n_trace));
+    PCG_TRY(prec_launch(prec, w.R, w.Z, n, batch, item_scale, w.prec_ws, w.prec_bytes, w.active, s, n_trace, 0,
+                        z32));
     rec_prec += n_trace;
-    PCG_LTRY(launch_dot_partial(w.R, w.Z, n, n, batch, w.part_a, w.active, s));
+    if (z32) {
+      PCG_LTRY(launch_dot_partial(w.R, z32, n, n, batch, w.part_a, w.active, s));
+    } else {
+      PCG_LTRY(launch_dot_partial(w.R, w.Z, n, n, batch, w.part_a, w.active, s));
+    }
     PCG_LTRY(launch_reduce(w.part_a, kVecBlocks, w.rz, batch, s));
-    PCG_LTRY(launch_direction(w.Q, w.Z, nullptr, n, n, batch, w.active, s));
+    if (z32) {
+      PCG_LTRY(launch_direction(w.Q, z32, nullptr, n, n, batch, w.active, s));
+    } else {
+      PCG_LTRY(launch_direction(w.Q, w.Z, nullptr, n, n, batch, w.active, s));
+    }
     return MOFEM_OK;
   }
 
@@ -1111,14 +1122,23 @@ struct PcgRun {
       PCG_LTRY(launch_pad_operand(w.R, n, op->qs, op->qt, pin.f64, pin.f32, pin.hi, pin.lo, pin.stride,
                                   (pin.hi != nullptr) ? 1 : 0, batch, w.restart, s));
     // Z = P^{-1}(R); <R, Z>, <Z, Y>; beta (zero after a restart); Q = Z + beta Q
-    PCG_TRY(prec_launch(prec, w.R, w.Z, n, batch, item_scale, w.prec_ws, w.prec_bytes, w.active, s, n_trace, 1));
+    PCG_TRY(prec_launch(prec, w.R, w.Z, n, batch, item_scale, w.prec_ws, w.prec_bytes, w.active, s, n_trace, 1,
+                        z32));
     rec_prec += n_trace;
-    PCG_LTRY(launch_dot2_partial(w.R, w.Z, w.Z, w.Y, n, n, batch, w.part_a, w.part_b, w.active, s));
+    if (z32) {
+      PCG_LTRY(launch_zdots_partial(w.R, z32, w.Y, n, n, batch, w.part_a, w.part_b, w.active, s));
+    } else {
+      PCG_LTRY(launch_zdots_partial(w.R, w.Z, w.Y, n, n, batch, w.part_a, w.part_b, w.active, s));
+    }
     PCG_LTRY(launch_reduce(w.part_a, kVecBlocks, w.rz_new, batch, s));
     PCG_LTRY(launch_reduce(w.part_b, kVecBlocks, w.zy, batch, s));
     PCG_LTRY(launch_beta_restart(w.rz_new, w.rz, w.zy, w.alpha, w.beta, w.restart,
                                  (flags & MOFEM_PCG_FLEXIBLE) ? 1 : 0, batch, w.active, s));
-    PCG_LTRY(launch_direction(w.Q, w.Z, w.beta, n, n, batch, w.active, s));
+    if (z32) {
+      PCG_LTRY(launch_direction(w.Q, z32, w.beta, n, n, batch, w.active, s));
+    } else {
+      PCG_LTRY(launch_direction(w.Q, w.Z, w.beta, n, n, batch, w.active, s));
+    }
     return MOFEM_OK;
   }
 
@@ -1164,6 +1184,9 @@ int pcg_prepare(PcgRun& r, mofem_op_t op, mofem_prec_t prec, const double* Rhs, 
   r.n_trace = batch;
   if (!carve_pcg(op, prec, batch, workspace, ws_bytes, &r.w)) return fail(MOFEM_E_ARG, "pcg_solve: workspace too small");
   r.pin = prec_input(prec, r.w.prec_ws, r.w.prec_bytes, batch);
+  // the preconditioned residual of a low-precision preconditioner is kept in
+  // FP32 (its own error is far larger); the recurrence stays FP64
+  r.z32 = (!prec->banded && prec->precision != MOFEM_PREC_F64) ? reinterpret_cast<float*>(r.w.Z) : nullptr;
   return MOFEM_OK;
 }
 

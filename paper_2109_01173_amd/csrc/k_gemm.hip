@@ -250,6 +250,8 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g) {
         if (!in) v = 0.0;
         if (OMODE == O_F64_RAW) {
           if (in) C64[(size_t)row * g.N + col] = v;
+        } else if (OMODE == O_F32_RAW) {
+          if (in) C32[(size_t)row * g.N + col] = (float)v;
         } else {
           const size_t idx = (OMODE == O_PAD_T) ? (size_t)col * Mp + row : (size_t)row * Np + col;
           C32[idx] = (float)v;
@@ -277,7 +279,8 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
   // the staging tile of the epilogue, so the output leaves in whole rows.
   constexpr int SLD = TB + 8;  // staging row length (16-byte aligned)
   constexpr int MAIN = (2 + (ALO ? 1 : 0) + (BLO ? 1 : 0)) * TB * LDS_K;
-  constexpr int STAGE = (OMODE == O_F64_RAW) ? 0 : TB * SLD;
+  constexpr bool RAW = (OMODE == O_F64_RAW || OMODE == O_F32_RAW);
+  constexpr int STAGE = RAW ? 0 : TB * SLD;
   __shared__ __attribute__((aligned(16))) unsigned short lds[MAIN > STAGE ? MAIN : STAGE];
   typedef unsigned short Row[LDS_K];
   Row* Ah = reinterpret_cast<Row*>(lds);
@@ -300,29 +303,31 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
   const unsigned short* __restrict__ Bhg = (const unsigned short*)g.b_hi + (size_t)b * g.b_stride;
   const unsigned short* __restrict__ Blg = (const unsigned short*)g.b_lo + (size_t)b * g.b_stride;
 
-  // staging: TPR threads per tile row, each a k segment of BK / TPR values
-  constexpr int TPR = 256 / TB;
-  constexpr int NV = BK / TPR / 8;  // 16-byte vectors per thread and operand
-  const int lrow = tid / TPR, lk = (tid % TPR) * (BK / TPR);
+  // staging of a k tile (BK values = CPR 16-byte chunks per row).  128-row
+  // tiles: consecutive threads take consecutive chunks of a row, so one load
+  // instruction of a wave covers whole 128-byte row pieces (RPP rows per pass,
+  // NV passes).  64-row tiles: each thread takes NV consecutive chunks of one
+  // row (measured faster at that size).
+  constexpr int CPR = BK / 8;
+  constexpr bool ROWWISE = (TB == 128);
+  constexpr int RPP = 256 / CPR;    // (row-wise staging)
+  constexpr int TPR = 256 / TB;     // threads per row (per-thread staging)
+  constexpr int NV = ROWWISE ? TB / RPP : CPR / TPR;  // 16-byte vectors per thread and operand
+  const int lrow = ROWWISE ? tid / CPR : tid / TPR;
+  const int lk = ROWWISE ? (tid % CPR) * 8 : (tid % TPR) * (BK / TPR);
+  // row and k offset of vector v of this thread inside the tile
+  auto vrow = [&](int v) { return ROWWISE ? lrow + RPP * v : lrow; };
+  auto vk = [&](int v) { return ROWWISE ? lk : lk + 8 * v; };
   us8_t ah[NV], al[NV], bh[NV], bl[NV];
   auto load_tile = [&](int k0) {
-    const int arow = m0 + lrow;
-    const us8_t* pa = (const us8_t*)(Ahg + (size_t)arow * Kp + k0 + lk);
-    const us8_t* pb = (const us8_t*)(Bhg + (size_t)(n0 + lrow) * Kp + k0 + lk);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      ah[v] = pa[v];
-      bh[v] = pb[v];
-    }
-    if (ALO) {
-      const us8_t* pal = (const us8_t*)(Alg + (size_t)arow * Kp + k0 + lk);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) al[v] = pal[v];
-    }
-    if (BLO) {
-      const us8_t* pbl = (const us8_t*)(Blg + (size_t)(n0 + lrow) * Kp + k0 + lk);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) bl[v] = pbl[v];
+      const size_t ao = (size_t)(m0 + vrow(v)) * Kp + k0 + vk(v);
+      const size_t bo = (size_t)(n0 + vrow(v)) * Kp + k0 + vk(v);
+      ah[v] = *(const us8_t*)(Ahg + ao);
+      bh[v] = *(const us8_t*)(Bhg + bo);
+      if (ALO) al[v] = *(const us8_t*)(Alg + ao);
+      if (BLO) bl[v] = *(const us8_t*)(Blg + bo);
     }
   };
 
@@ -338,10 +343,10 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
     __syncthreads();
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      *(us8_t*)&Ah[lrow][lk + 8 * v] = ah[v];
-      *(us8_t*)&Bh[lrow][lk + 8 * v] = bh[v];
-      if (ALO) *(us8_t*)&Al[lrow][lk + 8 * v] = al[v];
-      if (BLO) *(us8_t*)&Bl[lrow][lk + 8 * v] = bl[v];
+      *(us8_t*)&Ah[vrow(v)][vk(v)] = ah[v];
+      *(us8_t*)&Bh[vrow(v)][vk(v)] = bh[v];
+      if (ALO) *(us8_t*)&Al[vrow(v)][vk(v)] = al[v];
+      if (BLO) *(us8_t*)&Bl[vrow(v)][vk(v)] = bl[v];
     }
     __syncthreads();
     if (kt + 1 < nk) load_tile((kt + 1) * BK);
@@ -385,6 +390,7 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
   // epilogue: acc[i][j][r] = C[row][col], row = 4*(lane/16) + r, col = lane%16
   const double s = g.item_scale ? g.item_scale[b] : 1.0;
   double* __restrict__ C64 = g.c64 + (size_t)b * g.c_stride;
+  float* __restrict__ C32r = (float*)g.c_hi + (size_t)b * g.c_stride;  // O_F32_RAW
 #pragma unroll
   for (int i = 0; i < WT; ++i)
 #pragma unroll
@@ -399,11 +405,13 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
         if (!in) v = 0.0;
         if (OMODE == O_F64_RAW) {
           if (in) C64[(size_t)row * g.N + col] = v;
+        } else if (OMODE == O_F32_RAW) {
+          if (in) C32r[(size_t)row * g.N + col] = (float)v;
         } else {
           acc[i][j][r] = (float)v;  // the FP32 value to split
         }
       }
-  if constexpr (OMODE != O_F64_RAW) {
+  if constexpr (!RAW) {
     // Padded split output through LDS: pass 0 writes hi, pass 1 lo.  In
     // LDS the tile is laid out as the output rows (C^T rows for O_PAD_T),
     // then every thread stores whole 16-byte pieces of those rows.
@@ -457,9 +465,9 @@ template <int OMODE, int WT>
 static void launch_mode(const GemmArgs& g, int prec, int batch, hipStream_t s) {
   constexpr int TB = 32 * WT;
   dim3 grid((pad_up(g.M) / TB) * (pad_up(g.N) / TB), batch);
-  if (prec == GEMM_F64)
-    hipLaunchKernelGGL((gemm_f64_kernel<OMODE, 16, WT>), grid, dim3(256), 0, s, g);
-  else if (prec == GEMM_F32)
+  if (prec == GEMM_F64) {
+    if constexpr (OMODE != O_F32_RAW) hipLaunchKernelGGL((gemm_f64_kernel<OMODE, 16, WT>), grid, dim3(256), 0, s, g);
+  } else if (prec == GEMM_F32)
     hipLaunchKernelGGL((gemm_f32_kernel<OMODE, WT>), grid, dim3(256), 0, s, g);
   else if (prec == GEMM_BF16X3)
     hipLaunchKernelGGL((gemm_bf16_kernel<BF_X3, OMODE, 64, 2, WT>), grid, dim3(256), 0, s, g);
@@ -479,6 +487,8 @@ int launch_gemm(const GemmArgs& g, int prec, int omode, int batch, int tile, hip
   if (omode == O_PAD_T) big ? launch_mode<O_PAD_T, 4>(g, prec, batch, s) : launch_mode<O_PAD_T, 2>(g, prec, batch, s);
   else if (omode == O_PAD_N) big ? launch_mode<O_PAD_N, 4>(g, prec, batch, s) : launch_mode<O_PAD_N, 2>(g, prec, batch, s);
   else if (omode == O_F64_RAW) big ? launch_mode<O_F64_RAW, 4>(g, prec, batch, s) : launch_mode<O_F64_RAW, 2>(g, prec, batch, s);
+  else if (omode == O_F32_RAW && prec != GEMM_F64)
+    big ? launch_mode<O_F32_RAW, 4>(g, prec, batch, s) : launch_mode<O_F32_RAW, 2>(g, prec, batch, s);
   else return -1;
   return 0;
 }

@@ -59,7 +59,8 @@ __global__ __launch_bounds__(kThreads) void reduce_axpy_kernel(const double* __r
   if (threadIdx.x == 0) out[b] = (beta == 0.0 ? 0.0 : beta * out[b]) + alpha * s;
 }
 
-__global__ __launch_bounds__(kThreads) void dot_kernel(const double* __restrict__ X, const double* __restrict__ Y,
+template <typename YT>
+__global__ __launch_bounds__(kThreads) void dot_kernel(const double* __restrict__ X, const YT* __restrict__ Y,
                                                        long long n, long long stride,
                                                        double* __restrict__ partial, const int* active) {
   const int b = blockIdx.y;
@@ -67,34 +68,13 @@ __global__ __launch_bounds__(kThreads) void dot_kernel(const double* __restrict_
   long long lo, hi;
   chunk_of(n, blockIdx.x, gridDim.x, &lo, &hi);
   const double* x = X + (size_t)b * stride;
-  const double* y = Y + (size_t)b * stride;
+  const YT* y = Y + (size_t)b * stride;
   double s = 0.0;
-  for (long long i = lo + threadIdx.x; i < hi; i += kThreads) s = fma(x[i], y[i], s);
+  for (long long i = lo + threadIdx.x; i < hi; i += kThreads) s = fma(x[i], (double)y[i], s);
   s = block_sum(s);
   if (threadIdx.x == 0) partial[(size_t)b * gridDim.x + blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(kThreads) void dot2_kernel(const double* __restrict__ A, const double* __restrict__ B,
-                                                        const double* __restrict__ C, const double* __restrict__ D,
-                                                        long long n, long long stride, double* __restrict__ p1,
-                                                        double* __restrict__ p2, const int* active) {
-  const int b = blockIdx.y;
-  if (active && !active[b]) return;
-  long long lo, hi;
-  chunk_of(n, blockIdx.x, gridDim.x, &lo, &hi);
-  const size_t off = (size_t)b * stride;
-  double s1 = 0.0, s2 = 0.0;
-  for (long long i = lo + threadIdx.x; i < hi; i += kThreads) {
-    s1 = fma(A[off + i], B[off + i], s1);
-    s2 = fma(C[off + i], D[off + i], s2);
-  }
-  s1 = block_sum(s1);
-  s2 = block_sum(s2);
-  if (threadIdx.x == 0) {
-    p1[(size_t)b * gridDim.x + blockIdx.x] = s1;
-    p2[(size_t)b * gridDim.x + blockIdx.x] = s2;
-  }
-}
 
 // R may alias Y (each element is read before it is written by the same thread)
 __global__ __launch_bounds__(kThreads) void residual_kernel(const double* __restrict__ Rhs, const double* Y,
@@ -196,7 +176,32 @@ __global__ __launch_bounds__(kThreads) void cg_update_pad_kernel(
   if (threadIdx.x == 0) partial[(size_t)b * gridDim.x + blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(kThreads) void direction_kernel(double* __restrict__ Q, const double* __restrict__ Z,
+// <R, Z> and <Z, Y> in one pass (Z read once); Z in FP64 or FP32
+template <typename ZT>
+__global__ __launch_bounds__(kThreads) void zdots_kernel(const double* __restrict__ R, const ZT* __restrict__ Z,
+                                                         const double* __restrict__ Y, long long n, long long stride,
+                                                         double* __restrict__ p1, double* __restrict__ p2,
+                                                         const int* active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  long long lo, hi;
+  chunk_of(n, blockIdx.x, gridDim.x, &lo, &hi);
+  const size_t off = (size_t)b * stride;
+  double s1 = 0.0, s2 = 0.0;
+  for (long long i = lo + threadIdx.x; i < hi; i += kThreads) {
+    const double z = (double)Z[off + i];
+    s1 = fma(R[off + i], z, s1);
+    s2 = fma(z, Y[off + i], s2);
+  }
+  s1 = block_sum(s1);
+  s2 = block_sum(s2);
+  if (threadIdx.x == 0) {
+    p1[(size_t)b * gridDim.x + blockIdx.x] = s1;
+    p2[(size_t)b * gridDim.x + blockIdx.x] = s2;
+  }
+}
+template <typename ZT>
+__global__ __launch_bounds__(kThreads) void direction_kernel(double* __restrict__ Q, const ZT* __restrict__ Z,
                                                              const double* __restrict__ beta, long long n,
                                                              long long stride, const int* active) {
   const int b = blockIdx.y;
@@ -205,8 +210,8 @@ __global__ __launch_bounds__(kThreads) void direction_kernel(double* __restrict_
   long long lo, hi;
   chunk_of(n, blockIdx.x, gridDim.x, &lo, &hi);
   double* q = Q + (size_t)b * stride;
-  const double* z = Z + (size_t)b * stride;
-  for (long long i = lo + threadIdx.x; i < hi; i += kThreads) q[i] = fma(be, q[i], z[i]);
+  const ZT* z = Z + (size_t)b * stride;
+  for (long long i = lo + threadIdx.x; i < hi; i += kThreads) q[i] = fma(be, q[i], (double)z[i]);
 }
 
 __global__ __launch_bounds__(kThreads) void copy_kernel(const double* __restrict__ X, double* __restrict__ Y,
@@ -413,12 +418,7 @@ int launch_dib_adjoint(const double* U, const double* V, const double* NU, const
 }
 int launch_dot_partial(const double* X, const double* Y, long long n, long long stride, int batch,
                        double* partial, const int* active, hipStream_t s) {
-  hipLaunchKernelGGL(dot_kernel, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, X, Y, n, stride, partial, active);
-  CHECK_LAUNCH();
-}
-int launch_dot2_partial(const double* A, const double* B, const double* C, const double* D, long long n,
-                        long long stride, int batch, double* p1, double* p2, const int* active, hipStream_t s) {
-  hipLaunchKernelGGL(dot2_kernel, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, A, B, C, D, n, stride, p1, p2,
+  hipLaunchKernelGGL(dot_kernel<double>, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, X, Y, n, stride, partial,
                      active);
   CHECK_LAUNCH();
 }
@@ -449,7 +449,31 @@ int launch_cg_update_pad(double* U, double* R, const double* Q, const double* Y,
 }
 int launch_direction(double* Q, const double* Z, const double* beta, long long n, long long stride, int batch,
                      const int* active, hipStream_t s) {
-  hipLaunchKernelGGL(direction_kernel, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, Q, Z, beta, n, stride,
+  hipLaunchKernelGGL(direction_kernel<double>, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, Q, Z, beta, n, stride,
+                     active);
+  CHECK_LAUNCH();
+}
+int launch_direction(double* Q, const float* Z, const double* beta, long long n, long long stride, int batch,
+                     const int* active, hipStream_t s) {
+  hipLaunchKernelGGL(direction_kernel<float>, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, Q, Z, beta, n, stride,
+                     active);
+  CHECK_LAUNCH();
+}
+int launch_dot_partial(const double* X, const float* Y, long long n, long long stride, int batch, double* partial,
+                       const int* active, hipStream_t s) {
+  hipLaunchKernelGGL(dot_kernel<float>, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, X, Y, n, stride, partial,
+                     active);
+  CHECK_LAUNCH();
+}
+int launch_zdots_partial(const double* R, const double* Z, const double* Y, long long n, long long stride, int batch,
+                         double* p1, double* p2, const int* active, hipStream_t s) {
+  hipLaunchKernelGGL(zdots_kernel<double>, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, R, Z, Y, n, stride, p1, p2,
+                     active);
+  CHECK_LAUNCH();
+}
+int launch_zdots_partial(const double* R, const float* Z, const double* Y, long long n, long long stride, int batch,
+                         double* p1, double* p2, const int* active, hipStream_t s) {
+  hipLaunchKernelGGL(zdots_kernel<float>, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, R, Z, Y, n, stride, p1, p2,
                      active);
   CHECK_LAUNCH();
 }

@@ -64,7 +64,8 @@ constexpr int kPad = 128;
 __host__ __device__ inline int pad_up(int x) { return (x + kPad - 1) / kPad * kPad; }
 
 enum GemmPrec { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_BF16 = 2, GEMM_BF16X3 = 3, GEMM_BF16X2 = 4 };
-enum GemmOMode { O_PAD_T = 0, O_PAD_N = 1, O_F64_RAW = 2 };  // raw: FP64 row-major ld = N
+// raw: row-major ld = N, FP64 or (FP32 and BF16 products only) FP32 into c_hi
+enum GemmOMode { O_PAD_T = 0, O_PAD_N = 1, O_F64_RAW = 2, O_F32_RAW = 3 };
 
 struct GemmArgs {
   int M, N, K;             // logical sizes
@@ -112,10 +113,6 @@ int launch_dib_adjoint(const double* U, const double* V, const double* NU, const
 // out[b] = sum(X_b * Y_b) partials (X may equal Y)
 int launch_dot_partial(const double* X, const double* Y, long long n, long long stride,
                        int batch, double* partial, const int* active, hipStream_t s);
-// two dots at once: <A, B> and <C, D>
-int launch_dot2_partial(const double* A, const double* B, const double* C, const double* D,
-                        long long n, long long stride, int batch, double* partial1,
-                        double* partial2, const int* active, hipStream_t s);
 // R = Rhs - Y  (and partial <R, R>)
 int launch_residual(const double* Rhs, const double* Y, double* R, long long n, long long stride,
                     long long rhs_stride, int batch, double* partial, const int* active, hipStream_t s);
@@ -130,9 +127,19 @@ int launch_cg_update(double* U, double* R, const double* Q, const double* Y, con
                      const double* den, double* alpha_out, long long n, long long stride,
                      long long u_stride, int batch, double* partial, const int* active,
                      hipStream_t s);
-// Q = Z + beta Q with beta_b given
+// Q = Z + beta Q with beta_b given (Z in FP64 or FP32)
 int launch_direction(double* Q, const double* Z, const double* beta, long long n,
                      long long stride, int batch, const int* active, hipStream_t s);
+int launch_direction(double* Q, const float* Z, const double* beta, long long n,
+                     long long stride, int batch, const int* active, hipStream_t s);
+// <X, Y> partials with Y in FP32
+int launch_dot_partial(const double* X, const float* Y, long long n, long long stride,
+                       int batch, double* partial, const int* active, hipStream_t s);
+// <R, Z> and <Z, Y> partials in one pass (Z in FP64 or FP32)
+int launch_zdots_partial(const double* R, const double* Z, const double* Y, long long n, long long stride,
+                         int batch, double* partial1, double* partial2, const int* active, hipStream_t s);
+int launch_zdots_partial(const double* R, const float* Z, const double* Y, long long n, long long stride,
+                         int batch, double* partial1, double* partial2, const int* active, hipStream_t s);
 // Y = X copy; X = 0
 int launch_copy(const double* X, double* Y, long long n, long long xs, long long ys, int batch,
                 hipStream_t s);
