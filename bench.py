@@ -73,7 +73,7 @@ def cpu_baseline(F0, k, m, gamma, tol, U_gpu0):
 # source they were taken on: if k_gemm.hip changes, traffic is reported null.
 TRAFFIC = {
     # mixed mode -> (sha256 of k_gemm.hip, (q, batch), bytes per launch)
-    "bf16fwd": ("1523b925ce7195b7cc5a9d49474cc57379364cef8179edc58bee508e28a6b4d1", (2047, 16), 2.576e9),
+    "bf16fwd": ("d2442d47e8167f4132dd3cc02a388d0a83e00ba42177b0a225053c84f789d083", (2047, 16), 2.480e9),
 }
 FETCH_SCALE = 2.000   # 512 MiB copy: true bytes / FETCH_SIZE reading
 WRITE_SCALE = 1.000   # 512 MiB copy: true bytes / WRITE_SIZE reading
