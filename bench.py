@@ -201,10 +201,11 @@ def imex_legs(mf, torch, np, nsteps, prec, prec_name):
         % (nsteps / dt, np.mean(its), nsteps / dtg))
     del g
     del G, st, ws, stepper
-    # DIB: rectangle preset (exact single-term operator), FP64 transforms
+    # DIB: rectangle preset (exact single-term operator), FP64 transforms; the
+    # eigenpairs of the lumped P1 pencil are the closed-form cosine basis
     p = dib_params()
     t0 = time.perf_counter()
-    G = Rect(1, 1024, "neumann", length=20.0, lumped=True, imex=True)
+    G = Rect(1, 1024, "neumann", length=20.0, lumped=True, imex=True, closed_form=True)
     setup = time.perf_counter() - t0
     eta, theta = dib_initial(G.q, seed=7)
     st = torch.from_numpy(np.stack([eta, theta])).cuda()

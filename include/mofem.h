@@ -121,6 +121,21 @@ int mofem_assemble_1d(int order, int m_elem, double x0, double x1, int di, int d
 int mofem_geneig_host(int n, int kb, const double* K, const double* M, int trim,
                       double* lam, double* V);
 
+/* Closed-form generalised eigenpairs of the uniform P1 pencil (A, M) on an
+   interval of length len with n_elem elements (host only), Sec. 4.1: with
+   Dirichlet conditions the P1 stiffness and consistent mass are tridiagonal
+   Toeplitz and related by eq. (60), so the sine vectors of eq. (64)
+   diagonalise both, with the eigenvalues of eqs. (63) and (65); the nodal
+   (lumped) mass keeps the sine basis, and with Neumann conditions the lumped
+   pencil is diagonalised by cosine vectors.  Output as mofem_geneig_host:
+   lam ascending, V row-major with V^T M V = I.
+     lumped     1 = nodal (trapezoid) mass, 0 = consistent mass.
+     dirichlet  1: q = n_elem - 1 interior nodes; 0: q = n_elem + 1 (lumped
+                only: MOFEM_E_UNSUPPORTED for the consistent Neumann pencil,
+                which has no closed form).
+   Errors: MOFEM_E_ARG (n_elem < 2, len <= 0, NULL), MOFEM_E_UNSUPPORTED. */
+int mofem_eig_p1_closed(int n_elem, double len, int lumped, int dirichlet, double* lam, double* V);
+
 /* ------------------------------------------------------------------------ */
 /* a2/a3. Multiterm operator  Y = sum_t c_t op(L_t) X op(R_t)               */
 /* ------------------------------------------------------------------------ */
@@ -223,6 +238,14 @@ typedef struct mofem_prec_s* mofem_prec_t;
    precision.  Errors: MOFEM_E_ARG, MOFEM_E_NUMERIC, MOFEM_E_NOMEM, MOFEM_E_HIP. */
 int mofem_prec_setup(const mofem_prec_desc* desc, mofem_prec_t* prec);
 int mofem_prec_destroy(mofem_prec_t prec);
+/* The same preconditioner from given generalised eigenpairs (host arrays:
+   lam [q_s], Vs [q_s x q_s] row-major with column j the eigenvector of
+   lam[j] and Vs^T Ms Vs = I; mu, Vt likewise), e.g. the closed forms of
+   mofem_eig_p1_closed: no eigen-decomposition.  The arrays are copied.
+   Errors: MOFEM_E_ARG, MOFEM_E_NOMEM, MOFEM_E_HIP. */
+int mofem_prec_setup_eig(int q_s, int q_t, const double* lam, const double* Vs, const double* mu,
+                         const double* Vt, double alpha, double beta_s, double beta_t, double delta,
+                         int precision, mofem_prec_t* prec);
 /* Change a, bs, bt, d (e.g. a new gamma, tau or diffusion coefficient)
    without a new eigen-decomposition. */
 int mofem_prec_set_coeffs(mofem_prec_t prec, double alpha, double beta_s,

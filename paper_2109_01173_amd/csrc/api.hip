@@ -472,6 +472,10 @@ extern "C" int mofem_prec_destroy(mofem_prec_t p) {
   return MOFEM_OK;
 }
 
+namespace {
+int prec_upload(mofem_prec_s* p, const std::vector<double>& Vs, const std::vector<double>& Vt);
+}
+
 extern "C" int mofem_prec_setup(const mofem_prec_desc* desc, mofem_prec_t* out) {
   clear_error();
   if (!desc || !out) return fail(MOFEM_E_ARG, "prec_setup: NULL argument");
@@ -506,6 +510,55 @@ extern "C" int mofem_prec_setup(const mofem_prec_desc* desc, mofem_prec_t* out) 
     mofem_prec_destroy(p);
     return fail(rc, "prec_setup: " + msg);
   }
+  rc = prec_upload(p, Vs, Vt);
+  if (rc) {
+    mofem_prec_destroy(p);
+    return rc;
+  }
+  *out = p;
+  return MOFEM_OK;
+}
+
+// Spectral preconditioner from given generalised eigenpairs (e.g. the closed
+// forms of mofem_eig_p1_closed), no eigen-decomposition.
+extern "C" int mofem_prec_setup_eig(int q_s, int q_t, const double* lam, const double* Vs, const double* mu,
+                                    const double* Vt, double alpha, double beta_s, double beta_t, double delta,
+                                    int precision, mofem_prec_t* out) {
+  clear_error();
+  if (!out || !lam || !Vs || !mu || !Vt) return fail(MOFEM_E_ARG, "prec_setup_eig: NULL argument");
+  *out = nullptr;
+  if (q_s < 1 || q_t < 1) return fail(MOFEM_E_ARG, "prec_setup_eig: empty matrices");
+  if (precision < MOFEM_PREC_F64 || precision > MOFEM_PREC_BF16_FWD)
+    return fail(MOFEM_E_ARG, "prec_setup_eig: unknown precision");
+  auto* p = new mofem_prec_s();
+  p->qs = q_s;
+  p->qt = q_t;
+  p->ps = pad_up(q_s);
+  p->pt = pad_up(q_t);
+  p->alpha = alpha;
+  p->bs = beta_s;
+  p->bt = beta_t;
+  p->dl = delta;
+  p->precision = precision;
+  p->h_lam.assign(lam, lam + q_s);
+  p->h_mu.assign(mu, mu + q_t);
+  std::vector<double> vs(Vs, Vs + (size_t)q_s * q_s), vt(Vt, Vt + (size_t)q_t * q_t);
+  int rc = prec_upload(p, vs, vt);
+  if (rc) {
+    mofem_prec_destroy(p);
+    return rc;
+  }
+  *out = p;
+  return MOFEM_OK;
+}
+
+namespace {
+// Upload the eigenvalues (p->h_lam, p->h_mu) and the bases V_s, V_t (row-major,
+// column j = eigenvector j) and their transposes, padded, in FP64, split BF16
+// and FP32.
+int prec_upload(mofem_prec_s* p, const std::vector<double>& Vs, const std::vector<double>& Vt) {
+  const int qs = p->qs, qt = p->qt;
+  int rc = MOFEM_OK;
   auto Vs_p = padded(Vs, qs, p->ps, p->ps, false), VsT_p = padded(Vs, qs, p->ps, p->ps, true);
   auto Vt_p = padded(Vt, qt, p->pt, p->pt, false), VtT_p = padded(Vt, qt, p->pt, p->pt, true);
   rc = upload_f64(&p->lam, p->h_lam);
@@ -522,13 +575,9 @@ extern "C" int mofem_prec_setup(const mofem_prec_desc* desc, mofem_prec_t* out) 
   if (!rc) rc = upload_f32(&p->VsT_f, VsT_p);
   if (!rc) rc = upload_f32(&p->Vt_f, Vt_p);
   if (!rc) rc = upload_f32(&p->VtT_f, VtT_p);
-  if (rc) {
-    mofem_prec_destroy(p);
-    return rc;
-  }
-  *out = p;
-  return MOFEM_OK;
+  return rc;
 }
+}  // namespace
 
 // Product preconditioner S U T by banded Cholesky: factor S_j = a Ms + c_j bs Ks
 // and T_j = a Mt + c_j bt Kt (interior rows and columns) for every scale c_j.

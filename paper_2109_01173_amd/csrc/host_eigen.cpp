@@ -350,3 +350,45 @@ extern "C" int mofem_geneig_host(int n, int kb, const double* K, const double* M
   if (rc != MOFEM_OK) return fail(rc, "geneig_host: mass matrix not positive definite or QL did not converge");
   return MOFEM_OK;
 }
+
+// Closed-form generalised eigenpairs of uniform P1 pencils (A, M) on an
+// interval of length `len` with N elements, h = len / N (Sec. 4.1: with
+// Dirichlet conditions A and the consistent M are tridiagonal Toeplitz
+// matrices, M = alpha A + beta I, eq. (60), so both are diagonalised by the
+// sine vectors of eq. (64); their eigenvalues follow eqs. (63) and (65)).
+//   Dirichlet (q = N - 1), v_i[j] = sin(i j pi / N), i, j = 1..N-1:
+//     A v_i = (2 / h)(1 - cos(i pi / N)) v_i,
+//     M v_i = (h / 3)(2 + cos(i pi / N)) v_i   (consistent)
+//             h v_i                             (lumped: trapezoid mass h I)
+//   Neumann, lumped only (q = N + 1), w_i[j] = cos(i j pi / N), i, j = 0..N:
+//     A w_i = (2 / h^2)(1 - cos(i pi / N)) M0 w_i,  M0 = h diag(1/2, 1, .., 1, 1/2).
+// The vectors are scaled to V^T M V = I and sorted by ascending eigenvalue
+// (ascending i).
+extern "C" int mofem_eig_p1_closed(int n_elem, double len, int lumped, int dirichlet, double* lam, double* V) {
+  clear_error();
+  if (n_elem < 2 || !(len > 0.0) || !lam || !V) return fail(MOFEM_E_ARG, "eig_p1_closed: bad n_elem/len/pointers");
+  if (!dirichlet && !lumped)
+    return fail(MOFEM_E_UNSUPPORTED, "eig_p1_closed: consistent mass with Neumann conditions has no closed form");
+  const int N = n_elem;
+  const double h = len / N, pi = 3.14159265358979323846;
+  if (dirichlet) {
+    const int q = N - 1;
+    for (int i = 1; i <= q; ++i) {
+      const double c = std::cos(i * pi / N);
+      const double la = 2.0 / h * (1.0 - c);
+      const double mu = lumped ? h : h / 3.0 * (2.0 + c);
+      lam[i - 1] = la / mu;
+      const double scale = 1.0 / std::sqrt(mu * 0.5 * N);  // sum_j sin^2 = N / 2
+      for (int j = 1; j <= q; ++j) V[(size_t)(j - 1) * q + (i - 1)] = scale * std::sin((double)i * j * pi / N);
+    }
+  } else {
+    const int q = N + 1;
+    for (int i = 0; i <= N; ++i) {
+      lam[i] = 2.0 / (h * h) * (1.0 - std::cos(i * pi / N));
+      // sum_j D_j cos^2 = N / 2 (0 < i < N) or N (i = 0, N)
+      const double scale = 1.0 / std::sqrt(h * ((i == 0 || i == N) ? N : 0.5 * N));
+      for (int j = 0; j <= N; ++j) V[(size_t)j * q + i] = scale * std::cos((double)i * j * pi / N);
+    }
+  }
+  return MOFEM_OK;
+}

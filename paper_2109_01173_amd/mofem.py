@@ -109,6 +109,8 @@ mofem_assemble_1d = _proto("mofem_assemble_1d", ctypes.c_int,
                             ctypes.c_int, ctypes.c_int, ctypes.POINTER(Weight), ctypes.c_int, _vp])
 mofem_geneig_host = _proto("mofem_geneig_host", ctypes.c_int,
                            [ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp, _vp])
+mofem_eig_p1_closed = _proto("mofem_eig_p1_closed", ctypes.c_int,
+                             [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, _vp, _vp])
 mofem_op_create = _proto("mofem_op_create", ctypes.c_int, [ctypes.POINTER(OpDesc), ctypes.POINTER(_vp)])
 mofem_op_destroy = _proto("mofem_op_destroy", ctypes.c_int, [_vp])
 mofem_op_shape = _proto("mofem_op_shape", ctypes.c_int, [_vp, _ip, _ip, _ip, _ip])
@@ -116,6 +118,9 @@ mofem_op_apply = _proto("mofem_op_apply", ctypes.c_int,
                         [_vp, _vp, _ll, _vp, _ll, ctypes.c_int, _vp, _vp, _vp])
 mofem_prec_setup = _proto("mofem_prec_setup", ctypes.c_int, [ctypes.POINTER(PrecDesc), ctypes.POINTER(_vp)])
 mofem_prec_destroy = _proto("mofem_prec_destroy", ctypes.c_int, [_vp])
+mofem_prec_setup_eig = _proto("mofem_prec_setup_eig", ctypes.c_int,
+                              [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_vp)])
 mofem_prec_setup_banded = _proto("mofem_prec_setup_banded", ctypes.c_int,
                                  [ctypes.POINTER(BPrecDesc), ctypes.POINTER(_vp)])
 mofem_prec_set_coeffs = _proto("mofem_prec_set_coeffs", ctypes.c_int,
@@ -157,7 +162,8 @@ mofem_trace_select = _proto("mofem_trace_select", ctypes.c_int, [ctypes.c_uint])
 mofem_trace_read = _proto("mofem_trace_read", ctypes.c_int,
                           [ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_longlong), _dp])
 
-EXPORTS = ["mofem_version", "mofem_last_error", "mofem_assemble_1d", "mofem_geneig_host",
+EXPORTS = ["mofem_version", "mofem_last_error", "mofem_assemble_1d", "mofem_geneig_host", "mofem_eig_p1_closed",
+           "mofem_prec_setup_eig",
            "mofem_op_create", "mofem_op_destroy", "mofem_op_shape", "mofem_op_apply",
            "mofem_prec_setup", "mofem_prec_destroy", "mofem_prec_set_coeffs",
            "mofem_prec_set_precision", "mofem_prec_eigenvalues", "mofem_prec_workspace_size",
@@ -216,6 +222,16 @@ def geneig_host(K_band, M_band, trim):
     K = np.ascontiguousarray(K_band, dtype=np.float64)
     M = np.ascontiguousarray(M_band, dtype=np.float64)
     _check(mofem_geneig_host(n, kb, _hptr(K), _hptr(M), trim, _hptr(lam), _hptr(V)), "mofem_geneig_host")
+    return lam, V
+
+
+def eig_p1_closed(n_elem, length=1.0, lumped=False, dirichlet=True):
+    """Closed-form (lam, V) of the uniform P1 pencil (mofem_eig_p1_closed)."""
+    q = n_elem - 1 if dirichlet else n_elem + 1
+    lam = np.zeros(max(q, 0))
+    V = np.zeros((max(q, 0), max(q, 0)))
+    _check(mofem_eig_p1_closed(n_elem, length, int(lumped), int(dirichlet), _hptr(lam), _hptr(V)),
+           "mofem_eig_p1_closed")
     return lam, V
 
 
@@ -332,6 +348,24 @@ class Preconditioner:
         if getattr(self, "handle", None):
             _destroy(self.handle)
             self.handle = None
+
+    @classmethod
+    def from_eigen(cls, lam, Vs, mu, Vt, coeffs, precision=PREC_F64):
+        """The same preconditioner from given generalised eigenpairs
+        (mofem_prec_setup_eig), e.g. eig_p1_closed's."""
+        self = cls.__new__(cls)
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (lam, Vs, mu, Vt)]
+        qs, qt = arrs[0].size, arrs[2].size
+        if arrs[1].shape != (qs, qs) or arrs[3].shape != (qt, qt):
+            raise ValueError("eigenvector matrices must be q x q")
+        h = _vp()
+        a, bs, bt, d = (float(c) for c in coeffs)
+        _check(mofem_prec_setup_eig(qs, qt, _hptr(arrs[0]), _hptr(arrs[1]), _hptr(arrs[2]), _hptr(arrs[3]),
+                                    a, bs, bt, d, precision, ctypes.byref(h)), "mofem_prec_setup_eig")
+        self.handle = h
+        self.shape = (qs, qt)
+        self.precision = precision
+        return self
 
     def set_coeffs(self, alpha, beta_s, beta_t, delta):
         _check(mofem_prec_set_coeffs(self.handle, alpha, beta_s, beta_t, delta), "mofem_prec_set_coeffs")

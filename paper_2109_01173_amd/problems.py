@@ -117,10 +117,14 @@ class XNormal:
 
 
 class Rect:
-    """Square Kronecker form eq. (28) on [0, length]^2 (P_k or lumped P1)."""
+    """Square Kronecker form eq. (28) on [0, length]^2 (P_k or lumped P1).
+
+    closed_form: for P1 (consistent mass with Dirichlet conditions, or lumped
+    mass) the preconditioner's eigenpairs come from the closed forms of
+    Sec. 4.1 (mofem_eig_p1_closed) instead of a dense eigen-decomposition."""
 
     def __init__(self, k, m, bc, length=1.0, gamma=0.0, lumped=False, precision=mf.PREC_F64,
-                 imex=False):
+                 imex=False, closed_form=False):
         order = 0 if lumped else k
         self.kb = 1 if lumped else k
         self.n = self.kb * m + 1
@@ -144,4 +148,10 @@ class Rect:
         self.rhs_adjoint_op = mf.Operator([dict(left=M, right=M)], full_output=True, **common)
         self.mass = mf.Operator([dict(left=M, right=M)], **common)
         self.stiff = mf.Operator([dict(t, scaled=False) for t in terms[1:]], **common) if imex else None
-        self.prec = mf.Preconditioner(A, M, A, M, coeffs, trim, trim, precision)
+        if closed_form:
+            if self.kb != 1:
+                raise ValueError("closed-form eigenpairs exist for P1 only")
+            lam, V = mf.eig_p1_closed(m, length, lumped, trim == 1)
+            self.prec = mf.Preconditioner.from_eigen(lam, V, lam, V, coeffs, precision)
+        else:
+            self.prec = mf.Preconditioner(A, M, A, M, coeffs, trim, trim, precision)

@@ -1,10 +1,12 @@
-"""GPU parity of the paper's own product preconditioners applied by banded
-Cholesky solves (Sec. 5, eq. (80); Sec. 6, eqs. (95)-(96)) against the
-oracle's dense Cholesky solves (oracle.solvers.BandedProductPrec), alone and
-inside MO-PCG and the IMEX step.
+"""GPU parity of the alternative preconditioner back-ends.
 
-Sizes span several 64-column blocks of the solve kernel with ragged tails
-and q_s != q_t (the two launches transpose)."""
+* The paper's own product preconditioners applied by banded Cholesky solves
+  (Sec. 5, eq. (80); Sec. 6, eqs. (95)-(96)) against the oracle's dense
+  Cholesky solves (oracle.solvers.BandedProductPrec), alone and inside MO-PCG
+  and the IMEX step.  Sizes span several 64-column blocks of the solve
+  kernel with ragged tails and q_s != q_t (the two launches transpose).
+* The spectral preconditioner built from the closed-form P1 eigenpairs of
+  Sec. 4.1 against the one built from a dense eigen-decomposition."""
 import numpy as np
 import pytest
 
@@ -117,3 +119,31 @@ def test_product_unsupported_calls():
     with pytest.raises(mf.MofemError):
         prec.tune(2)
     prec.set_precision(mf.PREC_F64)
+
+
+@pytest.mark.parametrize("lumped,bc", [(False, "dirichlet"), (True, "neumann")])
+def test_closed_form_eigenbasis_preconditioner(lumped, bc):
+    """Sec. 4.1's closed-form P1 eigenpairs (mofem_eig_p1_closed +
+    mofem_prec_setup_eig) give the same preconditioner as the dense
+    eigen-decomposition (P^-1 does not depend on the basis), and the same
+    IMEX solve."""
+    import torch
+    from paper_2109_01173_amd import mofem as mf
+    from paper_2109_01173_amd.problems import Rect
+    A = Rect(1, 150, bc, length=20.0, lumped=lumped, imex=True)
+    Bc = Rect(1, 150, bc, length=20.0, lumped=lumped, imex=True, closed_form=True)
+    rng = np.random.default_rng(8)
+    R = to_dev(rng.standard_normal((2, A.q, A.q)))
+    sc = torch.tensor([1e-2, 0.2], dtype=torch.float64, device="cuda")
+    Z1 = to_host(A.prec.apply(R, item_scale=sc))
+    Z2 = to_host(Bc.prec.apply(R, item_scale=sc))
+    assert rel(Z2, Z1) < 1e-12
+    lam1, _ = A.prec.eigenvalues()
+    lam2, _ = Bc.prec.eigenvalues()
+    assert np.allclose(lam2, lam1, rtol=1e-10, atol=1e-12 * lam1.max())
+    U1 = torch.zeros_like(R)
+    U2 = torch.zeros_like(R)
+    it1, _, _ = mf.pcg_solve(A.op, A.prec, R, U1, tol=1e-12, maxit=50, item_scale=sc, flags=mf.PCG_ZERO_GUESS)
+    it2, _, _ = mf.pcg_solve(Bc.op, Bc.prec, R, U2, tol=1e-12, maxit=50, item_scale=sc, flags=mf.PCG_ZERO_GUESS)
+    assert np.array_equal(it1, it2) and it1.max() <= 2   # the rectangle preset is exact
+    assert rel(to_host(U2), to_host(U1)) < 1e-12

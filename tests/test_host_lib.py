@@ -145,3 +145,31 @@ def test_banded_product_setup_errors_on_the_host():
     d.a = 1.0  # a != 0 needs the mass bands
     assert mf.mofem_prec_setup_banded(ctypes.byref(d), ctypes.byref(h)) == mf.E_ARG
     assert mf.mofem_prec_setup_banded(None, None) == mf.E_ARG
+
+
+@pytest.mark.parametrize("lumped,dirichlet", [(False, True), (True, True), (True, False)])
+def test_closed_form_p1_eigenpairs(lumped, dirichlet):
+    """mofem_eig_p1_closed (Sec. 4.1) against a dense symmetric-definite
+    eigen-solve of the assembled P1 pencil on [0, 2], N = 37."""
+    N, length = 37, 2.0
+    order = 0 if lumped else 1
+    trim = 1 if dirichlet else 0
+    K = mf.band_to_dense(mf.assemble_1d(order, N, 1, 1, None, 0.0, length))
+    M = mf.band_to_dense(mf.assemble_1d(order, N, 0, 0, None, 0.0, length))
+    if trim:
+        K, M = K[1:-1, 1:-1], M[1:-1, 1:-1]
+    lam, V = mf.eig_p1_closed(N, length, lumped, dirichlet)
+    ref = sla.eigh(K, M, eigvals_only=True)
+    assert np.allclose(lam, ref, rtol=1e-12, atol=1e-12 * ref.max())
+    assert np.abs(V.T @ M @ V - np.eye(len(lam))).max() < 1e-12
+    assert np.linalg.norm(K @ V - M @ V * lam) <= 1e-12 * np.linalg.norm(K) * np.linalg.norm(V)
+    # the unit-interval stiffness eigenvalues of the corrected eq. (63): 2N(1 - cos(i pi / N))
+    lamA = np.linalg.eigvalsh(mf.band_to_dense(mf.assemble_1d(1, N, 1, 1))[1:-1, 1:-1])
+    i = np.arange(1, N)
+    assert np.allclose(np.sort(lamA), 2 * N * (1 - np.cos(i * np.pi / N)), rtol=1e-12)
+
+
+def test_closed_form_rejects_consistent_neumann():
+    with pytest.raises(mf.MofemError) as e:
+        mf.eig_p1_closed(16, 1.0, lumped=False, dirichlet=False)
+    assert e.value.code == mf.E_UNSUPPORTED
