@@ -24,6 +24,8 @@
 //   GEMM_BF16    the hi * hi product only.
 // A transform writes the lo half of a split output only when its consumer
 // reads it (c_lo set).
+// LDS operand rows hold BK values with their 16-byte chunks XOR-swizzled by
+// row, so the 16 rows read by one ds_read_b128 fall on distinct banks.
 // Tiling: 256 threads = 4 waves, block tile 128 x 128, each wave 64 x 64
 // (4 x 4 MFMA tiles of 16 x 16), or 64 x 64 blocks of 32 x 32 wave tiles for
 // grids too small to fill the chip (picked per shape, see mofem_prec_tune);
@@ -272,7 +274,9 @@ template <int MODE, int OMODE, int BK = 64, int MINW = 2, int WT = 4>
 __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
   // block tile TB x TB: 4 waves in 2 x 2, each WT x WT MFMA tiles of 16 x 16
   constexpr int TB = 32 * WT;
-  constexpr int LDS_K = BK + 8;   // padded rows keep 16-byte alignment
+  // operand rows of BK values, 16-byte chunks XOR-swizzled by row (see sw)
+  constexpr int LDS_K = BK;
+  static_assert(BK == 64, "the swizzle assumes 8 chunks per row");
   constexpr bool ALO = (MODE == BF_X3 || MODE == BF_X2A);
   constexpr bool BLO = (MODE == BF_X3 || MODE == BF_X2B);
   // One LDS buffer: the operand tiles of the main loop, then (padded output)
@@ -287,6 +291,9 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
   Row* Bh = Ah + TB;
   Row* Al = Bh + TB;                 // used when ALO
   Row* Bl = Al + (ALO ? TB : 0);     // used when BLO
+  // element offset of the 16-byte chunk holding k (a multiple of 8) in row r:
+  // chunk index XOR (r / 2) % 8 spreads 16 consecutive rows over all banks
+  auto sw = [](int r, int k) { return (((k >> 3) ^ ((r >> 1) & 7)) << 3); };
 
   const int b = blockIdx.y;
   if (g.active && !g.active[b]) return;
@@ -343,10 +350,11 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
     __syncthreads();
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      *(us8_t*)&Ah[vrow(v)][vk(v)] = ah[v];
-      *(us8_t*)&Bh[vrow(v)][vk(v)] = bh[v];
-      if (ALO) *(us8_t*)&Al[vrow(v)][vk(v)] = al[v];
-      if (BLO) *(us8_t*)&Bl[vrow(v)][vk(v)] = bl[v];
+      const int so = sw(vrow(v), vk(v));
+      *(us8_t*)&Ah[vrow(v)][so] = ah[v];
+      *(us8_t*)&Bh[vrow(v)][so] = bh[v];
+      if (ALO) *(us8_t*)&Al[vrow(v)][so] = al[v];
+      if (BLO) *(us8_t*)&Bl[vrow(v)][so] = bl[v];
     }
     __syncthreads();
     if (kt + 1 < nk) load_tile((kt + 1) * BK);
@@ -356,15 +364,20 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
       const int kq = ks * 32 + (lane >> 4) * 8;
 #pragma unroll
       for (int i = 0; i < WT; ++i) {
-        fa[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Ah[wm * (16 * WT) + i * 16 + (lane & 15)][kq]);
-        if (ALO) fal[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Al[wm * (16 * WT) + i * 16 + (lane & 15)][kq]);
+        const int r = wm * (16 * WT) + i * 16 + (lane & 15);
+        fa[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Ah[r][sw(r, kq)]);
+        if (ALO) fal[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Al[r][sw(r, kq)]);
       }
 #pragma unroll
       for (int j = 0; j < WT; ++j) {
-        fb[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Bh[wn * (16 * WT) + j * 16 + (lane & 15)][kq]);
-        if (BLO) fbl[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Bl[wn * (16 * WT) + j * 16 + (lane & 15)][kq]);
+        const int r = wn * (16 * WT) + j * 16 + (lane & 15);
+        fb[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Bh[r][sw(r, kq)]);
+        if (BLO) fbl[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Bl[r][sw(r, kq)]);
       }
-      // products outermost: consecutive MFMAs write different accumulators
+      // products outermost: consecutive MFMAs write different accumulators;
+      // the wave issuing its MFMA block runs at raised priority (the other
+      // wave of the SIMD meanwhile stages and loads)
+      __builtin_amdgcn_s_setprio(1);
       if (ALO) {
 #pragma unroll
         for (int i = 0; i < WT; ++i)
@@ -384,6 +397,7 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
 #pragma unroll
         for (int j = 0; j < WT; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+      __builtin_amdgcn_s_setprio(0);
     }
   }
 
