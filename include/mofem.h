@@ -330,9 +330,11 @@ size_t mofem_pcg_workspace_size(mofem_op_t op, mofem_prec_t prec, int batch);
 
 /* Solve every item to   ||Rhs_b - L_b(U_b)||_F <= tol ||Rhs_b||_F   on the
    FP64 true residual (recomputed at exit; if the recurrence drifted, the
-   solve restarts from the true residual).  The recurrence scalars and all
-   inner products are FP64 on the device; only the preconditioner runs in
-   the handle's precision.
+   solve restarts from the true residual).  The recurrence scalars, all
+   inner products and U, R, Q are FP64 on the device; the preconditioner runs
+   in the handle's precision, and with an FP32 or BF16-family preconditioner
+   its output Z is kept in FP32 (far below its own error), so the inner
+   products with Z and the direction update read 4 bytes per entry.
      Rhs        device, q_s x q_t items at `stride`.
      U          device, in: initial guess (unless ZERO_GUESS), out: solution.
      item_scale device [batch] or NULL, passed to op and preconditioner.
