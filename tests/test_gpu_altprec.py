@@ -147,3 +147,16 @@ def test_closed_form_eigenbasis_preconditioner(lumped, bc):
     it2, _, _ = mf.pcg_solve(Bc.op, Bc.prec, R, U2, tol=1e-12, maxit=50, item_scale=sc, flags=mf.PCG_ZERO_GUESS)
     assert np.array_equal(it1, it2) and it1.max() <= 2   # the rectangle preset is exact
     assert rel(to_host(U2), to_host(U1)) < 1e-12
+
+
+@pytest.mark.parametrize("k,m", [(1, 2), (1, 3), (2, 2), (3, 1), (1, 66)])
+def test_product_apply_tiny(k, m):
+    """Degenerate sizes of the banded solves: one or two unknowns per
+    dimension, a single element, one more column than a 64-column block."""
+    G, P = _pair(k, m, "dirichlet", 1.0)
+    T = P.mat
+    B = BandedProductPrec(T["B1"], T["A"] + T["B2"])
+    R = np.random.default_rng(m).standard_normal((2, P.q, P.q_t))
+    Z = to_host(G.product_prec().apply(to_dev(R)))
+    for b in range(2):
+        assert rel(Z[b], B.apply(R[b])) < 1e-12
