@@ -1020,7 +1020,7 @@ struct PcgWs {
   double *R, *Z, *Q, *Y;
   double *part_a, *part_b, *part_op;
   double *rz, *rz_new, *qy, *rr, *zy, *alpha, *beta, *rhs2, *tr, *target2;
-  int *active, *claim, *restart, *status, *iters;  // device-side control, see k_vec.hip
+  int *active, *claim, *restart, *status, *iters, *live;  // device-side control, see k_vec.hip
   void* prec_ws;
   size_t prec_bytes;
 };
@@ -1032,7 +1032,7 @@ size_t pcg_bytes(mofem_op_t op, mofem_prec_t prec, int batch, size_t* prec_part)
   b += 2 * align_up((size_t)batch * kVecBlocks * 8, 256);
   b += align_up((size_t)batch * op->n_tiles * 8, 256);
   b += 11 * align_up((size_t)batch * 8, 256);
-  b += 5 * align_up((size_t)batch * 4, 256);
+  b += 6 * align_up((size_t)batch * 4, 256);
   size_t pp = mofem_prec_workspace_size(prec, batch);
   if (prec_part) *prec_part = pp;
   return b + pp + 4096;
@@ -1052,7 +1052,7 @@ bool carve_pcg(mofem_op_t op, mofem_prec_t prec, int batch, void* ws, size_t byt
                      &w->target2};
   for (double** x : scal) *x = c.take<double>(batch);
   (void)c.take<double>(batch);  // spare
-  int** flags[] = {&w->active, &w->claim, &w->restart, &w->status, &w->iters};
+  int** flags[] = {&w->active, &w->claim, &w->restart, &w->status, &w->iters, &w->live};
   for (int** x : flags) *x = c.take<int>(batch);
   w->prec_bytes = mofem_prec_workspace_size(prec, batch);
   w->prec_ws = c.take<char>(w->prec_bytes);
@@ -1155,15 +1155,18 @@ struct PcgRun {
     PCG_TRY(op_launch(op, w.Q, n, w.Y, n, batch, item_scale, w.part_op, w.active, s, n_trace));
     rec_band += n_trace;
     PCG_LTRY(launch_reduce(w.part_op, op->n_tiles, w.qy, batch, s));
-    // alpha = <R, Z> / <Q, Y>; U += alpha Q; R -= alpha Y; ||R||^2; R's padded transform operand
-    PCG_LTRY(launch_cg_update_pad(U, w.R, w.Q, w.Y, w.rz, w.qy, w.alpha, op->qs, op->qt, n, stride, batch, w.part_a,
-                                  w.active, pin.hi, pin.lo, pin.f64, pin.f32, pin.stride, s));
+    // alpha = <R, Z> / <Q, Y>; R -= alpha Y; ||R||^2; R's padded transform operand.
+    // U += alpha Q is deferred to the direction pass of this iteration (which
+    // reads Q anyway), for every item whose step is valid (live)
+    PCG_LTRY(launch_cg_update_pad(nullptr, w.R, w.Q, w.Y, w.rz, w.qy, w.alpha, op->qs, op->qt, n, stride, batch,
+                                  w.part_a, w.active, pin.hi, pin.lo, pin.f64, pin.f32, pin.stride, s));
     PCG_LTRY(launch_reduce(w.part_a, kVecBlocks, w.rr, batch, s));
-    PCG_LTRY(launch_pcg_check(w.qy, w.rr, w.target2, w.active, w.claim, w.status, w.iters, batch, s));
-    // items that claim convergence: confirm on the true residual Rhs - L(U); where it
-    // fails, continue from the true residual with a fresh direction
+    PCG_LTRY(launch_pcg_check(w.qy, w.rr, w.target2, w.active, w.claim, w.status, w.iters, w.live, batch, s));
+    // items that claim convergence: confirm on the true residual of U + alpha Q,
+    // Rhs - L(U) - alpha Y (Y = L(Q)); where it fails, continue from the true
+    // residual with a fresh direction
     PCG_TRY(op_launch(op, U, stride, w.Z, n, batch, item_scale, nullptr, w.claim, s, 0));
-    PCG_LTRY(launch_residual(Rhs, w.Z, w.Z, n, n, stride, batch, w.part_b, w.claim, s));
+    PCG_LTRY(launch_residual_step(Rhs, w.Z, w.Y, w.alpha, w.Z, n, n, stride, batch, w.part_b, w.claim, s));
     PCG_LTRY(launch_reduce(w.part_b, kVecBlocks, w.tr, batch, s));
     PCG_LTRY(launch_pcg_confirm(w.tr, w.target2, w.active, w.claim, w.restart, batch, s));
     PCG_LTRY(launch_copy_masked(w.Z, w.R, n, n, n, batch, w.restart, s));
@@ -1183,10 +1186,11 @@ struct PcgRun {
     PCG_LTRY(launch_reduce(w.part_b, kVecBlocks, w.zy, batch, s));
     PCG_LTRY(launch_beta_restart(w.rz_new, w.rz, w.zy, w.alpha, w.beta, w.restart,
                                  (flags & MOFEM_PCG_FLEXIBLE) ? 1 : 0, batch, w.active, s));
+    // U += alpha Q (live items), Q = Z + beta Q (items still active)
     if (z32) {
-      PCG_LTRY(launch_direction(w.Q, z32, w.beta, n, n, batch, w.active, s));
+      PCG_LTRY(launch_step_direction(w.Q, z32, w.beta, U, w.alpha, n, n, stride, batch, w.live, w.active, s));
     } else {
-      PCG_LTRY(launch_direction(w.Q, w.Z, w.beta, n, n, batch, w.active, s));
+      PCG_LTRY(launch_step_direction(w.Q, w.Z, w.beta, U, w.alpha, n, n, stride, batch, w.live, w.active, s));
     }
     return MOFEM_OK;
   }

@@ -110,13 +110,13 @@ __global__ __launch_bounds__(kThreads) void cg_update_kernel(double* __restrict_
   if (blockIdx.x == 0 && threadIdx.x == 0 && alpha_out) alpha_out[b] = alpha;
   long long lo, hi;
   chunk_of(n, blockIdx.x, gridDim.x, &lo, &hi);
-  double* u = U + (size_t)b * u_stride;
+  double* u = U ? U + (size_t)b * u_stride : nullptr;
   double* r = R + (size_t)b * stride;
   const double* q = Q + (size_t)b * stride;
   const double* y = Y + (size_t)b * stride;
   double s = 0.0;
   for (long long i = lo + threadIdx.x; i < hi; i += kThreads) {
-    u[i] = fma(alpha, q[i], u[i]);
+    if (u) u[i] = fma(alpha, q[i], u[i]);
     double v = fma(-alpha, y[i], r[i]);
     r[i] = v;
     s = fma(v, v, s);
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(kThreads) void cg_update_pad_kernel(
   if (blockIdx.x == 0 && threadIdx.x == 0 && alpha_out) alpha_out[b] = alpha;
   long long lo, hi;
   chunk_of(n, blockIdx.x, gridDim.x, &lo, &hi);
-  double* u = U + (size_t)b * u_stride;
+  double* u = U ? U + (size_t)b * u_stride : nullptr;  // null: the solution update is deferred
   double* r = R + (size_t)b * stride;
   const double* q = Q + (size_t)b * stride;
   const double* y = Y + (size_t)b * stride;
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(kThreads) void cg_update_pad_kernel(
   int col = (int)(i - row * qt);
   double s = 0.0;
   for (; i < hi; i += kThreads) {
-    u[i] = fma(alpha, q[i], u[i]);
+    if (u) u[i] = fma(alpha, q[i], u[i]);
     const double v = fma(-alpha, y[i], r[i]);
     r[i] = v;
     s = fma(v, v, s);
@@ -198,6 +198,35 @@ __global__ __launch_bounds__(kThreads) void zdots_kernel(const double* __restric
   if (threadIdx.x == 0) {
     p1[(size_t)b * gridDim.x + blockIdx.x] = s1;
     p2[(size_t)b * gridDim.x + blockIdx.x] = s2;
+  }
+}
+// The deferred solution update and the new direction in one pass, for items
+// live in this iteration: U += alpha Q (every live item), then Q = Z + beta Q
+// (items still active).
+template <typename ZT>
+__global__ __launch_bounds__(kThreads) void step_direction_kernel(double* __restrict__ Q, const ZT* __restrict__ Z,
+                                                                  const double* __restrict__ beta,
+                                                                  double* __restrict__ U,
+                                                                  const double* __restrict__ alpha, long long n,
+                                                                  long long stride, long long u_stride,
+                                                                  const int* live, const int* active) {
+  const int b = blockIdx.y;
+  if (!live[b]) return;
+  const bool act = active[b] != 0;
+  const double al = alpha[b], be = act ? beta[b] : 0.0;
+  long long lo, hi;
+  chunk_of(n, blockIdx.x, gridDim.x, &lo, &hi);
+  double* q = Q + (size_t)b * stride;
+  const ZT* z = Z + (size_t)b * stride;
+  double* u = U + (size_t)b * u_stride;
+  if (act) {
+    for (long long i = lo + threadIdx.x; i < hi; i += kThreads) {
+      const double qo = q[i];
+      u[i] = fma(al, qo, u[i]);
+      q[i] = fma(be, qo, (double)z[i]);
+    }
+  } else {
+    for (long long i = lo + threadIdx.x; i < hi; i += kThreads) u[i] = fma(al, q[i], u[i]);
   }
 }
 template <typename ZT>
@@ -270,13 +299,17 @@ __global__ void pcg_init_kernel(const double* __restrict__ rhs2, const double* _
   active[b] = (f == 0.0 || r <= t) ? 0 : 1;
 }
 
+// live[b]: this iteration's step alpha Q is valid and still to be added to U
+// (by the direction pass, which runs for live items); not set on breakdown,
+// so U keeps the last valid iterate.
 __global__ void pcg_check_kernel(const double* __restrict__ qy, const double* __restrict__ rr,
                                  const double* __restrict__ target2, int* __restrict__ active,
                                  int* __restrict__ claim, int* __restrict__ status, int* __restrict__ iters,
-                                 int batch) {
+                                 int* __restrict__ live, int batch) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= batch) return;
   claim[b] = 0;
+  if (live) live[b] = 0;
   if (!active[b]) return;
   iters[b] += 1;
   const double a = qy[b], r = rr[b];
@@ -286,11 +319,36 @@ __global__ void pcg_check_kernel(const double* __restrict__ qy, const double* __
   } else if (!isfinite(r)) {
     status[b] = kStatusNotFinite;
     active[b] = 0;
-  } else if (r <= target2[b]) {
-    claim[b] = 1;
+  } else {
+    if (live) live[b] = 1;
+    if (r <= target2[b]) claim[b] = 1;
   }
 }
 
+// R = Rhs - LU - alpha_b Y: the residual of U + alpha Q with Y = L(Q)
+__global__ __launch_bounds__(kThreads) void residual_step_kernel(const double* __restrict__ Rhs, const double* LU,
+                                                                 const double* __restrict__ Y,
+                                                                 const double* __restrict__ alpha, double* R,
+                                                                 long long n, long long stride, long long rhs_stride,
+                                                                 double* __restrict__ partial, const int* active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  long long lo, hi;
+  chunk_of(n, blockIdx.x, gridDim.x, &lo, &hi);
+  const double al = alpha[b];
+  const double* f = Rhs + (size_t)b * rhs_stride;
+  const double* ly = LU + (size_t)b * stride;
+  const double* y = Y + (size_t)b * stride;
+  double* r = R + (size_t)b * stride;
+  double s = 0.0;
+  for (long long i = lo + threadIdx.x; i < hi; i += kThreads) {
+    const double v = fma(-al, y[i], f[i] - ly[i]);
+    r[i] = v;
+    s = fma(v, v, s);
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0 && partial) partial[(size_t)b * gridDim.x + blockIdx.x] = s;
+}
 __global__ void pcg_confirm_kernel(const double* __restrict__ tr, const double* __restrict__ target2,
                                    int* __restrict__ active, int* __restrict__ claim, int* __restrict__ restart,
                                    int batch) {
@@ -453,6 +511,27 @@ int launch_direction(double* Q, const double* Z, const double* beta, long long n
                      active);
   CHECK_LAUNCH();
 }
+int launch_step_direction(double* Q, const double* Z, const double* beta, double* U, const double* alpha,
+                          long long n, long long stride, long long u_stride, int batch, const int* live,
+                          const int* active, hipStream_t s) {
+  hipLaunchKernelGGL(step_direction_kernel<double>, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, Q, Z, beta, U,
+                     alpha, n, stride, u_stride, live, active);
+  CHECK_LAUNCH();
+}
+int launch_step_direction(double* Q, const float* Z, const double* beta, double* U, const double* alpha,
+                          long long n, long long stride, long long u_stride, int batch, const int* live,
+                          const int* active, hipStream_t s) {
+  hipLaunchKernelGGL(step_direction_kernel<float>, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, Q, Z, beta, U,
+                     alpha, n, stride, u_stride, live, active);
+  CHECK_LAUNCH();
+}
+int launch_residual_step(const double* Rhs, const double* LU, const double* Y, const double* alpha, double* R,
+                         long long n, long long stride, long long rhs_stride, int batch, double* partial,
+                         const int* active, hipStream_t s) {
+  hipLaunchKernelGGL(residual_step_kernel, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, Rhs, LU, Y, alpha, R, n,
+                     stride, rhs_stride, partial, active);
+  CHECK_LAUNCH();
+}
 int launch_direction(double* Q, const float* Z, const double* beta, long long n, long long stride, int batch,
                      const int* active, hipStream_t s) {
   hipLaunchKernelGGL(direction_kernel<float>, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, Q, Z, beta, n, stride,
@@ -498,9 +577,9 @@ int launch_pcg_init(const double* rhs2, const double* rr, double* target2, int* 
   CHECK_LAUNCH();
 }
 int launch_pcg_check(const double* qy, const double* rr, const double* target2, int* active, int* claim,
-                     int* status, int* iters, int batch, hipStream_t s) {
+                     int* status, int* iters, int* live, int batch, hipStream_t s) {
   hipLaunchKernelGGL(pcg_check_kernel, dim3((batch + 63) / 64), dim3(64), 0, s, qy, rr, target2, active, claim,
-                     status, iters, batch);
+                     status, iters, live, batch);
   CHECK_LAUNCH();
 }
 int launch_pcg_confirm(const double* tr, const double* target2, int* active, int* claim, int* restart, int batch,

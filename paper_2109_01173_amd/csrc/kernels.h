@@ -116,7 +116,7 @@ int launch_dot_partial(const double* X, const double* Y, long long n, long long 
 // R = Rhs - Y  (and partial <R, R>)
 int launch_residual(const double* Rhs, const double* Y, double* R, long long n, long long stride,
                     long long rhs_stride, int batch, double* partial, const int* active, hipStream_t s);
-// alpha_b = num_b / den_b; U += alpha Q; R -= alpha Y; partial <R, R>
+// alpha_b = num_b / den_b; U += alpha Q (skipped when U is null); R -= alpha Y; partial <R, R>
 // cg_update that also writes R's padded transform operand (row length
 // pad_up(qt)): FP64 (o64), FP32 (o32) or split BF16 (ohi, olo); padding left untouched
 int launch_cg_update_pad(double* U, double* R, const double* Q, const double* Y, const double* num,
@@ -132,6 +132,18 @@ int launch_direction(double* Q, const double* Z, const double* beta, long long n
                      long long stride, int batch, const int* active, hipStream_t s);
 int launch_direction(double* Q, const float* Z, const double* beta, long long n,
                      long long stride, int batch, const int* active, hipStream_t s);
+// deferred solution update and new direction, items with live[b]:
+// U += alpha Q; then, if active[b], Q = Z + beta Q
+int launch_step_direction(double* Q, const double* Z, const double* beta, double* U, const double* alpha,
+                          long long n, long long stride, long long u_stride, int batch, const int* live,
+                          const int* active, hipStream_t s);
+int launch_step_direction(double* Q, const float* Z, const double* beta, double* U, const double* alpha,
+                          long long n, long long stride, long long u_stride, int batch, const int* live,
+                          const int* active, hipStream_t s);
+// R = Rhs - LU - alpha_b Y (and partial <R, R>): the residual of U + alpha Q
+int launch_residual_step(const double* Rhs, const double* LU, const double* Y, const double* alpha, double* R,
+                         long long n, long long stride, long long rhs_stride, int batch, double* partial,
+                         const int* active, hipStream_t s);
 // <X, Y> partials with Y in FP32
 int launch_dot_partial(const double* X, const float* Y, long long n, long long stride,
                        int batch, double* partial, const int* active, hipStream_t s);
@@ -153,8 +165,9 @@ int launch_scale_items(double* x, const double* f, int batch, hipStream_t s);
 // device-side control of the PCG iteration (see k_vec.hip)
 int launch_pcg_init(const double* rhs2, const double* rr, double* target2, int* active, int* claim, int* restart,
                     int* status, int* iters, double tol2, int tau_stop, int batch, hipStream_t s);
+// live (may be null): set for items whose step alpha Q of this iteration is valid
 int launch_pcg_check(const double* qy, const double* rr, const double* target2, int* active, int* claim,
-                     int* status, int* iters, int batch, hipStream_t s);
+                     int* status, int* iters, int* live, int batch, hipStream_t s);
 int launch_pcg_confirm(const double* tr, const double* target2, int* active, int* claim, int* restart, int batch,
                        hipStream_t s);
 int launch_pcg_final(const double* tr, const double* rhs2, const double* target2, const int* status,
