@@ -340,8 +340,8 @@ size_t mofem_pcg_workspace_size(mofem_op_t op, mofem_prec_t prec, int batch);
      item_scale device [batch] or NULL, passed to op and preconditioner.
      iters_out, relres_out  host [batch] or NULL.
    Errors: MOFEM_E_MAXIT (U holds the last iterate, relres_out its true
-   relative residual), MOFEM_E_BREAKDOWN, MOFEM_E_NOTFINITE, MOFEM_E_ARG,
-   MOFEM_E_NOMEM.  The iteration runs under device-side control; the host
+   relative residual), MOFEM_E_BREAKDOWN (U holds the last iterate with a
+   valid step), MOFEM_E_NOTFINITE, MOFEM_E_ARG, MOFEM_E_NOMEM.  The iteration runs under device-side control; the host
    reads a few bytes of flags one iteration behind and synchronises once at
    the end. */
 int mofem_pcg_solve(mofem_op_t op, mofem_prec_t prec, const double* Rhs, double* U,
