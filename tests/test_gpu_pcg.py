@@ -106,11 +106,18 @@ def test_failure_reporting():
     U = to_dev(np.zeros((1, G.q, G.q)))
     iters, relres, rc = mf.pcg_solve(G.op, G.prec, Rhs, U, tol=1e-12, maxit=2, raise_on_error=False)
     assert rc == mf.E_MAXIT and relres[0] > 1e-12 and iters[0] == 2
-    # indefinite operator (gamma below minus the largest eigenvalue): breakdown is reported
+    # U holds the last iterate (both steps applied) and relres is its true residual
+    Rh, Uh = to_host(Rhs)[0], to_host(U)[0]
+    true = np.linalg.norm(Rh - to_host(G.op.apply(U))[0]) / np.linalg.norm(Rh)
+    assert abs(true - relres[0]) <= 1e-10 * relres[0]
+    assert np.linalg.norm(Uh) > 0
+    # indefinite operator (gamma below minus the largest eigenvalue): breakdown is
+    # reported and U keeps the last iterate with a valid step (here the zero start)
     Gn = gpu_xnormal(1, 30, "dirichlet", -1e6)
     U = to_dev(np.zeros((1, G.q, G.q)))
     iters, relres, rc = mf.pcg_solve(Gn.op, G.prec, Rhs, U, tol=1e-10, maxit=50, raise_on_error=False)
-    assert rc == mf.E_BREAKDOWN
+    assert rc == mf.E_BREAKDOWN and iters[0] == 1
+    assert np.all(to_host(U) == 0.0)
     # non-finite data
     bad = Rhs.clone()
     bad[0, 3, 3] = float("nan")
