@@ -123,3 +123,29 @@ def test_failure_reporting():
     bad[0, 3, 3] = float("nan")
     iters, relres, rc = mf.pcg_solve(G.op, G.prec, bad, U, tol=1e-10, maxit=50, raise_on_error=False)
     assert rc == mf.E_NOTFINITE
+
+
+@pytest.mark.parametrize("precision,flags", [("F64", 0), ("BF16_FWD", 1)])
+def test_unattainable_tolerance_restarts(precision, flags):
+    """A tolerance below the attainable accuracy: the recurrence residual
+    keeps claiming convergence, the FP64 true residual refuses it and the
+    solve restarts from the true residual until MAXIT (an FP64 emulation of
+    the same recurrence restarts 14 times in the 90 iterations).  The returned
+    iterate must stay at the rounding floor (restarts must not lose it) and
+    the reported residual must be that iterate's true residual."""
+    from paper_2109_01173_amd import mofem as mf
+    G = gpu_xnormal(2, 20, "dirichlet", 1.0, precision=getattr(mf, "PREC_" + precision))
+    P = oracle_xnormal(2, 20, "dirichlet", 1.0)
+    Rh = np.random.default_rng(13).standard_normal((2, G.q, G.q))
+    U = to_dev(np.zeros_like(Rh))
+    its, relres, rc = mf.pcg_solve(G.op, G.prec, to_dev(Rh), U, tol=1e-17, maxit=90,
+                                   flags=flags | mf.PCG_ZERO_GUESS, raise_on_error=False)
+    assert rc == mf.E_MAXIT and np.all(its == 90)
+    Uh = to_host(U)
+    LU = to_host(G.op.apply(U))
+    K = P.kron()
+    for b in range(2):
+        true = np.linalg.norm(Rh[b] - LU[b]) / np.linalg.norm(Rh[b])
+        assert abs(true - relres[b]) <= 1e-6 * true + 1e-18
+        assert true < 1e-13
+        assert rel(Uh[b], direct_solve(K, Rh[b])) < 1e-11
