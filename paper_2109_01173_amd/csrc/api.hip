@@ -1121,7 +1121,7 @@ struct PcgRun {
   // ||Rhs||^2, R = Rhs - L(U) (or Rhs with a zero guess), targets, Z = P^-1(R), Q = Z
   int begin() {
     PCG_LTRY(launch_dot_partial(Rhs, Rhs, n, stride, batch, w.part_a, nullptr, s));
-    PCG_LTRY(launch_reduce(w.part_a, kVecBlocks, w.rhs2, batch, s));
+    PCG_LTRY(launch_reduce(w.part_a, vec_blocks(n), w.rhs2, batch, s));
     if (flags & MOFEM_PCG_ZERO_GUESS) {
       PCG_LTRY(launch_fill(U, 0.0, n, stride, batch, s));
       PCG_LTRY(launch_copy(Rhs, w.R, n, stride, n, batch, s));
@@ -1130,7 +1130,7 @@ struct PcgRun {
       PCG_TRY(op_launch(op, U, stride, w.Y, n, batch, item_scale, nullptr, nullptr, s, n_trace));
       PCG_LTRY(launch_residual(Rhs, w.Y, w.R, n, n, stride, batch, w.part_a, nullptr, s));
     }
-    PCG_LTRY(launch_reduce(w.part_a, kVecBlocks, w.rr, batch, s));
+    PCG_LTRY(launch_reduce(w.part_a, vec_blocks(n), w.rr, batch, s));
     PCG_LTRY(launch_pcg_init(w.rhs2, w.rr, w.target2, w.active, w.claim, w.restart, w.status, w.iters, tol * tol,
                              (flags & MOFEM_PCG_TAU_STOP) ? 1 : 0, batch, s));
     PCG_TRY(prec_launch(prec, w.R, w.Z, n, batch, item_scale, w.prec_ws, w.prec_bytes, w.active, s, n_trace, 0,
@@ -1141,7 +1141,7 @@ struct PcgRun {
     } else {
       PCG_LTRY(launch_dot_partial(w.R, w.Z, n, n, batch, w.part_a, w.active, s));
     }
-    PCG_LTRY(launch_reduce(w.part_a, kVecBlocks, w.rz, batch, s));
+    PCG_LTRY(launch_reduce(w.part_a, vec_blocks(n), w.rz, batch, s));
     if (z32) {
       PCG_LTRY(launch_direction(w.Q, z32, nullptr, n, n, batch, w.active, s));
     } else {
@@ -1160,14 +1160,14 @@ struct PcgRun {
     // reads Q anyway), for every item whose step is valid (live)
     PCG_LTRY(launch_cg_update_pad(nullptr, w.R, w.Q, w.Y, w.rz, w.qy, w.alpha, op->qs, op->qt, n, stride, batch,
                                   w.part_a, w.active, pin.hi, pin.lo, pin.f64, pin.f32, pin.stride, s));
-    PCG_LTRY(launch_reduce(w.part_a, kVecBlocks, w.rr, batch, s));
+    PCG_LTRY(launch_reduce(w.part_a, vec_blocks(n), w.rr, batch, s));
     PCG_LTRY(launch_pcg_check(w.qy, w.rr, w.target2, w.active, w.claim, w.status, w.iters, w.live, batch, s));
     // items that claim convergence: confirm on the true residual of U + alpha Q,
     // Rhs - L(U) - alpha Y (Y = L(Q)); where it fails, continue from the true
     // residual with a fresh direction
     PCG_TRY(op_launch(op, U, stride, w.Z, n, batch, item_scale, nullptr, w.claim, s, 0));
     PCG_LTRY(launch_residual_step(Rhs, w.Z, w.Y, w.alpha, w.Z, n, n, stride, batch, w.part_b, w.claim, s));
-    PCG_LTRY(launch_reduce(w.part_b, kVecBlocks, w.tr, batch, s));
+    PCG_LTRY(launch_reduce(w.part_b, vec_blocks(n), w.tr, batch, s));
     PCG_LTRY(launch_pcg_confirm(w.tr, w.target2, w.active, w.claim, w.restart, batch, s));
     PCG_LTRY(launch_copy_masked(w.Z, w.R, n, n, n, batch, w.restart, s));
     if (pin.f64 || pin.f32 || pin.hi)
@@ -1182,8 +1182,8 @@ struct PcgRun {
     } else {
       PCG_LTRY(launch_zdots_partial(w.R, w.Z, w.Y, n, n, batch, w.part_a, w.part_b, w.active, s));
     }
-    PCG_LTRY(launch_reduce(w.part_a, kVecBlocks, w.rz_new, batch, s));
-    PCG_LTRY(launch_reduce(w.part_b, kVecBlocks, w.zy, batch, s));
+    PCG_LTRY(launch_reduce(w.part_a, vec_blocks(n), w.rz_new, batch, s));
+    PCG_LTRY(launch_reduce(w.part_b, vec_blocks(n), w.zy, batch, s));
     PCG_LTRY(launch_beta_restart(w.rz_new, w.rz, w.zy, w.alpha, w.beta, w.restart,
                                  (flags & MOFEM_PCG_FLEXIBLE) ? 1 : 0, batch, w.active, s));
     // U += alpha Q (live items), Q = Z + beta Q (items still active)
@@ -1199,7 +1199,7 @@ struct PcgRun {
   int finish(int* iters_dev, int* status_dev, double* relres_dev) {
     PCG_TRY(op_launch(op, U, stride, w.Z, n, batch, item_scale, nullptr, nullptr, s, batch));
     PCG_LTRY(launch_residual(Rhs, w.Z, w.Z, n, n, stride, batch, w.part_b, nullptr, s));
-    PCG_LTRY(launch_reduce(w.part_b, kVecBlocks, w.tr, batch, s));
+    PCG_LTRY(launch_reduce(w.part_b, vec_blocks(n), w.tr, batch, s));
     PCG_LTRY(launch_pcg_final(w.tr, w.rhs2, w.target2, w.status, w.iters, iters_dev, status_dev, relres_dev, batch,
                               s));
     return MOFEM_OK;
@@ -1726,7 +1726,7 @@ extern "C" int mofem_dot_accumulate(const double* X, const double* Y, long long 
   int rc = ensure_internal_ws(&part, &have, (size_t)batch * kVecBlocks * 8, s);
   if (rc) return rc;
   if (launch_dot_partial(X, Y, n, stride, batch, (double*)part, nullptr, s) ||
-      launch_reduce_axpy((const double*)part, kVecBlocks, out, alpha, beta, batch, s))
+      launch_reduce_axpy((const double*)part, vec_blocks(n), out, alpha, beta, batch, s))
     return fail(MOFEM_E_HIP, "dot_accumulate: launch failed");
   return MOFEM_OK;
 }
@@ -1795,7 +1795,7 @@ extern "C" int mofem_imex_adjoint_step(const mofem_imex_desc* d, mofem_op_t stif
   {
     TraceScope trace(MOFEM_TRACE_VEC, items, s);
     if (launch_dot_partial(mu, tmp, n, n, items, part, nullptr, s) ||
-        launch_reduce_axpy(part, kVecBlocks, grad_d, -d->tau, 1.0, items, s))
+        launch_reduce_axpy(part, vec_blocks(n), grad_d, -d->tau, 1.0, items, s))
       return fail(MOFEM_E_HIP, "imex_adjoint_step: launch failed");
   }
   // nu = Mass(mu), then the transpose of the explicit kinetics

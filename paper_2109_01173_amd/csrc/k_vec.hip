@@ -1,8 +1,8 @@
 // Vector kernels of the MO-PCG recurrence (Sec. 5, eqs. (77)-(78)), FP64.
 //
 // Every nodal matrix of one batch item is treated as a flat contiguous array
-// of n = q_s * q_t doubles.  Each item is processed by kVecBlocks blocks of
-// 256 threads; a block owns one contiguous chunk, so its loads are
+// of n = q_s * q_t doubles.  Each item is processed by vec_blocks(n) blocks
+// of 256 threads; a block owns one contiguous chunk, so its loads are
 // coalesced.  Frobenius products (sum(sum(X o Y)) of eq. (77)) are reduced
 // deterministically: per-block partial sums in a fixed order, then one block
 // per item adds the partials in a fixed order (no floating-point atomics),
@@ -470,26 +470,26 @@ int launch_reduce_axpy(const double* partial, int n_partial, double* out, double
 }
 int launch_dib_adjoint(const double* U, const double* V, const double* NU, const double* NV, double* LU, double* LV,
                        long long n, long long stride, int batch, const double* k, double tau, hipStream_t s) {
-  hipLaunchKernelGGL(dib_adjoint_kernel, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, U, V, NU, NV, LU, LV, n,
+  hipLaunchKernelGGL(dib_adjoint_kernel, dim3(vec_blocks(n), batch), dim3(kThreads), 0, s, U, V, NU, NV, LU, LV, n,
                      stride, k[0], k[1], k[2], k[3], k[4], k[5], k[7], k[8], k[9], tau);
   CHECK_LAUNCH();
 }
 int launch_dot_partial(const double* X, const double* Y, long long n, long long stride, int batch,
                        double* partial, const int* active, hipStream_t s) {
-  hipLaunchKernelGGL(dot_kernel<double>, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, X, Y, n, stride, partial,
+  hipLaunchKernelGGL(dot_kernel<double>, dim3(vec_blocks(n), batch), dim3(kThreads), 0, s, X, Y, n, stride, partial,
                      active);
   CHECK_LAUNCH();
 }
 int launch_residual(const double* Rhs, const double* Y, double* R, long long n, long long stride,
                     long long rhs_stride, int batch, double* partial, const int* active, hipStream_t s) {
-  hipLaunchKernelGGL(residual_kernel, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, Rhs, Y, R, n, stride,
+  hipLaunchKernelGGL(residual_kernel, dim3(vec_blocks(n), batch), dim3(kThreads), 0, s, Rhs, Y, R, n, stride,
                      rhs_stride, partial, active);
   CHECK_LAUNCH();
 }
 int launch_cg_update(double* U, double* R, const double* Q, const double* Y, const double* num, const double* den,
                      double* alpha_out, long long n, long long stride, long long u_stride, int batch,
                      double* partial, const int* active, hipStream_t s) {
-  hipLaunchKernelGGL(cg_update_kernel, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, U, R, Q, Y, num, den,
+  hipLaunchKernelGGL(cg_update_kernel, dim3(vec_blocks(n), batch), dim3(kThreads), 0, s, U, R, Q, Y, num, den,
                      alpha_out, n, stride, u_stride, partial, active);
   CHECK_LAUNCH();
 }
@@ -500,68 +500,68 @@ int launch_cg_update_pad(double* U, double* R, const double* Q, const double* Y,
   if (!ohi && !o64 && !o32)  // no transform operand wanted
     return launch_cg_update(U, R, Q, Y, num, den, alpha_out, (long long)qs * qt, stride, u_stride, batch, partial,
                             active, s);
-  hipLaunchKernelGGL(cg_update_pad_kernel, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, U, R, Q, Y, num, den,
+  hipLaunchKernelGGL(cg_update_pad_kernel, dim3(vec_blocks((long long)qs * qt), batch), dim3(kThreads), 0, s, U, R, Q, Y, num, den,
                      alpha_out, qt, (long long)qs * qt, stride, u_stride, partial, active, ohi, olo, o64, o32,
                      o_stride);
   CHECK_LAUNCH();
 }
 int launch_direction(double* Q, const double* Z, const double* beta, long long n, long long stride, int batch,
                      const int* active, hipStream_t s) {
-  hipLaunchKernelGGL(direction_kernel<double>, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, Q, Z, beta, n, stride,
+  hipLaunchKernelGGL(direction_kernel<double>, dim3(vec_blocks(n), batch), dim3(kThreads), 0, s, Q, Z, beta, n, stride,
                      active);
   CHECK_LAUNCH();
 }
 int launch_step_direction(double* Q, const double* Z, const double* beta, double* U, const double* alpha,
                           long long n, long long stride, long long u_stride, int batch, const int* live,
                           const int* active, hipStream_t s) {
-  hipLaunchKernelGGL(step_direction_kernel<double>, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, Q, Z, beta, U,
+  hipLaunchKernelGGL(step_direction_kernel<double>, dim3(vec_blocks(n), batch), dim3(kThreads), 0, s, Q, Z, beta, U,
                      alpha, n, stride, u_stride, live, active);
   CHECK_LAUNCH();
 }
 int launch_step_direction(double* Q, const float* Z, const double* beta, double* U, const double* alpha,
                           long long n, long long stride, long long u_stride, int batch, const int* live,
                           const int* active, hipStream_t s) {
-  hipLaunchKernelGGL(step_direction_kernel<float>, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, Q, Z, beta, U,
+  hipLaunchKernelGGL(step_direction_kernel<float>, dim3(vec_blocks(n), batch), dim3(kThreads), 0, s, Q, Z, beta, U,
                      alpha, n, stride, u_stride, live, active);
   CHECK_LAUNCH();
 }
 int launch_residual_step(const double* Rhs, const double* LU, const double* Y, const double* alpha, double* R,
                          long long n, long long stride, long long rhs_stride, int batch, double* partial,
                          const int* active, hipStream_t s) {
-  hipLaunchKernelGGL(residual_step_kernel, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, Rhs, LU, Y, alpha, R, n,
+  hipLaunchKernelGGL(residual_step_kernel, dim3(vec_blocks(n), batch), dim3(kThreads), 0, s, Rhs, LU, Y, alpha, R, n,
                      stride, rhs_stride, partial, active);
   CHECK_LAUNCH();
 }
 int launch_direction(double* Q, const float* Z, const double* beta, long long n, long long stride, int batch,
                      const int* active, hipStream_t s) {
-  hipLaunchKernelGGL(direction_kernel<float>, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, Q, Z, beta, n, stride,
+  hipLaunchKernelGGL(direction_kernel<float>, dim3(vec_blocks(n), batch), dim3(kThreads), 0, s, Q, Z, beta, n, stride,
                      active);
   CHECK_LAUNCH();
 }
 int launch_dot_partial(const double* X, const float* Y, long long n, long long stride, int batch, double* partial,
                        const int* active, hipStream_t s) {
-  hipLaunchKernelGGL(dot_kernel<float>, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, X, Y, n, stride, partial,
+  hipLaunchKernelGGL(dot_kernel<float>, dim3(vec_blocks(n), batch), dim3(kThreads), 0, s, X, Y, n, stride, partial,
                      active);
   CHECK_LAUNCH();
 }
 int launch_zdots_partial(const double* R, const double* Z, const double* Y, long long n, long long stride, int batch,
                          double* p1, double* p2, const int* active, hipStream_t s) {
-  hipLaunchKernelGGL(zdots_kernel<double>, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, R, Z, Y, n, stride, p1, p2,
+  hipLaunchKernelGGL(zdots_kernel<double>, dim3(vec_blocks(n), batch), dim3(kThreads), 0, s, R, Z, Y, n, stride, p1, p2,
                      active);
   CHECK_LAUNCH();
 }
 int launch_zdots_partial(const double* R, const float* Z, const double* Y, long long n, long long stride, int batch,
                          double* p1, double* p2, const int* active, hipStream_t s) {
-  hipLaunchKernelGGL(zdots_kernel<float>, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, R, Z, Y, n, stride, p1, p2,
+  hipLaunchKernelGGL(zdots_kernel<float>, dim3(vec_blocks(n), batch), dim3(kThreads), 0, s, R, Z, Y, n, stride, p1, p2,
                      active);
   CHECK_LAUNCH();
 }
 int launch_copy(const double* X, double* Y, long long n, long long xs, long long ys, int batch, hipStream_t s) {
-  hipLaunchKernelGGL(copy_kernel, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, X, Y, n, xs, ys);
+  hipLaunchKernelGGL(copy_kernel, dim3(vec_blocks(n), batch), dim3(kThreads), 0, s, X, Y, n, xs, ys);
   CHECK_LAUNCH();
 }
 int launch_fill(double* X, double v, long long n, long long stride, int batch, hipStream_t s) {
-  hipLaunchKernelGGL(fill_kernel, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, X, v, n, stride);
+  hipLaunchKernelGGL(fill_kernel, dim3(vec_blocks(n), batch), dim3(kThreads), 0, s, X, v, n, stride);
   CHECK_LAUNCH();
 }
 int launch_beta(const double* rz_new, double* rz_old, const double* zy, const double* alpha, double* beta,
@@ -603,7 +603,7 @@ int launch_beta_restart(const double* rz_new, double* rz_old, const double* zy, 
 }
 int launch_copy_masked(const double* X, double* Y, long long n, long long xs, long long ys, int batch,
                        const int* mask, hipStream_t s) {
-  hipLaunchKernelGGL(copy_masked_kernel, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, X, Y, n, xs, ys, mask);
+  hipLaunchKernelGGL(copy_masked_kernel, dim3(vec_blocks(n), batch), dim3(kThreads), 0, s, X, Y, n, xs, ys, mask);
   CHECK_LAUNCH();
 }
 int launch_scale_items(double* x, const double* f, int batch, hipStream_t s) {
@@ -612,7 +612,7 @@ int launch_scale_items(double* x, const double* f, int batch, hipStream_t s) {
 }
 int launch_dib_source(const double* U, const double* V, double* TU, double* TV, long long n, long long stride,
                       int batch, const double* k, double tau, hipStream_t s) {
-  hipLaunchKernelGGL(dib_source_kernel, dim3(kVecBlocks, batch), dim3(kThreads), 0, s, U, V, TU, TV, n, stride,
+  hipLaunchKernelGGL(dib_source_kernel, dim3(vec_blocks(n), batch), dim3(kThreads), 0, s, U, V, TU, TV, n, stride,
                      k[0], k[1], k[2], k[3], k[4], k[5], k[6], k[7], k[8], k[9], tau);
   CHECK_LAUNCH();
 }

@@ -102,7 +102,14 @@ int launch_pad_operand(const double* A, long long a_stride, int M, int K, double
                        const int* active, hipStream_t s);
 
 // ---- vector kernels of the PCG recurrence (k_vec.hip) -----------------------
-constexpr int kVecBlocks = 240;   // partial sums per item
+// Blocks per item of the vector kernels: one per 2048 entries, at most
+// kVecBlocks (the partial-sum arrays hold kVecBlocks per item).  Every
+// reduction of partial sums uses the count of the kernel that wrote them.
+constexpr int kVecBlocks = 1920;
+inline int vec_blocks(long long n) {
+  const long long b = (n + 2047) / 2048;
+  return b < 1 ? 1 : (b > kVecBlocks ? kVecBlocks : (int)b);
+}
 int launch_reduce(const double* partial, int n_partial, double* out, int batch, hipStream_t s);
 // out[b] = beta out[b] + alpha (sum of partials)
 int launch_reduce_axpy(const double* partial, int n_partial, double* out, double alpha, double beta, int batch,
