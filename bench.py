@@ -158,8 +158,8 @@ def uneven_leg(mf, torch, np, n_inst, prec, prec_name):
 def imex_legs(mf, torch, np, nsteps, prec, prec_name):
     """Per-step throughput of the IMEX Euler step (eqs. (91)-(96)) on the heat
     workload (P4, Neumann, n = 2049, d = 0.1, tau = 1e-3, U0 ~ U[0,1) seed 42)
-    and the DIB workload (lumped P1 on [0,20]^2, n = 1025, tau = 1e-2, cap
-    parameters, equilibrium + U[-1e-3,1e-3) seed 7)."""
+    and the DIB workload (lumped P1 and P2 on [0,20]^2, n = 1025, tau = 1e-2,
+    cap parameters, equilibrium + U[-1e-3,1e-3) seed 7)."""
     from paper_2109_01173_amd.problems import Rect, XNormal
     from workloads import dib_initial, dib_params, heat_initial
     out = {}
@@ -201,45 +201,48 @@ def imex_legs(mf, torch, np, nsteps, prec, prec_name):
         % (nsteps / dt, np.mean(its), nsteps / dtg))
     del g
     del G, st, ws, stepper
-    # DIB: rectangle preset (exact single-term operator), FP64 transforms; the
-    # eigenpairs of the lumped P1 pencil are the closed-form cosine basis
+    # DIB: rectangle preset (exact single-term operator), FP64 transforms; lumped
+    # P1 (m = 1024, closed-form cosine eigenbasis) and P2 (m = 512)
     p = dib_params()
-    t0 = time.perf_counter()
-    G = Rect(1, 1024, "neumann", length=20.0, lumped=True, imex=True, closed_form=True)
-    setup = time.perf_counter() - t0
-    eta, theta = dib_initial(G.q, seed=7)
-    st = torch.from_numpy(np.stack([eta, theta])).cuda()
     kin = [p["rho"], p["A1"], p["A2"], p["B"], p["C"], p["D"], p["alpha"], p["gamma"], p["k2"], p["k3"]]
-    stepper = mf.Imex(G.op, G.prec, G.mass, 1e-2, [1.0, p["d_theta"]], kinetics=mf.KIN_DIB, kin=kin,
-                      tol=1e-10, maxit=50)
-    ws = stepper.workspace(1)
-    stepper.step(st, 1, workspace=ws)
-    torch.cuda.synchronize()
-    n4 = 10 * nsteps
-    t = time.perf_counter()
-    its = [stepper.step(st, 1, workspace=ws).max() for _ in range(n4)]
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t
-    g = mf.ImexGraph(mf.Imex(G.op, G.prec, G.mass, 1e-2, [1.0, p["d_theta"]], kinetics=mf.KIN_DIB, kin=kin,
-                             tol=1e-10, maxit=50), st, 1, iters_per_step=2)
-    g.launch(1)
-    g.result()
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    g.launch(n4)
-    torch.cuda.synchronize()
-    dtg = time.perf_counter() - t
-    gi, _, _ = g.result()
-    out["imex_dib_p1"] = {"workload": "DIB lumped P1 rectangle [0,20]^2, Neumann, n=1025, tau=1e-2, "
-                                      "two species, rel 1e-10 per step",
-                          "steps_per_s": round(n4 / dt, 2), "steps": n4,
-                          "iterations_per_step": round(float(np.mean(its)), 2),
-                          "graph_steps_per_s": round(n4 / dtg, 2), "graph_iteration_budget": 2,
-                          "graph_max_iterations": int(gi.max()), "transforms": "f64",
-                          "setup_s": round(setup, 2)}
-    log("imex DIB P1: %.1f steps/s, %.1f iterations/step; graph replay %.1f steps/s"
-        % (n4 / dt, np.mean(its), n4 / dtg))
-    del g
+    for key, k, m, lumped in (("imex_dib_p1", 1, 1024, True), ("imex_dib_p2", 2, 512, False)):
+        t0 = time.perf_counter()
+        G = Rect(k, m, "neumann", length=20.0, lumped=lumped, imex=True, closed_form=lumped)
+        setup = time.perf_counter() - t0
+        eta, theta = dib_initial(G.q, seed=7)
+        st = torch.from_numpy(np.stack([eta, theta])).cuda()
+        stepper = mf.Imex(G.op, G.prec, G.mass, 1e-2, [1.0, p["d_theta"]], kinetics=mf.KIN_DIB, kin=kin,
+                          tol=1e-10, maxit=50)
+        ws = stepper.workspace(1)
+        stepper.step(st, 1, workspace=ws)
+        torch.cuda.synchronize()
+        n4 = 10 * nsteps
+        t = time.perf_counter()
+        its = [stepper.step(st, 1, workspace=ws).max() for _ in range(n4)]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        g = mf.ImexGraph(mf.Imex(G.op, G.prec, G.mass, 1e-2, [1.0, p["d_theta"]], kinetics=mf.KIN_DIB, kin=kin,
+                                 tol=1e-10, maxit=50), st, 1, iters_per_step=2)
+        g.launch(1)
+        g.result()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        g.launch(n4)
+        torch.cuda.synchronize()
+        dtg = time.perf_counter() - t
+        gi, _, _ = g.result()
+        name = "lumped P1" if lumped else "P2"
+        out[key] = {"workload": "DIB %s rectangle [0,20]^2, Neumann, n=1025, tau=1e-2, two species, "
+                                "rel 1e-10 per step" % name,
+                    "steps_per_s": round(n4 / dt, 2), "steps": n4,
+                    "iterations_per_step": round(float(np.mean(its)), 2),
+                    "graph_steps_per_s": round(n4 / dtg, 2), "graph_iteration_budget": 2,
+                    "graph_max_iterations": int(gi.max()), "transforms": "f64",
+                    "eigenbasis": "closed form" if lumped else "dense eigen-solve",
+                    "setup_s": round(setup, 2)}
+        log("imex DIB %s: %.1f steps/s, %.1f iterations/step; graph replay %.1f steps/s"
+            % (name, n4 / dt, np.mean(its), n4 / dtg))
+        del g, G, st, stepper, ws
     return out
 
 

@@ -1160,15 +1160,14 @@ struct PcgRun {
     // reads Q anyway), for every item whose step is valid (live)
     PCG_LTRY(launch_cg_update_pad(nullptr, w.R, w.Q, w.Y, w.rz, w.qy, w.alpha, op->qs, op->qt, n, stride, batch,
                                   w.part_a, w.active, pin.hi, pin.lo, pin.f64, pin.f32, pin.stride, s));
-    PCG_LTRY(launch_reduce(w.part_a, vec_blocks(n), w.rr, batch, s));
-    PCG_LTRY(launch_pcg_check(w.qy, w.rr, w.target2, w.active, w.claim, w.status, w.iters, w.live, batch, s));
+    PCG_LTRY(launch_check(w.part_a, vec_blocks(n), w.rr, w.qy, w.target2, w.active, w.claim, w.status, w.iters,
+                          w.live, batch, s));
     // items that claim convergence: confirm on the true residual of U + alpha Q,
     // Rhs - L(U) - alpha Y (Y = L(Q)); where it fails, continue from the true
     // residual with a fresh direction
     PCG_TRY(op_launch(op, U, stride, w.Z, n, batch, item_scale, nullptr, w.claim, s, 0));
     PCG_LTRY(launch_residual_step(Rhs, w.Z, w.Y, w.alpha, w.Z, n, n, stride, batch, w.part_b, w.claim, s));
-    PCG_LTRY(launch_reduce(w.part_b, vec_blocks(n), w.tr, batch, s));
-    PCG_LTRY(launch_pcg_confirm(w.tr, w.target2, w.active, w.claim, w.restart, batch, s));
+    PCG_LTRY(launch_confirm(w.part_b, vec_blocks(n), w.tr, w.target2, w.active, w.claim, w.restart, batch, s));
     PCG_LTRY(launch_copy_masked(w.Z, w.R, n, n, n, batch, w.restart, s));
     if (pin.f64 || pin.f32 || pin.hi)
       PCG_LTRY(launch_pad_operand(w.R, n, op->qs, op->qt, pin.f64, pin.f32, pin.hi, pin.lo, pin.stride,
@@ -1182,10 +1181,8 @@ struct PcgRun {
     } else {
       PCG_LTRY(launch_zdots_partial(w.R, w.Z, w.Y, n, n, batch, w.part_a, w.part_b, w.active, s));
     }
-    PCG_LTRY(launch_reduce(w.part_a, vec_blocks(n), w.rz_new, batch, s));
-    PCG_LTRY(launch_reduce(w.part_b, vec_blocks(n), w.zy, batch, s));
-    PCG_LTRY(launch_beta_restart(w.rz_new, w.rz, w.zy, w.alpha, w.beta, w.restart,
-                                 (flags & MOFEM_PCG_FLEXIBLE) ? 1 : 0, batch, w.active, s));
+    PCG_LTRY(launch_beta(w.part_a, w.part_b, vec_blocks(n), w.rz_new, w.zy, w.rz, w.alpha, w.beta, w.restart,
+                         (flags & MOFEM_PCG_FLEXIBLE) ? 1 : 0, w.active, batch, s));
     // U += alpha Q (live items), Q = Z + beta Q (items still active)
     if (z32) {
       PCG_LTRY(launch_step_direction(w.Q, z32, w.beta, U, w.alpha, n, n, stride, batch, w.live, w.active, s));

@@ -299,20 +299,41 @@ __global__ void pcg_init_kernel(const double* __restrict__ rhs2, const double* _
   active[b] = (f == 0.0 || r <= t) ? 0 : 1;
 }
 
-// live[b]: this iteration's step alpha Q is valid and still to be added to U
-// (by the direction pass, which runs for live items); not set on breakdown,
-// so U keeps the last valid iterate.
-__global__ void pcg_check_kernel(const double* __restrict__ qy, const double* __restrict__ rr,
-                                 const double* __restrict__ target2, int* __restrict__ active,
-                                 int* __restrict__ claim, int* __restrict__ status, int* __restrict__ iters,
-                                 int* __restrict__ live, int batch) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= batch) return;
+
+// The per-iteration control kernels run one block per item: they first add
+// the item's partial sums in the fixed order of reduce_kernel (so the result
+// is the same), then thread 0 takes the item's decision.
+__device__ __forceinline__ double item_sum(const double* __restrict__ partial, int np, int b) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < np; i += kThreads) s += partial[(size_t)b * np + i];
+  return block_sum(s);  // valid in thread 0
+}
+
+// rr_b = ||R_b||^2 from the CG update's partials; breakdown / non-finite
+// checks; claim of convergence when rr_b <= target2_b.  live[b]: this
+// iteration's step alpha Q is valid and still to be added to U (by the
+// direction pass, which runs for live items); not set on breakdown, so U
+// keeps the last valid iterate.
+__global__ __launch_bounds__(kThreads) void check_kernel(const double* __restrict__ part, int np,
+                                                         double* __restrict__ rr, const double* __restrict__ qy,
+                                                         const double* __restrict__ target2, int* __restrict__ active,
+                                                         int* __restrict__ claim, int* __restrict__ status,
+                                                         int* __restrict__ iters, int* __restrict__ live) {
+  const int b = blockIdx.x;
+  if (!active[b]) {
+    if (threadIdx.x == 0) {
+      claim[b] = 0;
+      if (live) live[b] = 0;
+    }
+    return;
+  }
+  const double r = item_sum(part, np, b);
+  if (threadIdx.x != 0) return;
+  rr[b] = r;
   claim[b] = 0;
   if (live) live[b] = 0;
-  if (!active[b]) return;
   iters[b] += 1;
-  const double a = qy[b], r = rr[b];
+  const double a = qy[b];
   if (!isfinite(a) || !(a > 0.0)) {
     status[b] = kStatusBreakdown;
     active[b] = 0;
@@ -324,7 +345,44 @@ __global__ void pcg_check_kernel(const double* __restrict__ qy, const double* __
     if (r <= target2[b]) claim[b] = 1;
   }
 }
-
+// tr_b = true residual ||Rhs - L(U)||^2 of a claiming item: converged, or
+// restart from the true residual
+__global__ __launch_bounds__(kThreads) void confirm_kernel(const double* __restrict__ part, int np,
+                                                           double* __restrict__ tr,
+                                                           const double* __restrict__ target2,
+                                                           int* __restrict__ active, const int* __restrict__ claim,
+                                                           int* __restrict__ restart) {
+  const int b = blockIdx.x;
+  if (!claim[b]) return;
+  const double t = item_sum(part, np, b);
+  if (threadIdx.x != 0) return;
+  tr[b] = t;
+  if (t <= target2[b]) active[b] = 0;
+  else restart[b] = 1;  // the recurrence drifted: continue from the true residual
+}
+// rz_new = <R, Z>, zy = <Z, Y> from the two-dot partials; beta (0 after a
+// restart): standard rz_new / rz_old or flexible -alpha zy / rz_old
+__global__ __launch_bounds__(kThreads) void beta_kernel(const double* __restrict__ part_rz,
+                                                        const double* __restrict__ part_zy, int np,
+                                                        double* __restrict__ rz_new, double* __restrict__ zy,
+                                                        double* __restrict__ rz_old, const double* __restrict__ alpha,
+                                                        double* __restrict__ beta, int* __restrict__ restart,
+                                                        int flexible, const int* __restrict__ active) {
+  const int b = blockIdx.x;
+  if (!active[b]) return;
+  const double s1 = item_sum(part_rz, np, b);
+  const double s2 = item_sum(part_zy, np, b);
+  if (threadIdx.x != 0) return;
+  rz_new[b] = s1;
+  zy[b] = s2;
+  double bt = flexible ? (-alpha[b] * s2 / rz_old[b]) : (s1 / rz_old[b]);
+  if (restart[b]) {
+    bt = 0.0;
+    restart[b] = 0;
+  }
+  beta[b] = bt;
+  rz_old[b] = s1;
+}
 // R = Rhs - LU - alpha_b Y: the residual of U + alpha Q with Y = L(Q)
 __global__ __launch_bounds__(kThreads) void residual_step_kernel(const double* __restrict__ Rhs, const double* LU,
                                                                  const double* __restrict__ Y,
@@ -349,15 +407,6 @@ __global__ __launch_bounds__(kThreads) void residual_step_kernel(const double* _
   s = block_sum(s);
   if (threadIdx.x == 0 && partial) partial[(size_t)b * gridDim.x + blockIdx.x] = s;
 }
-__global__ void pcg_confirm_kernel(const double* __restrict__ tr, const double* __restrict__ target2,
-                                   int* __restrict__ active, int* __restrict__ claim, int* __restrict__ restart,
-                                   int batch) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= batch) return;
-  if (!claim[b]) return;
-  if (tr[b] <= target2[b]) active[b] = 0;
-  else restart[b] = 1;  // the recurrence drifted: continue from the true residual
-}
 
 // per-item result of a solve: iterations, status (MAXIT if the final true
 // residual misses the item's target), relative true residual
@@ -377,20 +426,6 @@ __global__ void pcg_final_kernel(const double* __restrict__ tr, const double* __
 }
 
 // beta of the next direction; zero (a fresh direction) for restarted items
-__global__ void beta_restart_kernel(const double* __restrict__ rz_new, double* __restrict__ rz_old,
-                                    const double* __restrict__ zy, const double* __restrict__ alpha,
-                                    double* __restrict__ beta, int* __restrict__ restart, int flexible, int batch,
-                                    const int* __restrict__ active) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= batch || !active[b]) return;
-  double bt = flexible ? (-alpha[b] * zy[b] / rz_old[b]) : (rz_new[b] / rz_old[b]);
-  if (restart[b]) {
-    bt = 0.0;
-    restart[b] = 0;
-  }
-  beta[b] = bt;
-  rz_old[b] = rz_new[b];
-}
 
 __global__ __launch_bounds__(kThreads) void copy_masked_kernel(const double* __restrict__ X, double* __restrict__ Y,
                                                                long long n, long long xs, long long ys,
@@ -576,18 +611,6 @@ int launch_pcg_init(const double* rhs2, const double* rr, double* target2, int* 
                      restart, status, iters, tol2, tau_stop, batch);
   CHECK_LAUNCH();
 }
-int launch_pcg_check(const double* qy, const double* rr, const double* target2, int* active, int* claim,
-                     int* status, int* iters, int* live, int batch, hipStream_t s) {
-  hipLaunchKernelGGL(pcg_check_kernel, dim3((batch + 63) / 64), dim3(64), 0, s, qy, rr, target2, active, claim,
-                     status, iters, live, batch);
-  CHECK_LAUNCH();
-}
-int launch_pcg_confirm(const double* tr, const double* target2, int* active, int* claim, int* restart, int batch,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(pcg_confirm_kernel, dim3((batch + 63) / 64), dim3(64), 0, s, tr, target2, active, claim,
-                     restart, batch);
-  CHECK_LAUNCH();
-}
 int launch_pcg_final(const double* tr, const double* rhs2, const double* target2, const int* status,
                      const int* iters, int* iters_out, int* status_out, double* relres_out, int batch,
                      hipStream_t s) {
@@ -595,10 +618,23 @@ int launch_pcg_final(const double* tr, const double* rhs2, const double* target2
                      iters_out, status_out, relres_out, batch);
   CHECK_LAUNCH();
 }
-int launch_beta_restart(const double* rz_new, double* rz_old, const double* zy, const double* alpha, double* beta,
-                        int* restart, int flexible, int batch, const int* active, hipStream_t s) {
-  hipLaunchKernelGGL(beta_restart_kernel, dim3((batch + 63) / 64), dim3(64), 0, s, rz_new, rz_old, zy, alpha, beta,
-                     restart, flexible, batch, active);
+int launch_check(const double* part, int np, double* rr, const double* qy, const double* target2, int* active,
+                 int* claim, int* status, int* iters, int* live, int batch, hipStream_t s) {
+  hipLaunchKernelGGL(check_kernel, dim3(batch), dim3(kThreads), 0, s, part, np, rr, qy, target2, active, claim,
+                     status, iters, live);
+  CHECK_LAUNCH();
+}
+int launch_confirm(const double* part, int np, double* tr, const double* target2, int* active, const int* claim,
+                   int* restart, int batch, hipStream_t s) {
+  hipLaunchKernelGGL(confirm_kernel, dim3(batch), dim3(kThreads), 0, s, part, np, tr, target2, active, claim,
+                     restart);
+  CHECK_LAUNCH();
+}
+int launch_beta(const double* part_rz, const double* part_zy, int np, double* rz_new, double* zy, double* rz_old,
+                const double* alpha, double* beta, int* restart, int flexible, const int* active, int batch,
+                hipStream_t s) {
+  hipLaunchKernelGGL(beta_kernel, dim3(batch), dim3(kThreads), 0, s, part_rz, part_zy, np, rz_new, zy, rz_old,
+                     alpha, beta, restart, flexible, active);
   CHECK_LAUNCH();
 }
 int launch_copy_masked(const double* X, double* Y, long long n, long long xs, long long ys, int batch,

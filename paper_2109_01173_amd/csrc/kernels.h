@@ -172,16 +172,21 @@ int launch_scale_items(double* x, const double* f, int batch, hipStream_t s);
 // device-side control of the PCG iteration (see k_vec.hip)
 int launch_pcg_init(const double* rhs2, const double* rr, double* target2, int* active, int* claim, int* restart,
                     int* status, int* iters, double tol2, int tau_stop, int batch, hipStream_t s);
-// live (may be null): set for items whose step alpha Q of this iteration is valid
-int launch_pcg_check(const double* qy, const double* rr, const double* target2, int* active, int* claim,
-                     int* status, int* iters, int* live, int batch, hipStream_t s);
-int launch_pcg_confirm(const double* tr, const double* target2, int* active, int* claim, int* restart, int batch,
-                       hipStream_t s);
+// One block per item; each first adds the item's np partial sums (fixed order).
+// check: rr = ||R||^2, breakdown / non-finite / claim; live (may be null) is set
+// for items whose step alpha Q of this iteration is valid
+int launch_check(const double* part, int np, double* rr, const double* qy, const double* target2, int* active,
+                 int* claim, int* status, int* iters, int* live, int batch, hipStream_t s);
+// confirm: tr = true residual^2 of claiming items; converged or restart
+int launch_confirm(const double* part, int np, double* tr, const double* target2, int* active, const int* claim,
+                   int* restart, int batch, hipStream_t s);
+// beta: rz_new = <R, Z>, zy = <Z, Y>; beta (0 after a restart); rz_old = rz_new
+int launch_beta(const double* part_rz, const double* part_zy, int np, double* rz_new, double* zy, double* rz_old,
+                const double* alpha, double* beta, int* restart, int flexible, const int* active, int batch,
+                hipStream_t s);
 int launch_pcg_final(const double* tr, const double* rhs2, const double* target2, const int* status,
                      const int* iters, int* iters_out, int* status_out, double* relres_out, int batch,
                      hipStream_t s);
-int launch_beta_restart(const double* rz_new, double* rz_old, const double* zy, const double* alpha, double* beta,
-                        int* restart, int flexible, int batch, const int* active, hipStream_t s);
 int launch_copy_masked(const double* X, double* Y, long long n, long long xs, long long ys, int batch,
                        const int* mask, hipStream_t s);
 // elementwise DIB kinetics: T_u = U + tau rho f(U, V), T_v = V + tau rho g(U, V)
