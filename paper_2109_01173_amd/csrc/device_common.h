@@ -56,4 +56,19 @@ __device__ __forceinline__ int xcd_tile(int id, int n) {
   return (x < r) ? x * (q + 1) + slot : r * (q + 1) + (x - r) * q + slot;
 }
 
+// Tile (row, column) of a tm x tn tile grid for dispatch id `id`.  Tile numbers
+// run down bands of G tile rows, column by column, and each XCD takes one
+// contiguous range of numbers (xcd_tile), so an XCD's share is a compact block
+// of about G rows: it reads fewer operand strips into its L2 than whole tile
+// rows would need.  Bijective for any tm, tn >= 1.
+__device__ __forceinline__ void grouped_tile(int id, int tm, int tn, int G, int* tr, int* tc) {
+  const int t = xcd_tile(id, tm * tn);
+  const int band = t / (G * tn);
+  const int first = band * G;
+  const int rows = min(G, tm - first);
+  const int w = t - band * G * tn;
+  *tr = first + w % rows;
+  *tc = w / rows;
+}
+
 }  // namespace mofem

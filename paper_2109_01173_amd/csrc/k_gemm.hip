@@ -29,11 +29,14 @@
 // Tiling: 256 threads = 4 waves, block tile 128 x 128, each wave 64 x 64
 // (4 x 4 MFMA tiles of 16 x 16), or 64 x 64 blocks of 32 x 32 wave tiles for
 // grids too small to fill the chip (picked per shape, see mofem_prec_tune);
-// k tiles of 16 (FP64), 32 (FP32), 64 (BF16).
-// Global -> register prefetch of the next k tile overlaps the MFMAs of the
-// current one; in the split products the three passes run one after the
-// other over all 16 accumulators, so back-to-back MFMAs are independent.
-// Block order is XCD-aware.
+// k tiles of 16 (FP64), 32 (FP32), 64 (BF16; 32 for the split products on
+// 128-row tiles).
+// The loads of the next k tile overlap the MFMAs of the current one (through
+// registers, or for the split products on 128-row tiles straight into a
+// second LDS stage); in the split products the three passes run one after
+// the other over all 16 accumulators, so back-to-back MFMAs are independent.
+// Block order is XCD-aware: each XCD takes a compact block of tiles, about
+// four (128 tiles) or eight (64 tiles) tile rows high, of one item.
 // Intermediates are padded to multiples of 128 in both dimensions and the
 // epilogue writes zeros into the padding, so consumers read whole tiles
 // without bounds checks.
@@ -62,10 +65,6 @@ __device__ __forceinline__ void split_bf16(float x, unsigned short* hi, unsigned
   *lo = bf16_bits(x - bf16_to_f(h));
 }
 
-__device__ __forceinline__ double eval_D(const GemmArgs& g, int row, int col, double s) {
-  double l = g.lam[row], m = g.mu[col];
-  return g.alpha + s * (g.beta_s * l + g.beta_t * m + g.delta * l * m);
-}
 
 // ------------------------------------------------------------------------------
 // FP64
@@ -81,8 +80,9 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmArgs g) {
   if (g.active && !g.active[b]) return;
   // tiles cover the padded extent, so every padded output entry is written
   const int tm = pad_up(g.M) / TB, tn = pad_up(g.N) / TB;
-  const int tile = xcd_tile(blockIdx.x, tm * tn);
-  const int m0 = (tile / tn) * TB, n0 = (tile % tn) * TB;
+  int tr, tc;
+  grouped_tile(blockIdx.x, tm, tn, TB == 128 ? 4 : 8, &tr, &tc);
+  const int m0 = tr * TB, n0 = tc * TB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
@@ -142,6 +142,17 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmArgs g) {
   const double s = g.item_scale ? g.item_scale[b] : 1.0;
   double* __restrict__ C = g.c64 + (size_t)b * g.c_stride;
   const int Mp = pad_up(g.M), Np = pad_up(g.N);
+  // eigenvalues of the lane's rows and columns, loaded together before the
+  // stores (indices clamped; padding entries are zeroed below)
+  double el[WT][4], em[WT];
+  if (g.divide) {
+#pragma unroll
+    for (int i = 0; i < WT; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) el[i][r] = g.lam[min(m0 + wm * (16 * WT) + i * 16 + 4 * r + (lane >> 4), g.M - 1)];
+#pragma unroll
+    for (int j = 0; j < WT; ++j) em[j] = g.mu[min(n0 + wn * (16 * WT) + j * 16 + (lane & 15), g.N - 1)];
+  }
 #pragma unroll
   for (int i = 0; i < WT; ++i)
 #pragma unroll
@@ -152,7 +163,10 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmArgs g) {
         const int col = n0 + wn * (16 * WT) + j * 16 + (lane & 15);
         const bool in = row < g.M && col < g.N;
         double v = acc[i][j][r] * g.out_scale;
-        if (g.divide && in) v /= eval_D(g, row, col, s);
+        if (g.divide) {
+          const double l = el[i][r], m = em[j];
+          v /= g.alpha + s * (g.beta_s * l + g.beta_t * m + g.delta * l * m);
+        }
         if (!in) v = 0.0;
         if (OMODE == O_PAD_T) C[(size_t)col * Mp + row] = v;
         else if (OMODE == O_PAD_N) C[(size_t)row * Np + col] = v;
@@ -175,8 +189,9 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g) {
   if (g.active && !g.active[b]) return;
   // tiles cover the padded extent, so every padded output entry is written
   const int tm = pad_up(g.M) / TB, tn = pad_up(g.N) / TB;
-  const int tile = xcd_tile(blockIdx.x, tm * tn);
-  const int m0 = (tile / tn) * TB, n0 = (tile % tn) * TB;
+  int tr, tc;
+  grouped_tile(blockIdx.x, tm, tn, TB == 128 ? 4 : 8, &tr, &tc);
+  const int m0 = tr * TB, n0 = tc * TB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
@@ -235,6 +250,24 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g) {
 
   // epilogue: acc[i][j][r] = C[row][col], row = 4*(lane/16) + r, col = lane%16
   const double s = g.item_scale ? g.item_scale[b] : 1.0;
+  // divisor D(row, col) = da(row) + db(row) mu(col), da = alpha + s beta_s lam,
+  // db = s (beta_t + delta lam), in FP32 like the accumulators; the lane's
+  // factors are loaded together before the stores (indices clamped; padding
+  // entries are zeroed below)
+  float da[WT][4], db[WT][4], dm[WT];
+  if (g.divide) {
+#pragma unroll
+    for (int i = 0; i < WT; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double l = g.lam[min(m0 + wm * (16 * WT) + i * 16 + 4 * (lane >> 4) + r, g.M - 1)];
+        da[i][r] = (float)(g.alpha + s * g.beta_s * l);
+        db[i][r] = (float)(s * (g.beta_t + g.delta * l));
+      }
+#pragma unroll
+    for (int j = 0; j < WT; ++j) dm[j] = (float)g.mu[min(n0 + wn * (16 * WT) + j * 16 + (lane & 15), g.N - 1)];
+  }
+  const float osc = (float)g.out_scale;
   const int Mp = pad_up(g.M), Np = pad_up(g.N);
   float* __restrict__ C32 = (float*)g.c_hi + (size_t)b * g.c_stride;
   double* __restrict__ C64 = g.c64 + (size_t)b * g.c_stride;
@@ -247,16 +280,16 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g) {
         const int row = m0 + wm * (16 * WT) + i * 16 + 4 * (lane >> 4) + r;
         const int col = n0 + wn * (16 * WT) + j * 16 + (lane & 15);
         const bool in = row < g.M && col < g.N;
-        double v = (double)acc[i][j][r] * g.out_scale;
-        if (g.divide && in) v /= eval_D(g, row, col, s);
-        if (!in) v = 0.0;
+        float v = acc[i][j][r] * osc;
+        if (g.divide) v *= __builtin_amdgcn_rcpf(fmaf(db[i][r], dm[j], da[i][r]));
+        if (!in) v = 0.f;
         if (OMODE == O_F64_RAW) {
-          if (in) C64[(size_t)row * g.N + col] = v;
+          if (in) C64[(size_t)row * g.N + col] = (double)v;
         } else if (OMODE == O_F32_RAW) {
-          if (in) C32[(size_t)row * g.N + col] = (float)v;
+          if (in) C32[(size_t)row * g.N + col] = v;
         } else {
           const size_t idx = (OMODE == O_PAD_T) ? (size_t)col * Mp + row : (size_t)row * Np + col;
-          C32[idx] = (float)v;
+          C32[idx] = v;
         }
       }
 }
@@ -270,19 +303,29 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g) {
 //       BF_X2B  B split, A exact in BF16       A_h B_l + A_h B_h
 enum { BF_HH = 0, BF_X3 = 1, BF_X2A = 2, BF_X2B = 3 };
 
-template <int MODE, int OMODE, int BK = 64, int MINW = 2, int WT = 4>
+__device__ __forceinline__ void lds_load16(const unsigned short* src, unsigned short* dst) {
+  __builtin_amdgcn_global_load_lds((const void*)src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+}
+
+// DMA = 0: each k tile is loaded into registers one tile ahead and stored
+// to LDS by the threads (k tile 64).  DMA = 1 (split products on 128-row
+// tiles, k tile 32): direct global -> LDS loads into two LDS stages and the
+// fragments of the next k tile read while the current one is multiplied
+// (measured about 2 % faster for the split products, slower for the plain one).
+template <int MODE, int OMODE, int BK = 64, int MINW = 2, int WT = 4, int DMA = 0>
 __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
   // block tile TB x TB: 4 waves in 2 x 2, each WT x WT MFMA tiles of 16 x 16
   constexpr int TB = 32 * WT;
   // operand rows of BK values, 16-byte chunks XOR-swizzled by row (see sw)
   constexpr int LDS_K = BK;
-  static_assert(BK == 64, "the swizzle assumes 8 chunks per row");
+  static_assert(BK == 64 || (BK == 32 && DMA), "k tile");
   constexpr bool ALO = (MODE == BF_X3 || MODE == BF_X2A);
   constexpr bool BLO = (MODE == BF_X3 || MODE == BF_X2B);
   // One LDS buffer: the operand tiles of the main loop, then (padded output)
   // the staging tile of the epilogue, so the output leaves in whole rows.
   constexpr int SLD = TB + 8;  // staging row length (16-byte aligned)
-  constexpr int MAIN = (2 + (ALO ? 1 : 0) + (BLO ? 1 : 0)) * TB * LDS_K;
+  constexpr int NOP = 2 + (ALO ? 1 : 0) + (BLO ? 1 : 0);
+  constexpr int MAIN = (DMA ? 2 : 1) * NOP * TB * LDS_K;
   constexpr bool RAW = (OMODE == O_F64_RAW || OMODE == O_F32_RAW);
   constexpr int STAGE = RAW ? 0 : TB * SLD;
   __shared__ __attribute__((aligned(16))) unsigned short lds[MAIN > STAGE ? MAIN : STAGE];
@@ -292,15 +335,18 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
   Row* Al = Bh + TB;                 // used when ALO
   Row* Bl = Al + (ALO ? TB : 0);     // used when BLO
   // element offset of the 16-byte chunk holding k (a multiple of 8) in row r:
-  // chunk index XOR (r / 2) % 8 spreads 16 consecutive rows over all banks
-  auto sw = [](int r, int k) { return (((k >> 3) ^ ((r >> 1) & 7)) << 3); };
+  // chunk index XOR (r / RP) % (BK / 8), RP rows per 256 bytes, spreads 16
+  // consecutive rows over all banks
+  constexpr int RP = 128 / BK;
+  auto sw = [](int r, int k) { return (((k >> 3) ^ ((r / RP) % (BK / 8))) << 3); };
 
   const int b = blockIdx.y;
   if (g.active && !g.active[b]) return;
   // tiles cover the padded extent, so every padded output entry is written
   const int tm = pad_up(g.M) / TB, tn = pad_up(g.N) / TB;
-  const int tile = xcd_tile(blockIdx.x, tm * tn);
-  const int m0 = (tile / tn) * TB, n0 = (tile % tn) * TB;
+  int tr, tc;
+  grouped_tile(blockIdx.x, tm, tn, TB == 128 ? 4 : 8, &tr, &tc);
+  const int m0 = tr * TB, n0 = tc * TB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
@@ -345,19 +391,8 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
     for (int j = 0; j < WT; ++j) acc[i][j] = (f4_t){0.f, 0.f, 0.f, 0.f};
 
   const int nk = (g.K + BK - 1) / BK;
-  load_tile(0);
-  for (int kt = 0; kt < nk; ++kt) {
-    __syncthreads();
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const int so = sw(vrow(v), vk(v));
-      *(us8_t*)&Ah[vrow(v)][so] = ah[v];
-      *(us8_t*)&Bh[vrow(v)][so] = bh[v];
-      if (ALO) *(us8_t*)&Al[vrow(v)][so] = al[v];
-      if (BLO) *(us8_t*)&Bl[vrow(v)][so] = bl[v];
-    }
-    __syncthreads();
-    if (kt + 1 < nk) load_tile((kt + 1) * BK);
+  // fragment reads and MFMAs of one k tile held in LDS
+  auto compute = [&](Row* Ah_, Row* Bh_, Row* Al_, Row* Bl_) {
 #pragma unroll
     for (int ks = 0; ks < BK / 32; ++ks) {
       bf8_t fa[WT], fb[WT], fal[WT], fbl[WT];
@@ -365,14 +400,14 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
 #pragma unroll
       for (int i = 0; i < WT; ++i) {
         const int r = wm * (16 * WT) + i * 16 + (lane & 15);
-        fa[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Ah[r][sw(r, kq)]);
-        if (ALO) fal[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Al[r][sw(r, kq)]);
+        fa[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Ah_[r][sw(r, kq)]);
+        if (ALO) fal[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Al_[r][sw(r, kq)]);
       }
 #pragma unroll
       for (int j = 0; j < WT; ++j) {
         const int r = wn * (16 * WT) + j * 16 + (lane & 15);
-        fb[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Bh[r][sw(r, kq)]);
-        if (BLO) fbl[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Bl[r][sw(r, kq)]);
+        fb[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Bh_[r][sw(r, kq)]);
+        if (BLO) fbl[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Bl_[r][sw(r, kq)]);
       }
       // products outermost: consecutive MFMAs write different accumulators;
       // the wave issuing its MFMA block runs at raised priority (the other
@@ -399,10 +434,147 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
       __builtin_amdgcn_s_setprio(0);
     }
+  };
+
+  if constexpr (DMA) {
+    // direct global -> LDS loads into two LDS stages, and the MFMA fragments
+    // of the next k tile read from LDS while the current one is multiplied:
+    // iteration kt waits for tile kt + 1, starts the loads of tile kt + 2
+    // into the stage tile kt occupied, reads tile kt + 1's fragments and runs
+    // the MFMAs of tile kt on fragments already in registers.
+    constexpr int TILE = TB * LDS_K;
+    constexpr int RPI = 64 / CPR;
+    constexpr int IPW = TB / RPI / 4;
+    constexpr int KS = BK / 32;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    const int irow = lane / CPR, islot = lane % CPR;
+    auto dma = [&](int k0, int stage) {
+      unsigned short* st = lds + stage * NOP * TILE;
+#pragma unroll
+      for (int j = 0; j < IPW; ++j) {
+        const int r0 = (wv * IPW + j) * RPI;
+        const int r = r0 + irow;
+        const int c = islot ^ ((r / RP) % CPR);
+        const size_t ao = (size_t)(m0 + r) * Kp + k0 + c * 8;
+        const size_t bo = (size_t)(n0 + r) * Kp + k0 + c * 8;
+        lds_load16(Ahg + ao, st + r0 * LDS_K);
+        lds_load16(Bhg + bo, st + TILE + r0 * LDS_K);
+        if (ALO) lds_load16(Alg + ao, st + 2 * TILE + r0 * LDS_K);
+        if (BLO) lds_load16(Blg + bo, st + (ALO ? 3 : 2) * TILE + r0 * LDS_K);
+      }
+    };
+    struct Frag {
+      bf8_t a[KS][WT], b[KS][WT], al[KS][WT], bl[KS][WT];
+    };
+    auto read = [&](Frag& f, int stage) {
+      Row* A_ = reinterpret_cast<Row*>(lds + stage * NOP * TILE);
+      Row* B_ = A_ + TB;
+      Row* Al_ = A_ + 2 * TB;
+      Row* Bl_ = A_ + (ALO ? 3 : 2) * TB;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int kq = ks * 32 + (lane >> 4) * 8;
+#pragma unroll
+        for (int i = 0; i < WT; ++i) {
+          const int r = wm * (16 * WT) + i * 16 + (lane & 15);
+          f.a[ks][i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&A_[r][sw(r, kq)]);
+          if (ALO) f.al[ks][i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Al_[r][sw(r, kq)]);
+        }
+#pragma unroll
+        for (int j = 0; j < WT; ++j) {
+          const int r = wn * (16 * WT) + j * 16 + (lane & 15);
+          f.b[ks][j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&B_[r][sw(r, kq)]);
+          if (BLO) f.bl[ks][j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Bl_[r][sw(r, kq)]);
+        }
+      }
+    };
+    auto mma = [&](const Frag& f) {
+      __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        if (ALO) {
+#pragma unroll
+          for (int i = 0; i < WT; ++i)
+#pragma unroll
+            for (int j = 0; j < WT; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.al[ks][i], f.b[ks][j], acc[i][j], 0, 0, 0);
+        }
+        if (BLO) {
+#pragma unroll
+          for (int i = 0; i < WT; ++i)
+#pragma unroll
+            for (int j = 0; j < WT; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.a[ks][i], f.bl[ks][j], acc[i][j], 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < WT; ++i)
+#pragma unroll
+          for (int j = 0; j < WT; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.a[ks][i], f.b[ks][j], acc[i][j], 0, 0, 0);
+      }
+      __builtin_amdgcn_s_setprio(0);
+    };
+    // one iteration: tile kt in cur (registers), tile kt + 1 in LDS stage
+    // (kt + 1) & 1 once its loads land.  The last iteration reads a stale
+    // stage into fragments never used, so that every iteration has the same
+    // wait structure (a conditional read makes the compiler wait for it
+    // before the MFMAs).  0x0070 = vmcnt(0) lgkmcnt(0), 0x0F70 = vmcnt(0).
+    auto step = [&](int kt, const Frag& cur, Frag& nxt) {
+      // this wave's loads of tile kt + 1 and its reads of tile kt are done
+      __builtin_amdgcn_s_waitcnt(0x0070);
+      __syncthreads();  // ... and every wave's
+      if (kt + 2 < nk) dma((kt + 2) * BK, kt & 1);
+      read(nxt, (kt + 1) & 1);
+      mma(cur);
+    };
+    Frag f0, f1;
+    dma(0, 0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+    if (nk > 1) dma(BK, 1);
+    read(f0, 0);
+    for (int kt = 0; kt < nk; kt += 2) {
+      step(kt, f0, f1);
+      if (kt + 1 < nk) step(kt + 1, f1, f0);
+    }
+  } else {
+    load_tile(0);
+    for (int kt = 0; kt < nk; ++kt) {
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int so = sw(vrow(v), vk(v));
+        *(us8_t*)&Ah[vrow(v)][so] = ah[v];
+        *(us8_t*)&Bh[vrow(v)][so] = bh[v];
+        if (ALO) *(us8_t*)&Al[vrow(v)][so] = al[v];
+        if (BLO) *(us8_t*)&Bl[vrow(v)][so] = bl[v];
+      }
+      __syncthreads();
+      if (kt + 1 < nk) load_tile((kt + 1) * BK);
+      compute(Ah, Bh, Al, Bl);
+    }
   }
 
   // epilogue: acc[i][j][r] = C[row][col], row = 4*(lane/16) + r, col = lane%16
   const double s = g.item_scale ? g.item_scale[b] : 1.0;
+  // divisor D(row, col) = da(row) + db(row) mu(col), da = alpha + s beta_s lam,
+  // db = s (beta_t + delta lam), in FP32 like the accumulators; the lane's
+  // factors are loaded together before the stores (indices clamped; padding
+  // entries are zeroed below)
+  float da[WT][4], db[WT][4], dm[WT];
+  if (g.divide) {
+#pragma unroll
+    for (int i = 0; i < WT; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double l = g.lam[min(m0 + wm * (16 * WT) + i * 16 + 4 * (lane >> 4) + r, g.M - 1)];
+        da[i][r] = (float)(g.alpha + s * g.beta_s * l);
+        db[i][r] = (float)(s * (g.beta_t + g.delta * l));
+      }
+#pragma unroll
+    for (int j = 0; j < WT; ++j) dm[j] = (float)g.mu[min(n0 + wn * (16 * WT) + j * 16 + (lane & 15), g.N - 1)];
+  }
+  const float osc = (float)g.out_scale;
   double* __restrict__ C64 = g.c64 + (size_t)b * g.c_stride;
   float* __restrict__ C32r = (float*)g.c_hi + (size_t)b * g.c_stride;  // O_F32_RAW
 #pragma unroll
@@ -414,15 +586,15 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
         const int row = m0 + wm * (16 * WT) + i * 16 + 4 * (lane >> 4) + r;
         const int col = n0 + wn * (16 * WT) + j * 16 + (lane & 15);
         const bool in = row < g.M && col < g.N;
-        double v = (double)acc[i][j][r] * g.out_scale;
-        if (g.divide && in) v /= eval_D(g, row, col, s);
-        if (!in) v = 0.0;
+        float v = acc[i][j][r] * osc;
+        if (g.divide) v *= __builtin_amdgcn_rcpf(fmaf(db[i][r], dm[j], da[i][r]));
+        if (!in) v = 0.f;
         if (OMODE == O_F64_RAW) {
-          if (in) C64[(size_t)row * g.N + col] = v;
+          if (in) C64[(size_t)row * g.N + col] = (double)v;
         } else if (OMODE == O_F32_RAW) {
-          if (in) C32r[(size_t)row * g.N + col] = (float)v;
+          if (in) C32r[(size_t)row * g.N + col] = v;
         } else {
-          acc[i][j][r] = (float)v;  // the FP32 value to split
+          acc[i][j][r] = v;  // the FP32 value to split
         }
       }
   if constexpr (!RAW) {
@@ -484,13 +656,14 @@ static void launch_mode(const GemmArgs& g, int prec, int batch, hipStream_t s) {
   } else if (prec == GEMM_F32)
     hipLaunchKernelGGL((gemm_f32_kernel<OMODE, WT>), grid, dim3(256), 0, s, g);
   else if (prec == GEMM_BF16X3)
-    hipLaunchKernelGGL((gemm_bf16_kernel<BF_X3, OMODE, 64, 2, WT>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_bf16_kernel<BF_X3, OMODE, WT == 4 ? 32 : 64, 2, WT, WT == 4>), grid, dim3(256), 0, s, g);
   else if (prec == GEMM_BF16X2 && g.data_is_a)
-    hipLaunchKernelGGL((gemm_bf16_kernel<BF_X2A, OMODE, 64, 2, WT>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_bf16_kernel<BF_X2A, OMODE, WT == 4 ? 32 : 64, 2, WT, WT == 4>), grid, dim3(256), 0, s, g);
   else if (prec == GEMM_BF16X2)
-    hipLaunchKernelGGL((gemm_bf16_kernel<BF_X2B, OMODE, 64, 2, WT>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_bf16_kernel<BF_X2B, OMODE, WT == 4 ? 32 : 64, 2, WT, WT == 4>), grid, dim3(256), 0, s, g);
   else
-    hipLaunchKernelGGL((gemm_bf16_kernel<BF_HH, OMODE, 64, 2, WT>), grid, dim3(256), 0, s, g);
+    // three waves per SIMD (at most 168 VGPRs): measured 15-20 % faster than two
+    hipLaunchKernelGGL((gemm_bf16_kernel<BF_HH, OMODE, 64, 3, WT, 0>), grid, dim3(256), 0, s, g);
 }
 
 int launch_gemm(const GemmArgs& g, int prec, int omode, int batch, int tile, hipStream_t s) {
