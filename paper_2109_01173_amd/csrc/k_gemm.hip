@@ -335,10 +335,10 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
   Row* Al = Bh + TB;                 // used when ALO
   Row* Bl = Al + (ALO ? TB : 0);     // used when BLO
   // element offset of the 16-byte chunk holding k (a multiple of 8) in row r:
-  // chunk index XOR (r / RP) % (BK / 8), RP rows per 256 bytes, spreads 16
-  // consecutive rows over all banks
-  constexpr int RP = 128 / BK;
-  auto sw = [](int r, int k) { return (((k >> 3) ^ ((r / RP) % (BK / 8))) << 3); };
+  // chunk index XOR (r / 2) % (BK / 8) (rocprofv3 SQ_LDS_BANK_CONFLICT: none
+  // for rows of 64 and of 32 values; XOR (r / 4) % 4 for rows of 32 values
+  // conflicts as much as no swizzle)
+  auto sw = [](int r, int k) { return (((k >> 3) ^ ((r >> 1) % (BK / 8))) << 3); };
 
   const int b = blockIdx.y;
   if (g.active && !g.active[b]) return;
@@ -356,21 +356,18 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
   const unsigned short* __restrict__ Bhg = (const unsigned short*)g.b_hi + (size_t)b * g.b_stride;
   const unsigned short* __restrict__ Blg = (const unsigned short*)g.b_lo + (size_t)b * g.b_stride;
 
-  // staging of a k tile (BK values = CPR 16-byte chunks per row).  128-row
-  // tiles: consecutive threads take consecutive chunks of a row, so one load
+  // register staging of a k tile (BK values = CPR 16-byte chunks per row):
+  // consecutive threads take consecutive chunks of a row, so one load
   // instruction of a wave covers whole 128-byte row pieces (RPP rows per pass,
-  // NV passes).  64-row tiles: each thread takes NV consecutive chunks of one
-  // row (measured faster at that size).
+  // NV passes); with the swizzle the LDS stores are free of bank conflicts
   constexpr int CPR = BK / 8;
-  constexpr bool ROWWISE = (TB == 128);
-  constexpr int RPP = 256 / CPR;    // (row-wise staging)
-  constexpr int TPR = 256 / TB;     // threads per row (per-thread staging)
-  constexpr int NV = ROWWISE ? TB / RPP : CPR / TPR;  // 16-byte vectors per thread and operand
-  const int lrow = ROWWISE ? tid / CPR : tid / TPR;
-  const int lk = ROWWISE ? (tid % CPR) * 8 : (tid % TPR) * (BK / TPR);
+  constexpr int RPP = 256 / CPR;
+  constexpr int NV = TB / RPP;       // 16-byte vectors per thread and operand
+  const int lrow = tid / CPR;
+  const int lk = (tid % CPR) * 8;
   // row and k offset of vector v of this thread inside the tile
-  auto vrow = [&](int v) { return ROWWISE ? lrow + RPP * v : lrow; };
-  auto vk = [&](int v) { return ROWWISE ? lk : lk + 8 * v; };
+  auto vrow = [&](int v) { return lrow + RPP * v; };
+  auto vk = [&](int v) { (void)v; return lk; };
   us8_t ah[NV], al[NV], bh[NV], bl[NV];
   auto load_tile = [&](int k0) {
 #pragma unroll
@@ -454,7 +451,7 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
       for (int j = 0; j < IPW; ++j) {
         const int r0 = (wv * IPW + j) * RPI;
         const int r = r0 + irow;
-        const int c = islot ^ ((r / RP) % CPR);
+        const int c = islot ^ ((r >> 1) % CPR);
         const size_t ao = (size_t)(m0 + r) * Kp + k0 + c * 8;
         const size_t bo = (size_t)(n0 + r) * Kp + k0 + c * 8;
         lds_load16(Ahg + ao, st + r0 * LDS_K);
