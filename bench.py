@@ -103,35 +103,57 @@ def copy_calibration(torch):
     print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "launches": 5}), flush=True)
 
 
-def uneven_leg(mf, torch, np, n_inst, prec, prec_name):
-    """Uneven batch: n_inst elliptic instances with n drawn from {257, 513,
-    1025, 2049} and k from 1..4 (seed 5; k = 3 uses m = round((n-1)/3)),
-    gamma = 1, manufactured f + 1e-3 noise, rel 1e-8, split-BF16 transforms.
-    Same-shape instances form one batched group; the groups are solved
-    one after another (pcg_solve) and together on four streams
-    (pcg_solve_many)."""
-    from paper_2109_01173_amd.problems import XNormal
-    from workloads import elliptic_batch
+def uneven_leg(mf, torch, np, n_inst, prec, prec_name, rds_steps=100):
+    """Uneven mixed batch: n_inst instances; seed 5 draws n from {257, 513,
+    1025, 2049}, then k from 1..4, then the type: elliptic (P_k x-normal,
+    Dirichlet, gamma = 1, manufactured f + 1e-3 noise, rel 1e-8, the mixed
+    path's transforms) or reaction-diffusion (DIB on the rectangle [0,20]^2,
+    Neumann, lumped P1 for k = 1 and P_k otherwise, tau = 1e-2, rds_steps IMEX
+    steps of both species at rel 1e-10, FP64 transforms).  Same-shape
+    instances of one type form one batched group.  The elliptic groups are
+    solved one after another (pcg_solve) and together on four streams
+    (pcg_solve_many); the reaction-diffusion groups step one after another."""
+    from paper_2109_01173_amd.problems import Rect, XNormal
+    from workloads import dib_initial, dib_params, elliptic_batch
     rng = np.random.default_rng(5)
     ns = rng.choice([257, 513, 1025, 2049], size=n_inst)
     ks = rng.integers(1, 5, size=n_inst)
+    types = rng.integers(0, 2, size=n_inst)  # 0 elliptic, 1 reaction-diffusion
     shapes = {}
-    for n, k in zip(ns.tolist(), ks.tolist()):
-        shapes[(n, k)] = shapes.get((n, k), 0) + 1
+    for n, k, ty in zip(ns.tolist(), ks.tolist(), types.tolist()):
+        shapes[(ty, n, k)] = shapes.get((ty, n, k), 0) + 1
     t0 = time.perf_counter()
-    groups = []
-    for gi, ((n, k), cnt) in enumerate(sorted(shapes.items())):
+    groups, rds = [], []
+    p = dib_params()
+    kin = [p["rho"], p["A1"], p["A2"], p["B"], p["C"], p["D"], p["alpha"], p["gamma"], p["k2"], p["k3"]]
+    for gi, ((ty, n, k), cnt) in enumerate(sorted(shapes.items())):
         m = int(round((n - 1) / k))
-        G = XNormal(k, m, "dirichlet", gamma=1.0, precision=prec)
-        F = torch.from_numpy(elliptic_batch(G.n, 1.0, cnt, sigma=1e-3, seed0=5000 + 100 * gi)).cuda()
-        rhs = G.rhs_op.apply(F)
-        groups.append(dict(op=G.op, prec=G.prec, rhs=rhs, U=torch.empty_like(rhs), tol=1e-8, maxit=300,
-                           flags=mf.PCG_FLEXIBLE | mf.PCG_ZERO_GUESS, _keep=G))
-        groups[-1]["workspace"] = mf.pcg_workspace(G.op, G.prec, cnt)
+        if ty == 0:
+            G = XNormal(k, m, "dirichlet", gamma=1.0, precision=prec)
+            F = torch.from_numpy(elliptic_batch(G.n, 1.0, cnt, sigma=1e-3, seed0=5000 + 100 * gi)).cuda()
+            rhs = G.rhs_op.apply(F)
+            groups.append(dict(op=G.op, prec=G.prec, rhs=rhs, U=torch.empty_like(rhs), tol=1e-8, maxit=300,
+                               flags=mf.PCG_FLEXIBLE | mf.PCG_ZERO_GUESS, _keep=G))
+            groups[-1]["workspace"] = mf.pcg_workspace(G.op, G.prec, cnt)
+        else:
+            lumped = k == 1
+            G = Rect(k, m, "neumann", length=20.0, lumped=lumped, imex=True, closed_form=lumped)
+            init = [dib_initial(G.q, seed=7000 + 100 * gi + j) for j in range(cnt)]
+            # species-major state: eta of every item, then theta of every item
+            st0 = torch.from_numpy(np.stack([e for e, _ in init] + [t for _, t in init])).cuda()
+            stepper = mf.Imex(G.op, G.prec, G.mass, 1e-2, [1.0, p["d_theta"]], kinetics=mf.KIN_DIB, kin=kin,
+                              tol=1e-10, maxit=50)
+            rds.append(dict(G=G, st0=st0, st=st0.clone(), stepper=stepper, batch=cnt,
+                            ws=stepper.workspace(cnt)))
     setup = time.perf_counter() - t0
+    n_ell = sum(int(g["rhs"].shape[0]) for g in groups)
+    n_rds = sum(r["batch"] for r in rds)
     for g in groups:  # warm-up (also the kernels' first use)
         mf.pcg_solve(g["op"], g["prec"], g["rhs"], g["U"], tol=1e-8, maxit=300, flags=g["flags"],
                      workspace=g["workspace"])
+    for r in rds:
+        r["stepper"].step(r["st"], r["batch"], workspace=r["ws"])
+        r["st"].copy_(r["st0"])
     torch.cuda.synchronize()
     t = time.perf_counter()
     for g in groups:
@@ -144,14 +166,34 @@ def uneven_leg(mf, torch, np, n_inst, prec, prec_name):
     outs, status = mf.pcg_solve_many(groups, [streams[i % 4] for i in range(len(groups))])
     torch.cuda.synchronize()
     dt_many = time.perf_counter() - t
-    its = np.concatenate([o[0] for o in outs])
-    log("uneven batch: %d instances in %d shape groups: %.1f solves/s one group at a time, %.1f together"
-        % (n_inst, len(groups), n_inst / dt_seq, n_inst / dt_many))
-    return {"uneven_batch": {"workload": "%d elliptic instances, n in {257,513,1025,2049}, k in 1..4 (seed 5), "
-                                         "Dirichlet, gamma=1, rel 1e-8, %s transforms" % (n_inst, prec_name),
-                             "groups": len(groups), "solves_per_s_sequential": round(n_inst / dt_seq, 2),
-                             "solves_per_s_streams": round(n_inst / dt_many, 2), "streams": 4,
+    its = np.concatenate([o[0] for o in outs]) if outs else np.zeros(1)
+    rds_its = []
+    t = time.perf_counter()
+    for r in rds:
+        for _ in range(rds_steps):
+            rds_its.append(int(r["stepper"].step(r["st"], r["batch"], workspace=r["ws"]).max()))
+    torch.cuda.synchronize()
+    dt_rds = time.perf_counter() - t
+    finite = all(bool(torch.isfinite(r["st"]).all()) for r in rds)
+    job = dt_many + dt_rds
+    log("uneven batch: %d instances (%d elliptic in %d groups, %d reaction-diffusion in %d groups): elliptic "
+        "%.1f solves/s one group at a time, %.1f together; reaction-diffusion %.1f instance-steps/s "
+        "(%d steps each); whole job %.2f s = %.1f instances/s"
+        % (n_inst, n_ell, len(groups), n_rds, len(rds), n_ell / dt_seq, n_ell / dt_many,
+           n_rds * rds_steps / dt_rds if dt_rds > 0 else 0.0, rds_steps, job, n_inst / job))
+    return {"uneven_batch": {"workload": "%d instances, n in {257,513,1025,2049}, k in 1..4, type in {elliptic, "
+                                         "reaction-diffusion} (seed 5); elliptic: P_k x-normal, Dirichlet, gamma=1, "
+                                         "rel 1e-8, %s transforms; reaction-diffusion: DIB rectangle [0,20]^2, "
+                                         "Neumann, tau=1e-2, %d steps, rel 1e-10, f64 transforms"
+                                         % (n_inst, prec_name, rds_steps),
+                             "elliptic_instances": n_ell, "elliptic_groups": len(groups),
+                             "solves_per_s_sequential": round(n_ell / dt_seq, 2),
+                             "solves_per_s_streams": round(n_ell / dt_many, 2), "streams": 4,
                              "iterations_max": int(its.max()), "status_ok": all(st == 0 for st in status),
+                             "rds_instances": n_rds, "rds_groups": len(rds),
+                             "rds_instance_steps_per_s": round(n_rds * rds_steps / dt_rds, 2) if dt_rds > 0 else None,
+                             "rds_iterations_max": max(rds_its) if rds_its else 0, "rds_finite": finite,
+                             "job_s": round(job, 3), "instances_per_s": round(n_inst / job, 2),
                              "setup_s": round(setup, 2)}}
 
 

@@ -85,3 +85,58 @@ def test_dib_equilibrium_is_fixed():
     stepper.step(st, 1)
     out = to_host(st)
     assert np.abs(out[0]).max() < 1e-13 and np.abs(out[1] - 0.5).max() < 1e-13
+
+
+def test_dib_batched_steps():
+    """Three DIB instances (species-major state, batch 3) stepped together:
+    each item equals its own batch-1 run (the items share bands and
+    eigenbases but nothing else), and item 1 equals the oracle's steps."""
+    from paper_2109_01173_amd import mofem as mf
+    from paper_2109_01173_amd.problems import Rect
+    p = dib_params()
+    tau, B = 1e-2, 3
+    G = Rect(2, 24, "neumann", length=20.0, lumped=False, imex=True)
+    P = RectProblem(2, 24, "neumann", lx=20.0, ly=20.0, lumped=False)
+    inits = [dib_initial(P.q, seed=70 + b) for b in range(B)]
+    kin = [p["rho"], p["A1"], p["A2"], p["B"], p["C"], p["D"], p["alpha"], p["gamma"], p["k2"], p["k3"]]
+    mk = lambda: mf.Imex(G.op, G.prec, G.mass, tau, [1.0, p["d_theta"]], kinetics=mf.KIN_DIB, kin=kin,
+                         tol=1e-12, maxit=50)
+    # species-major: eta of items 0..B-1, then theta of items 0..B-1
+    st = to_dev(np.stack([e for e, _ in inits] + [t for _, t in inits]))
+    batched = mk()
+    singles = [to_dev(np.stack(inits[b])) for b in range(B)]
+    single = mk()
+    solve = oracle_solver(P, "rect")
+    eta, theta = inits[1]
+    for _ in range(3):
+        iters = batched.step(st, B)
+        assert iters.shape == (2 * B,) and np.all(iters <= 2)
+        for b in range(B):
+            single.step(singles[b], 1)
+        eta, theta = imex.rds_step(P, eta, theta, tau, p, solve)
+    out = to_host(st)
+    for b in range(B):
+        one = to_host(singles[b])
+        assert rel(out[b], one[0]) < 1e-13, b
+        assert rel(out[B + b], one[1]) < 1e-13, b
+    assert rel(out[1], eta) < 1e-10
+    assert rel(out[B + 1], theta) < 1e-12
+
+
+def test_heat_batched_steps():
+    """Two heat instances stepped as a batch equal their batch-1 runs."""
+    from paper_2109_01173_amd import mofem as mf
+    G = gpu_xnormal(2, 30, "neumann", 0.0, imex=True)
+    U0 = [heat_initial(G.q, seed=s) for s in (42, 43)]
+    st = to_dev(np.stack(U0))
+    mk = lambda: mf.Imex(G.op, G.prec, G.mass, 1e-3, [0.1], tol=1e-12, maxit=100)
+    batched, single = mk(), mk()
+    singles = [to_dev(u[None]) for u in U0]
+    for _ in range(3):
+        iters = batched.step(st, 2)
+        assert iters.shape == (2,)
+        for b in range(2):
+            single.step(singles[b], 1)
+    out = to_host(st)
+    for b in range(2):
+        assert rel(out[b], to_host(singles[b])[0]) < 1e-13, b
