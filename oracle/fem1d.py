@@ -14,7 +14,7 @@ What the paper fixes (Sec. 2.1, Sec. 3):
 * lumped P1 (Sec. 3.3): every integrand is replaced by its element-wise
   P1 interpolant I_h before integrating, eqs. (36)-(39), (42)-(44).
 
-Readings where the paper is silent (listed in the design doc):
+Readings where the paper is silent:
 * P_k nodes are equispaced inside each element ("Lagrangian P_k");
 * element integrals use 12-point Gauss-Legendre quadrature;
 * lumping = integrating the I_h interpolant exactly, which on each element

@@ -14,7 +14,7 @@ Sources in the paper:
   (Sec. 3.3) and the dimension q of eq. (48);
 * the vec identity of Sec. 1 (eq. (8)) for the Kronecker form.
 
-Readings (the design doc lists them all):
+Readings where the paper is silent or ambiguous:
 * Dirichlet right-hand side keeps the full-node interpolant of f: the load
   is M3[I,:] F M[:,I] with F sampled at all n x n nodes;
 * the lumped IMEX operator eq. (92) is left-multiplied by D1; the oracle
