@@ -29,12 +29,12 @@
 // Tiling: 256 threads = 4 waves, block tile 128 x 128, each wave 64 x 64
 // (4 x 4 MFMA tiles of 16 x 16), or 64 x 64 blocks of 32 x 32 wave tiles for
 // grids too small to fill the chip (picked per shape, see mofem_prec_tune);
-// k tiles of 16 (FP64), 32 (FP32), 64 (BF16; 32 for the split products on
-// 128-row tiles).
-// The loads of the next k tile overlap the MFMAs of the current one (through
-// registers, or for the split products on 128-row tiles straight into a
-// second LDS stage); in the split products the three passes run one after
-// the other over all 16 accumulators, so back-to-back MFMAs are independent.
+// k tiles of 16 (FP64), 32 (FP32), 64 (BF16).
+// The loads of the next k tile overlap the MFMAs of the current one (BF16 on
+// 128-row tiles: direct global -> LDS loads issued once the current tile's
+// fragments are in registers; otherwise through registers); in the split
+// products the three passes run one after the other over all 16
+// accumulators, so back-to-back MFMAs are independent.
 // Block order is XCD-aware: each XCD takes a compact block of tiles, about
 // four (128 tiles) or eight (64 tiles) tile rows high, of one item.
 // Intermediates are padded to multiples of 128 in both dimensions and the
@@ -307,25 +307,27 @@ __device__ __forceinline__ void lds_load16(const unsigned short* src, unsigned s
   __builtin_amdgcn_global_load_lds((const void*)src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
 }
 
-// DMA = 0: each k tile is loaded into registers one tile ahead and stored
-// to LDS by the threads (k tile 64).  DMA = 1 (split products on 128-row
-// tiles, k tile 32): direct global -> LDS loads into two LDS stages and the
-// fragments of the next k tile read while the current one is multiplied
-// (measured about 2 % faster for the split products, slower for the plain one).
+// DMA = 0 (64-row tiles): each k tile is loaded into registers one tile
+// ahead and stored to LDS by the threads.  DMA = 1 (128-row tiles): direct
+// global -> LDS loads (global_load_lds_dwordx4) into one LDS stage; the loads
+// of tile kt + 1 start as soon as every wave holds tile kt's fragments in
+// registers and run under its MFMAs.  Whole 128-byte row pieces per load (k
+// tile 64) halve the L2 requests of a k tile of 32 with two stages, which
+// kept the texture addresser 72 % busy and was 12 % slower.
 template <int MODE, int OMODE, int BK = 64, int MINW = 2, int WT = 4, int DMA = 0>
 __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
   // block tile TB x TB: 4 waves in 2 x 2, each WT x WT MFMA tiles of 16 x 16
   constexpr int TB = 32 * WT;
   // operand rows of BK values, 16-byte chunks XOR-swizzled by row (see sw)
   constexpr int LDS_K = BK;
-  static_assert(BK == 64 || (BK == 32 && DMA), "k tile");
+  static_assert(BK == 64, "the swizzle and the staging assume rows of 64 values");
   constexpr bool ALO = (MODE == BF_X3 || MODE == BF_X2A);
   constexpr bool BLO = (MODE == BF_X3 || MODE == BF_X2B);
   // One LDS buffer: the operand tiles of the main loop, then (padded output)
   // the staging tile of the epilogue, so the output leaves in whole rows.
   constexpr int SLD = TB + 8;  // staging row length (16-byte aligned)
   constexpr int NOP = 2 + (ALO ? 1 : 0) + (BLO ? 1 : 0);
-  constexpr int MAIN = (DMA ? 2 : 1) * NOP * TB * LDS_K;
+  constexpr int MAIN = NOP * TB * LDS_K;
   constexpr bool RAW = (OMODE == O_F64_RAW || OMODE == O_F32_RAW);
   constexpr int STAGE = RAW ? 0 : TB * SLD;
   __shared__ __attribute__((aligned(16))) unsigned short lds[MAIN > STAGE ? MAIN : STAGE];
@@ -434,19 +436,16 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
   };
 
   if constexpr (DMA) {
-    // direct global -> LDS loads into two LDS stages, and the MFMA fragments
-    // of the next k tile read from LDS while the current one is multiplied:
-    // iteration kt waits for tile kt + 1, starts the loads of tile kt + 2
-    // into the stage tile kt occupied, reads tile kt + 1's fragments and runs
-    // the MFMAs of tile kt on fragments already in registers.
+    // One wave instruction moves 64 x 16 bytes into RPI consecutive LDS rows;
+    // lane (row, slot) fetches the global chunk that the swizzle places in
+    // that slot.
     constexpr int TILE = TB * LDS_K;
     constexpr int RPI = 64 / CPR;
     constexpr int IPW = TB / RPI / 4;
     constexpr int KS = BK / 32;
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     const int irow = lane / CPR, islot = lane % CPR;
-    auto dma = [&](int k0, int stage) {
-      unsigned short* st = lds + stage * NOP * TILE;
+    auto dma = [&](int k0) {
 #pragma unroll
       for (int j = 0; j < IPW; ++j) {
         const int r0 = (wv * IPW + j) * RPI;
@@ -454,38 +453,32 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
         const int c = islot ^ ((r >> 1) % CPR);
         const size_t ao = (size_t)(m0 + r) * Kp + k0 + c * 8;
         const size_t bo = (size_t)(n0 + r) * Kp + k0 + c * 8;
-        lds_load16(Ahg + ao, st + r0 * LDS_K);
-        lds_load16(Bhg + bo, st + TILE + r0 * LDS_K);
-        if (ALO) lds_load16(Alg + ao, st + 2 * TILE + r0 * LDS_K);
-        if (BLO) lds_load16(Blg + bo, st + (ALO ? 3 : 2) * TILE + r0 * LDS_K);
+        lds_load16(Ahg + ao, lds + r0 * LDS_K);
+        lds_load16(Bhg + bo, lds + TILE + r0 * LDS_K);
+        if (ALO) lds_load16(Alg + ao, lds + 2 * TILE + r0 * LDS_K);
+        if (BLO) lds_load16(Blg + bo, lds + (ALO ? 3 : 2) * TILE + r0 * LDS_K);
       }
     };
-    struct Frag {
-      bf8_t a[KS][WT], b[KS][WT], al[KS][WT], bl[KS][WT];
-    };
-    auto read = [&](Frag& f, int stage) {
-      Row* A_ = reinterpret_cast<Row*>(lds + stage * NOP * TILE);
-      Row* B_ = A_ + TB;
-      Row* Al_ = A_ + 2 * TB;
-      Row* Bl_ = A_ + (ALO ? 3 : 2) * TB;
+    bf8_t fa[KS][WT], fb[KS][WT], fal[KS][WT], fbl[KS][WT];
+    auto read = [&]() {
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
         const int kq = ks * 32 + (lane >> 4) * 8;
 #pragma unroll
         for (int i = 0; i < WT; ++i) {
           const int r = wm * (16 * WT) + i * 16 + (lane & 15);
-          f.a[ks][i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&A_[r][sw(r, kq)]);
-          if (ALO) f.al[ks][i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Al_[r][sw(r, kq)]);
+          fa[ks][i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Ah[r][sw(r, kq)]);
+          if (ALO) fal[ks][i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Al[r][sw(r, kq)]);
         }
 #pragma unroll
         for (int j = 0; j < WT; ++j) {
           const int r = wn * (16 * WT) + j * 16 + (lane & 15);
-          f.b[ks][j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&B_[r][sw(r, kq)]);
-          if (BLO) f.bl[ks][j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Bl_[r][sw(r, kq)]);
+          fb[ks][j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Bh[r][sw(r, kq)]);
+          if (BLO) fbl[ks][j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Bl[r][sw(r, kq)]);
         }
       }
     };
-    auto mma = [&](const Frag& f) {
+    auto mma = [&]() {
       __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
@@ -494,45 +487,31 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
           for (int i = 0; i < WT; ++i)
 #pragma unroll
             for (int j = 0; j < WT; ++j)
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.al[ks][i], f.b[ks][j], acc[i][j], 0, 0, 0);
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fal[ks][i], fb[ks][j], acc[i][j], 0, 0, 0);
         }
         if (BLO) {
 #pragma unroll
           for (int i = 0; i < WT; ++i)
 #pragma unroll
             for (int j = 0; j < WT; ++j)
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.a[ks][i], f.bl[ks][j], acc[i][j], 0, 0, 0);
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[ks][i], fbl[ks][j], acc[i][j], 0, 0, 0);
         }
 #pragma unroll
         for (int i = 0; i < WT; ++i)
 #pragma unroll
           for (int j = 0; j < WT; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.a[ks][i], f.b[ks][j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[ks][i], fb[ks][j], acc[i][j], 0, 0, 0);
       }
       __builtin_amdgcn_s_setprio(0);
     };
-    // one iteration: tile kt in cur (registers), tile kt + 1 in LDS stage
-    // (kt + 1) & 1 once its loads land.  The last iteration reads a stale
-    // stage into fragments never used, so that every iteration has the same
-    // wait structure (a conditional read makes the compiler wait for it
-    // before the MFMAs).  0x0070 = vmcnt(0) lgkmcnt(0), 0x0F70 = vmcnt(0).
-    auto step = [&](int kt, const Frag& cur, Frag& nxt) {
-      // this wave's loads of tile kt + 1 and its reads of tile kt are done
-      __builtin_amdgcn_s_waitcnt(0x0070);
-      __syncthreads();  // ... and every wave's
-      if (kt + 2 < nk) dma((kt + 2) * BK, kt & 1);
-      read(nxt, (kt + 1) & 1);
-      mma(cur);
-    };
-    Frag f0, f1;
-    dma(0, 0);
-    __builtin_amdgcn_s_waitcnt(0x0F70);
-    __syncthreads();
-    if (nk > 1) dma(BK, 1);
-    read(f0, 0);
-    for (int kt = 0; kt < nk; kt += 2) {
-      step(kt, f0, f1);
-      if (kt + 1 < nk) step(kt + 1, f1, f0);
+    dma(0);
+    for (int kt = 0; kt < nk; ++kt) {
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's loads of tile kt landed
+      __syncthreads();                     // and every wave's
+      read();
+      __syncthreads();                     // every wave holds its fragments: the stage is free
+      if (kt + 1 < nk) dma((kt + 1) * BK);
+      mma();
     }
   } else {
     load_tile(0);
@@ -653,14 +632,14 @@ static void launch_mode(const GemmArgs& g, int prec, int batch, hipStream_t s) {
   } else if (prec == GEMM_F32)
     hipLaunchKernelGGL((gemm_f32_kernel<OMODE, WT>), grid, dim3(256), 0, s, g);
   else if (prec == GEMM_BF16X3)
-    hipLaunchKernelGGL((gemm_bf16_kernel<BF_X3, OMODE, WT == 4 ? 32 : 64, 2, WT, WT == 4>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_bf16_kernel<BF_X3, OMODE, 64, 2, WT, WT == 4>), grid, dim3(256), 0, s, g);
   else if (prec == GEMM_BF16X2 && g.data_is_a)
-    hipLaunchKernelGGL((gemm_bf16_kernel<BF_X2A, OMODE, WT == 4 ? 32 : 64, 2, WT, WT == 4>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_bf16_kernel<BF_X2A, OMODE, 64, 2, WT, WT == 4>), grid, dim3(256), 0, s, g);
   else if (prec == GEMM_BF16X2)
-    hipLaunchKernelGGL((gemm_bf16_kernel<BF_X2B, OMODE, WT == 4 ? 32 : 64, 2, WT, WT == 4>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_bf16_kernel<BF_X2B, OMODE, 64, 2, WT, WT == 4>), grid, dim3(256), 0, s, g);
   else
     // three waves per SIMD (at most 168 VGPRs): measured 15-20 % faster than two
-    hipLaunchKernelGGL((gemm_bf16_kernel<BF_HH, OMODE, 64, 3, WT, 0>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_bf16_kernel<BF_HH, OMODE, 64, 3, WT, WT == 4>), grid, dim3(256), 0, s, g);
 }
 
 int launch_gemm(const GemmArgs& g, int prec, int omode, int batch, int tile, hipStream_t s) {
