@@ -86,9 +86,9 @@ def test_prec_tiny_and_errors():
 @pytest.mark.parametrize("precision", ["F64", "F32", "BF16X3", "BF16X2", "BF16", "BF16_FWD"])
 def test_block_tiles_agree_and_tuner(precision):
     """Both block tiles of the transforms compute the same products in the same
-    k order (the split products on 128-row tiles load through LDS directly, k
-    tile 32; on 64-row tiles through registers, k tile 64): the results agree
-    to the last bits; the tuner picks one of them."""
+    k order (BF16 on 128-row tiles loads through LDS directly, on 64-row tiles
+    through registers): the results agree to the last bits; the tuner picks
+    one of them."""
     from paper_2109_01173_amd import mofem as mf
     G = gpu_xnormal(2, 150, "dirichlet", 1.0)   # q = 299: ragged against 64 and 128
     G.prec.set_precision(getattr(mf, "PREC_" + precision))
