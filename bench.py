@@ -73,7 +73,7 @@ def cpu_baseline(F0, k, m, gamma, tol, U_gpu0):
 # source they were taken on: if k_gemm.hip changes, traffic is reported null.
 TRAFFIC = {
     # mixed mode -> (sha256 of k_gemm.hip, (q, batch), bytes per launch)
-    "bf16fwd": ("3ccabc6d6bcec0d532a2e379211181cd2df3d5b1fecd339f96bc3fdefbbf4802", (2047, 16), 1.738e9),
+    "bf16fwd": ("0c0cdc478b2efa069a1799a7ef5fe39cd27b3ac423b341903b1c0882ad0a1ee5", (2047, 16), 1.736e9),
 }
 FETCH_SCALE = 2.000   # 512 MiB copy: true bytes / FETCH_SIZE reading
 WRITE_SCALE = 1.000   # 512 MiB copy: true bytes / WRITE_SIZE reading

@@ -30,11 +30,11 @@
 // (4 x 4 MFMA tiles of 16 x 16), or 64 x 64 blocks of 32 x 32 wave tiles for
 // grids too small to fill the chip (picked per shape, see mofem_prec_tune);
 // k tiles of 16 (FP64), 32 (FP32), 64 (BF16).
-// The loads of the next k tile overlap the MFMAs of the current one (BF16 on
-// 128-row tiles: direct global -> LDS loads issued once the current tile's
-// fragments are in registers; otherwise through registers); in the split
-// products the three passes run one after the other over all 16
-// accumulators, so back-to-back MFMAs are independent.
+// The loads of the next k tile overlap the MFMAs of the current one (BF16:
+// direct global -> LDS loads issued once the current tile's fragments are in
+// registers; FP32 and FP64: through registers); in the split products the
+// three passes run one after the other over all 16 accumulators, so
+// back-to-back MFMAs are independent.
 // Block order is XCD-aware: each XCD takes a compact block of tiles, about
 // four (128 tiles) or eight (64 tiles) tile rows high, of one item.
 // Intermediates are padded to multiples of 128 in both dimensions and the
@@ -307,14 +307,13 @@ __device__ __forceinline__ void lds_load16(const unsigned short* src, unsigned s
   __builtin_amdgcn_global_load_lds((const void*)src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
 }
 
-// DMA = 0 (64-row tiles): each k tile is loaded into registers one tile
-// ahead and stored to LDS by the threads.  DMA = 1 (128-row tiles): direct
-// global -> LDS loads (global_load_lds_dwordx4) into one LDS stage; the loads
-// of tile kt + 1 start as soon as every wave holds tile kt's fragments in
-// registers and run under its MFMAs.  Whole 128-byte row pieces per load (k
-// tile 64) halve the L2 requests of a k tile of 32 with two stages, which
-// kept the texture addresser 72 % busy and was 12 % slower.
-template <int MODE, int OMODE, int BK = 64, int MINW = 2, int WT = 4, int DMA = 0>
+// k tiles reach LDS by direct global -> LDS loads (global_load_lds_dwordx4)
+// into one LDS stage; the loads of tile kt + 1 start as soon as every wave
+// holds tile kt's fragments in registers and run under its MFMAs.  Whole
+// 128-byte row pieces per load (k tile 64): a k tile of 32 with two stages
+// (64-byte pieces) doubled the L2 requests, kept the texture addresser 72 %
+// busy and was 12 % slower; register staging was 7-21 % slower.
+template <int MODE, int OMODE, int BK = 64, int MINW = 2, int WT = 4>
 __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
   // block tile TB x TB: 4 waves in 2 x 2, each WT x WT MFMA tiles of 16 x 16
   constexpr int TB = 32 * WT;
@@ -337,9 +336,7 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
   Row* Al = Bh + TB;                 // used when ALO
   Row* Bl = Al + (ALO ? TB : 0);     // used when BLO
   // element offset of the 16-byte chunk holding k (a multiple of 8) in row r:
-  // chunk index XOR (r / 2) % (BK / 8) (rocprofv3 SQ_LDS_BANK_CONFLICT: none
-  // for rows of 64 and of 32 values; XOR (r / 4) % 4 for rows of 32 values
-  // conflicts as much as no swizzle)
+  // chunk index XOR (r / 2) % 8 (rocprofv3 SQ_LDS_BANK_CONFLICT: none)
   auto sw = [](int r, int k) { return (((k >> 3) ^ ((r >> 1) % (BK / 8))) << 3); };
 
   const int b = blockIdx.y;
@@ -358,30 +355,7 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
   const unsigned short* __restrict__ Bhg = (const unsigned short*)g.b_hi + (size_t)b * g.b_stride;
   const unsigned short* __restrict__ Blg = (const unsigned short*)g.b_lo + (size_t)b * g.b_stride;
 
-  // register staging of a k tile (BK values = CPR 16-byte chunks per row):
-  // consecutive threads take consecutive chunks of a row, so one load
-  // instruction of a wave covers whole 128-byte row pieces (RPP rows per pass,
-  // NV passes); with the swizzle the LDS stores are free of bank conflicts
-  constexpr int CPR = BK / 8;
-  constexpr int RPP = 256 / CPR;
-  constexpr int NV = TB / RPP;       // 16-byte vectors per thread and operand
-  const int lrow = tid / CPR;
-  const int lk = (tid % CPR) * 8;
-  // row and k offset of vector v of this thread inside the tile
-  auto vrow = [&](int v) { return lrow + RPP * v; };
-  auto vk = [&](int v) { (void)v; return lk; };
-  us8_t ah[NV], al[NV], bh[NV], bl[NV];
-  auto load_tile = [&](int k0) {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const size_t ao = (size_t)(m0 + vrow(v)) * Kp + k0 + vk(v);
-      const size_t bo = (size_t)(n0 + vrow(v)) * Kp + k0 + vk(v);
-      ah[v] = *(const us8_t*)(Ahg + ao);
-      bh[v] = *(const us8_t*)(Bhg + bo);
-      if (ALO) al[v] = *(const us8_t*)(Alg + ao);
-      if (BLO) bl[v] = *(const us8_t*)(Blg + bo);
-    }
-  };
+  constexpr int CPR = BK / 8;  // 16-byte chunks per row
 
   f4_t acc[WT][WT];
 #pragma unroll
@@ -390,145 +364,82 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
     for (int j = 0; j < WT; ++j) acc[i][j] = (f4_t){0.f, 0.f, 0.f, 0.f};
 
   const int nk = (g.K + BK - 1) / BK;
-  // fragment reads and MFMAs of one k tile held in LDS
-  auto compute = [&](Row* Ah_, Row* Bh_, Row* Al_, Row* Bl_) {
+  // One wave instruction moves 64 x 16 bytes into RPI consecutive LDS rows;
+  // lane (row, slot) fetches the global chunk that the swizzle places in
+  // that slot.
+  constexpr int TILE = TB * LDS_K;
+  constexpr int RPI = 64 / CPR;
+  constexpr int IPW = TB / RPI / 4;
+  constexpr int KS = BK / 32;
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+  const int irow = lane / CPR, islot = lane % CPR;
+  auto dma = [&](int k0) {
 #pragma unroll
-    for (int ks = 0; ks < BK / 32; ++ks) {
-      bf8_t fa[WT], fb[WT], fal[WT], fbl[WT];
+    for (int j = 0; j < IPW; ++j) {
+      const int r0 = (wv * IPW + j) * RPI;
+      const int r = r0 + irow;
+      const int c = islot ^ ((r >> 1) % CPR);
+      const size_t ao = (size_t)(m0 + r) * Kp + k0 + c * 8;
+      const size_t bo = (size_t)(n0 + r) * Kp + k0 + c * 8;
+      lds_load16(Ahg + ao, lds + r0 * LDS_K);
+      lds_load16(Bhg + bo, lds + TILE + r0 * LDS_K);
+      if (ALO) lds_load16(Alg + ao, lds + 2 * TILE + r0 * LDS_K);
+      if (BLO) lds_load16(Blg + bo, lds + (ALO ? 3 : 2) * TILE + r0 * LDS_K);
+    }
+  };
+  bf8_t fa[KS][WT], fb[KS][WT], fal[KS][WT], fbl[KS][WT];
+  auto read = [&]() {
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
       const int kq = ks * 32 + (lane >> 4) * 8;
 #pragma unroll
       for (int i = 0; i < WT; ++i) {
         const int r = wm * (16 * WT) + i * 16 + (lane & 15);
-        fa[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Ah_[r][sw(r, kq)]);
-        if (ALO) fal[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Al_[r][sw(r, kq)]);
+        fa[ks][i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Ah[r][sw(r, kq)]);
+        if (ALO) fal[ks][i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Al[r][sw(r, kq)]);
       }
 #pragma unroll
       for (int j = 0; j < WT; ++j) {
         const int r = wn * (16 * WT) + j * 16 + (lane & 15);
-        fb[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Bh_[r][sw(r, kq)]);
-        if (BLO) fbl[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Bl_[r][sw(r, kq)]);
+        fb[ks][j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Bh[r][sw(r, kq)]);
+        if (BLO) fbl[ks][j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Bl[r][sw(r, kq)]);
       }
-      // products outermost: consecutive MFMAs write different accumulators;
-      // the wave issuing its MFMA block runs at raised priority (the other
-      // wave of the SIMD meanwhile stages and loads)
-      __builtin_amdgcn_s_setprio(1);
+    }
+  };
+  auto mma = [&]() {
+    __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
       if (ALO) {
 #pragma unroll
         for (int i = 0; i < WT; ++i)
 #pragma unroll
           for (int j = 0; j < WT; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fal[i], fb[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fal[ks][i], fb[ks][j], acc[i][j], 0, 0, 0);
       }
       if (BLO) {
 #pragma unroll
         for (int i = 0; i < WT; ++i)
 #pragma unroll
           for (int j = 0; j < WT; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fbl[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[ks][i], fbl[ks][j], acc[i][j], 0, 0, 0);
       }
 #pragma unroll
       for (int i = 0; i < WT; ++i)
 #pragma unroll
         for (int j = 0; j < WT; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
-      __builtin_amdgcn_s_setprio(0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[ks][i], fb[ks][j], acc[i][j], 0, 0, 0);
     }
+    __builtin_amdgcn_s_setprio(0);
   };
-
-  if constexpr (DMA) {
-    // One wave instruction moves 64 x 16 bytes into RPI consecutive LDS rows;
-    // lane (row, slot) fetches the global chunk that the swizzle places in
-    // that slot.
-    constexpr int TILE = TB * LDS_K;
-    constexpr int RPI = 64 / CPR;
-    constexpr int IPW = TB / RPI / 4;
-    constexpr int KS = BK / 32;
-    const int wv = __builtin_amdgcn_readfirstlane(wave);
-    const int irow = lane / CPR, islot = lane % CPR;
-    auto dma = [&](int k0) {
-#pragma unroll
-      for (int j = 0; j < IPW; ++j) {
-        const int r0 = (wv * IPW + j) * RPI;
-        const int r = r0 + irow;
-        const int c = islot ^ ((r >> 1) % CPR);
-        const size_t ao = (size_t)(m0 + r) * Kp + k0 + c * 8;
-        const size_t bo = (size_t)(n0 + r) * Kp + k0 + c * 8;
-        lds_load16(Ahg + ao, lds + r0 * LDS_K);
-        lds_load16(Bhg + bo, lds + TILE + r0 * LDS_K);
-        if (ALO) lds_load16(Alg + ao, lds + 2 * TILE + r0 * LDS_K);
-        if (BLO) lds_load16(Blg + bo, lds + (ALO ? 3 : 2) * TILE + r0 * LDS_K);
-      }
-    };
-    bf8_t fa[KS][WT], fb[KS][WT], fal[KS][WT], fbl[KS][WT];
-    auto read = [&]() {
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const int kq = ks * 32 + (lane >> 4) * 8;
-#pragma unroll
-        for (int i = 0; i < WT; ++i) {
-          const int r = wm * (16 * WT) + i * 16 + (lane & 15);
-          fa[ks][i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Ah[r][sw(r, kq)]);
-          if (ALO) fal[ks][i] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Al[r][sw(r, kq)]);
-        }
-#pragma unroll
-        for (int j = 0; j < WT; ++j) {
-          const int r = wn * (16 * WT) + j * 16 + (lane & 15);
-          fb[ks][j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Bh[r][sw(r, kq)]);
-          if (BLO) fbl[ks][j] = __builtin_bit_cast(bf8_t, *(const us8_t*)&Bl[r][sw(r, kq)]);
-        }
-      }
-    };
-    auto mma = [&]() {
-      __builtin_amdgcn_s_setprio(1);
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        if (ALO) {
-#pragma unroll
-          for (int i = 0; i < WT; ++i)
-#pragma unroll
-            for (int j = 0; j < WT; ++j)
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fal[ks][i], fb[ks][j], acc[i][j], 0, 0, 0);
-        }
-        if (BLO) {
-#pragma unroll
-          for (int i = 0; i < WT; ++i)
-#pragma unroll
-            for (int j = 0; j < WT; ++j)
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[ks][i], fbl[ks][j], acc[i][j], 0, 0, 0);
-        }
-#pragma unroll
-        for (int i = 0; i < WT; ++i)
-#pragma unroll
-          for (int j = 0; j < WT; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[ks][i], fb[ks][j], acc[i][j], 0, 0, 0);
-      }
-      __builtin_amdgcn_s_setprio(0);
-    };
-    dma(0);
-    for (int kt = 0; kt < nk; ++kt) {
-      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's loads of tile kt landed
-      __syncthreads();                     // and every wave's
-      read();
-      __syncthreads();                     // every wave holds its fragments: the stage is free
-      if (kt + 1 < nk) dma((kt + 1) * BK);
-      mma();
-    }
-  } else {
-    load_tile(0);
-    for (int kt = 0; kt < nk; ++kt) {
-      __syncthreads();
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const int so = sw(vrow(v), vk(v));
-        *(us8_t*)&Ah[vrow(v)][so] = ah[v];
-        *(us8_t*)&Bh[vrow(v)][so] = bh[v];
-        if (ALO) *(us8_t*)&Al[vrow(v)][so] = al[v];
-        if (BLO) *(us8_t*)&Bl[vrow(v)][so] = bl[v];
-      }
-      __syncthreads();
-      if (kt + 1 < nk) load_tile((kt + 1) * BK);
-      compute(Ah, Bh, Al, Bl);
-    }
+  dma(0);
+  for (int kt = 0; kt < nk; ++kt) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's loads of tile kt landed
+    __syncthreads();                     // and every wave's
+    read();
+    __syncthreads();                     // every wave holds its fragments: the stage is free
+    if (kt + 1 < nk) dma((kt + 1) * BK);
+    mma();
   }
 
   // epilogue: acc[i][j][r] = C[row][col], row = 4*(lane/16) + r, col = lane%16
@@ -632,14 +543,14 @@ static void launch_mode(const GemmArgs& g, int prec, int batch, hipStream_t s) {
   } else if (prec == GEMM_F32)
     hipLaunchKernelGGL((gemm_f32_kernel<OMODE, WT>), grid, dim3(256), 0, s, g);
   else if (prec == GEMM_BF16X3)
-    hipLaunchKernelGGL((gemm_bf16_kernel<BF_X3, OMODE, 64, 2, WT, WT == 4>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_bf16_kernel<BF_X3, OMODE, 64, 2, WT>), grid, dim3(256), 0, s, g);
   else if (prec == GEMM_BF16X2 && g.data_is_a)
-    hipLaunchKernelGGL((gemm_bf16_kernel<BF_X2A, OMODE, 64, 2, WT, WT == 4>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_bf16_kernel<BF_X2A, OMODE, 64, 2, WT>), grid, dim3(256), 0, s, g);
   else if (prec == GEMM_BF16X2)
-    hipLaunchKernelGGL((gemm_bf16_kernel<BF_X2B, OMODE, 64, 2, WT, WT == 4>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_bf16_kernel<BF_X2B, OMODE, 64, 2, WT>), grid, dim3(256), 0, s, g);
   else
     // three waves per SIMD (at most 168 VGPRs): measured 15-20 % faster than two
-    hipLaunchKernelGGL((gemm_bf16_kernel<BF_HH, OMODE, 64, 3, WT, WT == 4>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_bf16_kernel<BF_HH, OMODE, 64, 3, WT>), grid, dim3(256), 0, s, g);
 }
 
 int launch_gemm(const GemmArgs& g, int prec, int omode, int batch, int tile, hipStream_t s) {
