@@ -9,11 +9,21 @@ of the working precisions of the library:
   f32  operands rounded to FP32, FP32 products and sums;
   hh   operands rounded to BF16 (round to nearest even), FP32 accumulation;
   x3   operands split x = hi + lo with hi = bf16(x), lo = bf16(x - hi) (in
-       FP32), and A B ~ Ah Bh + Ah Bl + Al Bh accumulated in FP32.
-FP32 accumulation order differs from the GPU's, so this emulates the error
-level, not the bits.  Pins: tests/test_oracle_precision.py (rounding against
-exhaustive bit-level checks, split exactness, error levels and iteration
-counts of the flexible MO-PCG with each mode).
+       FP32), and A B ~ Ah Bh + Ah Bl + Al Bh accumulated in FP32;
+  x2a  A split, B rounded to BF16:  Ah Bh + Al Bh  (the product with the
+       BF16-rounded B, to FP32 accuracy);
+  x2b  B split, A rounded to BF16:  Ah Bh + Ah Bl.
+Accumulation: acc="f32" sums in FP32 (NumPy's single-precision BLAS, one
+blocked accumulation order); acc="seq" adds the rank-one terms one k at a
+time into FP32 sums (the longest chain of FP32 roundings, as a matrix-core
+accumulator over k does); acc="exact" sums the same rounded operands in FP64
+and rounds the result to FP32 once (the limit of any FP32 accumulation
+order).  Their spread bounds what another FP32 summation order (the GPU's)
+can change, so the GPU's result is compared with this emulation at that
+level, not bit for bit.  Pins: tests/test_oracle_precision.py
+(rounding against exhaustive bit-level checks, split exactness, error levels,
+accumulation-order sensitivity and iteration counts of the flexible MO-PCG
+with each mode).
 """
 import numpy as np
 
@@ -32,30 +42,82 @@ def split(x):
     return hi, bf16(x - hi)
 
 
-def product(A, B, mode):
+def _mm(A, B, acc):
+    if acc == "f32":
+        return A @ B
+    if acc == "exact":
+        return (A.astype(np.float64) @ B.astype(np.float64)).astype(np.float32)
+    raise ValueError(acc)
+
+
+def _seq(pairs):
+    """sum over k and over the (A, B) operand pairs of A[:, k] B[k, :], added
+    one rank-one term at a time into FP32 sums (pairs innermost)."""
+    A0, B0 = pairs[0]
+    out = np.zeros((A0.shape[0], B0.shape[1]), dtype=np.float32)
+    for k in range(A0.shape[1]):
+        for A, B in pairs:
+            out += np.multiply.outer(A[:, k], B[k, :]).astype(np.float32)
+    return out
+
+
+def product(A, B, mode, acc="f32"):
     """A @ B in the given transform precision, returned as FP64."""
     if mode == "f64":
         return A @ B
     if mode == "f32":
-        return (A.astype(np.float32) @ B.astype(np.float32)).astype(np.float64)
+        A32, B32 = A.astype(np.float32), B.astype(np.float32)
+        if acc == "seq":
+            return _seq([(A32, B32)]).astype(np.float64)
+        return _mm(A32, B32, acc).astype(np.float64)
     Ah, Al = split(A)
     Bh, Bl = split(B)
+    if acc == "seq":
+        pairs = {"hh": [(Ah, Bh)], "x3": [(Ah, Bh), (Ah, Bl), (Al, Bh)],
+                 "x2a": [(Ah, Bh), (Al, Bh)], "x2b": [(Ah, Bh), (Ah, Bl)]}
+        if mode not in pairs:
+            raise ValueError(mode)
+        return _seq(pairs[mode]).astype(np.float64)
     if mode == "hh":
-        return (Ah @ Bh).astype(np.float64)
-    if mode == "x3":
-        return (Ah @ Bh + Ah @ Bl + Al @ Bh).astype(np.float64)
-    raise ValueError(mode)
+        out = _mm(Ah, Bh, acc)
+    elif mode == "x3":
+        if acc == "exact":
+            out = (Ah.astype(np.float64) @ Bh + Ah.astype(np.float64) @ Bl
+                   + Al.astype(np.float64) @ Bh).astype(np.float32)
+        else:
+            out = Ah @ Bh + Ah @ Bl + Al @ Bh
+    elif mode == "x2a":
+        out = _mm(Ah, Bh, acc) + _mm(Al, Bh, acc) if acc == "f32" else \
+            (Ah.astype(np.float64) @ Bh + Al.astype(np.float64) @ Bh).astype(np.float32)
+    elif mode == "x2b":
+        out = _mm(Ah, Bh, acc) + _mm(Ah, Bl, acc) if acc == "f32" else \
+            (Ah.astype(np.float64) @ Bh + Ah.astype(np.float64) @ Bl).astype(np.float32)
+    else:
+        raise ValueError(mode)
+    return out.astype(np.float64)
 
 
-def prec_apply(S, modes):
+def prec_apply(S, modes, acc="f32"):
     """P^-1 with the four products in modes = (G1, G2, G3, G4):
     G1 = R V_t, G2 = V_s^T (.), G3 = V_s (. ./ D), G4 = (.) V_t^T.
     S: oracle.solvers.SpectralPrec (eigenbases Vs, Vt, divisor D)."""
     Vs, Vt, D = S.Vs, S.Vt, S.D
 
     def apply(R):
-        T1 = product(R, Vt, modes[0])
-        T2 = product(Vs.T, T1, modes[1]) / D
-        T3 = product(Vs, T2, modes[2])
-        return product(T3, Vt.T, modes[3])
+        T1 = product(R, Vt, modes[0], acc)
+        T2 = product(Vs.T, T1, modes[1], acc) / D
+        T3 = product(Vs, T2, modes[2], acc)
+        return product(T3, Vt.T, modes[3], acc)
     return apply
+
+
+# the library's transform precisions as emulation modes (G1, G2, G3, G4);
+# in G1 and G4 the eigenbasis is the right operand, in G2 and G3 the left
+MODES = {
+    "F64": ("f64",) * 4,
+    "F32": ("f32",) * 4,
+    "BF16": ("hh",) * 4,
+    "BF16X3": ("x3",) * 4,
+    "BF16X2": ("x2a", "x2b", "x2b", "x2a"),
+    "BF16_FWD": ("hh", "hh", "x3", "x3"),
+}
