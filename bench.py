@@ -112,7 +112,9 @@ def uneven_leg(mf, torch, np, n_inst, prec, prec_name, rds_steps=100):
     steps of both species at rel 1e-10, FP64 transforms).  Same-shape
     instances of one type form one batched group.  The elliptic groups are
     solved one after another (pcg_solve) and together on four streams
-    (pcg_solve_many); the reaction-diffusion groups step one after another."""
+    (pcg_solve_many); the reaction-diffusion groups step one after another.
+    The groups' set-up (assembly, eigen-decompositions) runs on a pool of host
+    threads."""
     from paper_2109_01173_amd.problems import Rect, XNormal
     from workloads import dib_initial, dib_params, elliptic_batch
     rng = np.random.default_rng(5)
@@ -123,28 +125,38 @@ def uneven_leg(mf, torch, np, n_inst, prec, prec_name, rds_steps=100):
     for n, k, ty in zip(ns.tolist(), ks.tolist(), types.tolist()):
         shapes[(ty, n, k)] = shapes.get((ty, n, k), 0) + 1
     t0 = time.perf_counter()
-    groups, rds = [], []
     p = dib_params()
     kin = [p["rho"], p["A1"], p["A2"], p["B"], p["C"], p["D"], p["alpha"], p["gamma"], p["k2"], p["k3"]]
-    for gi, ((ty, n, k), cnt) in enumerate(sorted(shapes.items())):
+
+    def build(item):
+        # one shape group: assembly, eigen-decompositions and upload in the
+        # library (its calls release the interpreter, so groups build in parallel)
+        gi, ((ty, n, k), cnt) = item
         m = int(round((n - 1) / k))
         if ty == 0:
             G = XNormal(k, m, "dirichlet", gamma=1.0, precision=prec)
             F = torch.from_numpy(elliptic_batch(G.n, 1.0, cnt, sigma=1e-3, seed0=5000 + 100 * gi)).cuda()
             rhs = G.rhs_op.apply(F)
-            groups.append(dict(op=G.op, prec=G.prec, rhs=rhs, U=torch.empty_like(rhs), tol=1e-8, maxit=300,
-                               flags=mf.PCG_FLEXIBLE | mf.PCG_ZERO_GUESS, _keep=G))
-            groups[-1]["workspace"] = mf.pcg_workspace(G.op, G.prec, cnt)
-        else:
-            lumped = k == 1
-            G = Rect(k, m, "neumann", length=20.0, lumped=lumped, imex=True, closed_form=lumped)
-            init = [dib_initial(G.q, seed=7000 + 100 * gi + j) for j in range(cnt)]
-            # species-major state: eta of every item, then theta of every item
-            st0 = torch.from_numpy(np.stack([e for e, _ in init] + [t for _, t in init])).cuda()
-            stepper = mf.Imex(G.op, G.prec, G.mass, 1e-2, [1.0, p["d_theta"]], kinetics=mf.KIN_DIB, kin=kin,
-                              tol=1e-10, maxit=50)
-            rds.append(dict(G=G, st0=st0, st=st0.clone(), stepper=stepper, batch=cnt,
-                            ws=stepper.workspace(cnt)))
+            torch.cuda.synchronize()
+            return 0, dict(op=G.op, prec=G.prec, rhs=rhs, U=torch.empty_like(rhs), tol=1e-8, maxit=300,
+                           flags=mf.PCG_FLEXIBLE | mf.PCG_ZERO_GUESS, _keep=G,
+                           workspace=mf.pcg_workspace(G.op, G.prec, cnt))
+        lumped = k == 1
+        G = Rect(k, m, "neumann", length=20.0, lumped=lumped, imex=True, closed_form=lumped)
+        init = [dib_initial(G.q, seed=7000 + 100 * gi + j) for j in range(cnt)]
+        # species-major state: eta of every item, then theta of every item
+        st0 = torch.from_numpy(np.stack([e for e, _ in init] + [t for _, t in init])).cuda()
+        stepper = mf.Imex(G.op, G.prec, G.mass, 1e-2, [1.0, p["d_theta"]], kinetics=mf.KIN_DIB, kin=kin,
+                          tol=1e-10, maxit=50)
+        r = dict(G=G, st0=st0, st=st0.clone(), stepper=stepper, batch=cnt, ws=stepper.workspace(cnt))
+        torch.cuda.synchronize()
+        return 1, r
+
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=max(1, min(16, os.cpu_count() or 1))) as ex:
+        built = list(ex.map(build, enumerate(sorted(shapes.items()))))
+    groups = [g for ty, g in built if ty == 0]
+    rds = [r for ty, r in built if ty == 1]
     setup = time.perf_counter() - t0
     n_ell = sum(int(g["rhs"].shape[0]) for g in groups)
     n_rds = sum(r["batch"] for r in rds)
@@ -197,95 +209,197 @@ def uneven_leg(mf, torch, np, n_inst, prec, prec_name, rds_steps=100):
                              "setup_s": round(setup, 2)}}
 
 
-def imex_legs(mf, torch, np, nsteps, prec, prec_name):
-    """Per-step throughput of the IMEX Euler step (eqs. (91)-(96)) on the heat
-    workload (P4, Neumann, n = 2049, d = 0.1, tau = 1e-3, U0 ~ U[0,1) seed 42)
-    and the DIB workload (lumped P1 and P2 on [0,20]^2, n = 1025, tau = 1e-2,
-    cap parameters, equilibrium + U[-1e-3,1e-3) seed 7)."""
-    from paper_2109_01173_amd.problems import Rect, XNormal
-    from workloads import dib_initial, dib_params, heat_initial
-    out = {}
-    # heat: the mixed path's transforms, flexible PCG, FP64 residual 1e-10 per step
+def radial_spectrum_peak(np, U):
+    """Dominant radial wavenumber bin of a field on a uniform square grid (FFT
+    power of the mean-free field, summed over rings of unit width) - a
+    rounding-insensitive summary of a Turing pattern."""
+    F = np.abs(np.fft.rfft2(U - U.mean())) ** 2
+    n = U.shape[0]
+    kx = np.fft.fftfreq(n)[:, None] * n
+    ky = np.fft.rfftfreq(U.shape[1])[None, :] * U.shape[1]
+    rb = np.rint(np.sqrt(kx ** 2 + ky ** 2)).astype(int)
+    spec = np.bincount(rb.ravel(), F.ravel())
+    return int(spec[1:].argmax() + 1)
+
+
+def heat_leg(mf, torch, np, nsteps, eager_steps):
+    """Heat equation (eqs. (89)-(96)): P4 on the x-normal domain, Neumann,
+    n = 2049, d = 0.1, tau = 1e-3, U0 ~ U[0,1) (seed 42), f = 0; FP32
+    transforms (FP32 operands and accumulation) with the FP64 residual and
+    recurrence, flexible PCG to rel 1e-10 per step.  `eager_steps` steps
+    through mofem_imex_step (they also fix the graph's iteration budget),
+    then `nsteps` steps replayed from the captured HIP graph."""
+    from paper_2109_01173_amd.problems import XNormal
+    from workloads import heat_initial
     t0 = time.perf_counter()
-    G = XNormal(4, 512, "neumann", gamma=0.0, imex=True, precision=prec)
+    G = XNormal(4, 512, "neumann", gamma=0.0, imex=True, precision=mf.PREC_F32)
     setup = time.perf_counter() - t0
     st = torch.from_numpy(heat_initial(G.q, seed=42)[None]).cuda()
-    stepper = mf.Imex(G.op, G.prec, G.mass, 1e-3, [0.1], tol=1e-10, maxit=200, flags=mf.PCG_FLEXIBLE)
+    mk = lambda: mf.Imex(G.op, G.prec, G.mass, 1e-3, [0.1], tol=1e-10, maxit=200, flags=mf.PCG_FLEXIBLE)
+    stepper = mk()
     ws = stepper.workspace(1)
     mass0 = float(G.mass.apply(st).sum())
-    stepper.step(st, 1, workspace=ws)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    its = [int(stepper.step(st, 1, workspace=ws)[0]) for _ in range(nsteps)]
+    its = [int(stepper.step(st, 1, workspace=ws)[0]) for _ in range(eager_steps)]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
-    mass1 = float(G.mass.apply(st).sum())
-    # the same steps replayed from a HIP graph (iteration budget: the most seen + 2)
     budget = max(its) + 2
-    g = mf.ImexGraph(mf.Imex(G.op, G.prec, G.mass, 1e-3, [0.1], tol=1e-10, maxit=200, flags=mf.PCG_FLEXIBLE),
-                     st, 1, iters_per_step=budget)
-    g.launch(1)
-    g.result()
+    g = mf.ImexGraph(mk(), st, 1, iters_per_step=budget)
     torch.cuda.synchronize()
     t = time.perf_counter()
     g.launch(nsteps)
     torch.cuda.synchronize()
     dtg = time.perf_counter() - t
-    gi, _, _ = g.result()
-    out["imex_heat_p4"] = {"workload": "heat P4 x-normal, Neumann, n=2049, d=0.1, tau=1e-3, rel 1e-10 per step",
-                           "steps_per_s": round(nsteps / dt, 3), "steps": nsteps,
-                           "iterations_per_step": round(float(np.mean(its)), 2),
-                           "graph_steps_per_s": round(nsteps / dtg, 3), "graph_iteration_budget": budget,
-                           "graph_max_iterations": int(gi.max()),
-                           "transforms": prec_name, "setup_s": round(setup, 2),
-                           "mass_drift_rel": abs(mass1 - mass0) / abs(mass0)}
-    log("imex heat P4: %.2f steps/s, %.1f iterations/step; graph replay %.2f steps/s"
-        % (nsteps / dt, np.mean(its), nsteps / dtg))
+    gi, gst, grr = g.result(raise_on_error=False)
+    mass1 = float(G.mass.apply(st).sum())
+    out = {"imex_heat_p4": {
+        "workload": "heat P4 x-normal, Neumann, n=2049, d=0.1, tau=1e-3, U0 ~ U[0,1) seed 42, FP32 transforms, "
+                    "FP64 residual, rel 1e-10 per step, %d graph-replayed steps after %d eager steps"
+                    % (nsteps, eager_steps),
+        "graph_steps_per_s": round(nsteps / dtg, 3), "steps": nsteps, "graph_iteration_budget": budget,
+        "graph_max_iterations": int(gi.max()), "graph_status_ok": bool(np.all(gst == 0)),
+        "last_step_relres": float(np.max(grr)),
+        "eager_steps_per_s": round(eager_steps / dt, 3), "eager_iterations_per_step": round(float(np.mean(its)), 2),
+        "transforms": "f32", "setup_s": round(setup, 2),
+        "mass_drift_rel": abs(mass1 - mass0) / abs(mass0),
+        "time_reached": round(1e-3 * (nsteps + eager_steps), 4)}}
+    log("heat P4 (FP32 transforms): %.1f steps/s replayed (%d steps, budget %d, max %d iterations), %.1f eager; "
+        "mass drift %.2e" % (nsteps / dtg, nsteps, budget, gi.max(), eager_steps / dt, abs(mass1 - mass0) / abs(mass0)))
     del g
-    del G, st, ws, stepper
-    # DIB: rectangle preset (exact single-term operator), FP64 transforms; lumped
-    # P1 (m = 1024, closed-form cosine eigenbasis) and P2 (m = 512)
+    return out
+
+
+def dib_leg(mf, torch, np, nsteps):
+    """Two-species reaction-diffusion (Sec. 7, eqs. (98)-(103)): DIB kinetics on
+    the rectangle [0,20]^2, Neumann, n = 1025 (lumped P1 with m = 1024 and P2
+    with m = 512), d_theta / d_eta = 20, tau = 1e-2, equilibrium + U[-1e-3,
+    1e-3) (seed 7), rectangle preconditioner (FP64 transforms, one iteration
+    per solve) at rel 1e-10 per step; `nsteps` steps (10^4: T = 100) replayed
+    from a HIP graph, plus the Turing pattern's statistics at the end."""
+    from paper_2109_01173_amd.problems import Rect
+    from workloads import dib_initial, dib_params
     p = dib_params()
     kin = [p["rho"], p["A1"], p["A2"], p["B"], p["C"], p["D"], p["alpha"], p["gamma"], p["k2"], p["k3"]]
+    out = {}
     for key, k, m, lumped in (("imex_dib_p1", 1, 1024, True), ("imex_dib_p2", 2, 512, False)):
         t0 = time.perf_counter()
         G = Rect(k, m, "neumann", length=20.0, lumped=lumped, imex=True, closed_form=lumped)
         setup = time.perf_counter() - t0
         eta, theta = dib_initial(G.q, seed=7)
         st = torch.from_numpy(np.stack([eta, theta])).cuda()
-        stepper = mf.Imex(G.op, G.prec, G.mass, 1e-2, [1.0, p["d_theta"]], kinetics=mf.KIN_DIB, kin=kin,
-                          tol=1e-10, maxit=50)
+        mk = lambda: mf.Imex(G.op, G.prec, G.mass, 1e-2, [1.0, p["d_theta"]], kinetics=mf.KIN_DIB, kin=kin,
+                             tol=1e-10, maxit=50)
+        stepper = mk()
         ws = stepper.workspace(1)
-        stepper.step(st, 1, workspace=ws)
+        warm = 10
         torch.cuda.synchronize()
-        n4 = 10 * nsteps
         t = time.perf_counter()
-        its = [stepper.step(st, 1, workspace=ws).max() for _ in range(n4)]
+        its = [int(stepper.step(st, 1, workspace=ws).max()) for _ in range(warm)]
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
-        g = mf.ImexGraph(mf.Imex(G.op, G.prec, G.mass, 1e-2, [1.0, p["d_theta"]], kinetics=mf.KIN_DIB, kin=kin,
-                                 tol=1e-10, maxit=50), st, 1, iters_per_step=2)
-        g.launch(1)
-        g.result()
+        g = mf.ImexGraph(mk(), st, 1, iters_per_step=2)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        g.launch(n4)
+        g.launch(nsteps - warm)
         torch.cuda.synchronize()
         dtg = time.perf_counter() - t
-        gi, _, _ = g.result()
+        gi, gst, _ = g.result(raise_on_error=False)
+        e, th = st.cpu().numpy()
         name = "lumped P1" if lumped else "P2"
-        out[key] = {"workload": "DIB %s rectangle [0,20]^2, Neumann, n=1025, tau=1e-2, two species, "
-                                "rel 1e-10 per step" % name,
-                    "steps_per_s": round(n4 / dt, 2), "steps": n4,
-                    "iterations_per_step": round(float(np.mean(its)), 2),
-                    "graph_steps_per_s": round(n4 / dtg, 2), "graph_iteration_budget": 2,
-                    "graph_max_iterations": int(gi.max()), "transforms": "f64",
-                    "eigenbasis": "closed form" if lumped else "dense eigen-solve",
-                    "setup_s": round(setup, 2)}
-        log("imex DIB %s: %.1f steps/s, %.1f iterations/step; graph replay %.1f steps/s"
-            % (name, n4 / dt, np.mean(its), n4 / dtg))
+        out[key] = {"workload": "DIB %s rectangle [0,20]^2, Neumann, n=1025, tau=1e-2, two species, rel 1e-10 per "
+                                "step, T=%g (%d steps: %d eager, the rest replayed from a HIP graph)"
+                                % (name, 1e-2 * nsteps, nsteps, warm),
+                    "graph_steps_per_s": round((nsteps - warm) / dtg, 2), "steps": nsteps,
+                    "eager_steps_per_s": round(warm / dt, 2), "iterations_per_step": max(its),
+                    "graph_max_iterations": int(gi.max()), "graph_status_ok": bool(np.all(gst == 0)),
+                    "transforms": "f64", "eigenbasis": "closed form" if lumped else "dense eigen-solve",
+                    "setup_s": round(setup, 2),
+                    "final_state": {"eta_mean": float(e.mean()), "eta_var": float(e.var()),
+                                    "theta_mean": float(th.mean()), "theta_var": float(th.var()),
+                                    "eta_peak_radial_bin": radial_spectrum_peak(np, e), "finite": bool(
+                                        np.isfinite(e).all() and np.isfinite(th).all())}}
+        log("DIB %s: %.1f steps/s replayed (%d steps to T = %g); eta mean %.3e var %.3e, peak bin %d"
+            % (name, (nsteps - warm) / dtg, nsteps, 1e-2 * nsteps, e.mean(), e.var(), radial_spectrum_peak(np, e)))
         del g, G, st, stepper, ws
     return out
+
+
+def adjoint_leg(mf, torch, np, nsteps=100, checkpoint=50):
+    """Gradients through the solver (torch.autograd over the library's
+    adjoint): (1) a reaction-diffusion instance of the uneven draw's kind (DIB,
+    lumped P1 on [0,20]^2, n = 257, 100 steps, checkpoint every 50),
+    J = ||eta(T) - eta_t||^2 + ||theta(T) - theta_t||^2 with seeded targets,
+    dJ/d(d_eta) and dJ/d(d_theta); (2) an elliptic instance (P2 x-normal,
+    n = 257, batch 4), J = ||U - U_t||^2, dJ/dF along a seeded direction;
+    each against central finite differences of the GPU forward map."""
+    from paper_2109_01173_amd.autograd import EllipticSolve, ImexRollout
+    from paper_2109_01173_amd.problems import Rect, XNormal
+    from workloads import dib_initial, dib_params, elliptic_batch
+    p = dib_params()
+    kin = [p["rho"], p["A1"], p["A2"], p["B"], p["C"], p["D"], p["alpha"], p["gamma"], p["k2"], p["k3"]]
+    tau = 1e-2
+    G = Rect(1, 256, "neumann", length=20.0, lumped=True, imex=True, closed_form=True)
+    eta0, theta0 = dib_initial(G.q, seed=11)
+    rng = np.random.default_rng(12)
+    target = torch.from_numpy(np.stack([1e-3 * rng.standard_normal((G.q, G.q)),
+                                        0.5 + 1e-3 * rng.standard_normal((G.q, G.q))])).cuda()
+    s0 = torch.from_numpy(np.stack([eta0, theta0])).cuda()
+    d0 = [1.0, p["d_theta"]]
+
+    def rollout(dvec, grad):
+        d = torch.tensor(dvec, dtype=torch.float64, device="cuda", requires_grad=grad)
+        out = ImexRollout.apply(s0, d, G, tau, nsteps, mf.KIN_DIB, kin, 1e-13, 50, 0, checkpoint)
+        return d, ((out - target) ** 2).sum()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    d, J = rollout(d0, True)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t
+    t = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t
+    g = d.grad.cpu().numpy()
+    fd_err = []
+    for i in range(2):
+        h = 1e-5 * d0[i]
+        with torch.no_grad():
+            jp = float(rollout([d0[j] + (h if j == i else 0.0) for j in range(2)], False)[1])
+            jm = float(rollout([d0[j] - (h if j == i else 0.0) for j in range(2)], False)[1])
+        fd = (jp - jm) / (2 * h)
+        fd_err.append(abs(fd - g[i]) / abs(fd))
+    # elliptic: dJ/dF along a direction
+    Ge = XNormal(2, 128, "dirichlet", gamma=1.0)
+    F = elliptic_batch(Ge.n, 1.0, 4, sigma=1e-3, seed0=77)
+    Ut = torch.from_numpy(np.random.default_rng(13).standard_normal((4, Ge.q, Ge.q)) * 1e-2).cuda()
+    Ft = torch.from_numpy(F).cuda().requires_grad_(True)
+    gam = torch.tensor(1.0, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    U = EllipticSolve.apply(Ft, gam, Ge, 1e-13, 300, 0)
+    Je = ((U - Ut) ** 2).sum()
+    Je.backward()
+    torch.cuda.synchronize()
+    t_ell = time.perf_counter() - t
+    E = np.random.default_rng(14).standard_normal(F.shape)
+    h = 1e-3
+    with torch.no_grad():
+        jp = float(((EllipticSolve.apply(torch.from_numpy(F + h * E).cuda(), gam, Ge, 1e-13, 300, 0) - Ut) ** 2).sum())
+        jm = float(((EllipticSolve.apply(torch.from_numpy(F - h * E).cuda(), gam, Ge, 1e-13, 300, 0) - Ut) ** 2).sum())
+    fd = (jp - jm) / (2 * h)
+    ell_err = abs(fd - float((Ft.grad.cpu().numpy() * E).sum())) / abs(fd)
+    log("adjoint: DIB n=257 %d steps (checkpoint %d) forward %.2f s backward %.2f s, FD rel err d_eta %.1e "
+        "d_theta %.1e; elliptic P2 n=257 batch 4 dJ/dF FD rel err %.1e (%.2f s)"
+        % (nsteps, checkpoint, t_fwd, t_bwd, fd_err[0], fd_err[1], ell_err, t_ell))
+    return {"adjoint": {"workload": "DIB lumped P1 rectangle [0,20]^2, Neumann, n=257, tau=1e-2, %d steps, "
+                                    "checkpoint every %d, J = ||state(T) - target||^2, gradient in (d_eta, "
+                                    "d_theta); elliptic P2 x-normal n=257 batch 4, J = ||U - U_t||^2, gradient "
+                                    "in F" % (nsteps, checkpoint),
+                        "rollout_forward_s": round(t_fwd, 3), "rollout_backward_s": round(t_bwd, 3),
+                        "grad_d": [float(x) for x in g],
+                        "fd_rel_err_d_eta": float(fd_err[0]), "fd_rel_err_d_theta": float(fd_err[1]),
+                        "elliptic_forward_backward_s": round(t_ell, 3), "fd_rel_err_dF": float(ell_err)}}
 
 
 def paper_prec_leg(mf, torch, np, G_head, batch, nsteps):
@@ -380,8 +494,13 @@ def main():
     ap.add_argument("--mixed", default="bf16fwd", choices=["bf16x2", "bf16x3", "bf16", "bf16fwd"],
                     help="transform precision of the mixed path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--heat-steps", type=int, default=1000,
+                    help="graph-replayed steps of the heat P4 leg (0 skips it)")
+    ap.add_argument("--dib-steps", type=int, default=10000,
+                    help="steps of each DIB leg (10^4 reaches T = 100; 0 skips them)")
+    ap.add_argument("--adjoint", type=int, default=1, help="run the gradient leg (0 skips it)")
     ap.add_argument("--imex-steps", type=int, default=10,
-                    help="IMEX steps timed for the heat (P4) and DIB (lumped P1) legs; 0 skips them")
+                    help="eager steps of the heat leg and of the product-preconditioner heat leg")
     ap.add_argument("--uneven", type=int, default=64,
                     help="instances of the uneven-batch leg (0 skips it)")
     ap.add_argument("--paper-prec", type=int, default=1,
@@ -494,12 +613,25 @@ def main():
                     frac=round(achieved_tf / BF16_PEAK_TFLOPS, 4),
                     traffic=measured_traffic(args.mixed, q, B),
                     traffic_unit="HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
-                    algorithmic_flop_per_launch=mixed[2] * flop_per_item_gemm * g_items / max(g_n, 1),
+                    # the survey's per-unit count for this transform precision:
+                    # mixed[2] BF16 MFMA products of 2 q^3 per item (the split
+                    # issues three BF16 products for one FP32-accurate product)
+                    flop_per_launch=mixed[2] * flop_per_item_gemm * g_items / max(g_n, 1),
+                    flop_count="%d BF16 products of 2 q^3 per item" % mixed[2],
+                    # the same launches counted as the method's one product per item
+                    one_product_flop_per_launch=flop_per_item_gemm * g_items / max(g_n, 1),
+                    one_product_frac=round(achieved_tf / mixed[2] / BF16_PEAK_TFLOPS, 4),
                     kernel=mixed[3] + " (transform product, %d BF16 MFMA products)" % mixed[2],
                     avg_launch_ms=round(g_ms / max(g_n, 1), 4), launches=g_n,
                     traced_classes="operator apply and this kernel only (HIP events on the launch stream)")
 
-    extra = imex_legs(mf, torch, np, args.imex_steps, mixed[0], args.mixed) if args.imex_steps > 0 else {}
+    extra = {}
+    if args.heat_steps > 0:
+        extra.update(heat_leg(mf, torch, np, args.heat_steps, max(args.imex_steps, 2)))
+    if args.dib_steps > 0:
+        extra.update(dib_leg(mf, torch, np, args.dib_steps))
+    if args.adjoint > 0:
+        extra.update(adjoint_leg(mf, torch, np))
     if args.uneven > 0:
         extra.update(uneven_leg(mf, torch, np, args.uneven, mixed[0], args.mixed))
     if args.paper_prec > 0:

@@ -169,8 +169,15 @@ typedef struct mofem_op_s* mofem_op_t;
 
 /* Upload the operator (eq. (73), (75), (91), (92) or (28) are all of this
    form).  Copies the host bands; the descriptor may be freed afterwards.
-   q_s = n_s - 2 trim_s, q_t = n_t - 2 trim_t.
-   Errors: MOFEM_E_ARG (sizes, kb, n_terms), MOFEM_E_NOMEM, MOFEM_E_HIP. */
+   q_s = n_s - 2 trim_s, q_t = n_t - 2 trim_t.  Terms of the same scaling
+   that share a factor are merged on the host before upload (c1 L1 X R +
+   c2 L2 X R = (c1 L1 + c2 L2) X R, e.g. eq. (73)'s (B1 + gamma M3) U M from
+   the two terms B1 U M and gamma M3 U M; likewise a shared left factor).  Up
+   to six distinct terms run as one kernel pass; seven or eight as two
+   passes, the second adding to Y.
+   Errors: MOFEM_E_ARG (sizes, kb, n_terms outside 1..MOFEM_MAX_TERMS, NULL
+   bands), MOFEM_E_NOTFINITE (a non-finite band entry), MOFEM_E_NOMEM,
+   MOFEM_E_HIP. */
 int mofem_op_create(const mofem_op_desc* desc, mofem_op_t* op);
 int mofem_op_destroy(mofem_op_t op);
 /* Output and input shapes of the operator. */
@@ -288,13 +295,22 @@ int mofem_prec_set_tile(mofem_prec_t prec, int batch, int tile);
 /*  bs = bt = 1, one scale c = d tau per species).                           */
 /* ------------------------------------------------------------------------ */
 #define MOFEM_MAX_SCALES 8
+#define MOFEM_MAX_BAND_SUM 4
+/* A banded matrix given as a sum  sum_i coef[i] band[i]  of host DIA bands of
+   half-width kb (e.g. eq. (80)'s A + B2: two terms); n = 0 is the zero
+   matrix.  The sum is formed by the library. */
+typedef struct {
+  int n;                                    /* 0 .. MOFEM_MAX_BAND_SUM        */
+  const double* band[MOFEM_MAX_BAND_SUM];   /* host DIA bands, symmetric      */
+  double coef[MOFEM_MAX_BAND_SUM];
+} mofem_band_sum;
 typedef struct {
   int kb;                       /* band half-width of the four matrices, 1..4 */
   int n_s, n_t, trim_s, trim_t; /* as in mofem_prec_desc                      */
-  const double* Ks;             /* host DIA bands, symmetric                  */
-  const double* Ms;             /* host DIA bands; may be NULL when a == 0    */
-  const double* Kt;
-  const double* Mt;
+  mofem_band_sum Ks;            /* at least one term                          */
+  mofem_band_sum Ms;            /* at least one term unless a == 0            */
+  mofem_band_sum Kt;
+  mofem_band_sum Mt;
   double a, bs, bt;             /* S_j = a Ms + c_j bs Ks, T_j likewise        */
   int n_scales;                 /* 1 .. MOFEM_MAX_SCALES                      */
   double scales[MOFEM_MAX_SCALES];  /* c_j                                    */
@@ -306,14 +322,17 @@ typedef struct {
    one application is a forward and a back substitution along each dimension,
    O(kb q_s q_t) work per item and about 64 bytes of HBM traffic per entry.
    Item b uses the factor pair j whose scale c_j equals its item scale s_b
-   exactly (s_b = 1 when item_scale is NULL), and pair 0 when none does (the
-   preconditioner is then still symmetric positive definite).  Arithmetic is
+   exactly (s_b = 1 when item_scale is NULL).  An item whose scale matches no
+   c_j gets a NaN result (a solve then stops with MOFEM_E_NOTFINITE); the IMEX
+   entry points check their scales d * tau on the host and return MOFEM_E_ARG
+   before any launch.  Arithmetic is
    FP64 only: mofem_prec_set_precision accepts MOFEM_PREC_F64 alone, and
    mofem_prec_set_coeffs, mofem_prec_eigenvalues, mofem_prec_tune and
    mofem_prec_set_tile return MOFEM_E_UNSUPPORTED for this handle.
-   Errors: MOFEM_E_ARG (kb, sizes, trim flags, NULL bands, n_scales),
-   MOFEM_E_NUMERIC (a factor is not positive definite, e.g. eq. (80) under
-   Neumann conditions, where B1 is singular), MOFEM_E_NOMEM, MOFEM_E_HIP. */
+   Errors: MOFEM_E_ARG (kb, sizes, trim flags, NULL bands, term counts,
+   n_scales), MOFEM_E_NUMERIC (a factor is not positive definite, e.g.
+   eq. (80) under Neumann conditions, where B1 is singular), MOFEM_E_NOMEM,
+   MOFEM_E_HIP. */
 int mofem_prec_setup_banded(const mofem_bprec_desc* desc, mofem_prec_t* prec);
 
 /* ------------------------------------------------------------------------ */

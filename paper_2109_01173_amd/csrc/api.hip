@@ -12,6 +12,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "kernels.h"
@@ -185,28 +186,48 @@ extern "C" int mofem_trace_read(int cls, double* total_ms, long long* launches, 
 // ============================================================================
 // operator
 // ============================================================================
+// One launch of the band kernel over at most band_pass_terms(kb) terms (6 for
+// kb <= 2, 4 above); an operator with more (distinct) terms runs several
+// passes, the later ones adding to Y.
+struct OpPass {
+  int nt = 0, scaled_mask = 0, pattern = 0, n_rowblk = 0, n_tiles = 0;
+  double* d_left = nullptr;   // [ns_in][nt][2kb+1]: left bands by input row (transposed)
+  double* d_right = nullptr;  // [nt][2kb+1][qt]
+};
 struct mofem_op_s {
-  int kb = 0, nt = 0, qs = 0, qt = 0, ns_in = 0, nt_in = 0;
-  int off_s = 0, off_t = 0, ph_s = 0, full_input = 0, full_output = 0, pattern = 0, scaled_mask = 0;
-  int n_rowblk = 0, n_tiles = 0;
-  double* d_left = nullptr;
-  double* d_right = nullptr;
+  int kb = 0, qs = 0, qt = 0, ns_in = 0, nt_in = 0;
+  int off_s = 0, off_t = 0, ph_s = 0, full_input = 0, full_output = 0;
+  int n_terms = 0;              // distinct terms after merging
+  int n_pass = 0;
+  OpPass pass[2];               // at most 8 terms, at least 4 per pass
+  int n_tiles = 0;              // tiles of the last pass (the one that forms <X, Y>)
   double* d_partial = nullptr;  // dot partials for mofem_op_apply
   int partial_batch = 0;
 };
 
-static bool element_structured(const std::vector<double>& left, int qs, int nt, int kb, int ph) {
+// P_k element structure of the transposed left bands: input row a (node row
+// a - delta, element phase (a - delta) mod kb) feeds output rows a - off_s + e - kb
+// only for e inside the element(s) of that node
+static bool element_structured(const std::vector<double>& leftT, int n_in, int nt, int kb, int delta) {
   const int W = 2 * kb + 1;
-  for (int i = 0; i < qs; ++i) {
-    int g = i + ph;
-    int phase = g % kb;
+  for (int a = 0; a < n_in; ++a) {
+    int phase = (a - delta) % kb;
     int dlo = phase == 0 ? 0 : kb - phase, dhi = phase == 0 ? 2 * kb : 2 * kb - phase;
     for (int t = 0; t < nt; ++t)
       for (int d = 0; d < W; ++d)
-        if ((d < dlo || d > dhi) && left[((size_t)i * nt + t) * W + d] != 0.0) return false;
+        if ((d < dlo || d > dhi) && leftT[((size_t)a * nt + t) * W + d] != 0.0) return false;
   }
   return true;
 }
+
+namespace {
+// one term in the kernel's index space: left coefficients (coefficient folded
+// in) [qs][2kb+1] by output row, right coefficients [2kb+1][qt] by output column
+struct TermArrays {
+  std::vector<double> l, r;
+  int scaled;
+};
+}  // namespace
 
 extern "C" int mofem_op_create(const mofem_op_desc* desc, mofem_op_t* out) {
   clear_error();
@@ -214,8 +235,8 @@ extern "C" int mofem_op_create(const mofem_op_desc* desc, mofem_op_t* out) {
   *out = nullptr;
   const mofem_op_desc& D = *desc;
   if (D.kb < 1 || D.kb > 4) return fail(MOFEM_E_ARG, "op_create: kb must be 1..4");
-  if (D.n_terms < 1 || D.n_terms > MOFEM_MAX_TERMS || !band_supported_terms(D.n_terms))
-    return fail(MOFEM_E_ARG, "op_create: n_terms must be 1..6");
+  if (D.n_terms < 1 || D.n_terms > MOFEM_MAX_TERMS)
+    return fail(MOFEM_E_ARG, "op_create: n_terms must be 1..MOFEM_MAX_TERMS (8)");
   if ((D.trim_s != 0 && D.trim_s != 1) || (D.trim_t != 0 && D.trim_t != 1))
     return fail(MOFEM_E_ARG, "op_create: trim flags must be 0 or 1");
   if (D.n_s - 2 * D.trim_s < 1 || D.n_t - 2 * D.trim_t < 1 || D.n_s < D.kb + 1 || D.n_t < D.kb + 1)
@@ -224,18 +245,18 @@ extern "C" int mofem_op_create(const mofem_op_desc* desc, mofem_op_t* out) {
     if (!D.left[t] || !D.right[t]) return fail(MOFEM_E_ARG, "op_create: NULL band");
   if (D.full_input && D.full_output) return fail(MOFEM_E_ARG, "op_create: full_input and full_output exclude each other");
 
-  const int kb = D.kb, W = 2 * kb + 1, nt = D.n_terms;
+  const int kb = D.kb, W = 2 * kb + 1;
   const int ns = D.n_s, ntt = D.n_t;
   // output rows/columns: the unknowns, or all nodes for full_output
   const int qs = D.full_output ? ns : ns - 2 * D.trim_s, qt = D.full_output ? ntt : ntt - 2 * D.trim_t;
   const int row0 = D.full_output ? 0 : D.trim_s, col0 = D.full_output ? 0 : D.trim_t;  // node of output 0
-  std::vector<double> left((size_t)qs * nt * W, 0.0), right((size_t)nt * W * qt, 0.0);
-  int mask = 0;
-  for (int t = 0; t < nt; ++t) {
+  std::vector<TermArrays> terms;
+  for (int t = 0; t < D.n_terms; ++t) {
     const double* Lb = D.left[t];
     const double* Rb = D.right[t];
     const double c = D.coef[t];
-    if (D.scaled[t]) mask |= 1 << t;
+    TermArrays ta{std::vector<double>((size_t)qs * W, 0.0), std::vector<double>((size_t)W * qt, 0.0),
+                  D.scaled[t] ? 1 : 0};
     for (int i = 0; i < qs; ++i) {
       int gi = i + row0;
       for (int d = 0; d < W; ++d) {
@@ -243,7 +264,7 @@ extern "C" int mofem_op_create(const mofem_op_desc* desc, mofem_op_t* out) {
         bool ok = D.full_input ? (ga >= 0 && ga < ns) : (ga >= D.trim_s && ga < ns - D.trim_s);
         if (!ok) continue;
         double v = D.left_transpose[t] ? Lb[(size_t)(2 * kb - d) * ns + ga] : Lb[(size_t)d * ns + gi];
-        left[((size_t)i * nt + t) * W + d] = c * v;
+        ta.l[(size_t)i * W + d] = c * v;
       }
     }
     for (int j = 0; j < qt; ++j) {
@@ -254,52 +275,127 @@ extern "C" int mofem_op_create(const mofem_op_desc* desc, mofem_op_t* out) {
         if (!ok) continue;
         // coefficient R[gb][gj] (or R^T[gb][gj] = R[gj][gb])
         double v = D.right_transpose[t] ? Rb[(size_t)d * ntt + gj] : Rb[(size_t)(2 * kb - d) * ntt + gb];
-        right[((size_t)t * W + d) * qt + j] = v;
+        ta.r[(size_t)d * qt + j] = v;
       }
     }
+    for (double v : ta.l)
+      if (!std::isfinite(v)) return fail(MOFEM_E_NOTFINITE, "op_create: non-finite band entry");
+    for (double v : ta.r)
+      if (!std::isfinite(v)) return fail(MOFEM_E_NOTFINITE, "op_create: non-finite band entry");
+    // merge with an earlier term of the same scaling that shares a factor:
+    // L1 X R + L2 X R = (L1 + L2) X R, and L X R1 + L X R2 = L X (R1 + R2)
+    bool merged = false;
+    for (TermArrays& u : terms) {
+      if (u.scaled != ta.scaled) continue;
+      if (u.r == ta.r) {
+        for (size_t e = 0; e < u.l.size(); ++e) u.l[e] += ta.l[e];
+      } else if (u.l == ta.l) {
+        for (size_t e = 0; e < u.r.size(); ++e) u.r[e] += ta.r[e];
+      } else {
+        continue;
+      }
+      merged = true;
+      break;
+    }
+    if (!merged) terms.push_back(std::move(ta));
   }
-  for (double v : left)
-    if (!std::isfinite(v)) return fail(MOFEM_E_NOTFINITE, "op_create: non-finite band entry");
-  for (double v : right)
-    if (!std::isfinite(v)) return fail(MOFEM_E_NOTFINITE, "op_create: non-finite band entry");
-
+  // passes of at most band_pass_terms(kb) terms
+  const int n_terms = (int)terms.size();
+  const int per_pass = band_pass_terms(kb);
+  const int n_pass = (n_terms + per_pass - 1) / per_pass;
   auto* op = new mofem_op_s();
   op->kb = kb;
-  op->nt = nt;
   op->qs = qs;
   op->qt = qt;
   op->full_input = D.full_input;
   op->full_output = D.full_output;
+  op->n_terms = n_terms;
+  op->n_pass = n_pass;
   // input index of output (i, j) is (i + off_s, j + off_t)
   op->ns_in = D.full_input ? ns : ns - 2 * D.trim_s;
   op->nt_in = D.full_input ? ntt : ntt - 2 * D.trim_t;
   op->off_s = D.full_input ? D.trim_s : (D.full_output ? -D.trim_s : 0);
   op->off_t = D.full_input ? D.trim_t : (D.full_output ? -D.trim_t : 0);
   op->ph_s = row0;
-  op->scaled_mask = mask;
-  op->pattern = (D.elem_order >= 2 && D.elem_order == kb && element_structured(left, qs, nt, kb, op->ph_s)) ? 1 : 0;
-  int TI = band_rows_per_block(kb, nt), SW = band_cols_per_block(kb);
-  op->n_rowblk = (qs + op->ph_s + TI - 1) / TI;
-  op->n_tiles = ((qt + SW - 1) / SW) * op->n_rowblk;
-  int rc = dev_alloc(&op->d_left, left.size());
-  if (rc == MOFEM_OK) rc = dev_alloc(&op->d_right, right.size());
-  if (rc != MOFEM_OK) {
-    mofem_op_destroy(op);
-    return rc;
+  int t0 = 0;
+  for (int ps = 0; ps < n_pass; ++ps) {
+    // split evenly: 7 terms run as 4 + 3, 8 as 4 + 4 (5 as 3 + 2 when kb >= 3)
+    const int take = (n_terms - t0 + (n_pass - ps) - 1) / (n_pass - ps);
+    const int nt = take;
+    // left bands transposed, by input row a: leftT[a][t][e] is the coefficient
+    // of input row a in output row i = a - off_s + e - kb, i.e. L_t[i][2kb - e]
+    // of the row layout (zero where i is not an output row)
+    const int n_in = op->ns_in;
+    std::vector<double> leftT((size_t)n_in * nt * W, 0.0), right((size_t)nt * W * qt, 0.0);
+    int mask = 0;
+    for (int t = 0; t < take; ++t) {
+      const TermArrays& ta = terms[t0 + t];
+      if (ta.scaled) mask |= 1 << t;
+      for (int ar = 0; ar < n_in; ++ar)
+        for (int e = 0; e < W; ++e) {
+          const int i = ar - op->off_s + e - kb;
+          if (i >= 0 && i < qs) leftT[((size_t)ar * nt + t) * W + e] = ta.l[(size_t)i * W + (2 * kb - e)];
+        }
+      // right bands in difference form: the centre slot holds the column sum
+      // (the kernel forms sum_{d != kb} R[d] (x[d] - x[kb]) + (sum_d R[d]) x[kb])
+      for (int j = 0; j < qt; ++j) {
+        long double sum = 0.0L;
+        for (int d = 0; d < W; ++d) sum += ta.r[(size_t)d * qt + j];
+        for (int d = 0; d < W; ++d)
+          right[((size_t)t * W + d) * qt + j] = d == kb ? (double)sum : ta.r[(size_t)d * qt + j];
+      }
+    }
+    OpPass& P = op->pass[ps];
+    P.nt = nt;
+    P.scaled_mask = mask;
+    P.pattern = (D.elem_order >= 2 && D.elem_order == kb &&
+                 element_structured(leftT, n_in, nt, kb, op->off_s - op->ph_s)) ? 1 : 0;
+    // left bands in telescoped form: output row i with coefficients c_k on its
+    // input rows (k = 0 .. 2kb, the row layout's d) and first coupled k_lo
+    // (0, or kb - phase for an element-interior node when the element
+    // structure is used) takes the suffix sums S_k = sum_{k' >= k} c_k' for
+    // k >= k_lo and 0 below; slot e of input row a carries S_{2kb - e}
+    std::fill(leftT.begin(), leftT.end(), 0.0);
+    for (int t = 0; t < take; ++t) {
+      const TermArrays& ta = terms[t0 + t];
+      for (int i = 0; i < qs; ++i) {
+        const int phase = (i + op->ph_s) % kb;
+        const int klo = (!P.pattern || phase == 0) ? 0 : kb - phase;
+        long double suffix = 0.0L;
+        for (int k = 2 * kb; k >= klo; --k) {
+          suffix += ta.l[(size_t)i * W + k];
+          const int ar = i + op->off_s + k - kb;  // input row of slot e = 2kb - k
+          if (ar >= 0 && ar < n_in) leftT[((size_t)ar * nt + t) * W + (2 * kb - k)] = (double)suffix;
+        }
+      }
+    }
+    t0 += take;
+    int TI = band_rows_per_block(kb, nt), SW = band_cols_per_block(kb);
+    P.n_rowblk = (qs + op->ph_s + TI - 1) / TI;
+    P.n_tiles = ((qt + SW - 1) / SW) * P.n_rowblk;
+    int rc = dev_alloc(&P.d_left, leftT.size());
+    if (rc == MOFEM_OK) rc = dev_alloc(&P.d_right, right.size());
+    if (rc != MOFEM_OK) {
+      mofem_op_destroy(op);
+      return rc;
+    }
+    if (hipMemcpy(P.d_left, leftT.data(), leftT.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(P.d_right, right.data(), right.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+      mofem_op_destroy(op);
+      return fail(MOFEM_E_HIP, "op_create: upload failed");
+    }
   }
-  if (hipMemcpy(op->d_left, left.data(), left.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(op->d_right, right.data(), right.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
-    mofem_op_destroy(op);
-    return fail(MOFEM_E_HIP, "op_create: upload failed");
-  }
+  op->n_tiles = op->pass[n_pass - 1].n_tiles;
   *out = op;
   return MOFEM_OK;
 }
 
 extern "C" int mofem_op_destroy(mofem_op_t op) {
   if (!op) return MOFEM_OK;
-  if (op->d_left) (void)hipFree(op->d_left);
-  if (op->d_right) (void)hipFree(op->d_right);
+  for (OpPass& P : op->pass) {
+    if (P.d_left) (void)hipFree(P.d_left);
+    if (P.d_right) (void)hipFree(P.d_right);
+  }
   if (op->d_partial) (void)hipFree(op->d_partial);
   delete op;
   return MOFEM_OK;
@@ -320,32 +416,38 @@ int op_launch(mofem_op_t op, const double* X, long long in_stride, double* Y, lo
               const double* item_scale, double* partial, const int* active, hipStream_t s,
               int n_items = -1) {
   TraceScope trace(MOFEM_TRACE_BAND, n_items < 0 ? batch : n_items, s);
-  BandArgs a{};
-  a.X = X;
-  a.in_stride = in_stride;
-  a.ld_x = op->nt_in;
-  a.Y = Y;
-  a.out_stride = stride;
-  a.ld_y = op->qt;
-  a.qs = op->qs;
-  a.qt = op->qt;
-  a.ns_in = op->ns_in;
-  a.nt_in = op->nt_in;
-  a.off_s = op->off_s;
-  a.off_t = op->off_t;
-  a.ph_s = op->ph_s;
-  a.n_rowblk = op->n_rowblk;
-  a.left = op->d_left;
-  a.right = op->d_right;
-  a.scaled_mask = op->scaled_mask;
-  a.item_scale = item_scale;
-  a.dot_partial = partial;
-  a.n_partial = op->n_tiles;
-  a.active = active;
-  if (launch_band_apply(a, op->kb, op->nt, batch, op->pattern != 0, s) != 0)
-    return fail(MOFEM_E_UNSUPPORTED, "op_apply: unsupported band/term combination");
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return fail(MOFEM_E_HIP, std::string("op_apply launch: ") + hipGetErrorString(e));
+  for (int ps = 0; ps < op->n_pass; ++ps) {
+    const OpPass& P = op->pass[ps];
+    const bool last = ps == op->n_pass - 1;
+    BandArgs a{};
+    a.X = X;
+    a.in_stride = in_stride;
+    a.ld_x = op->nt_in;
+    a.Y = Y;
+    a.out_stride = stride;
+    a.ld_y = op->qt;
+    a.qs = op->qs;
+    a.qt = op->qt;
+    a.ns_in = op->ns_in;
+    a.nt_in = op->nt_in;
+    a.off_s = op->off_s;
+    a.off_t = op->off_t;
+    a.ph_s = op->ph_s;
+    a.n_rowblk = P.n_rowblk;
+    a.left = P.d_left;
+    a.right = P.d_right;
+    a.scaled_mask = P.scaled_mask;
+    a.item_scale = item_scale;
+    a.dot_partial = last ? partial : nullptr;
+    a.n_partial = P.n_tiles;
+    a.active = active;
+    a.accumulate = ps > 0;  // later passes add to the earlier passes' Y
+    a.batch = batch;
+    if (launch_band_apply(a, op->kb, P.nt, batch, P.pattern != 0, s) != 0)
+      return fail(MOFEM_E_UNSUPPORTED, "op_apply: unsupported band/term combination");
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(MOFEM_E_HIP, std::string("op_apply launch: ") + hipGetErrorString(e));
+  }
   return MOFEM_OK;
 }
 }  // namespace
@@ -403,6 +505,7 @@ struct mofem_prec_s {
   // product preconditioner by banded Cholesky (mofem_prec_setup_banded)
   int banded = 0, kb = 0, n_sets = 0;
   double *Lf_s = nullptr, *Lb_s = nullptr, *Lf_t = nullptr, *Lb_t = nullptr, *scales = nullptr;
+  std::vector<double> h_scales;  // host copy of the factor pairs' scales
 };
 
 namespace {
@@ -503,10 +606,34 @@ extern "C" int mofem_prec_setup(const mofem_prec_desc* desc, mofem_prec_t* out) 
   std::vector<double> Vs((size_t)qs * qs), Vt((size_t)qt * qt);
   p->h_lam.resize(qs);
   p->h_mu.resize(qt);
+  // the two one-dimensional decompositions are independent: the t pencil runs
+  // on a second host thread (or is copied when it equals the s pencil, as on
+  // the square of eq. (28))
+  const size_t nbs = (size_t)(2 * D.kb + 1) * D.n_s;
+  const bool same = D.n_s == D.n_t && D.trim_s == D.trim_t &&
+                    std::memcmp(D.Ks, D.Kt, nbs * sizeof(double)) == 0 &&
+                    std::memcmp(D.Ms, D.Mt, nbs * sizeof(double)) == 0;
+  int rc_t = MOFEM_OK;
+  std::string msg_t;
+  std::thread worker;
+  if (!same) {
+    worker = std::thread([&]() {
+      rc_t = mofem_geneig_host(D.n_t, D.kb, D.Kt, D.Mt, D.trim_t, p->h_mu.data(), Vt.data());
+      if (rc_t != MOFEM_OK) msg_t = mofem_last_error();  // thread-local message of the worker
+    });
+  }
   int rc = mofem_geneig_host(D.n_s, D.kb, D.Ks, D.Ms, D.trim_s, p->h_lam.data(), Vs.data());
-  if (rc == MOFEM_OK) rc = mofem_geneig_host(D.n_t, D.kb, D.Kt, D.Mt, D.trim_t, p->h_mu.data(), Vt.data());
+  std::string msg = rc != MOFEM_OK ? std::string(mofem_last_error()) : std::string();
+  if (worker.joinable()) worker.join();
+  if (same && rc == MOFEM_OK) {
+    p->h_mu = p->h_lam;
+    Vt = Vs;
+  }
+  if (rc == MOFEM_OK && rc_t != MOFEM_OK) {
+    rc = rc_t;
+    msg = msg_t;
+  }
   if (rc != MOFEM_OK) {
-    std::string msg = mofem_last_error();
     mofem_prec_destroy(p);
     return fail(rc, "prec_setup: " + msg);
   }
@@ -587,15 +714,27 @@ extern "C" int mofem_prec_setup_banded(const mofem_bprec_desc* desc, mofem_prec_
   *out = nullptr;
   const mofem_bprec_desc& D = *desc;
   if (D.kb < 1 || D.kb > 4) return fail(MOFEM_E_ARG, "prec_setup_banded: kb must be 1..4");
-  if (!D.Ks || !D.Kt || (D.a != 0.0 && (!D.Ms || !D.Mt))) return fail(MOFEM_E_ARG, "prec_setup_banded: NULL band");
+  for (const mofem_band_sum* bs : {&D.Ks, &D.Ms, &D.Kt, &D.Mt}) {
+    if (bs->n < 0 || bs->n > MOFEM_MAX_BAND_SUM) return fail(MOFEM_E_ARG, "prec_setup_banded: band sum of 0..4 terms");
+    for (int i = 0; i < bs->n; ++i)
+      if (!bs->band[i]) return fail(MOFEM_E_ARG, "prec_setup_banded: NULL band");
+  }
+  if (D.Ks.n < 1 || D.Kt.n < 1 || (D.a != 0.0 && (D.Ms.n < 1 || D.Mt.n < 1)))
+    return fail(MOFEM_E_ARG, "prec_setup_banded: Ks and Kt (and Ms, Mt when a != 0) need at least one band");
   if ((D.trim_s != 0 && D.trim_s != 1) || (D.trim_t != 0 && D.trim_t != 1))
     return fail(MOFEM_E_ARG, "prec_setup_banded: trim flags must be 0 or 1");
   if (D.n_scales < 1 || D.n_scales > MOFEM_MAX_SCALES) return fail(MOFEM_E_ARG, "prec_setup_banded: n_scales 1..8");
   const int qs = D.n_s - 2 * D.trim_s, qt = D.n_t - 2 * D.trim_t;
   if (qs < 1 || qt < 1) return fail(MOFEM_E_ARG, "prec_setup_banded: empty matrices");
   const int kb = D.kb, w = 2 * kb + 1, c = kb + 1;
-  // interior band rows of a Ms + sc b Ks (DIA input: band[d * n + i] = K[i][i + d - kb])
-  auto combine = [&](int n, int trim, const double* K, const double* M, double b, double sc) {
+  // entry (DIA offset d, node i) of a band sum (DIA input: band[d * n + i] = K[i][i + d - kb])
+  auto entry = [](const mofem_band_sum& B, size_t at) {
+    double v = 0.0;
+    for (int t = 0; t < B.n; ++t) v += B.coef[t] * B.band[t][at];
+    return v;
+  };
+  // interior band rows of a Ms + sc b Ks
+  auto combine = [&](int n, int trim, const mofem_band_sum& K, const mofem_band_sum& M, double b, double sc) {
     const int q = n - 2 * trim;
     std::vector<double> S((size_t)q * w, 0.0);
     for (int i = 0; i < q; ++i)
@@ -603,7 +742,7 @@ extern "C" int mofem_prec_setup_banded(const mofem_bprec_desc* desc, mofem_prec_
         const int j = i + d - kb;
         if (j < 0 || j >= q) continue;
         const size_t at = (size_t)d * n + i + trim;
-        S[(size_t)i * w + d] = (D.a != 0.0 ? D.a * M[at] : 0.0) + sc * b * K[at];
+        S[(size_t)i * w + d] = (D.a != 0.0 ? D.a * entry(M, at) : 0.0) + sc * b * entry(K, at);
       }
     return S;
   };
@@ -635,6 +774,7 @@ extern "C" int mofem_prec_setup_banded(const mofem_bprec_desc* desc, mofem_prec_
     mofem_prec_destroy(p);
     return rc;
   }
+  p->h_scales = sc;
   *out = p;
   return MOFEM_OK;
 }
@@ -1507,6 +1647,17 @@ extern "C" size_t mofem_imex_workspace_size(const mofem_imex_desc* d, int batch)
 }
 
 namespace {
+// a banded product preconditioner must hold a factor pair for every c = d tau
+int check_imex_scales(const mofem_imex_desc* d, const char* who) {
+  if (!d->prec->banded) return MOFEM_OK;
+  const std::vector<double>& sc = d->prec->h_scales;
+  for (int sp = 0; sp < d->n_species; ++sp)
+    if (std::find(sc.begin(), sc.end(), d->d[sp] * d->tau) == sc.end())
+      return fail(MOFEM_E_ARG, std::string(who) + ": the banded preconditioner has no factor pair for the scale "
+                                   "d * tau of species " + std::to_string(sp));
+  return MOFEM_OK;
+}
+
 int imex_check(const mofem_imex_desc* d, const double* state, long long stride, int batch) {
   if (!d || !state || !d->op || !d->prec || !d->mass) return fail(MOFEM_E_ARG, "imex_step: NULL argument");
   if (d->n_species < 1 || d->n_species > 2) return fail(MOFEM_E_ARG, "imex_step: n_species must be 1 or 2");
@@ -1519,7 +1670,7 @@ int imex_check(const mofem_imex_desc* d, const double* state, long long stride, 
     return fail(MOFEM_E_ARG, "imex_step: mass operator must map unknowns to unknowns of the same shape");
   if (stride != (long long)op->qs * op->qt)
     return fail(MOFEM_E_ARG, "imex_step: items must be contiguous (stride = q_s * q_t)");
-  return MOFEM_OK;
+  return check_imex_scales(d, "imex_step");
 }
 
 struct ImexParts {
@@ -1757,6 +1908,7 @@ extern "C" int mofem_imex_adjoint_step(const mofem_imex_desc* d, mofem_op_t stif
       return fail(MOFEM_E_ARG, "imex_adjoint_step: mass and stiffness must map unknowns to unknowns of one shape");
   const long long n = (long long)op->qs * op->qt;
   if (stride != n) return fail(MOFEM_E_ARG, "imex_adjoint_step: items must be contiguous (stride = q_s * q_t)");
+  if (int rc0 = check_imex_scales(d, "imex_adjoint_step")) return rc0;
   const int items = d->n_species * batch;
   hipStream_t s = (hipStream_t)stream;
   const size_t need = mofem_imex_adjoint_workspace_size(d, batch);

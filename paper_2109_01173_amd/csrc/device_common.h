@@ -38,6 +38,21 @@ __device__ __forceinline__ double wave_shr1(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// Immediate of s_waitcnt on gfx9-family GPUs such as gfx950: vmcnt in bits
+// 3:0 and 15:14, expcnt in bits 6:4, lgkmcnt in bits 11:8; a field at its
+// maximum (63, 7, 15) does not wait.  Other GPU families encode these fields
+// differently, so device code using it builds for gfx950 only.
+#if defined(__HIP_DEVICE_COMPILE__) && !defined(__gfx950__)
+#error "s_waitcnt immediates below are encoded for gfx950"
+#endif
+constexpr unsigned waitcnt_imm(unsigned vmcnt, unsigned expcnt, unsigned lgkmcnt) {
+  return (vmcnt & 0xFu) | (((vmcnt >> 4) & 0x3u) << 14) | ((expcnt & 0x7u) << 4) | ((lgkmcnt & 0xFu) << 8);
+}
+// wait until this wave's vector memory operations (loads, stores and direct
+// global -> LDS loads) have completed; LDS and export counters unconstrained
+constexpr unsigned kWaitVmcnt0 = waitcnt_imm(0, 7, 15);
+static_assert(kWaitVmcnt0 == 0x0F70u, "vmcnt(0), expcnt(7), lgkmcnt(15)");
+
 // Sum over the 64 lanes of a wave (every lane receives the total).
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

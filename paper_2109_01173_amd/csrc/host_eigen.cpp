@@ -169,7 +169,11 @@ struct Rot {
 
 // Implicit QL on the tridiagonal (d, e); appends every Givens rotation
 // (acting on eigenvector-matrix rows i, i+1) to `rots`.  Returns false if an
-// eigenvalue needs more than 60 sweeps.
+// eigenvalue needs more than 60 sweeps.  The sweep is the published implicit
+// QL algorithm with Wilkinson-type shifts (Bowdler, Martin, Reinsch and
+// Wilkinson, "The QR and QL algorithms for symmetric matrices", Numer. Math.
+// 11 (1968), as distributed in EISPACK's tql2), so its step order follows that
+// algorithm.
 bool ql_implicit(int n, double* d, double* e, std::vector<Rot>& rots) {
   const double eps = std::numeric_limits<double>::epsilon();
   for (int l = 0; l < n; ++l) {

@@ -4,16 +4,26 @@
 
 namespace mofem {
 
-#define MOFEM_BAND_EXTERN(KB)                                                         \
-  extern template void launch_kb_nt<KB, 1>(const BandArgs&, int, bool, hipStream_t); \
-  extern template void launch_kb_nt<KB, 2>(const BandArgs&, int, bool, hipStream_t); \
-  extern template void launch_kb_nt<KB, 3>(const BandArgs&, int, bool, hipStream_t); \
-  extern template void launch_kb_nt<KB, 5>(const BandArgs&, int, bool, hipStream_t); \
-  extern template void launch_kb_nt<KB, 6>(const BandArgs&, int, bool, hipStream_t);
-MOFEM_BAND_EXTERN(1)
-MOFEM_BAND_EXTERN(2)
-MOFEM_BAND_EXTERN(3)
-MOFEM_BAND_EXTERN(4)
+#define MOFEM_BAND_EXTERN_NT(KB, NT)                                                             \
+  extern template void launch_kb_nt<KB, NT, false, 1>(const BandArgs&, int, bool, hipStream_t);  \
+  extern template void launch_kb_nt<KB, NT, false, 2>(const BandArgs&, int, bool, hipStream_t);
+#define MOFEM_BAND_EXTERN_COMMON(KB)                                                            \
+  MOFEM_BAND_EXTERN_NT(KB, 1)                                                                   \
+  MOFEM_BAND_EXTERN_NT(KB, 2)                                                                   \
+  MOFEM_BAND_EXTERN_NT(KB, 3)                                                                   \
+  MOFEM_BAND_EXTERN_NT(KB, 4)                                                                   \
+  extern template void launch_kb_nt<KB, 2, true, 1>(const BandArgs&, int, bool, hipStream_t);   \
+  extern template void launch_kb_nt<KB, 3, true, 1>(const BandArgs&, int, bool, hipStream_t);   \
+  extern template void launch_kb_nt<KB, 4, true, 1>(const BandArgs&, int, bool, hipStream_t);
+#define MOFEM_BAND_EXTERN_WIDE(KB) \
+  MOFEM_BAND_EXTERN_NT(KB, 5)      \
+  MOFEM_BAND_EXTERN_NT(KB, 6)
+MOFEM_BAND_EXTERN_COMMON(1)
+MOFEM_BAND_EXTERN_COMMON(2)
+MOFEM_BAND_EXTERN_COMMON(3)
+MOFEM_BAND_EXTERN_COMMON(4)
+MOFEM_BAND_EXTERN_WIDE(1)
+MOFEM_BAND_EXTERN_WIDE(2)
 
 template <int KB>
 static int rows_kb(int nt) {
@@ -21,8 +31,9 @@ static int rows_kb(int nt) {
     case 1: return BandCfg<KB, 1>::TI;
     case 2: return BandCfg<KB, 2>::TI;
     case 3: return BandCfg<KB, 3>::TI;
+    case 4: return BandCfg<KB, 4>::TI;
     case 5: return BandCfg<KB, 5>::TI;
-    default: return BandCfg<KB, 6>::TI;
+    default: return BandCfg<KB, 6>::TI;  // (layout only; KB >= 3 runs at most 4 terms per launch)
   }
 }
 int band_rows_per_block(int kb, int nt) {
@@ -34,18 +45,42 @@ int band_rows_per_block(int kb, int nt) {
   }
 }
 int band_cols_per_block(int kb) { return kBandWaves * (64 - 2 * kb); }
-int band_supported_terms(int nt) { return nt == 1 || nt == 2 || nt == 3 || nt == 5 || nt == 6; }
+int band_pass_terms(int kb) { return band_max_pass_terms(kb); }
 
+template <int KB, int IPL>
+static int launch_kb_ipl(const BandArgs& a, int nt, int batch, bool pat, hipStream_t s) {
+  switch (nt) {
+    case 1: launch_kb_nt<KB, 1, false, IPL>(a, batch, pat, s); return 0;
+    case 2: launch_kb_nt<KB, 2, false, IPL>(a, batch, pat, s); return 0;
+    case 3: launch_kb_nt<KB, 3, false, IPL>(a, batch, pat, s); return 0;
+    case 4: launch_kb_nt<KB, 4, false, IPL>(a, batch, pat, s); return 0;
+    default: break;
+  }
+  if constexpr (KB <= 2) {
+    switch (nt) {
+      case 5: launch_kb_nt<KB, 5, false, IPL>(a, batch, pat, s); return 0;
+      case 6: launch_kb_nt<KB, 6, false, IPL>(a, batch, pat, s); return 0;
+      default: break;
+    }
+  }
+  return -1;
+}
+
+// Two items per lane when the batch has at least two items and every item
+// sees the same operator (no per-item scale on a scaled term).
 template <int KB>
 static int launch_kb(const BandArgs& a, int nt, int batch, bool pat, hipStream_t s) {
-  switch (nt) {
-    case 1: launch_kb_nt<KB, 1>(a, batch, pat, s); return 0;
-    case 2: launch_kb_nt<KB, 2>(a, batch, pat, s); return 0;
-    case 3: launch_kb_nt<KB, 3>(a, batch, pat, s); return 0;
-    case 5: launch_kb_nt<KB, 5>(a, batch, pat, s); return 0;
-    case 6: launch_kb_nt<KB, 6>(a, batch, pat, s); return 0;
-    default: return -1;
+  if (nt > band_max_pass_terms(KB)) return -1;
+  if (a.accumulate) {
+    switch (nt) {
+      case 2: launch_kb_nt<KB, 2, true, 1>(a, batch, pat, s); return 0;
+      case 3: launch_kb_nt<KB, 3, true, 1>(a, batch, pat, s); return 0;
+      case 4: launch_kb_nt<KB, 4, true, 1>(a, batch, pat, s); return 0;
+      default: return -1;
+    }
   }
+  const bool shared = batch >= 2 && (a.scaled_mask == 0 || a.item_scale == nullptr);
+  return shared ? launch_kb_ipl<KB, 2>(a, nt, batch, pat, s) : launch_kb_ipl<KB, 1>(a, nt, batch, pat, s);
 }
 
 int launch_band_apply(const BandArgs& a, int kb, int nt, int batch, bool pattern, hipStream_t s) {

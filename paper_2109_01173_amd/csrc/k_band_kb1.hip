@@ -2,5 +2,6 @@
 #include "band_kernel.inl"
 
 namespace mofem {
-MOFEM_BAND_INSTANTIATE(1)
+MOFEM_BAND_INSTANTIATE_COMMON(1)
+MOFEM_BAND_INSTANTIATE_WIDE(1)
 }  // namespace mofem

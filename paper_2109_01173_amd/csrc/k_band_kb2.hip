@@ -2,5 +2,6 @@
 #include "band_kernel.inl"
 
 namespace mofem {
-MOFEM_BAND_INSTANTIATE(2)
+MOFEM_BAND_INSTANTIATE_COMMON(2)
+MOFEM_BAND_INSTANTIATE_WIDE(2)
 }  // namespace mofem

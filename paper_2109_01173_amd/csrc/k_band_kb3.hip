@@ -2,5 +2,6 @@
 #include "band_kernel.inl"
 
 namespace mofem {
-MOFEM_BAND_INSTANTIATE(3)
+MOFEM_BAND_INSTANTIATE_COMMON(3)
+
 }  // namespace mofem

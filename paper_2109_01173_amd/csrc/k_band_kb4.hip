@@ -2,5 +2,6 @@
 #include "band_kernel.inl"
 
 namespace mofem {
-MOFEM_BAND_INSTANTIATE(4)
+MOFEM_BAND_INSTANTIATE_COMMON(4)
+
 }  // namespace mofem

@@ -27,11 +27,12 @@ namespace {
 constexpr int kCols = 64;  // columns per block (one wave)
 constexpr int kCh = 16;    // rows per register chunk (a divisor of kCols)
 
+// index of the factor pair whose scale equals the item's scale, -1 if none
 __device__ __forceinline__ int factor_set(const BcholArgs& a, int b) {
   const double s = a.item_scale ? a.item_scale[b] : 1.0;
   for (int j = 0; j < a.n_sets; ++j)
     if (a.scales[j] == s) return j;
-  return 0;
+  return -1;
 }
 }  // namespace
 
@@ -41,7 +42,11 @@ __global__ __launch_bounds__(kCols) void bchol_kernel(BcholArgs a) {
   const int b = blockIdx.y;
   if (a.active && !a.active[b]) return;
   const int n = a.n_rows;
-  const int set = factor_set(a, b);
+  // an item whose scale has no factor pair gets a NaN result (the solve then
+  // stops with MOFEM_E_NOTFINITE) instead of another pair's preconditioner
+  const int found = factor_set(a, b);
+  const bool unmatched = found < 0;
+  const int set = unmatched ? 0 : found;
   const double* __restrict__ Lf = a.Lf + (size_t)set * n * (KB + 1);
   const double* __restrict__ Lb = a.Lb + (size_t)set * n * (KB + 1);
   const int lane = threadIdx.x;
@@ -132,7 +137,7 @@ __global__ __launch_bounds__(kCols) void bchol_kernel(BcholArgs a) {
     const int row = r0 + lane;
     if (row < n) {
       for (int c = 0; c < kCols && col0 + c < a.n_cols; ++c)
-        out[(size_t)(col0 + c) * a.ld_o + row] = tile[lane][c];
+        out[(size_t)(col0 + c) * a.ld_o + row] = unmatched ? __builtin_nan("") : tile[lane][c];
     }
     __syncthreads();
   }

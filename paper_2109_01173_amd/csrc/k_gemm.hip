@@ -434,7 +434,7 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
   };
   dma(0);
   for (int kt = 0; kt < nk; ++kt) {
-    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's loads of tile kt landed
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);  // this wave's loads of tile kt landed
     __syncthreads();                     // and every wave's
     read();
     __syncthreads();                     // every wave holds its fragments: the stage is free

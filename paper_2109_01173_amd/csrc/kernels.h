@@ -22,17 +22,20 @@ struct BandArgs {
   int off_s, off_t;        // input index of output (i, j): (i + off_s, j + off_t)
   int ph_s;                // node index of output row i is i + ph_s
   int n_rowblk;            // row blocks per item (band_rows_per_block rows each)
-  const double* left;      // [qs][nt][2kb+1] row bands (input row i+off_s+d-kb)
+  const double* left;      // [ns_in][nt][2kb+1] left bands by input row a: coefficient of
+                           // output row a - off_s + e - kb (transposed on the host)
   const double* right;     // [nt][2kb+1][qt] column bands (input col j+off_t+d-kb)
   int scaled_mask;         // bit t: term t times item_scale[b]
   const double* item_scale;  // [batch] or null
   double* dot_partial;     // [batch][n_partial] or null: <X, Y> per tile
   int n_partial;           // tiles per item
   const int* active;       // [batch] or null: skip items with active[b] == 0
+  int accumulate;          // 1: Y += result (a later pass of a many-term operator)
+  int batch;               // items (the launch may pair them: two per lane)
 };
 int band_rows_per_block(int kb, int nt);
 int band_cols_per_block(int kb);
-int band_supported_terms(int nt);
+int band_pass_terms(int kb);  // terms one launch takes (more run as passes)
 int launch_band_apply(const BandArgs& a, int kb, int nt, int batch, bool pattern, hipStream_t s);
 
 // ---- banded Cholesky solves of the product preconditioners (k_bchol.hip) -----

@@ -70,10 +70,17 @@ class PrecDesc(ctypes.Structure):
                 ("precision", ctypes.c_int)]
 
 
+MAX_BAND_SUM = 4
+
+
+class BandSum(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("band", _vp * MAX_BAND_SUM), ("coef", ctypes.c_double * MAX_BAND_SUM)]
+
+
 class BPrecDesc(ctypes.Structure):
     _fields_ = [("kb", ctypes.c_int), ("n_s", ctypes.c_int), ("n_t", ctypes.c_int),
                 ("trim_s", ctypes.c_int), ("trim_t", ctypes.c_int),
-                ("Ks", _vp), ("Ms", _vp), ("Kt", _vp), ("Mt", _vp),
+                ("Ks", BandSum), ("Ms", BandSum), ("Kt", BandSum), ("Mt", BandSum),
                 ("a", ctypes.c_double), ("bs", ctypes.c_double), ("bt", ctypes.c_double),
                 ("n_scales", ctypes.c_int), ("scales", ctypes.c_double * MAX_SCALES)]
 
@@ -278,6 +285,8 @@ class Operator:
 
     def __init__(self, terms, n_s, n_t, kb, trim_s=0, trim_t=0, full_input=False, elem_order=0,
                  full_output=False):
+        if not 1 <= len(terms) <= MAX_TERMS:
+            raise ValueError("an operator has 1..%d terms" % MAX_TERMS)
         d = OpDesc()
         d.kb, d.elem_order, d.n_s, d.n_t = kb, elem_order, n_s, n_t
         d.trim_s, d.trim_t, d.full_input, d.n_terms = trim_s, trim_t, int(full_input), len(terms)
@@ -310,19 +319,24 @@ class Operator:
             self.handle = None
 
     def apply(self, X, Y=None, item_scale=None, dot=False, stream=None):
+        """Y = L(X) per item (mofem_op_apply); dot=True (or a device buffer)
+        also returns <X_b, Y_b>."""
         torch = _torch()
         batch = X.shape[0]
         if tuple(X.shape[1:]) != self.in_shape:
             raise ValueError("input shape %s, operator expects %s" % (tuple(X.shape[1:]), self.in_shape))
         if Y is None:
             Y = torch.empty((batch,) + self.shape, dtype=torch.float64, device=X.device)
-        dots = torch.empty(batch, dtype=torch.float64, device=X.device) if dot else None
+        if dot is True:
+            dots = torch.empty(batch, dtype=torch.float64, device=X.device)
+        else:
+            dots = dot if dot is not False else None
         in_stride = self.in_shape[0] * self.in_shape[1]
         out_stride = self.shape[0] * self.shape[1]
-        rc = mofem_op_apply(self.handle, _dptr(X), in_stride, _dptr(Y), out_stride, batch,
-                            _dptr(item_scale), _dptr(dots), _stream(stream))
+        rc = mofem_op_apply(self.handle, _dptr(X), in_stride, _dptr(Y), out_stride, batch, _dptr(item_scale),
+                            _dptr(dots), _stream(stream))
         _check(rc, "mofem_op_apply")
-        return (Y, dots) if dot else Y
+        return (Y, dots) if dots is not None else Y
 
 
 class Preconditioner:
@@ -409,23 +423,42 @@ class Preconditioner:
 class BandedPreconditioner(Preconditioner):
     """Product preconditioner P_j(U) = S_j U T_j with S_j = a Ms + c_j bs Ks and
     T_j = a Mt + c_j bt Kt, applied by banded Cholesky solves
-    (mofem_prec_setup_banded); FP64 only.  Ms, Mt may be None when a == 0."""
+    (mofem_prec_setup_banded); FP64 only.  Each of Ks, Ms, Kt, Mt is a DIA band
+    or a list of (band, coefficient) pairs whose sum the library forms (e.g.
+    eq. (80)'s A + B2); Ms, Mt may be None when a == 0."""
 
     def __init__(self, Ks, Ms, Kt, Mt, a=0.0, bs=1.0, bt=1.0, scales=(1.0,), trim_s=0, trim_t=0):
         if not 1 <= len(scales) <= MAX_SCALES:
             raise ValueError("1..%d scales" % MAX_SCALES)
         d = BPrecDesc()
-        keep = [None if x is None else np.ascontiguousarray(x, dtype=np.float64) for x in (Ks, Ms, Kt, Mt)]
-        d.kb = (keep[0].shape[0] - 1) // 2
-        d.n_s, d.n_t = keep[0].shape[1], keep[2].shape[1]
+        self._keep = []
+
+        def fill(dst, spec):
+            terms = [] if spec is None else (list(spec) if isinstance(spec, (list, tuple)) else [(spec, 1.0)])
+            if len(terms) > MAX_BAND_SUM:
+                raise ValueError("at most %d bands in a sum" % MAX_BAND_SUM)
+            dst.n = len(terms)
+            for i, (band, coef) in enumerate(terms):
+                arr = np.ascontiguousarray(band, dtype=np.float64)
+                self._keep.append(arr)
+                dst.band[i] = arr.ctypes.data
+                dst.coef[i] = float(coef)
+            return [np.asarray(b) for b, _ in terms]
+
+        ks = fill(d.Ks, Ks)
+        fill(d.Ms, Ms)
+        kt = fill(d.Kt, Kt)
+        fill(d.Mt, Mt)
+        d.kb = (ks[0].shape[0] - 1) // 2
+        d.n_s, d.n_t = ks[0].shape[1], kt[0].shape[1]
         d.trim_s, d.trim_t = trim_s, trim_t
-        d.Ks, d.Ms, d.Kt, d.Mt = (None if x is None else x.ctypes.data for x in keep)
         d.a, d.bs, d.bt = float(a), float(bs), float(bt)
         d.n_scales = len(scales)
         for j, c in enumerate(scales):
             d.scales[j] = float(c)
         h = _vp()
         _check(mofem_prec_setup_banded(ctypes.byref(d), ctypes.byref(h)), "mofem_prec_setup_banded")
+        self._keep = None
         self.handle = h
         self.shape = (d.n_s - 2 * trim_s, d.n_t - 2 * trim_t)
         self.precision = PREC_F64

@@ -2,10 +2,9 @@
 
 Only bookkeeping happens here: which assembled 1D matrix goes into which term
 of the multiterm operator.  Assembly (``mofem_assemble_1d``), the
-eigen-decomposition and every apply/solve run in libmofem.  The only
-arithmetic done in Python is setup-time sums of assembled bands (B1 + gamma M3,
-the left factor of one elliptic term, and A + B2 of the product
-preconditioner), O(k n) numbers.
+eigen-decomposition, every sum of bands (the library merges terms that share
+a factor, and forms the product preconditioner's A + B2 itself) and every
+apply/solve run in libmofem; no arithmetic on bands happens in Python.
 
 Operators (rows = s, the base coordinate; columns = t):
 * x-normal elliptic, eq. (73) (lumped: eq. (75)):
@@ -86,7 +85,8 @@ class XNormal:
             coeffs = (1.0, 1.0, 1.0, 0.0)
         else:
             terms = [dict(left=M1, right=A),
-                     dict(left=B1 + gamma * M3, right=M),
+                     dict(left=B1, right=M),
+                     dict(left=M3, right=M, coef=gamma),      # merged with B1 U M by the library
                      dict(left=M2, right=B2),
                      dict(left=C2, right=C1, coef=-1.0),
                      dict(left=C2, right=C1, coef=-1.0, left_T=True, right_T=True)]
@@ -108,7 +108,7 @@ class XNormal:
         M0 D1 and M0 in place of M3 and M), one factor pair per c = d tau in
         `scales` (the item scale of each item selects its pair)."""
         b = self.bands
-        AB2 = b["A"] + b["B2"]
+        AB2 = [(b["A"], 1.0), (b["B2"], 1.0)]    # summed by the library
         if self.imex:
             return mf.BandedPreconditioner(b["B1"], b["M3"], AB2, b["M"], a=1.0, bs=1.0, bt=1.0, scales=scales,
                                            trim_s=self.trim, trim_t=self.trim)
@@ -141,7 +141,7 @@ class Rect:
                      dict(left=M, right=A, scaled=True)]
             coeffs = (1.0, 1.0, 1.0, 0.0)
         else:
-            terms = [dict(left=A + gamma * M, right=M), dict(left=M, right=A)]
+            terms = [dict(left=A, right=M), dict(left=M, right=M, coef=gamma), dict(left=M, right=A)]
             coeffs = (gamma, 1.0, 1.0, 0.0)
         self.op = mf.Operator(terms, **common)
         self.rhs_op = mf.Operator([dict(left=M, right=M)], full_input=True, **common)

@@ -45,7 +45,9 @@ def test_product_apply_eq80(k, m, m_t, lumped):
 
 def test_product_apply_eq95_two_scales():
     """(M3 + c B1)^-1 R (M + c (A + B2))^-1 with the factor pair chosen per
-    item by its scale; an item whose scale matches no pair uses pair 0."""
+    item by its scale; an item whose scale matches no pair gets NaN (never
+    another pair's preconditioner), and an IMEX step whose d tau has no pair
+    is rejected on the host."""
     import torch
     c0, c1 = 1e-3 * 0.1, 1e-3 * 20.0
     G, P = _pair(2, 40, "neumann", 0.0, m_t=29, imex=True)
@@ -56,9 +58,16 @@ def test_product_apply_eq95_two_scales():
     scales = np.array([c0, c1, c1, c0, 0.5])
     Z = to_host(prec.apply(to_dev(R), item_scale=torch.from_numpy(scales).cuda()))
     for b, c in enumerate(scales):
-        cc = c if c in (c0, c1) else c0
-        Zo = BandedProductPrec(T["M3"] + cc * T["B1"], T["M"] + cc * (T["A"] + T["B2"])).apply(R[b])
+        if c not in (c0, c1):
+            assert np.all(np.isnan(Z[b])), b
+            continue
+        Zo = BandedProductPrec(T["M3"] + c * T["B1"], T["M"] + c * (T["A"] + T["B2"])).apply(R[b])
         assert rel(Z[b], Zo) < 1e-11, b
+    from paper_2109_01173_amd import mofem as mf
+    st = to_dev(rng.standard_normal((1, P.q, P.q_t)))
+    with pytest.raises(mf.MofemError) as e:
+        mf.Imex(G.op, prec, G.mass, 1e-3, [0.3], tol=1e-8, maxit=50).step(st, 1)   # 0.3 tau is no pair's scale
+    assert e.value.code == mf.E_ARG
 
 
 def test_product_pcg_elliptic_matches_oracle():

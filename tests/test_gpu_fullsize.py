@@ -8,9 +8,10 @@ this size), so whole items 0 and 15 of the batch are compared: the load and
 the operator element by element within the rounding bound of the smaller
 operator tests, the FP64 preconditioner backward through the oracle's
 explicit single-term operator, the forward-BF16 preconditioner against the
-FP64 one within its arithmetic, and the solve by its backward error under
-the oracle's operator and its forward error against the oracle's own
-MO-PCG solution; the FP64 path of the bench likewise at 1e-10."""
+FP64 one within its arithmetic, and the solves (mixed to 1e-8, FP64 to
+1e-10) by their backward errors under the oracle's load and operator and
+their forward errors against the oracle's own MO-PCG solutions (recurrence
+residual 1e-13)."""
 import numpy as np
 import pytest
 
@@ -51,7 +52,19 @@ def test_fullsize_load_and_operator(full):
 
 
 def test_fullsize_preconditioner(full):
+    """FP64 transforms backward through the oracle's explicit single-term
+    operator (items 0 and 15); the forward-BF16 transforms of the bench
+    against the oracle's CPU emulation of that mode (oracle/precision.py) on
+    every item of the batch: the library's own eigenbasis and the oracle's
+    agree to about 1e-13, so their BF16 roundings coincide (a sign flip of an
+    eigenvector negates every rounding it touches and cancels), and the GPU
+    must reproduce the emulated rounding pattern to AGREE_FRAC of the
+    emulated error.  (The error itself varies from item to item by a factor
+    of about two: the few lowest modes, divided by the smallest D, dominate
+    Z.)"""
+    from oracle import precision as em
     from paper_2109_01173_amd import mofem as mf
+    from test_oracle_precision import AGREE_FRAC
     G, P, _, S = full
     R = np.random.default_rng(78).standard_normal((B, G.q, G.q))
     G.prec.set_precision(mf.PREC_F64)
@@ -63,24 +76,55 @@ def test_fullsize_preconditioner(full):
     condD = np.abs(S.D).max() / np.abs(S.D).min()
     for b in ITEMS:
         assert rel(S.forward(Z64[b]), R[b]) < 50 * EPS * condD
-        assert rel(Zmx[b], Z64[b]) < 3e-2
-    # every item of the batch: the mixed result within the same bound
+    emulate = em.prec_apply(S, em.MODES["BF16_FWD"], "f32")
     for b in range(B):
-        assert rel(Zmx[b], Z64[b]) < 3e-2, b
+        Zx = S.apply(R[b])
+        Zem = emulate(R[b])
+        err_em = rel(Zem, Zx)
+        assert rel(Zmx[b], Zem) <= AGREE_FRAC * err_em, (b, rel(Zmx[b], Zem), err_em)
 
 
 @pytest.fixture(scope="module")
-def oracle_u0(full):
-    """The oracle's FP64 MO-PCG solution of item 0 to 1e-10 (its attainable
-    accuracy at this size is a few 1e-11: eps times the operator's condition
-    number)."""
+def oracle_ref(full):
+    """The oracle's FP64 MO-PCG solutions of items 0 and 15, iterated until the
+    recurrence residual is 1e-13 (about 40 iterations each): three orders
+    below the FP64 path's stopping tolerance, so they stand for the exact
+    solution in the forward-error checks.  Their TRUE residual cannot be
+    certified below the rounding floor of one FP64 evaluation of the operator
+    at this size (0.6-2e-10 measured: the true residual stagnates there), so
+    it is asserted below the first-order rounding scale eps ||(|L| |U|)|| /
+    ||R|| instead."""
     _, P, F, S = full
-    Uo, info = mo_pcg(P.apply, S.apply, P.rhs(F[0]), tol=1e-10, maxit=200)
-    assert info["relres"] <= 1e-10
-    return Uo
+    out = {}
+    for b in ITEMS:
+        R = P.rhs(F[b])
+        Uo, info = mo_pcg(P.apply, S.apply, R, tol=1e-13, maxit=200, check_true=False)
+        floor = EPS * np.linalg.norm(oracle_abs_apply(P, Uo)) / np.linalg.norm(R)
+        assert info["relres"] <= floor, (b, info["relres"], floor)
+        out[b] = Uo
+    return out
 
 
-def test_fullsize_solve(full, oracle_u0):
+def _backward_under_oracle(G, P, F, Uh, b):
+    """Backward error of the GPU solution of item b under the oracle's load
+    and operator, and the part of it that is only the two implementations'
+    rounding difference: ||Rg - Ro|| + ||G.op(U) - P.apply(U)||, both measured
+    on this U (triangle inequality: back <= relres_gpu + that difference),
+    plus the first-order rounding scale of one FP64 evaluation of the
+    operator on U, eps ||(|L| |U|)||_F / ||R||, that the difference must stay
+    under."""
+    Ro = P.rhs(F[b])
+    Rg = to_host(G.rhs_op.apply(to_dev(F[b:b + 1])))[0]
+    LgU = to_host(G.op.apply(to_dev(Uh[b:b + 1])))[0]
+    LoU = P.apply(Uh[b])
+    nR = np.linalg.norm(Ro)
+    back = np.linalg.norm(Ro - LoU) / nR
+    diff = (np.linalg.norm(Rg - Ro) + np.linalg.norm(LgU - LoU)) / nR
+    scale = EPS * np.linalg.norm(oracle_abs_apply(P, Uh[b])) / nR
+    return back, diff, scale
+
+
+def test_fullsize_solve(full, oracle_ref):
     import torch
     from paper_2109_01173_amd import mofem as mf
     G, P, F, S = full
@@ -91,16 +135,20 @@ def test_fullsize_solve(full, oracle_u0):
     assert np.all(relres <= 1e-8) and its.max() <= 30
     Uh = to_host(U)
     for b in ITEMS:
-        Ro = P.rhs(F[b])
-        back = np.linalg.norm(Ro - P.apply(Uh[b])) / np.linalg.norm(Ro)
-        assert back <= 1.05e-8, (b, back)
-    assert rel(Uh[0], oracle_u0) < 1e-8
+        back, diff, scale = _backward_under_oracle(G, P, F, Uh, b)
+        assert diff <= scale, (b, diff, scale)
+        assert back <= relres[b] * (1 + 1e-12) + diff, (b, back)
+        assert rel(Uh[b], oracle_ref[b]) < 1e-8, b
 
 
-def test_fullsize_solve_fp64(full, oracle_u0):
+def test_fullsize_solve_fp64(full, oracle_ref):
     """The FP64 path of the bench (FP64 transforms, standard PCG) at the same
-    size: every item to 1e-10 on the true residual, item 0 against the
-    oracle's solution to the oracle's own attainable accuracy."""
+    size: every item to 1e-10 on the true residual; items 0 and 15 within
+    1e-10 of the oracle's reference solution (forward) and, under the
+    oracle's load and operator, within their GPU residual plus the measured
+    rounding difference of the two FP64 operator evaluations (backward; that
+    difference sits at the evaluation's own rounding floor, 1e-10 at this
+    size, and is asserted below its first-order rounding scale)."""
     import torch
     from paper_2109_01173_amd import mofem as mf
     G, P, F, _ = full
@@ -113,11 +161,8 @@ def test_fullsize_solve_fp64(full, oracle_u0):
         G.prec.set_precision(mf.PREC_BF16_FWD)
     assert np.all(relres <= 1e-10) and its.max() <= 40
     Uh = to_host(U)
-    # at 1e-10 the residual is near the rounding level of the operator itself:
-    # under the oracle's operator the backward error may exceed the GPU's own
-    # by the two operators' rounding difference (the bound of the operator test)
-    Ro = P.rhs(F[15])
-    back = np.linalg.norm(Ro - P.apply(Uh[15])) / np.linalg.norm(Ro)
-    slack = np.linalg.norm(64 * (2 * G.kb + 1) * EPS * oracle_abs_apply(P, Uh[15])) / np.linalg.norm(Ro)
-    assert back <= 1.05e-10 + slack, (back, slack)
-    assert rel(Uh[0], oracle_u0) < 1e-9
+    for b in ITEMS:
+        back, diff, scale = _backward_under_oracle(G, P, F, Uh, b)
+        assert diff <= scale, (b, diff, scale)
+        assert back <= relres[b] * (1 + 1e-12) + diff, (b, back, diff)
+        assert rel(Uh[b], oracle_ref[b]) < 1e-10, b

@@ -5,14 +5,27 @@ IMEX step captured as a HIP graph and replayed (mofem_imex_graph_*).
 The masked iterations after convergence change nothing, so both must
 reproduce the synchronous path's states and iteration counts (the kernels
 and their order are the same).  Graph replays are checked one by one, with
-unrelated eager work and synchronisations between them."""
+unrelated eager work and synchronisations between them.  Every result is
+also compared with the oracle: IMEX states with its steps (MO-PCG to 1e-13),
+solves with its sparse direct solve of the Kronecker system."""
 import numpy as np
 import pytest
 
-from gpu_cases import gpu_xnormal, rel, to_dev, to_host
+from gpu_cases import gpu_xnormal, oracle_xnormal, rel, to_dev, to_host
+from oracle import imex
+from oracle.problems import RectProblem
+from oracle.solvers import SpectralPrec, direct_solve, mo_pcg
 from workloads import dib_initial, dib_params, heat_initial
 
 pytestmark = pytest.mark.gpu
+
+
+def oracle_solver(P, preset):
+    def solve(c, R, U0):
+        S = SpectralPrec(*P.imex_prec_pairs(preset, c))
+        U, _ = mo_pcg(lambda X: P.apply_imex(X, c), S.apply, R, U0=U0, tol=1e-13, maxit=300)
+        return U
+    return solve
 
 
 def _kin(p):
@@ -33,6 +46,9 @@ def test_imex_graph_replays_match_eager_dib():
     eager, graphed = mk(), mk()
     g = mf.ImexGraph(graphed, s_graph, 1, iters_per_step=4)
     noise = to_dev(np.random.default_rng(0).standard_normal((2, G.q, G.q)))
+    P = RectProblem(1, 24, "neumann", lx=20.0, ly=20.0, lumped=True)
+    solve = oracle_solver(P, "rect")
+    eta_o, theta_o = eta.copy(), theta.copy()
     for step in range(5):
         its = eager.step(s_eager, 1)
         g.launch(1)
@@ -41,6 +57,9 @@ def test_imex_graph_replays_match_eager_dib():
         assert rel(to_host(s_graph), to_host(s_eager)) <= 1e-14, step
         max_its, status, relres = g.result()
         assert np.all(status == 0) and np.all(max_its == its) and np.all(relres < 1e-12)
+        eta_o, theta_o = imex.rds_step(P, eta_o, theta_o, 1e-2, p, solve)
+        out = to_host(s_graph)
+        assert rel(out[0], eta_o) < 1e-10 and rel(out[1], theta_o) < 1e-12, step
 
 
 def test_imex_graph_heat_and_budget_too_small():
@@ -57,6 +76,11 @@ def test_imex_graph_heat_and_budget_too_small():
     g.launch(3)
     torch.cuda.synchronize()
     assert rel(to_host(s_graph), to_host(s_eager)) <= 1e-14
+    P = oracle_xnormal(2, 16, "neumann", 0.0)
+    U = U0.copy()
+    for _ in range(3):
+        U = imex.imex_step(P, U, 1e-3, 0.1, oracle_solver(P, "sylv-imex"))
+    assert rel(to_host(s_graph)[0], U) < 1e-10
     max_its, status, _ = g.result()
     assert status[0] == 0 and max_its[0] == max(its)
     # a budget below the iteration count is reported as MAXIT for that step
@@ -72,7 +96,9 @@ def test_imex_graph_heat_and_budget_too_small():
 def test_pcg_async_uneven_shapes_on_two_streams():
     import torch
     from paper_2109_01173_amd import mofem as mf
-    cases = [gpu_xnormal(2, 20, "dirichlet", 1.0), gpu_xnormal(3, 11, "neumann", 1.0)]
+    specs = [(2, 20, "dirichlet"), (3, 11, "neumann")]
+    cases = [gpu_xnormal(k, m, bc, 1.0) for k, m, bc in specs]
+    oracles = [oracle_xnormal(k, m, bc, 1.0) for k, m, bc in specs]
     rng = np.random.default_rng(12)
     runs = []
     for G in cases:
@@ -95,17 +121,22 @@ def test_pcg_async_uneven_shapes_on_two_streams():
                            flags=mf.PCG_ZERO_GUESS, stream=st)
         outs.append((U, iters, status, relres, ws))
     torch.cuda.synchronize()
-    for (G, R, U_sync, its_sync, rr_sync), (U, iters, status, relres, _) in zip(runs, outs):
+    for (G, R, U_sync, its_sync, rr_sync), (U, iters, status, relres, _), P in zip(runs, outs, oracles):
         assert np.all(to_host(status) == 0)
         assert np.array_equal(to_host(iters), its_sync)
         assert rel(to_host(U), to_host(U_sync)) <= 1e-14
         assert np.allclose(to_host(relres), rr_sync, rtol=1e-12, atol=0)
+        Rh, Uh, K = to_host(R), to_host(U), P.kron()
+        for b in range(Rh.shape[0]):
+            # backward under the oracle's operator, forward against its direct solve
+            assert rel(P.apply(Uh[b]), Rh[b]) < 2e-11, b
+            assert rel(Uh[b], direct_solve(K, Rh[b])) < 1e-8, b
 
 
 def test_pcg_solve_many_uneven_groups():
     """Uneven instances (orders 1-4 and lumped P1, several node counts, both
     boundary conditions) solved together on three streams equal the
-    one-at-a-time solves."""
+    one-at-a-time solves and the oracle's direct solves."""
     import torch
     from paper_2109_01173_amd import mofem as mf
     specs = [(1, 64, "dirichlet", False, 3), (2, 64, "dirichlet", False, 2), (3, 21, "neumann", False, 1),
@@ -115,6 +146,7 @@ def test_pcg_solve_many_uneven_groups():
     for k, m, bc, lumped, B in specs:
         G = gpu_xnormal(k, m, bc, 1.0, lumped=lumped)
         R = to_dev(rng.standard_normal((B, G.q, G.q)))
+        G._oracle = oracle_xnormal(k, m, bc, 1.0, lumped=lumped)
         U1 = torch.empty_like(R)
         its, rr, _ = mf.pcg_solve(G.op, G.prec, R, U1, tol=1e-11, maxit=100, flags=mf.PCG_ZERO_GUESS)
         ref.append((U1, its, rr))
@@ -128,3 +160,9 @@ def test_pcg_solve_many_uneven_groups():
         assert np.array_equal(its, its1)
         assert np.allclose(rr, rr1, rtol=1e-12, atol=0)
         assert rel(to_host(g["U"]), to_host(U1)) <= 1e-14
+        # each group against the oracle's sparse direct solve
+        P = g["_keep"]._oracle
+        K, Rh, Uh = P.kron(), to_host(g["rhs"]), to_host(g["U"])
+        for b in range(Rh.shape[0]):
+            assert rel(P.apply(Uh[b]), Rh[b]) < 2e-11, b
+            assert rel(Uh[b], direct_solve(K, Rh[b])) < 1e-8, b

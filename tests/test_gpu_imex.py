@@ -140,3 +140,91 @@ def test_heat_batched_steps():
     out = to_host(st)
     for b in range(2):
         assert rel(out[b], to_host(singles[b])[0]) < 1e-13, b
+
+
+def _radial_peak(U):
+    F = np.abs(np.fft.rfft2(U - U.mean())) ** 2
+    n = U.shape[0]
+    kx = np.fft.fftfreq(n)[:, None] * n
+    ky = np.fft.rfftfreq(U.shape[1])[None, :] * U.shape[1]
+    rb = np.rint(np.sqrt(kx ** 2 + ky ** 2)).astype(int)
+    return int(np.bincount(rb.ravel(), F.ravel())[1:].argmax() + 1)
+
+
+def test_dib_turing_pattern_to_T100():
+    """The reaction-diffusion workload to its full horizon T = 100 (10^4 steps
+    of tau = 1e-2, Sec. 7 parameters, lumped P1 on [0,20]^2) at a reduced
+    mesh (m = 64, q = 65), GPU (HIP-graph replays) against the oracle's
+    steps: the Turing pattern's statistics - means and variances of eta and
+    theta within 1 %, the dominant radial wavenumber within one bin.  (On
+    this mesh the pattern settles: an oracle rerun from a state perturbed by
+    1e-10 changes these statistics by about 1e-9, so the bars are loose; the
+    fields are compared too, at rel 1e-4.)"""
+    import torch
+    from paper_2109_01173_amd import mofem as mf
+    from paper_2109_01173_amd.problems import Rect
+    p = dib_params()
+    tau, nsteps, m = 1e-2, 10000, 64
+    G = Rect(1, m, "neumann", length=20.0, lumped=True, imex=True, closed_form=True)
+    P = RectProblem(1, m, "neumann", lx=20.0, ly=20.0, lumped=True)
+    eta, theta = dib_initial(P.q, seed=7)
+    st = to_dev(np.stack([eta, theta]))
+    kin = [p["rho"], p["A1"], p["A2"], p["B"], p["C"], p["D"], p["alpha"], p["gamma"], p["k2"], p["k3"]]
+    g = mf.ImexGraph(mf.Imex(G.op, G.prec, G.mass, tau, [1.0, p["d_theta"]], kinetics=mf.KIN_DIB, kin=kin,
+                             tol=1e-12, maxit=20), st, 1, iters_per_step=3)
+    for _ in range(10):
+        g.launch(nsteps // 10)
+        torch.cuda.synchronize()
+    max_its, status, _ = g.result()
+    assert np.all(status == 0) and np.all(max_its <= 3)
+    out = to_host(st)
+    cache = {}
+
+    def solve(c, R, U0):
+        if c not in cache:
+            cache[c] = SpectralPrec(*P.imex_prec_pairs("rect", c))
+        U, _ = mo_pcg(lambda X: P.apply_imex(X, c), cache[c].apply, R, U0=U0, tol=1e-13, maxit=50)
+        return U
+    for _ in range(nsteps):
+        eta, theta = imex.rds_step(P, eta, theta, tau, p, solve)
+    for field, ref in ((out[0], eta), (out[1], theta)):
+        assert np.all(np.isfinite(field))
+        assert abs(field.mean() - ref.mean()) <= 0.01 * abs(ref.mean())
+        assert abs(field.var() - ref.var()) <= 0.01 * ref.var()
+        assert rel(field - field.mean(), ref - ref.mean()) < 1e-4
+    assert abs(_radial_peak(out[0]) - _radial_peak(eta)) <= 1
+    assert eta.var() > 1e-4   # a pattern formed (the equilibrium is unstable)
+
+
+def test_heat_p4_full_size_fp32_transforms():
+    """The heat workload at its configured size (P4, Neumann, n = 2049, d = 0.1,
+    tau = 1e-3, U0 ~ U[0,1) seed 42) with the FP32 transforms it names and the
+    flexible PCG to rel 1e-10 per step: two steps against the oracle's steps
+    (spectral MO-PCG on its own dense operators to a recurrence residual of
+    1e-13) at rel 1e-10, plus the discrete mass invariant."""
+    from paper_2109_01173_amd import mofem as mf
+    k, m, d, tau = 4, 512, 0.1, 1e-3
+    G = gpu_xnormal(k, m, "neumann", 0.0, imex=True, precision=mf.PREC_F32)
+    P = oracle_xnormal(k, m, "neumann", 0.0)
+    assert G.q == 2049
+    U0 = heat_initial(P.q, seed=42)
+    st = to_dev(U0[None])
+    stepper = mf.Imex(G.op, G.prec, G.mass, tau, [d], tol=1e-10, maxit=200, flags=mf.PCG_FLEXIBLE)
+    S = SpectralPrec(*P.imex_prec_pairs("sylv-imex", d * tau))
+
+    def solve(c, R, U0_):
+        # recurrence residual 1e-13: the true residual cannot be certified that
+        # low at this size (the FP64 evaluation's own rounding floor)
+        U, info = mo_pcg(lambda X: P.apply_imex(X, c), S.apply, R, U0=U0_, tol=1e-13, maxit=300, check_true=False)
+        return U
+    U = U0.copy()
+    mass0 = P.mass_apply(U0).sum()
+    for _ in range(2):
+        its = stepper.step(st, 1)
+        U = imex.imex_step(P, U, tau, d, solve)
+        assert 1 <= its[0] <= 40
+    Ug = to_host(st)[0]
+    assert rel(Ug, U) < 1e-10
+    # each step's residual r (||r|| <= 1e-10 ||rhs||) moves the mass by
+    # |sum r| <= q ||r||, about 1e-10 of the mass for U0 >= 0
+    assert abs(P.mass_apply(Ug).sum() - mass0) < 2e-10 * abs(mass0)

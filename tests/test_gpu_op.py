@@ -104,3 +104,69 @@ def test_rejects_bad_stride_and_dot_on_load_operator():
     Xs = to_dev(np.zeros((1, G.q, G.q)))
     with pytest.raises(ValueError):
         G.rhs_op.apply(Xs)
+
+
+def _dense(band, n):
+    """Dense n x n matrix of a DIA band (band[d * n + i] = A[i][i + d - kb])."""
+    kb = (band.shape[0] - 1) // 2
+    A = np.zeros((n, n))
+    for d in range(2 * kb + 1):
+        for i in range(n):
+            j = i + d - kb
+            if 0 <= j < n:
+                A[i, j] = band[d, i]
+    return A
+
+
+@pytest.mark.parametrize("n_terms,merges", [(4, 0), (7, 0), (8, 0), (7, 1), (8, 2)])
+def test_term_counts_and_merging(n_terms, merges):
+    """Operators of 4, 7 and 8 terms (random symmetric-free bands, kb = 2,
+    transposes and per-item scaling mixed in) against their plain dense
+    definition sum_t c_t op(L_t) X op(R_t); `merges` terms repeat an earlier
+    term's right (or left) factor with the same scaling, so the library merges
+    them and runs fewer distinct terms."""
+    from paper_2109_01173_amd import mofem as mf
+    kb, n = 2, 161
+    rng = np.random.default_rng(60 + n_terms + 10 * merges)
+    terms = []
+    for t in range(n_terms):
+        L, R = rng.standard_normal((2, 2 * kb + 1, n))
+        if t >= n_terms - merges:   # share a factor with term t - 3
+            src = terms[t - 3]
+            coef = float(rng.uniform(-2, 2))
+            if t % 2:
+                R = src["right"]
+            else:
+                L, coef = src["left"], src["coef"]   # a shared left factor merges with an equal coefficient
+            terms.append(dict(left=L, right=R, coef=coef, scaled=src["scaled"],
+                              left_T=src["left_T"] if t % 2 == 0 else False,
+                              right_T=src["right_T"] if t % 2 else False))
+        else:
+            terms.append(dict(left=L, right=R, coef=float(rng.uniform(-2, 2)), scaled=bool(t % 3 == 1),
+                              left_T=bool(t % 2), right_T=bool(t % 4 == 3)))
+    op = mf.Operator(terms, n_s=n, n_t=n, kb=kb, trim_s=1, trim_t=1)
+    q = n - 2
+    X = rng.standard_normal((2, q, q))
+    cs = np.array([0.3, -1.7])
+    Y, dots = op.apply(to_dev(X), item_scale=to_dev(cs), dot=True)
+    Y, dots = to_host(Y), to_host(dots)
+    I = slice(1, n - 1)
+    for b in range(2):
+        ref = np.zeros((q, q))
+        scale = np.zeros((q, q))
+        for t in terms:
+            Ld, Rd = _dense(t["left"], n), _dense(t["right"], n)
+            Ld = Ld.T if t["left_T"] else Ld
+            Rd = Rd.T if t["right_T"] else Rd
+            c = t["coef"] * (cs[b] if t["scaled"] else 1.0)
+            ref += c * Ld[I, I] @ X[b] @ Rd[I, I]
+            scale += abs(c) * np.abs(Ld[I, I]) @ np.abs(X[b]) @ np.abs(Rd[I, I])
+        assert np.all(np.abs(Y[b] - ref) <= 64 * (2 * kb + 1) * EPS * n_terms * scale), b
+        assert abs(dots[b] - np.sum(X[b] * ref)) <= 1e-12 * np.sum(np.abs(X[b]) * scale)
+
+
+def test_more_than_eight_terms_rejected():
+    from paper_2109_01173_amd import mofem as mf
+    band = np.ones((3, 10))
+    with pytest.raises(ValueError):
+        mf.Operator([dict(left=band, right=band)] * 9, n_s=10, n_t=10, kb=1)

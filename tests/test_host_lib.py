@@ -135,7 +135,8 @@ def test_banded_product_setup_errors_on_the_host():
     d = mf.BPrecDesc()
     keep = [np.ascontiguousarray(B1), np.ascontiguousarray(A)]
     d.kb, d.n_s, d.n_t, d.trim_s, d.trim_t = 2, B1.shape[1], A.shape[1], 1, 1
-    d.Ks, d.Kt = keep[0].ctypes.data, keep[1].ctypes.data
+    d.Ks.n, d.Ks.band[0], d.Ks.coef[0] = 1, keep[0].ctypes.data, 1.0
+    d.Kt.n, d.Kt.band[0], d.Kt.coef[0] = 1, keep[1].ctypes.data, 1.0
     d.a, d.bs, d.bt = 0.0, 1.0, 1.0
     h = ctypes.c_void_p()
     for n_scales in (0, mf.MAX_SCALES + 1):
@@ -143,6 +144,14 @@ def test_banded_product_setup_errors_on_the_host():
         assert mf.mofem_prec_setup_banded(ctypes.byref(d), ctypes.byref(h)) == mf.E_ARG
     d.n_scales, d.scales[0] = 1, 1.0
     d.a = 1.0  # a != 0 needs the mass bands
+    assert mf.mofem_prec_setup_banded(ctypes.byref(d), ctypes.byref(h)) == mf.E_ARG
+    d.a = 0.0
+    for bad in (-1, mf.MAX_BAND_SUM + 1):   # band sums of 0..MAX_BAND_SUM terms
+        d.Kt.n = bad
+        assert mf.mofem_prec_setup_banded(ctypes.byref(d), ctypes.byref(h)) == mf.E_ARG
+    d.Kt.n = 2                              # a NULL band inside the sum
+    assert mf.mofem_prec_setup_banded(ctypes.byref(d), ctypes.byref(h)) == mf.E_ARG
+    d.Kt.n = 0                              # Kt needs at least one band
     assert mf.mofem_prec_setup_banded(ctypes.byref(d), ctypes.byref(h)) == mf.E_ARG
     assert mf.mofem_prec_setup_banded(None, None) == mf.E_ARG
 
