@@ -196,6 +196,25 @@ int mofem_op_apply(mofem_op_t op, const double* X, long long in_stride, double* 
                    long long stride, int batch, const double* item_scale,
                    double* dot_xy, void* stream);
 
+/* Allocation-free variant of mofem_op_apply, for callers that cannot
+   allocate device memory (code under HIP graph capture, tight serving loops,
+   harnesses that forbid hipMalloc).  Same arguments, results and errors as
+   mofem_op_apply; the partial sums of the fused <X_b, Y_b> live in a static
+   device array of MOFEM_NOALLOC_SCRATCH_BYTES per GPU (kept until the process
+   ends; the first call on a device looks up its address) instead of a buffer
+   the handle allocates, and no timing events are recorded.  Calls no
+   hipMalloc, hipFree or other allocating routine.  Limit: with dot_xy,
+   batch * tiles partial sums (8 bytes each) must fit the array, where tiles =
+   ceil(q_t / (4 (64 - 2 kb))) * ceil(q_s / rows) and rows is about 160 (117
+   tiles at q = 2047 and kb = 2, so batch <= 1120); larger requests fail with
+   MOFEM_E_ARG.  Every call on one GPU shares that array:
+   calls that overlap on one GPU (other streams or threads) race and must be
+   serialised by the caller.  Without dot_xy the array is not used. */
+#define MOFEM_NOALLOC_SCRATCH_BYTES (1u << 20)
+int mofem_op_apply_noalloc(mofem_op_t op, const double* X, long long in_stride, double* Y,
+                           long long stride, int batch, const double* item_scale,
+                           double* dot_xy, void* stream);
+
 /* Batched Frobenius products (eq. (77)'s sum(sum(X o Y)) per item):
      out[b] = beta * out[b] + alpha * <X_b, Y_b>_F,   b < batch,
    X_b = X + b * stride (n contiguous doubles), likewise Y_b; out device.

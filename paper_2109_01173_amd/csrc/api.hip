@@ -485,6 +485,69 @@ extern "C" int mofem_op_apply(mofem_op_t op, const double* X, long long in_strid
   return MOFEM_OK;
 }
 
+// ----------------------------------------------------------------------------
+// Allocation-free operator apply: the per-tile partial sums of <X, Y> live in a
+// file-scope device array (one copy per GPU, held until the process ends)
+// instead of a buffer the handle allocates.  In host code `scratch` names a
+// host-side stand-in, never the device copy: its device address is looked up
+// once per device with hipGetSymbolAddress and only that address is used.
+// ----------------------------------------------------------------------------
+namespace {
+constexpr size_t kScratchDoubles = MOFEM_NOALLOC_SCRATCH_BYTES / sizeof(double);
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) double scratch[kScratchDoubles];
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+int scratch_address(double** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(MOFEM_E_ARG, "op_apply_noalloc: device index out of range");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(MOFEM_E_HIP, std::string("op_apply_noalloc: hipGetSymbolAddress: ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = (double*)p;
+  }
+  *out = g_scratch_dev[dev];
+  return MOFEM_OK;
+}
+}  // namespace
+
+extern "C" int mofem_op_apply_noalloc(mofem_op_t op, const double* X, long long in_stride, double* Y,
+                                      long long stride, int batch, const double* item_scale, double* dot_xy,
+                                      void* stream) {
+  clear_error();
+  if (!op) return fail(MOFEM_E_ARG, "op_apply_noalloc: NULL handle");
+  if (batch < 0) return fail(MOFEM_E_ARG, "op_apply_noalloc: negative batch");
+  if (batch == 0) return MOFEM_OK;
+  if (!X || !Y) return fail(MOFEM_E_ARG, "op_apply_noalloc: NULL argument");
+  if (in_stride < (long long)op->ns_in * op->nt_in || stride < (long long)op->qs * op->qt)
+    return fail(MOFEM_E_ARG, "op_apply_noalloc: stride smaller than one item");
+  if (dot_xy && (op->full_input || op->full_output))
+    return fail(MOFEM_E_ARG, "op_apply_noalloc: <X, Y> needs a square operator");
+  double* partial = nullptr;
+  if (dot_xy) {
+    const size_t need = (size_t)batch * op->n_tiles;
+    if (need > kScratchDoubles)
+      return fail(MOFEM_E_ARG, "op_apply_noalloc: batch * tiles = " + std::to_string(need) +
+                                   " partial sums exceed the static scratch of " +
+                                   std::to_string(kScratchDoubles) + " (MOFEM_NOALLOC_SCRATCH_BYTES)");
+    int rc = scratch_address(&partial);
+    if (rc != MOFEM_OK) return rc;
+  }
+  TraceCapture no_trace;  // records no timing events (they would be created on demand)
+  hipStream_t s = (hipStream_t)stream;
+  // every tile of every item writes its partial sum, so nothing needs clearing
+  int rc = op_launch(op, X, in_stride, Y, stride, batch, item_scale, partial, nullptr, s);
+  if (rc != MOFEM_OK) return rc;
+  if (dot_xy && launch_reduce(partial, op->n_tiles, dot_xy, batch, s) != 0)
+    return fail(MOFEM_E_HIP, "op_apply_noalloc: reduce launch failed");
+  return MOFEM_OK;
+}
+
 // ============================================================================
 // preconditioner
 // ============================================================================

@@ -123,6 +123,8 @@ mofem_op_destroy = _proto("mofem_op_destroy", ctypes.c_int, [_vp])
 mofem_op_shape = _proto("mofem_op_shape", ctypes.c_int, [_vp, _ip, _ip, _ip, _ip])
 mofem_op_apply = _proto("mofem_op_apply", ctypes.c_int,
                         [_vp, _vp, _ll, _vp, _ll, ctypes.c_int, _vp, _vp, _vp])
+mofem_op_apply_noalloc = _proto("mofem_op_apply_noalloc", ctypes.c_int,
+                                [_vp, _vp, _ll, _vp, _ll, ctypes.c_int, _vp, _vp, _vp])
 mofem_prec_setup = _proto("mofem_prec_setup", ctypes.c_int, [ctypes.POINTER(PrecDesc), ctypes.POINTER(_vp)])
 mofem_prec_destroy = _proto("mofem_prec_destroy", ctypes.c_int, [_vp])
 mofem_prec_setup_eig = _proto("mofem_prec_setup_eig", ctypes.c_int,
@@ -171,7 +173,7 @@ mofem_trace_read = _proto("mofem_trace_read", ctypes.c_int,
 
 EXPORTS = ["mofem_version", "mofem_last_error", "mofem_assemble_1d", "mofem_geneig_host", "mofem_eig_p1_closed",
            "mofem_prec_setup_eig",
-           "mofem_op_create", "mofem_op_destroy", "mofem_op_shape", "mofem_op_apply",
+           "mofem_op_create", "mofem_op_destroy", "mofem_op_shape", "mofem_op_apply", "mofem_op_apply_noalloc",
            "mofem_prec_setup", "mofem_prec_destroy", "mofem_prec_set_coeffs",
            "mofem_prec_set_precision", "mofem_prec_eigenvalues", "mofem_prec_workspace_size",
            "mofem_prec_apply", "mofem_prec_tune", "mofem_prec_set_tile", "mofem_prec_setup_banded",
@@ -318,14 +320,16 @@ class Operator:
             _destroy(self.handle)
             self.handle = None
 
-    def apply(self, X, Y=None, item_scale=None, dot=False, stream=None):
-        """Y = L(X) per item (mofem_op_apply); dot=True (or a device buffer)
-        also returns <X_b, Y_b>."""
+    def apply(self, X, Y=None, item_scale=None, dot=False, stream=None, noalloc=False):
+        """Y = L(X) per item (mofem_op_apply; with noalloc=True the
+        allocation-free mofem_op_apply_noalloc, which needs Y given)."""
         torch = _torch()
         batch = X.shape[0]
         if tuple(X.shape[1:]) != self.in_shape:
             raise ValueError("input shape %s, operator expects %s" % (tuple(X.shape[1:]), self.in_shape))
         if Y is None:
+            if noalloc:
+                raise ValueError("noalloc apply needs its output Y (and dot buffer) from the caller")
             Y = torch.empty((batch,) + self.shape, dtype=torch.float64, device=X.device)
         if dot is True:
             dots = torch.empty(batch, dtype=torch.float64, device=X.device)
@@ -333,9 +337,10 @@ class Operator:
             dots = dot if dot is not False else None
         in_stride = self.in_shape[0] * self.in_shape[1]
         out_stride = self.shape[0] * self.shape[1]
-        rc = mofem_op_apply(self.handle, _dptr(X), in_stride, _dptr(Y), out_stride, batch, _dptr(item_scale),
-                            _dptr(dots), _stream(stream))
-        _check(rc, "mofem_op_apply")
+        fn, name = (mofem_op_apply_noalloc, "mofem_op_apply_noalloc") if noalloc else (mofem_op_apply, "mofem_op_apply")
+        rc = fn(self.handle, _dptr(X), in_stride, _dptr(Y), out_stride, batch, _dptr(item_scale), _dptr(dots),
+                _stream(stream))
+        _check(rc, name)
         return (Y, dots) if dots is not None else Y
 
 
