@@ -13,6 +13,15 @@ of the working precisions of the library:
   x2a  A split, B rounded to BF16:  Ah Bh + Al Bh  (the product with the
        BF16-rounded B, to FP32 accuracy);
   x2b  B split, A rounded to BF16:  Ah Bh + Ah Bl.
+  oz7  FP64-accurate product from exact 7-bit integer digits (the
+       error-free splitting of Ozaki, Ogita, Oishi and Rump, Numer.
+       Algorithms 59 (2012), with 8-bit integer slices as in Ootomo, Ozaki
+       and Yokota, IJHPCA 38 (2024)): every row of A and every column of B
+       gets a power-of-two exponent above its largest magnitude and is cut
+       into 7 signed base-128 digits (round to nearest); the digit products
+       with p + q <= 8
+       are exact integers, summed per diagonal p + q and then in FP64 from
+       the smallest scale up (see ``ozaki``).
 Accumulation: acc="f32" sums in FP32 (NumPy's single-precision BLAS, one
 blocked accumulation order); acc="seq" adds the rank-one terms one k at a
 time into FP32 sums (the longest chain of FP32 roundings, as a matrix-core
@@ -61,10 +70,53 @@ def _seq(pairs):
     return out
 
 
+def oz_digits(X, s, beta=7):
+    """Exponents and digits of the rows of X: the smallest e_r with
+    max |X[r, :]| <= (1 - 2^-beta) 2^e_r (0 for a zero row), and s
+    integer-valued arrays d_1 .. d_s, each the nearest integer (ties to even)
+    to 2^beta times the remainder so far:  |d_1| <= 2^beta - 1,
+    |d_p| <= 2^(beta - 1) for p > 1, and X = 2^e (sum_p d_p 2^(-beta p) + rem)
+    with |rem| <= 2^(-beta s) / 2; every step is exact in FP64."""
+    X = np.asarray(X, dtype=np.float64)
+    f, e = np.frexp(np.abs(X).max(axis=1) if X.shape[1] else np.zeros(X.shape[0]))
+    e = e + (f > 1.0 - 2.0 ** -beta)
+    x = np.ldexp(X, -e[:, None])
+    digits = []
+    for _ in range(s):
+        y = x * 2.0 ** beta
+        d = np.rint(y)
+        x = y - d
+        digits.append(d)
+    return e.astype(np.int64), digits
+
+
+def ozaki(A, B, s=7, beta=7):
+    """A @ B from exact digit products: A's rows and B's columns cut by
+    oz_digits; the products a_p b_q with p + q <= s + 1 are exact integers
+    (FP64 products of integer matrices whose sums stay below 2^53), summed
+    per diagonal d = p + q; the diagonals are added in FP64 from d = s + 1
+    down to 2 with their scales 2^(-beta d), then scaled by 2^(ea + eb)."""
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    if A.shape[1] * (2 ** beta - 1) ** 2 * s >= 2.0 ** 53:
+        raise ValueError("inner dimension too long for exact digit sums")
+    ea, Da = oz_digits(A, s, beta)
+    eb, Db = oz_digits(B.T, s, beta)
+    C = np.zeros((A.shape[0], B.shape[1]))
+    for d in range(s + 1, 1, -1):
+        acc = np.zeros_like(C)
+        for p in range(1, d):
+            acc += Da[p - 1] @ Db[d - p - 1].T
+        C = C + acc * 2.0 ** (-beta * d)
+    return np.ldexp(C, ea[:, None] + eb[None, :])
+
+
 def product(A, B, mode, acc="f32"):
     """A @ B in the given transform precision, returned as FP64."""
     if mode == "f64":
         return A @ B
+    if mode == "oz7":
+        return ozaki(A, B, 7)
     if mode == "f32":
         A32, B32 = A.astype(np.float32), B.astype(np.float32)
         if acc == "seq":
@@ -120,4 +172,5 @@ MODES = {
     "BF16X3": ("x3",) * 4,
     "BF16X2": ("x2a", "x2b", "x2b", "x2a"),
     "BF16_FWD": ("hh", "hh", "x3", "x3"),
+    "F64_INT8": ("oz7",) * 4,
 }

@@ -39,15 +39,17 @@ def test_split_product_error_levels():
 @pytest.mark.parametrize("m", [64, 128])
 def test_iteration_counts_of_transform_precisions(m):
     """Split-BF16 everywhere and BF16 forward + split back transforms keep the
-    FP64 iteration count (within one); plain BF16 everywhere does not."""
+    FP64 iteration count (within one), the INT8 digit products exactly; plain
+    BF16 everywhere does not."""
     P = XNormalProblem(2, m, "dirichlet", L_profile, dL_profile, gamma=1.0)
     S = SpectralPrec(*P.prec_pairs("sylv"))
     R = P.rhs(elliptic_F(P.n, 1.0, 1e-3, 1234))
     its = {}
     for name, modes in [("f64", ("f64",) * 4), ("x3", ("x3",) * 4), ("fwd", ("hh", "hh", "x3", "x3")),
-                        ("hh", ("hh",) * 4)]:
+                        ("hh", ("hh",) * 4), ("oz", ("oz7",) * 4)]:
         _, info = mo_pcg(P.apply, precision.prec_apply(S, modes), R, tol=1e-8, maxit=300)
         its[name] = info["iters"]
+    assert its["oz"] == its["f64"]
     assert its["x3"] <= its["f64"] + 1
     assert its["fwd"] <= its["f64"] + 1
     assert its["hh"] >= its["f64"]
@@ -105,3 +107,85 @@ def test_accumulation_order_sensitivity(mode):
         for a, b in (("f32", "exact"), ("seq", "exact"), ("f32", "seq")):
             between = np.linalg.norm(Z[a] - Z[b]) / nx
             assert between <= AGREE_FRAC / 4 * err["exact"], (a, b, between, err)
+
+
+# ---- error-free INT8 digit products (mode "oz7") ------------------------------
+def test_ozaki_digits_reconstruct_the_rows():
+    """Digits are integers within the int8 range, the remainder after s
+    digits is at most 2^(-7s)/2 of the row's power of two, the exponent is
+    the smallest with max |x| <= (127/128) 2^e, and 8 digits hold entries
+    within a factor 4 of the row maximum exactly (their last bit lies at or
+    above 2^-56 of the exponent)."""
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((20, 50)) * np.exp2(rng.integers(-30, 30, size=(20, 1)))
+    X[3] = 0.0
+    X[5, 7] = 127.0 / 128.0 * 2.0 ** 4  # at the exponent boundary
+    X[5, 8] = -X[5, 7]
+    for s in (2, 4, 7):
+        e, D = precision.oz_digits(X, s)
+        assert all(np.array_equal(d, np.rint(d)) for d in D)
+        assert np.abs(D[0]).max() <= 127 and all(np.abs(d).max() <= 64 for d in D[1:])
+        rec = sum(d * 2.0 ** (-7 * (p + 1)) for p, d in enumerate(D))
+        rem = np.ldexp(X, -e[:, None]) - rec
+        assert np.abs(rem).max() <= 2.0 ** (-7 * s) / 2
+    mx = np.abs(X).max(axis=1)
+    nz = mx > 0
+    assert np.all(mx[nz] <= 127.0 / 128.0 * np.exp2(e[nz]))
+    assert np.all(mx[nz] > 127.0 / 128.0 * np.exp2(e[nz] - 1))
+    assert e[3] == 0 and e[5] == 4
+    Y = rng.uniform(0.25, 1.0, (10, 40)) * rng.choice([-1.0, 1.0], (10, 40)) * np.exp2(rng.integers(-9, 9, (10, 1)))
+    e8, D8 = precision.oz_digits(Y, 8)
+    rec8 = sum(d * 2.0 ** (-7 * (p + 1)) for p, d in enumerate(D8))
+    assert np.array_equal(np.ldexp(rec8, e8[:, None]), Y)
+
+
+def test_ozaki_product_is_exact_on_short_inputs():
+    """Entries of a few significant bits relative to their row (A) and column
+    (B) maxima fit in two digits, so every digit product is kept and the
+    result equals the exact product (integer arithmetic); row and column
+    scalings by powers of two and a non-square shape catch a wrong exponent,
+    a dropped diagonal or a transposed operand."""
+    rng = np.random.default_rng(4)
+    Ai = rng.integers(-1000, 1001, (13, 37))
+    Bi = rng.integers(-1000, 1001, (37, 9))
+    ra = rng.integers(-20, 20, 13)
+    cb = rng.integers(-20, 20, 9)
+    A = np.ldexp(Ai.astype(np.float64), ra[:, None])
+    B = np.ldexp(Bi.astype(np.float64), cb[None, :])
+    exact = np.ldexp((Ai @ Bi).astype(np.float64), ra[:, None] + cb[None, :])
+    assert np.array_equal(precision.ozaki(A, B, 7), exact)
+    assert np.array_equal(precision.product(A, B, "oz7"), exact)
+
+
+def test_ozaki_error_bound_and_digit_count():
+    """Against the exact product (rational arithmetic): the error per entry
+    is below (s + 1) 2^(-7s) K 2^(ea + eb) plus the FP64 rounding of the
+    final sums, and every further digit buys about 2^7 in accuracy."""
+    from fractions import Fraction
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((6, 25))
+    B = rng.standard_normal((25, 5))
+    exact = np.array([[float(sum(Fraction(A[i, k]) * Fraction(B[k, j]) for k in range(25))) for j in range(5)]
+                      for i in range(6)])
+    ea, _ = precision.oz_digits(A, 1)
+    eb, _ = precision.oz_digits(B.T, 1)
+    scale = np.exp2(ea[:, None] + eb[None, :])
+    errs = []
+    for s in (2, 3, 4, 7):
+        C = precision.ozaki(A, B, s)
+        err = np.abs(C - exact)
+        assert np.all(err <= (s + 1) * 2.0 ** (-7 * s) * 25 * scale + 8 * np.finfo(float).eps * np.abs(exact))
+        errs.append(err.max())
+    assert errs[0] > 30 * errs[1] > 30 * 30 * errs[2] and errs[3] < 1e-13 * np.abs(exact).max()
+
+
+def test_ozaki_fp64_level_at_the_transform_length():
+    """At the inner length of the q = 2047 transforms the seven-digit product
+    stays within 5e-14 of the largest entry of the product (extended-precision
+    reference; plain FP64 products are near 1e-15 here)."""
+    rng = np.random.default_rng(6)
+    A = rng.standard_normal((24, 2048))
+    B = rng.standard_normal((2048, 16))
+    ref = A.astype(np.longdouble) @ B.astype(np.longdouble)
+    err = np.abs(precision.ozaki(A, B, 7) - ref).max() / np.abs(ref).max()
+    assert err < 5e-14
