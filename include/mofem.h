@@ -121,6 +121,14 @@ int mofem_assemble_1d(int order, int m_elem, double x0, double x1, int di, int d
 int mofem_geneig_host(int n, int kb, const double* K, const double* M, int trim,
                       double* lam, double* V);
 
+/* Host threads used by one host-side call (assembly, eigen-decomposition;
+   mofem_prec_setup splits its share between its two decompositions).
+   n <= 0 restores the default (the hardware's threads, at most 16).  Callers
+   that run several set-ups concurrently divide the machine with it (e.g. four
+   concurrent set-ups on 16 cores: n = 4) instead of oversubscribing it.
+   Process-wide; returns the previous count.  Never fails. */
+int mofem_set_host_threads(int n);
+
 /* Closed-form generalised eigenpairs of the uniform P1 pencil (A, M) on an
    interval of length len with n_elem elements (host only), Sec. 4.1: with
    Dirichlet conditions the P1 stiffness and consistent mass are tridiagonal
@@ -242,10 +250,21 @@ enum {
                              with the rounded (still nonsingular) bases, so
                              P stays symmetric positive definite and each
                              transform needs two products; FP32 accumulation */
-  MOFEM_PREC_BF16_FWD = 5 /* forward transforms (V_s^T R V_t) in BF16 (one
+  MOFEM_PREC_BF16_FWD = 5, /* forward transforms (V_s^T R V_t) in BF16 (one
                              product), back transforms (V_s (.) V_t^T) in
                              split BF16 (three); FP32 accumulation.  Not
                              symmetric: use the flexible PCG.               */
+  MOFEM_PREC_F64_INT8 = 6 /* FP64-accurate transforms on INT8 MFMA: every
+                             row of an operand cut into 7 exact signed
+                             base-128 digits (round to nearest) below its
+                             power-of-two exponent, the 28 digit products
+                             with p + q <= 8 formed exactly in int32 and
+                             summed in FP64 (error-free splitting of Ozaki,
+                             Ogita, Oishi and Rump); error per entry below
+                             2^-46 K 2^(e_row + e_col).
+                             FP64 intermediates and Z; operand widths
+                             (padded) up to 16384, else MOFEM_E_UNSUPPORTED
+                             at set-up or on mofem_prec_set_precision.      */
 };
 typedef struct {
   int kb;                       /* band half-width of the four matrices       */
@@ -526,7 +545,9 @@ enum {
   MOFEM_TRACE_GEMM_F32 = 6,     /* one FP32 transform product                  */
   MOFEM_TRACE_BCHOL = 7,        /* one banded Cholesky solve (two per product-
                                    preconditioner application)               */
-  MOFEM_TRACE_CLASSES = 8
+  MOFEM_TRACE_GEMM_I8 = 8,      /* one FP64-accurate transform product on INT8
+                                   MFMA (28 digit products)                  */
+  MOFEM_TRACE_CLASSES = 9
 };
 /* on != 0: discard earlier records and start recording; on == 0: stop. */
 int mofem_trace_enable(int on);

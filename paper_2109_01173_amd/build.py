@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libmofem.so")
 
 HOST_SOURCES = ["host_fem.cpp", "host_eigen.cpp", "host_chol.cpp"]
 HIP_SOURCES = ["k_band_kb2.hip", "k_band_kb3.hip", "k_band_kb4.hip", "k_band_kb1.hip",
-               "k_band.hip", "k_gemm.hip", "k_vec.hip", "k_bchol.hip", "api.hip"]
+               "k_band.hip", "k_gemm.hip", "k_ozaki.hip", "k_vec.hip", "k_bchol.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CXX = os.environ.get("CXX", "g++")

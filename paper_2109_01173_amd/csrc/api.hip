@@ -562,6 +562,9 @@ struct mofem_prec_s {
   unsigned short *Vs_h = nullptr, *Vs_l = nullptr, *VsT_h = nullptr, *VsT_l = nullptr;
   unsigned short *Vt_h = nullptr, *Vt_l = nullptr, *VtT_h = nullptr, *VtT_l = nullptr;
   float *Vs_f = nullptr, *VsT_f = nullptr, *Vt_f = nullptr, *VtT_f = nullptr;  // FP32 padded
+  // INT8 digit planes and row exponents of the padded bases (MOFEM_PREC_F64_INT8)
+  signed char *Vs_i8 = nullptr, *VsT_i8 = nullptr, *Vt_i8 = nullptr, *VtT_i8 = nullptr;
+  int *Vs_ex = nullptr, *VsT_ex = nullptr, *Vt_ex = nullptr, *VtT_ex = nullptr;
   std::vector<std::pair<long long, int>> tuned;  // (precision << 32 | batch) -> block tile
   void* ws = nullptr;
   size_t ws_bytes = 0;
@@ -631,6 +634,7 @@ extern "C" int mofem_prec_destroy(mofem_prec_t p) {
   if (!p) return MOFEM_OK;
   void* ptrs[] = {p->lam, p->mu, p->Vs, p->VsT, p->Vt, p->VtT, p->Vs_h, p->Vs_l, p->VsT_h,
                   p->VsT_l, p->Vt_h, p->Vt_l, p->VtT_h, p->VtT_l, p->Vs_f, p->VsT_f, p->Vt_f, p->VtT_f,
+                  p->Vs_i8, p->VsT_i8, p->Vt_i8, p->VtT_i8, p->Vs_ex, p->VsT_ex, p->Vt_ex, p->VtT_ex,
                   p->ws, p->Lf_s, p->Lb_s, p->Lf_t, p->Lb_t, p->scales};
   for (void* x : ptrs)
     if (x) (void)hipFree(x);
@@ -651,7 +655,7 @@ extern "C" int mofem_prec_setup(const mofem_prec_desc* desc, mofem_prec_t* out) 
   if (!D.Ks || !D.Ms || !D.Kt || !D.Mt) return fail(MOFEM_E_ARG, "prec_setup: NULL band");
   if ((D.trim_s != 0 && D.trim_s != 1) || (D.trim_t != 0 && D.trim_t != 1))
     return fail(MOFEM_E_ARG, "prec_setup: trim flags must be 0 or 1");
-  if (D.precision < MOFEM_PREC_F64 || D.precision > MOFEM_PREC_BF16_FWD)
+  if (D.precision < MOFEM_PREC_F64 || D.precision > MOFEM_PREC_F64_INT8)
     return fail(MOFEM_E_ARG, "prec_setup: unknown precision");
   const int qs = D.n_s - 2 * D.trim_s, qt = D.n_t - 2 * D.trim_t;
   if (qs < 1 || qt < 1) return fail(MOFEM_E_ARG, "prec_setup: empty matrices");
@@ -679,13 +683,18 @@ extern "C" int mofem_prec_setup(const mofem_prec_desc* desc, mofem_prec_t* out) 
   int rc_t = MOFEM_OK;
   std::string msg_t;
   std::thread worker;
+  // the two decompositions share this call's host threads
+  const int threads = host_threads(), share = same ? threads : std::max(1, (threads + 1) / 2);
   if (!same) {
     worker = std::thread([&]() {
+      set_thread_share(share);
       rc_t = mofem_geneig_host(D.n_t, D.kb, D.Kt, D.Mt, D.trim_t, p->h_mu.data(), Vt.data());
       if (rc_t != MOFEM_OK) msg_t = mofem_last_error();  // thread-local message of the worker
     });
   }
+  const int prev_share = set_thread_share(share);
   int rc = mofem_geneig_host(D.n_s, D.kb, D.Ks, D.Ms, D.trim_s, p->h_lam.data(), Vs.data());
+  set_thread_share(prev_share);
   std::string msg = rc != MOFEM_OK ? std::string(mofem_last_error()) : std::string();
   if (worker.joinable()) worker.join();
   if (same && rc == MOFEM_OK) {
@@ -718,7 +727,7 @@ extern "C" int mofem_prec_setup_eig(int q_s, int q_t, const double* lam, const d
   if (!out || !lam || !Vs || !mu || !Vt) return fail(MOFEM_E_ARG, "prec_setup_eig: NULL argument");
   *out = nullptr;
   if (q_s < 1 || q_t < 1) return fail(MOFEM_E_ARG, "prec_setup_eig: empty matrices");
-  if (precision < MOFEM_PREC_F64 || precision > MOFEM_PREC_BF16_FWD)
+  if (precision < MOFEM_PREC_F64 || precision > MOFEM_PREC_F64_INT8)
     return fail(MOFEM_E_ARG, "prec_setup_eig: unknown precision");
   auto* p = new mofem_prec_s();
   p->qs = q_s;
@@ -765,6 +774,26 @@ int prec_upload(mofem_prec_s* p, const std::vector<double>& Vs, const std::vecto
   if (!rc) rc = upload_f32(&p->VsT_f, VsT_p);
   if (!rc) rc = upload_f32(&p->Vt_f, Vt_p);
   if (!rc) rc = upload_f32(&p->VtT_f, VtT_p);
+  // INT8 digit planes of the padded FP64 bases, cut on the device (bases
+  // wider than the INT8 products take stay without them)
+  if (!rc && p->ps <= kOzMaxK && p->pt <= kOzMaxK) {
+    struct {
+      const double* src;
+      int n;
+      signed char** out;
+      int** ex;
+    } bases[4] = {{p->Vs, p->ps, &p->Vs_i8, &p->Vs_ex}, {p->VsT, p->ps, &p->VsT_i8, &p->VsT_ex},
+                  {p->Vt, p->pt, &p->Vt_i8, &p->Vt_ex}, {p->VtT, p->pt, &p->VtT_i8, &p->VtT_ex}};
+    for (auto& B : bases) {
+      if (!rc) rc = dev_alloc(B.out, (size_t)kOzSlices * B.n * B.n);
+      if (!rc) rc = dev_alloc(B.ex, (size_t)B.n);
+      if (!rc && launch_slice_rows(B.src, 0, B.n, B.n, B.n, *B.out, 0, *B.ex, 0, 1, nullptr, nullptr))
+        rc = fail(MOFEM_E_HIP, "prec_setup: slice launch failed");
+    }
+    if (!rc) HIP_TRY(hipStreamSynchronize(nullptr));
+  }
+  if (!rc && p->precision == MOFEM_PREC_F64_INT8 && !p->Vs_i8)
+    rc = fail(MOFEM_E_UNSUPPORTED, "prec_setup: INT8 transforms take padded widths up to 16384");
   return rc;
 }
 }  // namespace
@@ -856,7 +885,9 @@ extern "C" int mofem_prec_set_coeffs(mofem_prec_t p, double a, double bs, double
 extern "C" int mofem_prec_set_precision(mofem_prec_t p, int precision) {
   clear_error();
   if (!p) return fail(MOFEM_E_ARG, "prec_set_precision: NULL handle");
-  if (precision < MOFEM_PREC_F64 || precision > MOFEM_PREC_BF16_FWD) return fail(MOFEM_E_ARG, "unknown precision");
+  if (precision < MOFEM_PREC_F64 || precision > MOFEM_PREC_F64_INT8) return fail(MOFEM_E_ARG, "unknown precision");
+  if (precision == MOFEM_PREC_F64_INT8 && !p->banded && (p->ps > kOzMaxK || p->pt > kOzMaxK))
+    return fail(MOFEM_E_UNSUPPORTED, "prec_set_precision: INT8 transforms take padded widths up to 16384");
   if (p->banded && precision != MOFEM_PREC_F64)
     return fail(MOFEM_E_UNSUPPORTED, "prec_set_precision: the banded product preconditioner is FP64 only");
   p->precision = precision;
@@ -910,8 +941,8 @@ PrecInput prec_input(mofem_prec_t p, void* ws, size_t ws_bytes, int batch) {
   if (p->banded) return in;  // the solves read R itself
   const size_t items = (size_t)p->ps * p->pt;
   Carve c(ws, ws_bytes);
-  if (p->precision == MOFEM_PREC_F64) {
-    in.f64 = c.take<double>(items * batch);
+  if (p->precision == MOFEM_PREC_F64 || p->precision == MOFEM_PREC_F64_INT8) {
+    in.f64 = c.take<double>(items * batch);  // INT8: cut into digits from there
   } else if (p->precision == MOFEM_PREC_F32) {
     in.f32 = c.take<float>(items * batch);
   } else {
@@ -983,15 +1014,17 @@ int prec_launch(mofem_prec_t p, const double* R, double* Z, long long stride, in
   g.item_scale = item_scale;
   g.out_scale = 1.0;
   g.active = active;
-  const int prec = p->precision == MOFEM_PREC_F64      ? GEMM_F64
-                   : p->precision == MOFEM_PREC_F32    ? GEMM_F32
-                   : p->precision == MOFEM_PREC_BF16   ? GEMM_BF16
-                   : p->precision == MOFEM_PREC_BF16X2 ? GEMM_BF16X2
-                                                       : GEMM_BF16X3;  // BF16X3, BF16_FWD: split branch
+  const int prec = p->precision == MOFEM_PREC_F64        ? GEMM_F64
+                   : p->precision == MOFEM_PREC_F32      ? GEMM_F32
+                   : p->precision == MOFEM_PREC_BF16     ? GEMM_BF16
+                   : p->precision == MOFEM_PREC_BF16X2   ? GEMM_BF16X2
+                   : p->precision == MOFEM_PREC_F64_INT8 ? GEMM_I8
+                                                         : GEMM_BF16X3;  // BF16X3, BF16_FWD: split branch
   const int tcls = prec == GEMM_F64      ? MOFEM_TRACE_GEMM_F64
                    : prec == GEMM_F32    ? MOFEM_TRACE_GEMM_F32
                    : prec == GEMM_BF16   ? MOFEM_TRACE_GEMM_BF16
                    : prec == GEMM_BF16X2 ? MOFEM_TRACE_GEMM_BF16X2
+                   : prec == GEMM_I8     ? MOFEM_TRACE_GEMM_I8
                                          : MOFEM_TRACE_GEMM_BF16X3;
   const int tile = prec_tile(p, batch);
   auto gemm = [&](int omode) -> int {
@@ -1030,6 +1063,51 @@ int prec_launch(mofem_prec_t p, const double* R, double* Z, long long stride, in
     g.a64 = T1; g.a_stride = istr; g.b64 = p->Vt; g.b_stride = 0;
     g.c64 = Z; g.c_stride = stride; g.divide = 0;
     if (gemm(O_F64_RAW)) return fail(MOFEM_E_HIP, "gemm launch");
+  } else if (prec == GEMM_I8) {
+    // FP64 intermediates (R padded, T', S', W in turn), each cut into digit
+    // planes before the product that reads it
+    double* T = c.take<double>(items * batch);
+    signed char* SL = c.take<signed char>((size_t)kOzSlices * items * batch);
+    const int pmax = std::max(p->ps, p->pt);
+    int* EX = c.take<int>((size_t)pmax * batch);
+    if (!T || !SL || !EX) return fail(MOFEM_E_ARG, "prec_apply: workspace too small");
+    if (!p->Vs_i8) return fail(MOFEM_E_UNSUPPORTED, "prec_apply: INT8 transforms take padded widths up to 16384");
+    const long long istr = (long long)items, sstr = (long long)kOzSlices * items;
+    auto slice = [&](const double* X, long long xs, int ld, int M, int K) -> int {
+      TraceScope trace(MOFEM_TRACE_VEC, items_done, s);
+      return launch_slice_rows(X, xs, ld, M, K, SL, sstr, EX, pmax, batch, active, s);
+    };
+    auto gemm8 = [&](int omode) -> int {
+      TraceScope trace(tcls, items_done, s);
+      return launch_gemm_i8(g, omode, batch, s);
+    };
+    // R (raw, or padded by the fused CG update) -> digits
+    if (input_ready ? slice(T, istr, p->pt, p->qs, p->qt) : slice(R, stride, p->qt, p->qs, p->qt))
+      return fail(MOFEM_E_HIP, "slice launch");
+    // G1: T' = (R V_t)^T
+    g.M = p->qs; g.N = p->qt; g.K = p->qt;
+    g.a_i8 = SL; g.a_stride = sstr; g.a_exp = EX; g.a_exp_stride = pmax;
+    g.b_i8 = p->VtT_i8; g.b_stride = 0; g.b_exp = p->VtT_ex; g.b_exp_stride = 0;
+    g.c64 = T; g.c_stride = istr; g.divide = 0;
+    if (gemm8(O_PAD_T) || slice(T, istr, p->ps, p->qt, p->qs)) return fail(MOFEM_E_HIP, "gemm launch");
+    // G2: S' = (V_s^T T ./ D)^T
+    g.M = p->qs; g.N = p->qt; g.K = p->qs;
+    g.a_i8 = p->VsT_i8; g.a_stride = 0; g.a_exp = p->VsT_ex; g.a_exp_stride = 0;
+    g.b_i8 = SL; g.b_stride = sstr; g.b_exp = EX; g.b_exp_stride = pmax;
+    g.c64 = T; g.c_stride = istr; g.divide = 1;
+    if (gemm8(O_PAD_T) || slice(T, istr, p->ps, p->qt, p->qs)) return fail(MOFEM_E_HIP, "gemm launch");
+    // G3: W = V_s S
+    g.M = p->qs; g.N = p->qt; g.K = p->qs;
+    g.a_i8 = p->Vs_i8; g.a_stride = 0; g.a_exp = p->Vs_ex; g.a_exp_stride = 0;
+    g.b_i8 = SL; g.b_stride = sstr; g.b_exp = EX; g.b_exp_stride = pmax;
+    g.c64 = T; g.c_stride = istr; g.divide = 0;
+    if (gemm8(O_PAD_N) || slice(T, istr, p->pt, p->qs, p->qt)) return fail(MOFEM_E_HIP, "gemm launch");
+    // G4: Z = W V_t^T
+    g.M = p->qs; g.N = p->qt; g.K = p->qt;
+    g.a_i8 = SL; g.a_stride = sstr; g.a_exp = EX; g.a_exp_stride = pmax;
+    g.b_i8 = p->Vt_i8; g.b_stride = 0; g.b_exp = p->Vt_ex; g.b_exp_stride = 0;
+    g.c64 = Z; g.c_stride = stride; g.divide = 0;
+    if (gemm8(O_F64_RAW)) return fail(MOFEM_E_HIP, "gemm launch");
   } else if (prec == GEMM_F32) {
     float* T0 = c.take<float>(items * batch);  // padded R
     float* T1 = c.take<float>(items * batch);  // T' then W
@@ -1439,17 +1517,20 @@ int pcg_prepare(PcgRun& r, mofem_op_t op, mofem_prec_t prec, const double* Rhs, 
   r.pin = prec_input(prec, r.w.prec_ws, r.w.prec_bytes, batch);
   // the preconditioned residual of a low-precision preconditioner is kept in
   // FP32 (its own error is far larger); the recurrence stays FP64
-  r.z32 = (!prec->banded && prec->precision != MOFEM_PREC_F64) ? reinterpret_cast<float*>(r.w.Z) : nullptr;
+  r.z32 = (!prec->banded && prec->precision != MOFEM_PREC_F64 && prec->precision != MOFEM_PREC_F64_INT8)
+              ? reinterpret_cast<float*>(r.w.Z)
+              : nullptr;
   return MOFEM_OK;
 }
 
 int trace_class_of(mofem_prec_t p) {
   if (p->banded) return MOFEM_TRACE_BCHOL;
-  return p->precision == MOFEM_PREC_F64      ? MOFEM_TRACE_GEMM_F64
-         : p->precision == MOFEM_PREC_F32    ? MOFEM_TRACE_GEMM_F32
-         : p->precision == MOFEM_PREC_BF16   ? MOFEM_TRACE_GEMM_BF16
-         : p->precision == MOFEM_PREC_BF16X2 ? MOFEM_TRACE_GEMM_BF16X2
-                                             : MOFEM_TRACE_GEMM_BF16X3;
+  return p->precision == MOFEM_PREC_F64        ? MOFEM_TRACE_GEMM_F64
+         : p->precision == MOFEM_PREC_F32      ? MOFEM_TRACE_GEMM_F32
+         : p->precision == MOFEM_PREC_BF16     ? MOFEM_TRACE_GEMM_BF16
+         : p->precision == MOFEM_PREC_BF16X2   ? MOFEM_TRACE_GEMM_BF16X2
+         : p->precision == MOFEM_PREC_F64_INT8 ? MOFEM_TRACE_GEMM_I8
+                                               : MOFEM_TRACE_GEMM_BF16X3;
 }
 
 int status_error(int result) {

@@ -11,8 +11,9 @@
 //   3. Householder reduction of C to tridiagonal T = Q^T C Q;
 //   4. implicit QL iteration with Wilkinson-type shifts on T; the Givens
 //      rotations are recorded and then applied to the eigenvector matrix
-//      in parallel over column blocks;
-//   5. eigenvectors of C: Q z (reflectors applied in reverse order);
+//      in parallel over column blocks, one sweep at a time;
+//   5. eigenvectors of C: Q z (reflectors applied in reverse order, to
+//      blocks of eight eigenvectors at a time);
 //   6. V = L^{-T} (Q z)  by banded back substitution;
 //   7. ascending sort.
 // Threads: steps 2, 3, 4-apply, 5 and 6 split rows/columns over the host
@@ -74,92 +75,164 @@ inline void split(long n, int t, int nt, long* b, long* e) {
 }
 
 // Householder tridiagonalisation of the symmetric q x q row-major matrix A
-// (full storage, overwritten).  On exit d, e hold T (e[i] = T[i][i+1]) and
-// the reflector vectors sit in A[k+1.., k] with factors tau[k].
+// (its lower triangle is read and updated; the upper one goes stale).  On
+// exit d, e hold T (e[i] = T[i][i+1]) and the reflector vectors sit in
+// A[k+1.., k] with factors tau[k].
+// Step k reflects column k of the trailing matrix (rows and columns k+1..):
+// p = tau A v, w = p - (tau / 2)(p . v) v, A -= v w^T + w v^T.  The rank-2
+// update of step k and the product p of step k+1 share one pass over the
+// lower triangle: the next reflector comes from the updated column k+1,
+// which is formed first; every updated entry a_ij (j < i) then adds a_ij v'_j
+// to row i's own p' entry and a_ij v'_i to its row chunk's partial array for
+// p'_j (the chunks' partials are then summed in chunk order).  The rows are
+// cut into NCH chunks of about equal triangle area, dealt to the threads in
+// turn: the arithmetic does not depend on the thread count.
 void tridiagonalise(int q, double* A, double* d, double* e, double* tau) {
-  int nt = q >= 256 ? team_size() : 1;
-  std::vector<double> v(q), p(q), w(q);
-  SpinBarrier bar(nt);
-  // shared scalars for the current step
-  double alpha = 0.0, t_k = 0.0;
-  auto make_reflector = [&](int k) {
-    // x = A[k+1 .. q-1][k]
-    int r = q - k - 1;
-    double xnorm2 = 0.0;
-    for (int i = 1; i < r; ++i) {
-      double xi = A[(size_t)(k + 1 + i) * q + k];
-      xnorm2 += xi * xi;
+  auto at = [&](int i, int j) -> double& { return A[(size_t)i * q + j]; };
+  if (q <= 2) {
+    d[0] = at(0, 0);
+    e[0] = 0.0;
+    tau[0] = 0.0;
+    if (q == 2) {
+      d[1] = at(1, 1);
+      e[0] = at(1, 0);
+      e[1] = 0.0;
+      tau[1] = 0.0;
     }
-    double x0 = A[(size_t)(k + 1) * q + k];
+    return;
+  }
+  const int nt = q >= 256 ? team_size() : 1;
+  constexpr int NCH = 64;
+  std::vector<double> v(q, 0.0), vn(q, 0.0), w(q, 0.0), p(q, 0.0);
+  std::vector<double> part((size_t)NCH * q, 0.0);
+  SpinBarrier bar(nt);
+  double alpha = 0.0, tk = 0.0, alpha_n = 0.0, tk_n = 0.0;
+  // reflector I - t u u^T (u[c+1] = 1) mapping A[c+1 .., c] to al e_1; u holds
+  // absolute indices c+1 .. q-1
+  auto reflector = [&](int c, std::vector<double>& u, double* al, double* t) {
+    const double x0 = at(c + 1, c);
+    double xnorm2 = 0.0;
+    for (int i = c + 2; i < q; ++i) xnorm2 += at(i, c) * at(i, c);
+    u[c + 1] = 1.0;
     if (xnorm2 == 0.0) {
-      alpha = x0;
-      t_k = 0.0;
+      *al = x0;
+      *t = 0.0;
+      for (int i = c + 2; i < q; ++i) u[i] = 0.0;
       return;
     }
-    double nrm = std::sqrt(x0 * x0 + xnorm2);
-    alpha = x0 >= 0.0 ? -nrm : nrm;
-    // v = x - alpha e1, scaled so that v[0] = 1
-    double v0 = x0 - alpha;
-    v[0] = 1.0;
-    for (int i = 1; i < r; ++i) v[i] = A[(size_t)(k + 1 + i) * q + k] / v0;
-    double vtv = 1.0 + xnorm2 / (v0 * v0);
-    t_k = 2.0 / vtv;
+    const double nrm = std::sqrt(x0 * x0 + xnorm2);
+    *al = x0 >= 0.0 ? -nrm : nrm;
+    const double u0 = x0 - *al;
+    for (int i = c + 2; i < q; ++i) u[i] = at(i, c) / u0;
+    *t = 2.0 / (1.0 + xnorm2 / (u0 * u0));
+  };
+  // rows [lo, q) split into nth ranges of about equal lower-triangle area
+  auto rows_of = [&](int lo, int t, int nth, int* b, int* en) {
+    const double m = q - lo, total = m * (m + 1.0) / 2.0;
+    auto first = [&](int tt) {
+      if (tt <= 0) return lo;
+      if (tt >= nth) return q;
+      const double a = total * tt / nth;
+      const int r = (int)std::ceil((std::sqrt(8.0 * a + 1.0) - 1.0) / 2.0);
+      return std::min(q, lo + r);
+    };
+    *b = first(t);
+    *en = first(t + 1);
+  };
+  // p[i] = t (p[i] + sum over the chunks of part[c][i]) for i in [lo, q)
+  auto reduce_p = [&](int lo, double t, int tid, int nth) {
+    long b, en;
+    split(q - lo, tid, nth, &b, &en);
+    for (long ii = b; ii < en; ++ii) {
+      const int i = lo + (int)ii;
+      double s = p[i];
+      for (int c = 0; c < NCH; ++c) s += part[(size_t)c * q + i];
+      p[i] = t * s;
+    }
   };
   run_team(nt, [&](int tid, int nth) {
-    for (int k = 0; k + 2 < q; ++k) {
-      int r = q - k - 1;
-      if (tid == 0) make_reflector(k);
-      bar.wait();
-      if (t_k == 0.0) {
-        if (tid == 0) {
-          d[k] = A[(size_t)k * q + k];
-          e[k] = alpha;
-          tau[k] = 0.0;
-          for (int i = 0; i < r; ++i) A[(size_t)(k + 1 + i) * q + k] = 0.0;
+    // step 0: reflector of column 0 and p = tau A v over rows/columns 1..
+    if (tid == 0) reflector(0, v, &alpha, &tk);
+    bar.wait();
+    for (int c = tid; c < NCH; c += nth) {
+      double* pt = part.data() + (size_t)c * q;
+      int b, en;
+      rows_of(1, c, NCH, &b, &en);
+      std::fill(pt, pt + q, 0.0);
+      for (int i = b; i < en; ++i) {
+        const double* row = A + (size_t)i * q;
+        const double vi = v[i];
+        double sacc = 0.0;
+        for (int j = 1; j < i; ++j) {
+          sacc += row[j] * v[j];
+          pt[j] += row[j] * vi;
         }
-        bar.wait();
-        continue;
+        p[i] = sacc + row[i] * vi;
       }
-      // p = tau * B v over the rows this thread owns
-      long b, en;
-      split(r, tid, nth, &b, &en);
-      for (long i = b; i < en; ++i) {
-        const double* row = A + (size_t)(k + 1 + i) * q + (k + 1);
-        double s = 0.0;
-        for (int j = 0; j < r; ++j) s += row[j] * v[j];
-        p[i] = t_k * s;
-      }
-      bar.wait();
+    }
+    bar.wait();
+    reduce_p(1, tk, tid, nth);
+    bar.wait();
+    for (int k = 0; k + 2 < q; ++k) {
+      const bool next = k + 3 < q;  // a reflector follows this step
       if (tid == 0) {
+        if (k > 0) {
+          std::swap(v, vn);
+          alpha = alpha_n;
+          tk = tk_n;
+        }
         double ptv = 0.0;
-        for (int i = 0; i < r; ++i) ptv += p[i] * v[i];
-        double K = 0.5 * t_k * ptv;
-        for (int i = 0; i < r; ++i) w[i] = p[i] - K * v[i];
-      }
-      bar.wait();
-      for (long i = b; i < en; ++i) {
-        double* row = A + (size_t)(k + 1 + i) * q + (k + 1);
-        double vi = v[i], wi = w[i];
-        for (int j = 0; j < r; ++j) row[j] -= vi * w[j] + wi * v[j];
-      }
-      bar.wait();
-      if (tid == 0) {
-        d[k] = A[(size_t)k * q + k];
+        for (int i = k + 1; i < q; ++i) ptv += p[i] * v[i];
+        const double K = 0.5 * tk * ptv;
+        for (int i = k + 1; i < q; ++i) w[i] = p[i] - K * v[i];
+        d[k] = at(k, k);
         e[k] = alpha;
-        tau[k] = t_k;
-        for (int i = 0; i < r; ++i) A[(size_t)(k + 1 + i) * q + k] = v[i];
+        tau[k] = tk;
+        for (int i = k + 1; i < q; ++i) at(i, k) = v[i];
+        // column k+1 of the updated trailing matrix, diagonal included
+        for (int i = k + 1; i < q; ++i) at(i, k + 1) -= v[i] * w[k + 1] + w[i] * v[k + 1];
+        if (next) reflector(k + 1, vn, &alpha_n, &tk_n);
       }
       bar.wait();
+      // rows k+2.., columns k+2 .. i: the update, and the next product
+      for (int c = tid; c < NCH; c += nth) {
+        double* pt = part.data() + (size_t)c * q;
+        int b, en;
+        rows_of(k + 2, c, NCH, &b, &en);
+        if (next) std::fill(pt + k + 2, pt + q, 0.0);
+        for (int i = b; i < en; ++i) {
+          double* row = A + (size_t)i * q;
+          const double vi = v[i], wi = w[i];
+          if (next) {
+            const double vni = vn[i];
+            double sacc = 0.0;
+            for (int j = k + 2; j < i; ++j) {
+              const double a = row[j] - (vi * w[j] + wi * v[j]);
+              row[j] = a;
+              sacc += a * vn[j];
+              pt[j] += a * vni;
+            }
+            const double a = row[i] - (vi * wi + wi * vi);
+            row[i] = a;
+            p[i] = sacc + a * vni;
+          } else {
+            for (int j = k + 2; j <= i; ++j) row[j] -= vi * w[j] + wi * v[j];
+          }
+        }
+      }
+      bar.wait();
+      if (next) {
+        reduce_p(k + 2, tk_n, tid, nth);
+        bar.wait();
+      }
     }
   });
-  if (q >= 2) {
-    d[q - 2] = A[(size_t)(q - 2) * q + (q - 2)];
-    e[q - 2] = A[(size_t)(q - 1) * q + (q - 2)];
-  }
-  d[q - 1] = A[(size_t)(q - 1) * q + (q - 1)];
-  if (q >= 1) e[q - 1] = 0.0;
-  if (q >= 2) tau[q - 2] = 0.0;
-  if (q >= 1) tau[q - 1] = 0.0;
+  d[q - 2] = at(q - 2, q - 2);
+  e[q - 2] = at(q - 1, q - 2);
+  d[q - 1] = at(q - 1, q - 1);
+  e[q - 1] = 0.0;
+  tau[q - 2] = 0.0;
+  tau[q - 1] = 0.0;
 }
 
 struct Rot {
@@ -168,13 +241,14 @@ struct Rot {
 };
 
 // Implicit QL on the tridiagonal (d, e); appends every Givens rotation
-// (acting on eigenvector-matrix rows i, i+1) to `rots`.  Returns false if an
+// (acting on eigenvector-matrix rows i, i+1) to `rots` and the index of each
+// sweep's first rotation to `sweeps`.  Returns false if an
 // eigenvalue needs more than 60 sweeps.  The sweep is the published implicit
 // QL algorithm with Wilkinson-type shifts (Bowdler, Martin, Reinsch and
 // Wilkinson, "The QR and QL algorithms for symmetric matrices", Numer. Math.
 // 11 (1968), as distributed in EISPACK's tql2), so its step order follows that
 // algorithm.
-bool ql_implicit(int n, double* d, double* e, std::vector<Rot>& rots) {
+bool ql_implicit(int n, double* d, double* e, std::vector<Rot>& rots, std::vector<size_t>& sweeps) {
   const double eps = std::numeric_limits<double>::epsilon();
   for (int l = 0; l < n; ++l) {
     int iter = 0;
@@ -191,6 +265,7 @@ bool ql_implicit(int n, double* d, double* e, std::vector<Rot>& rots) {
       g = d[m] - d[l] + e[l] / (g + std::copysign(r, g));
       double s = 1.0, c = 1.0, p = 0.0;
       bool early = false;
+      sweeps.push_back(rots.size());  // a sweep's rotations act on rows m-1, m-2, .. in turn
       for (int i = m - 1; i >= l; --i) {
         double f = s * e[i], b = c * e[i];
         r = std::hypot(f, g);
@@ -275,49 +350,185 @@ int geneig_dense(int q, int kb, const double* K, const double* M, double* lam, d
   std::vector<double> d(q), e(q), tau(q);
   tridiagonalise(q, C.data(), d.data(), e.data(), tau.data());
 
-  // 4. QL with recorded rotations; Z rows = eigenvectors of T (starts as I)
+  // 4. QL with recorded rotations; Z rows = eigenvectors of T (starts as I).
+  // Z is padded to whole blocks of NB rows and NR columns (zeros stay zeros).
   std::vector<Rot> rots;
+  std::vector<size_t> sweeps;
   rots.reserve((size_t)q * 8);
-  if (!ql_implicit(q, d.data(), e.data(), rots)) return MOFEM_E_NUMERIC;
-  std::vector<double> Z((size_t)q * q, 0.0);
-  for (int i = 0; i < q; ++i) Z[(size_t)i * q + i] = 1.0;
+  if (!ql_implicit(q, d.data(), e.data(), rots, sweeps)) return MOFEM_E_NUMERIC;
+  sweeps.push_back(rots.size());
+  constexpr int NR = 32, NB = 8;
+  const long ldz = (q + NR - 1) / NR * NR;
+  const long rows = (q + NB - 1) / NB * NB;
+  std::vector<double> Z((size_t)rows * ldz, 0.0);
+  for (int i = 0; i < q; ++i) Z[(size_t)i * ldz + i] = 1.0;
+  // (c, s) of every rotation, sweep by sweep (row indices implied)
+  std::vector<double> cs(2 * rots.size() + 2);
+  for (size_t r = 0; r < rots.size(); ++r) {
+    cs[2 * r] = rots[r].c;
+    cs[2 * r + 1] = rots[r].s;
+  }
   // rotation (i, c, s) acts on rows i, i+1 of Z:
-  //   f = Z[i+1]; Z[i+1] = s Z[i] + c f; Z[i] = c Z[i] - s f
-  // (row j of Z is the j-th eigenvector of T written in the basis of e_c)
-  parallel_for(q, 32, [&](long c0, long c1) {
-    for (const Rot& R : rots) {
-      double* zi = Z.data() + (size_t)R.i * q;
-      double* zj = zi + q;
-      for (long c = c0; c < c1; ++c) {
-        double f = zj[c];
-        zj[c] = R.s * zi[c] + R.c * f;
-        zi[c] = R.c * zi[c] - R.s * f;
+  //   f = Z[i+1]; Z[i+1] = s Z[i] + c f; Z[i] = c Z[i] - s f.
+  // Within a sweep the next rotation acts on rows i-1, i, so the new row i is
+  // carried in registers: one load and one store per rotation and column.
+  // Columns in blocks of NR (a block of Z stays in cache while the rotation
+  // list streams past), blocks in parallel.
+  parallel_for(ldz / NR, 1, [&](long b0, long b1) {
+    for (long cb = b0; cb < b1; ++cb) {
+      double* zc = Z.data() + cb * NR;
+      for (size_t w = 0; w + 1 < sweeps.size(); ++w) {
+        const size_t r0 = sweeps[w], r1 = sweeps[w + 1];
+        if (r0 == r1) continue;
+        const int top = rots[r0].i + 1;
+        double carry[NR];
+        const double* zt = zc + (size_t)top * ldz;
+        for (int c = 0; c < NR; ++c) carry[c] = zt[c];
+        const double* rc = cs.data() + 2 * r0;
+        int i = top - 1;
+        for (size_t r = r0; r < r1; ++r, --i, rc += 2) {
+          const double co = rc[0], si = rc[1];
+          const double* __restrict__ zi = zc + (size_t)i * ldz;
+          double* __restrict__ zj = zc + (size_t)(i + 1) * ldz;
+          for (int c = 0; c < NR; ++c) {
+            const double x = zi[c], f = carry[c];
+            zj[c] = si * x + co * f;
+            carry[c] = co * x - si * f;
+          }
+        }
+        double* zb = zc + (size_t)(i + 1) * ldz;
+        for (int c = 0; c < NR; ++c) zb[c] = carry[c];
       }
     }
   });
   rots.clear();
   rots.shrink_to_fit();
+  cs.clear();
+  cs.shrink_to_fit();
   // Row j of Z is eigenvector j of T (the rotations act on eigenvector pairs).
   std::vector<double>& Y = Z;
 
-  // 5 + 6. apply reflectors H_{q-3} .. H_0, then solve L^T v = x, per eigenvector
-  parallel_for(q, 8, [&](long j0, long j1) {
-    std::vector<double> x(q);
-    for (long j = j0; j < j1; ++j) {
-      double* y = Y.data() + (size_t)j * q;
-      for (int k = q - 3; k >= 0; --k) {
-        if (tau[k] == 0.0) continue;
-        // v stored in C[k+1 .., k]
-        double s = 0.0;
-        for (int i = k + 1; i < q; ++i) s += C[(size_t)i * q + k] * y[i];
-        s *= tau[k];
-        for (int i = k + 1; i < q; ++i) y[i] -= s * C[(size_t)i * q + k];
+  // 5. reflector k (k = 0 .. q-3) packed contiguously: v_k = C[k+1 .., k]
+  std::vector<size_t> off(q > 2 ? q - 2 : 1);
+  size_t tot = 0;
+  for (int k = 0; k + 2 < q; ++k) {
+    off[k] = tot;
+    tot += (size_t)(q - k - 1);
+  }
+  std::vector<double> Vr(tot > 0 ? tot : 1);
+  parallel_for(q > 2 ? q - 2 : 0, 16, [&](long k0, long k1) {
+    for (long k = k0; k < k1; ++k)
+      for (int i = 0; i < q - k - 1; ++i) Vr[off[k] + i] = C[(size_t)(k + 1 + i) * q + k];
+  });
+  C.clear();
+  C.shrink_to_fit();
+  // Reflectors are applied GR at a time (k = k1, k1 - 1, .., k1 - GR + 1):
+  // with d_j = v_j^T y (one pass over y for the whole group) the factors of
+  // the successive reflections are s_k1 = tau_k1 d_k1 and
+  //   s_j = tau_j (d_j - sum_{i > j in the group} (v_j^T v_i) s_i),
+  // and y -= sum_j s_j v_j (a second pass): two passes over y per group
+  // instead of two per reflector.  The Gram entries v_j^T v_i are shared by
+  // every block of eigenvectors.
+  constexpr int GR = 4;
+  const int nref = q > 2 ? q - 2 : 0;
+  const int ngroups = (nref + GR - 1) / GR;
+  auto vat = [&](int j, int i) { return i >= j + 1 ? Vr[off[j] + (i - j - 1)] : 0.0; };
+  // group g holds k1 = nref - 1 - g GR down to max(0, k1 - GR + 1)
+  std::vector<double> gram((size_t)ngroups * GR * GR, 0.0);
+  parallel_for(ngroups, 8, [&](long g0, long g1) {
+    for (long g = g0; g < g1; ++g) {
+      const int k1 = nref - 1 - (int)g * GR;
+      for (int a = 0; a < GR; ++a)
+        for (int b = 0; b < a; ++b) {
+          const int ja = k1 - a, jb = k1 - b;  // ja < jb
+          if (ja < 0) continue;
+          double acc = 0.0;
+          for (int i = jb + 1; i < q; ++i) acc += vat(ja, i) * vat(jb, i);
+          gram[((size_t)g * GR + a) * GR + b] = acc;
+        }
+    }
+  });
+  // 5 + 6. per block of NB eigenvectors, interleaved (entry i of the block's
+  // vectors contiguous): apply H_{q-3} .. H_0, then solve L^T v = x for each
+  parallel_for(rows / NB, 1, [&](long b0, long b1) {
+    std::vector<double> yt((size_t)q * NB);
+    for (long jb = b0; jb < b1; ++jb) {
+      double* yb = Y.data() + (size_t)jb * NB * ldz;
+      for (int t = 0; t < NB; ++t)
+        for (int i = 0; i < q; ++i) yt[(size_t)i * NB + t] = yb[(size_t)t * ldz + i];
+      for (int g = 0; g < ngroups; ++g) {
+        const int k1 = nref - 1 - g * GR;
+        const int ng = std::min(GR, k1 + 1);  // reflectors k1 .. k1 - ng + 1
+        const int kl = k1 - ng + 1;
+        double d[GR][NB] = {};
+        // head rows kl+1 .. k1 (some reflectors still zero there)
+        for (int i = kl + 1; i <= k1 && i < q; ++i) {
+          const double* yi = yt.data() + (size_t)i * NB;
+          for (int a = 0; a < ng; ++a) {
+            const double va = vat(k1 - a, i);
+            for (int t = 0; t < NB; ++t) d[a][t] += va * yi[t];
+          }
+        }
+        // bulk rows k1+1 .. q-1
+        const double* vp[GR];
+        for (int a = 0; a < GR; ++a) vp[a] = a < ng ? Vr.data() + off[k1 - a] + a : nullptr;
+        if (ng == GR) {
+          for (int i = k1 + 1; i < q; ++i) {
+            const double* yi = yt.data() + (size_t)i * NB;
+            const int o = i - k1 - 1;
+            for (int a = 0; a < GR; ++a) {
+              const double va = vp[a][o];
+              for (int t = 0; t < NB; ++t) d[a][t] += va * yi[t];
+            }
+          }
+        } else {
+          for (int i = k1 + 1; i < q; ++i) {
+            const double* yi = yt.data() + (size_t)i * NB;
+            const int o = i - k1 - 1;
+            for (int a = 0; a < ng; ++a) {
+              const double va = vp[a][o];
+              for (int t = 0; t < NB; ++t) d[a][t] += va * yi[t];
+            }
+          }
+        }
+        // factors of the successive reflections
+        double sf[GR][NB] = {};
+        for (int a = 0; a < ng; ++a) {
+          const double ta = tau[k1 - a];
+          for (int t = 0; t < NB; ++t) {
+            double x = d[a][t];
+            for (int b = 0; b < a; ++b) x -= gram[((size_t)g * GR + a) * GR + b] * sf[b][t];
+            sf[a][t] = ta * x;
+          }
+        }
+        for (int i = kl + 1; i <= k1 && i < q; ++i) {
+          double* yi = yt.data() + (size_t)i * NB;
+          for (int a = 0; a < ng; ++a) {
+            const double va = vat(k1 - a, i);
+            for (int t = 0; t < NB; ++t) yi[t] -= sf[a][t] * va;
+          }
+        }
+        for (int i = k1 + 1; i < q; ++i) {
+          double* __restrict__ yi = yt.data() + (size_t)i * NB;
+          const int o = i - k1 - 1;
+          for (int a = 0; a < ng; ++a) {
+            const double va = vp[a][o];
+            for (int t = 0; t < NB; ++t) yi[t] -= sf[a][t] * va;
+          }
+        }
       }
       for (int i = q - 1; i >= 0; --i) {
-        double s = y[i];
-        for (int p = i + 1; p <= std::min(q - 1, i + kb); ++p) s -= Lat(p, i) * y[p];
-        y[i] = s / Lat(i, i);
+        double* __restrict__ yi = yt.data() + (size_t)i * NB;
+        for (int p = i + 1; p <= std::min(q - 1, i + kb); ++p) {
+          const double l = Lat(p, i);
+          const double* yp = yt.data() + (size_t)p * NB;
+          for (int t = 0; t < NB; ++t) yi[t] -= l * yp[t];
+        }
+        const double dii = Lat(i, i);
+        for (int t = 0; t < NB; ++t) yi[t] /= dii;
       }
+      for (int t = 0; t < NB; ++t)
+        for (int i = 0; i < q; ++i) yb[(size_t)t * ldz + i] = yt[(size_t)i * NB + t];
     }
   });
 
@@ -331,7 +542,7 @@ int geneig_dense(int q, int kb, const double* K, const double* M, double* lam, d
   }
   parallel_for(q, 16, [&](long r0, long r1) {
     for (long i = r0; i < r1; ++i)
-      for (int j = 0; j < q; ++j) V[(size_t)i * q + j] = Y[(size_t)order[j] * q + i];
+      for (int j = 0; j < q; ++j) V[(size_t)i * q + j] = Y[(size_t)order[j] * ldz + i];
   });
   return MOFEM_OK;
 }

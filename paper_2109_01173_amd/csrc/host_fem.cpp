@@ -30,13 +30,29 @@ int fail(int code, const std::string& msg) {
 }
 const char* last_error_cstr() { return g_last_error.c_str(); }
 
-int host_threads() {
+namespace {
+int default_threads() {
   static int n = [] {
     unsigned h = std::thread::hardware_concurrency();
     int t = h ? (int)h : 4;
     return t > 16 ? 16 : t;
   }();
   return n;
+}
+std::atomic<int> g_host_threads{0};  // 0: default_threads()
+thread_local int t_thread_share = 0;  // > 0: this thread's calls use that many
+}  // namespace
+
+int host_threads() {
+  if (t_thread_share > 0) return t_thread_share;
+  const int g = g_host_threads.load(std::memory_order_relaxed);
+  return g > 0 ? g : default_threads();
+}
+
+int set_thread_share(int n) {
+  const int prev = t_thread_share;
+  t_thread_share = n > 0 ? n : 0;
+  return prev;
 }
 
 void parallel_for(long n, long min_chunk, const std::function<void(long, long)>& fn) {
@@ -234,4 +250,11 @@ extern "C" int mofem_assemble_1d(int order, int m_elem, double x0, double x1, in
   for (size_t i = 0; i < (size_t)(2 * kb + 1) * n; ++i)
     if (!std::isfinite(band[i])) return fail(MOFEM_E_NOTFINITE, "assemble_1d: weight produced a non-finite value");
   return MOFEM_OK;
+}
+
+extern "C" int mofem_set_host_threads(int n) {
+  clear_error();
+  const int prev = mofem::host_threads();
+  mofem::g_host_threads.store(n > 0 ? (n > 256 ? 256 : n) : 0, std::memory_order_relaxed);
+  return prev;
 }

@@ -66,7 +66,7 @@ int launch_bchol(const BcholArgs& a, int kb, int batch, hipStream_t s);
 constexpr int kPad = 128;
 __host__ __device__ inline int pad_up(int x) { return (x + kPad - 1) / kPad * kPad; }
 
-enum GemmPrec { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_BF16 = 2, GEMM_BF16X3 = 3, GEMM_BF16X2 = 4 };
+enum GemmPrec { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_BF16 = 2, GEMM_BF16X3 = 3, GEMM_BF16X2 = 4, GEMM_I8 = 5 };
 // raw: row-major ld = N, FP64 or (FP32 and BF16 products only) FP32 into c_hi
 enum GemmOMode { O_PAD_T = 0, O_PAD_N = 1, O_F64_RAW = 2, O_F32_RAW = 3 };
 
@@ -96,9 +96,28 @@ struct GemmArgs {
   double out_scale;        // multiply the result (before the epilogue division)
   const int* active;
   int data_is_a;           // GEMM_BF16X2: the split (data) operand is A (else B)
+  // GEMM_I8 (k_ozaki.hip): kOzSlices digit planes per operand and item,
+  // [plane][pad_up(rows)][pad_up(K)] int8, a_stride / b_stride in bytes; row
+  // exponents [pad_up(rows)] per item (stride 0 = shared)
+  const signed char* a_i8;
+  const signed char* b_i8;
+  const int* a_exp;
+  const int* b_exp;
+  long long a_exp_stride, b_exp_stride;
 };
 // tile: block tile edge, 128 (4 waves of 64 x 64) or 64 (4 waves of 32 x 32)
 int launch_gemm(const GemmArgs& g, int prec, int omode, int batch, int tile, hipStream_t s);
+// FP64-accurate products from exact INT8 slice products (k_ozaki.hip):
+// kOzSlices 7-bit digits per entry, K (padded) at most kOzMaxK so that the
+// int32 diagonal sums cannot overflow
+constexpr int kOzSlices = 7;
+constexpr int kOzMaxK = 16384;
+// rows of X (M x K, row length ld, item stride xs) -> digit planes (item
+// stride os bytes, planes of pad_up(M) x pad_up(K)) and row exponents (item
+// stride es); every padded row is written
+int launch_slice_rows(const double* X, long long xs, int ld, int M, int K, signed char* out, long long os, int* ex,
+                      long long es, int batch, const int* active, hipStream_t s);
+int launch_gemm_i8(const GemmArgs& g, int omode, int batch, hipStream_t s);
 // raw FP64 items (M x K) -> padded FP64, FP32 or split BF16 operand
 int launch_pad_operand(const double* A, long long a_stride, int M, int K, double* o64, float* o32,
                        unsigned short* ohi, unsigned short* olo, long long o_stride, int split, int batch,

@@ -19,7 +19,12 @@ int fail(int code, const std::string& msg);
 // Run fn(begin, end) over [0, n) split into contiguous chunks on up to
 // host_threads() threads (serially when n is small).
 void parallel_for(long n, long min_chunk, const std::function<void(long, long)>& fn);
+// threads of one host-side call: mofem_set_host_threads, or the hardware's
+// (at most 16), or the calling thread's share (set_thread_share)
 int host_threads();
+// give the calling thread's host-side calls n threads (0: the process
+// setting); returns the previous share
+int set_thread_share(int n);
 
 // ---- one-dimensional assembly (host_fem.cpp) --------------------------------
 void gauss_legendre01(int nq, double* x, double* w);

@@ -31,12 +31,12 @@ E_ARG, E_HIP, E_NOMEM, E_BREAKDOWN, E_MAXIT, E_UNSUPPORTED, E_NOTFINITE, E_NUMER
     -1, -2, -3, -4, -5, -6, -7, -8)
 W_ONE, W_POLY, W_PROFILE, W_PROFILE_D, W_PROFILE_INV, W_PROFILE_D2L, W_CALLBACK = range(7)
 W_PPROFILE_D, W_PPROFILE_INV, W_PPROFILE_D2L = 7, 8, 9
-PREC_F64, PREC_F32, PREC_BF16, PREC_BF16X3, PREC_BF16X2, PREC_BF16_FWD = range(6)
+PREC_F64, PREC_F32, PREC_BF16, PREC_BF16X3, PREC_BF16X2, PREC_BF16_FWD, PREC_F64_INT8 = range(7)
 PCG_FLEXIBLE, PCG_ZERO_GUESS, PCG_TAU_STOP = 1, 2, 4
 KIN_NONE, KIN_DIB = 0, 1
 (TRACE_BAND, TRACE_GEMM_F64, TRACE_GEMM_BF16X3, TRACE_GEMM_BF16, TRACE_VEC, TRACE_GEMM_BF16X2, TRACE_GEMM_F32,
- TRACE_BCHOL) = range(8)
-TRACE_CLASSES = 8
+ TRACE_BCHOL, TRACE_GEMM_I8) = range(9)
+TRACE_CLASSES = 9
 MAX_TERMS = 8
 MAX_SCALES = 8
 
@@ -116,6 +116,7 @@ mofem_assemble_1d = _proto("mofem_assemble_1d", ctypes.c_int,
                             ctypes.c_int, ctypes.c_int, ctypes.POINTER(Weight), ctypes.c_int, _vp])
 mofem_geneig_host = _proto("mofem_geneig_host", ctypes.c_int,
                            [ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp, _vp])
+mofem_set_host_threads = _proto("mofem_set_host_threads", ctypes.c_int, [ctypes.c_int])
 mofem_eig_p1_closed = _proto("mofem_eig_p1_closed", ctypes.c_int,
                              [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, _vp, _vp])
 mofem_op_create = _proto("mofem_op_create", ctypes.c_int, [ctypes.POINTER(OpDesc), ctypes.POINTER(_vp)])
@@ -172,6 +173,7 @@ mofem_trace_read = _proto("mofem_trace_read", ctypes.c_int,
                           [ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_longlong), _dp])
 
 EXPORTS = ["mofem_version", "mofem_last_error", "mofem_assemble_1d", "mofem_geneig_host", "mofem_eig_p1_closed",
+           "mofem_set_host_threads",
            "mofem_prec_setup_eig",
            "mofem_op_create", "mofem_op_destroy", "mofem_op_shape", "mofem_op_apply", "mofem_op_apply_noalloc",
            "mofem_prec_setup", "mofem_prec_destroy", "mofem_prec_set_coeffs",
@@ -220,6 +222,12 @@ def assemble_1d(order, m_elem, di, dj, w=None, x0=0.0, x1=1.0, nq=0):
                            nq, _hptr(band))
     _check(rc, "mofem_assemble_1d")
     return band
+
+
+def set_host_threads(n):
+    """Host threads of one host-side call (0 restores the default); returns
+    the previous count."""
+    return int(mofem_set_host_threads(int(n)))
 
 
 def geneig_host(K_band, M_band, trim):

@@ -141,9 +141,11 @@ def test_fullsize_solve(full, oracle_ref):
         assert rel(Uh[b], oracle_ref[b]) < 1e-8, b
 
 
-def test_fullsize_solve_fp64(full, oracle_ref):
-    """The FP64 path of the bench (FP64 transforms, standard PCG) at the same
-    size: every item to 1e-10 on the true residual; items 0 and 15 within
+@pytest.mark.parametrize("precision", ["F64", "F64_INT8"])
+def test_fullsize_solve_fp64(full, oracle_ref, precision):
+    """The FP64-accurate paths of the bench (FP64 transforms on FP64 MFMA, or
+    the same transforms from exact INT8 digit products; standard PCG) at the
+    same size: every item to 1e-10 on the true residual; items 0 and 15 within
     1e-10 of the oracle's reference solution (forward) and, under the
     oracle's load and operator, within their GPU residual plus the measured
     rounding difference of the two FP64 operator evaluations (backward; that
@@ -154,7 +156,7 @@ def test_fullsize_solve_fp64(full, oracle_ref):
     G, P, F, _ = full
     rhs = G.rhs_op.apply(to_dev(F))
     U = torch.empty_like(rhs)
-    G.prec.set_precision(mf.PREC_F64)
+    G.prec.set_precision(getattr(mf, "PREC_" + precision))
     try:
         its, relres, _ = mf.pcg_solve(G.op, G.prec, rhs, U, tol=1e-10, maxit=300, flags=mf.PCG_ZERO_GUESS)
     finally:

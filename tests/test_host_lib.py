@@ -82,7 +82,10 @@ def test_assembly_interval_and_callback():
     assert len(calls) == 3 * 12
 
 
-@pytest.mark.parametrize("k,m,trim", [(1, 40, 1), (2, 30, 1), (3, 20, 0), (4, 15, 1)])
+# sizes around the solver's blocking (blocks of 8 and 32 eigenvector entries,
+# groups of four reflectors) and degenerate orders: q = 1, 2, 5, 256, 301, 209
+@pytest.mark.parametrize("k,m,trim", [(1, 40, 1), (2, 30, 1), (3, 20, 0), (4, 15, 1), (1, 2, 1), (1, 3, 1),
+                                      (1, 4, 0), (1, 257, 1), (2, 150, 0), (3, 70, 1)])
 def test_geneig_matches_scipy(k, m, trim):
     K = mf.assemble_1d(k, m, 1, 1, mf.weight(mf.W_PROFILE, PROF))
     M = mf.assemble_1d(k, m, 0, 0, mf.weight(mf.W_PROFILE, PROF))
@@ -95,6 +98,25 @@ def test_geneig_matches_scipy(k, m, trim):
     assert np.abs(V.T @ Md @ V - np.eye(V.shape[0])).max() < 1e-12
     res = Kd @ V - Md @ V * lam
     assert np.linalg.norm(res) <= 1e-13 * np.linalg.norm(Kd, 2) * np.linalg.norm(V)
+
+
+def test_geneig_independent_of_host_threads():
+    """Every entry is computed by one thread in a fixed order, so the result
+    does not depend on the thread count (mofem_set_host_threads)."""
+    K = mf.assemble_1d(2, 150, 1, 1, mf.weight(mf.W_PROFILE, PROF))   # q = 299: the threaded path
+    M = mf.assemble_1d(2, 150, 0, 0, mf.weight(mf.W_PROFILE, PROF))
+    lam1, V1 = mf.geneig_host(K, M, 1)
+    prev = mf.set_host_threads(1)
+    try:
+        assert mf.set_host_threads(3) == 1
+        lam3, V3 = mf.geneig_host(K, M, 1)
+        mf.set_host_threads(1)
+        lam0, V0 = mf.geneig_host(K, M, 1)
+    finally:
+        mf.set_host_threads(0)
+    assert prev >= 1
+    assert np.array_equal(lam0, lam1) and np.array_equal(V0, V1)
+    assert np.array_equal(lam3, lam1) and np.array_equal(V3, V1)
 
 
 def test_geneig_rejects_indefinite_mass():
@@ -182,3 +204,14 @@ def test_closed_form_rejects_consistent_neumann():
     with pytest.raises(mf.MofemError) as e:
         mf.eig_p1_closed(16, 1.0, lumped=False, dirichlet=False)
     assert e.value.code == mf.E_UNSUPPORTED
+
+
+def test_header_constants_match_binding():
+    """Every MOFEM_PREC_* and MOFEM_TRACE_* value of include/mofem.h equals the
+    binding's constant of the same name."""
+    import re
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "mofem.h")).read()
+    found = re.findall(r"MOFEM_((?:PREC|TRACE)_[A-Z0-9_]+)\s*=\s*(\d+)", hdr)
+    assert len(found) >= 15
+    for name, val in found:
+        assert getattr(mf, name) == int(val), name
