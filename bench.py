@@ -114,8 +114,10 @@ def uneven_leg(mf, torch, np, n_inst, prec, prec_name, rds_steps=100):
     instances of one type form one batched group.  The elliptic groups are
     solved one after another (pcg_solve) and together on four streams
     (pcg_solve_many); the reaction-diffusion groups step one after another.
-    The groups' set-up (assembly, eigen-decompositions) runs on a pool of host
-    threads."""
+    The elliptic groups are also solved grouped by shape (pcg_solve_many
+    with grouped=True: one batched solve per shape class, all element orders
+    in the same launches), which the whole-job time uses.  The groups' set-up
+    (assembly, eigen-decompositions) runs on a pool of host threads."""
     from paper_2109_01173_amd.problems import Rect, XNormal
     from workloads import dib_initial, dib_params, elliptic_batch
     rng = np.random.default_rng(5)
@@ -190,6 +192,27 @@ def uneven_leg(mf, torch, np, n_inst, prec, prec_name, rds_steps=100):
     torch.cuda.synchronize()
     dt_many = time.perf_counter() - t
     its = np.concatenate([o[0] for o in outs]) if outs else np.zeros(1)
+    # grouped: one batched solve per shape class (one launch per stage over its
+    # instances of every k), the classes on their own streams
+    shape_of = sorted({int(g["rhs"].shape[1]) for g in groups})
+    gstreams = [streams[shape_of.index(int(g["rhs"].shape[1])) % 4] for g in groups]
+    mf.pcg_solve_many(groups, gstreams, grouped=True)   # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    outs_g, status_g = mf.pcg_solve_many(groups, gstreams, grouped=True)
+    torch.cuda.synchronize()
+    dt_grp = time.perf_counter() - t
+    its_g = np.concatenate([o[0] for o in outs_g]) if outs_g else np.zeros(1)
+    # each shape class alone (where the grouped time goes)
+    class_ms = {}
+    for q_c in shape_of:
+        idx = [i for i, g in enumerate(groups) if int(g["rhs"].shape[1]) == q_c]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        mf.pcg_solve_many([groups[i] for i in idx], [streams[0]] * len(idx), grouped=True)
+        torch.cuda.synchronize()
+        class_ms[str(q_c)] = [sum(int(groups[i]["rhs"].shape[0]) for i in idx),
+                              round((time.perf_counter() - t) * 1e3, 2)]
     rds_its = []
     t = time.perf_counter()
     for r in rds:
@@ -198,12 +221,12 @@ def uneven_leg(mf, torch, np, n_inst, prec, prec_name, rds_steps=100):
     torch.cuda.synchronize()
     dt_rds = time.perf_counter() - t
     finite = all(bool(torch.isfinite(r["st"]).all()) for r in rds)
-    job = dt_many + dt_rds
-    log("uneven batch: %d instances (%d elliptic in %d groups, %d reaction-diffusion in %d groups): elliptic "
-        "%.1f solves/s one group at a time, %.1f together; reaction-diffusion %.1f instance-steps/s "
-        "(%d steps each); whole job %.2f s = %.1f instances/s"
-        % (n_inst, n_ell, len(groups), n_rds, len(rds), n_ell / dt_seq, n_ell / dt_many,
-           n_rds * rds_steps / dt_rds if dt_rds > 0 else 0.0, rds_steps, job, n_inst / job))
+    job = dt_grp + dt_rds
+    log("uneven batch: %d instances (%d elliptic in %d groups, %d shapes, %d reaction-diffusion in %d groups): "
+        "elliptic %.1f solves/s one group at a time, %.1f groups on streams, %.1f grouped by shape; "
+        "reaction-diffusion %.1f instance-steps/s (%d steps each); whole job %.2f s = %.1f instances/s"
+        % (n_inst, n_ell, len(groups), len(shape_of), n_rds, len(rds), n_ell / dt_seq, n_ell / dt_many,
+           n_ell / dt_grp, n_rds * rds_steps / dt_rds if dt_rds > 0 else 0.0, rds_steps, job, n_inst / job))
     return {"uneven_batch": {"workload": "%d instances, n in {257,513,1025,2049}, k in 1..4, type in {elliptic, "
                                          "reaction-diffusion} (seed 5); elliptic: P_k x-normal, Dirichlet, gamma=1, "
                                          "rel 1e-8, %s transforms; reaction-diffusion: DIB rectangle [0,20]^2, "
@@ -212,7 +235,10 @@ def uneven_leg(mf, torch, np, n_inst, prec, prec_name, rds_steps=100):
                              "elliptic_instances": n_ell, "elliptic_groups": len(groups),
                              "solves_per_s_sequential": round(n_ell / dt_seq, 2),
                              "solves_per_s_streams": round(n_ell / dt_many, 2), "streams": 4,
-                             "iterations_max": int(its.max()), "status_ok": all(st == 0 for st in status),
+                             "solves_per_s_grouped": round(n_ell / dt_grp, 2), "shape_classes": len(shape_of),
+                             "class_items_ms": class_ms,
+                             "iterations_max": int(max(its.max(), its_g.max())),
+                             "status_ok": all(st == 0 for st in status + status_g),
                              "rds_instances": n_rds, "rds_groups": len(rds),
                              "rds_instance_steps_per_s": round(n_rds * rds_steps / dt_rds, 2) if dt_rds > 0 else None,
                              "rds_iterations_max": max(rds_its) if rds_its else 0, "rds_finite": finite,

@@ -181,8 +181,8 @@ typedef struct mofem_op_s* mofem_op_t;
    that share a factor are merged on the host before upload (c1 L1 X R +
    c2 L2 X R = (c1 L1 + c2 L2) X R, e.g. eq. (73)'s (B1 + gamma M3) U M from
    the two terms B1 U M and gamma M3 U M; likewise a shared left factor).  Up
-   to six distinct terms run as one kernel pass; seven or eight as two
-   passes, the second adding to Y.
+   to six distinct terms (kb <= 2) or four (kb >= 3) run as one kernel pass;
+   the rest (at most MOFEM_MAX_TERMS in all) as a second pass adding to Y.
    Errors: MOFEM_E_ARG (sizes, kb, n_terms outside 1..MOFEM_MAX_TERMS, NULL
    bands), MOFEM_E_NOTFINITE (a non-finite band entry), MOFEM_E_NOMEM,
    MOFEM_E_HIP. */
@@ -450,6 +450,23 @@ typedef struct {
    Synchronises every stream once at the end. */
 int mofem_pcg_solve_many(int n_groups, const mofem_pcg_group* groups, void* const* streams,
                          int* status_out);
+
+/* Grouped solves of uneven instances (same arguments and results as
+   mofem_pcg_solve_many).  Groups with the same shape (q_s, q_t), transform
+   precision, preconditioner coefficients (a, bs, bt, d), tolerance, maxit,
+   flags and presence of item_scale form one class, solved as ONE batched
+   MO-PCG: every stage of an iteration is one launch over all the class's
+   items (the operator apply: one launch per distinct operator, e.g. per
+   element order k), and each item reaches its own preconditioner bases and
+   eigenvalues through per-item pointer tables (instances of different k or
+   geometry that share a shape share the launches).  Classes advance together
+   on the streams of their first groups.  The groups' workspace fields are not
+   used: each class allocates (hipMalloc) and frees one buffer holding its
+   gathered right-hand sides, solutions, tables and PCG workspace; solutions
+   are scattered back to the groups' U.  Spectral preconditioners only
+   (MOFEM_E_UNSUPPORTED for banded ones).  Synchronises every stream used. */
+int mofem_pcg_solve_grouped(int n_groups, const mofem_pcg_group* groups, void* const* streams,
+                            int* status_out);
 
 /* ------------------------------------------------------------------------ */
 /* a7. IMEX Euler step (Sec. 6, eqs. (87)-(96); DIB kinetics Sec. 7)        */

@@ -412,9 +412,11 @@ extern "C" int mofem_op_shape(mofem_op_t op, int* qs, int* qt, int* in_s, int* i
 }
 
 namespace {
+// partial_stride: entries between items of `partial` (0: the operator's own
+// tile count; a grouped solve of several operators uses their maximum)
 int op_launch(mofem_op_t op, const double* X, long long in_stride, double* Y, long long stride, int batch,
               const double* item_scale, double* partial, const int* active, hipStream_t s,
-              int n_items = -1) {
+              int n_items = -1, int partial_stride = 0) {
   TraceScope trace(MOFEM_TRACE_BAND, n_items < 0 ? batch : n_items, s);
   for (int ps = 0; ps < op->n_pass; ++ps) {
     const OpPass& P = op->pass[ps];
@@ -439,7 +441,7 @@ int op_launch(mofem_op_t op, const double* X, long long in_stride, double* Y, lo
     a.scaled_mask = P.scaled_mask;
     a.item_scale = item_scale;
     a.dot_partial = last ? partial : nullptr;
-    a.n_partial = P.n_tiles;
+    a.n_partial = partial_stride > 0 ? partial_stride : P.n_tiles;
     a.active = active;
     a.accumulate = ps > 0;  // later passes add to the earlier passes' Y
     a.batch = batch;
@@ -967,13 +969,33 @@ int prec_tile(mofem_prec_t p, int batch) {
   return blocks128 < 2 * 256 ? 64 : 128;
 }
 
+// Per-item device pointer tables of a grouped solve (instances of one shape,
+// each with its own preconditioner): table k of item b at tabs[k * batch + b].
+enum PrecTab {
+  TB_VS64, TB_VST64, TB_VT64, TB_VTT64, TB_VS32, TB_VST32, TB_VT32, TB_VTT32,
+  TB_VSH, TB_VSTH, TB_VTH, TB_VTTH, TB_VSL, TB_VSTL, TB_VTL, TB_VTTL,
+  TB_VSI8, TB_VSTI8, TB_VTI8, TB_VTTI8, TB_VSEX, TB_VSTEX, TB_VTEX, TB_VTTEX,
+  TB_LAM, TB_MU, TB_COUNT
+};
+// the tables' entries for one preconditioner
+void prec_tab_entries(mofem_prec_t p, const void** e) {
+  const void* v[TB_COUNT] = {p->Vs, p->VsT, p->Vt, p->VtT, p->Vs_f, p->VsT_f, p->Vt_f, p->VtT_f,
+                             p->Vs_h, p->VsT_h, p->Vt_h, p->VtT_h, p->Vs_l, p->VsT_l, p->Vt_l, p->VtT_l,
+                             p->Vs_i8, p->VsT_i8, p->Vt_i8, p->VtT_i8, p->Vs_ex, p->VsT_ex, p->Vt_ex, p->VtT_ex,
+                             p->lam, p->mu};
+  for (int k = 0; k < TB_COUNT; ++k) e[k] = v[k];
+}
+
 // input_ready: the padded operand of R is already in the workspace (written
 // by the fused CG update).  z32: if set (FP32 and BF16 transforms only), the
 // last transform writes Z in FP32 there (same item stride) instead of Z.
+// tabs: per-item bases and eigenvalues of a grouped solve (PrecTab), or null
+// (every item uses p's).
 int prec_launch(mofem_prec_t p, const double* R, double* Z, long long stride, int batch,
                 const double* item_scale, void* ws, size_t ws_bytes, const int* active, hipStream_t s,
-                int n_items = -1, int input_ready = 0, float* z32 = nullptr) {
+                int n_items = -1, int input_ready = 0, float* z32 = nullptr, const void* const* tabs = nullptr) {
   const double items_done = n_items < 0 ? batch : n_items;
+  if (tabs && p->banded) return fail(MOFEM_E_UNSUPPORTED, "prec_apply: grouped banded preconditioners");
   const size_t items = (size_t)p->ps * p->pt;
   if (p->banded) {
     // Z = S^-1 R T^-1: two transposing banded solves
@@ -1014,6 +1036,18 @@ int prec_launch(mofem_prec_t p, const double* R, double* Z, long long stride, in
   g.item_scale = item_scale;
   g.out_scale = 1.0;
   g.active = active;
+  // per-item basis operands (grouped solves): the data operand never has a table
+  auto tab = [&](int k) -> const void* const* { return (tabs && k >= 0) ? tabs + (size_t)k * batch : nullptr; };
+  g.lam_item = (const double* const*)tab(TB_LAM);
+  g.mu_item = (const double* const*)tab(TB_MU);
+  auto item_tabs = [&](int ah, int al, int ae, int bh, int bl, int be) {
+    g.a_item = tab(ah);
+    g.a_item_lo = tab(al);
+    g.a_exp_item = (const int* const*)tab(ae);
+    g.b_item = tab(bh);
+    g.b_item_lo = tab(bl);
+    g.b_exp_item = (const int* const*)tab(be);
+  };
   const int prec = p->precision == MOFEM_PREC_F64        ? GEMM_F64
                    : p->precision == MOFEM_PREC_F32      ? GEMM_F32
                    : p->precision == MOFEM_PREC_BF16     ? GEMM_BF16
@@ -1047,21 +1081,25 @@ int prec_launch(mofem_prec_t p, const double* R, double* Z, long long stride, in
     g.M = p->qs; g.N = p->qt; g.K = p->qt;
     g.a64 = T0; g.a_stride = istr; g.b64 = p->VtT; g.b_stride = 0;
     g.c64 = T1; g.c_stride = istr; g.divide = 0;
+    item_tabs(-1, -1, -1, TB_VTT64, -1, -1);
     if (gemm(O_PAD_T)) return fail(MOFEM_E_HIP, "gemm launch");
     // G2: S' = (V_s^T T ./ D)^T
     g.M = p->qs; g.N = p->qt; g.K = p->qs;
     g.a64 = p->VsT; g.a_stride = 0; g.b64 = T1; g.b_stride = istr;
     g.c64 = T2; g.c_stride = istr; g.divide = 1;
+    item_tabs(TB_VST64, -1, -1, -1, -1, -1);
     if (gemm(O_PAD_T)) return fail(MOFEM_E_HIP, "gemm launch");
     // G3: W = V_s S
     g.M = p->qs; g.N = p->qt; g.K = p->qs;
     g.a64 = p->Vs; g.a_stride = 0; g.b64 = T2; g.b_stride = istr;
     g.c64 = T1; g.c_stride = istr; g.divide = 0;
+    item_tabs(TB_VS64, -1, -1, -1, -1, -1);
     if (gemm(O_PAD_N)) return fail(MOFEM_E_HIP, "gemm launch");
     // G4: Z = W V_t^T
     g.M = p->qs; g.N = p->qt; g.K = p->qt;
     g.a64 = T1; g.a_stride = istr; g.b64 = p->Vt; g.b_stride = 0;
     g.c64 = Z; g.c_stride = stride; g.divide = 0;
+    item_tabs(-1, -1, -1, TB_VT64, -1, -1);
     if (gemm(O_F64_RAW)) return fail(MOFEM_E_HIP, "gemm launch");
   } else if (prec == GEMM_I8) {
     // FP64 intermediates (R padded, T', S', W in turn), each cut into digit
@@ -1089,24 +1127,28 @@ int prec_launch(mofem_prec_t p, const double* R, double* Z, long long stride, in
     g.a_i8 = SL; g.a_stride = sstr; g.a_exp = EX; g.a_exp_stride = pmax;
     g.b_i8 = p->VtT_i8; g.b_stride = 0; g.b_exp = p->VtT_ex; g.b_exp_stride = 0;
     g.c64 = T; g.c_stride = istr; g.divide = 0;
+    item_tabs(-1, -1, -1, TB_VTTI8, -1, TB_VTTEX);
     if (gemm8(O_PAD_T) || slice(T, istr, p->ps, p->qt, p->qs)) return fail(MOFEM_E_HIP, "gemm launch");
     // G2: S' = (V_s^T T ./ D)^T
     g.M = p->qs; g.N = p->qt; g.K = p->qs;
     g.a_i8 = p->VsT_i8; g.a_stride = 0; g.a_exp = p->VsT_ex; g.a_exp_stride = 0;
     g.b_i8 = SL; g.b_stride = sstr; g.b_exp = EX; g.b_exp_stride = pmax;
     g.c64 = T; g.c_stride = istr; g.divide = 1;
+    item_tabs(TB_VSTI8, -1, TB_VSTEX, -1, -1, -1);
     if (gemm8(O_PAD_T) || slice(T, istr, p->ps, p->qt, p->qs)) return fail(MOFEM_E_HIP, "gemm launch");
     // G3: W = V_s S
     g.M = p->qs; g.N = p->qt; g.K = p->qs;
     g.a_i8 = p->Vs_i8; g.a_stride = 0; g.a_exp = p->Vs_ex; g.a_exp_stride = 0;
     g.b_i8 = SL; g.b_stride = sstr; g.b_exp = EX; g.b_exp_stride = pmax;
     g.c64 = T; g.c_stride = istr; g.divide = 0;
+    item_tabs(TB_VSI8, -1, TB_VSEX, -1, -1, -1);
     if (gemm8(O_PAD_N) || slice(T, istr, p->pt, p->qs, p->qt)) return fail(MOFEM_E_HIP, "gemm launch");
     // G4: Z = W V_t^T
     g.M = p->qs; g.N = p->qt; g.K = p->qt;
     g.a_i8 = SL; g.a_stride = sstr; g.a_exp = EX; g.a_exp_stride = pmax;
     g.b_i8 = p->Vt_i8; g.b_stride = 0; g.b_exp = p->Vt_ex; g.b_exp_stride = 0;
     g.c64 = Z; g.c_stride = stride; g.divide = 0;
+    item_tabs(-1, -1, -1, TB_VTI8, -1, TB_VTEX);
     if (gemm8(O_F64_RAW)) return fail(MOFEM_E_HIP, "gemm launch");
   } else if (prec == GEMM_F32) {
     float* T0 = c.take<float>(items * batch);  // padded R
@@ -1122,18 +1164,22 @@ int prec_launch(mofem_prec_t p, const double* R, double* Z, long long stride, in
     g.M = p->qs; g.N = p->qt; g.K = p->qt;
     g.a_hi = T0; g.a_stride = istr; g.b_hi = p->VtT_f; g.b_stride = 0;
     g.c_hi = T1; g.c_stride = istr; g.divide = 0;
+    item_tabs(-1, -1, -1, TB_VTT32, -1, -1);
     if (gemm(O_PAD_T)) return fail(MOFEM_E_HIP, "gemm launch");
     g.M = p->qs; g.N = p->qt; g.K = p->qs;
     g.a_hi = p->VsT_f; g.a_stride = 0; g.b_hi = T1; g.b_stride = istr;
     g.c_hi = T2; g.c_stride = istr; g.divide = 1;
+    item_tabs(TB_VST32, -1, -1, -1, -1, -1);
     if (gemm(O_PAD_T)) return fail(MOFEM_E_HIP, "gemm launch");
     g.M = p->qs; g.N = p->qt; g.K = p->qs;
     g.a_hi = p->Vs_f; g.a_stride = 0; g.b_hi = T2; g.b_stride = istr;
     g.c_hi = T1; g.c_stride = istr; g.divide = 0;
+    item_tabs(TB_VS32, -1, -1, -1, -1, -1);
     if (gemm(O_PAD_N)) return fail(MOFEM_E_HIP, "gemm launch");
     g.M = p->qs; g.N = p->qt; g.K = p->qt;
     g.a_hi = T1; g.a_stride = istr; g.b_hi = p->Vt_f; g.b_stride = 0;
     g.c64 = Z; g.c_hi = z32; g.c_stride = stride; g.divide = 0;
+    item_tabs(-1, -1, -1, TB_VT32, -1, -1);
     if (gemm(z32 ? O_F32_RAW : O_F64_RAW)) return fail(MOFEM_E_HIP, "gemm launch");
   } else {
     unsigned short* T0h = c.take<unsigned short>(items * batch);
@@ -1165,24 +1211,28 @@ int prec_launch(mofem_prec_t p, const double* R, double* Z, long long stride, in
     g.M = p->qs; g.N = p->qt; g.K = p->qt;
     g.a_hi = T0h; g.a_lo = T0l; g.a_stride = istr; g.b_hi = p->VtT_h; g.b_lo = p->VtT_l; g.b_stride = 0;
     g.c_hi = T1h; g.c_lo = b_lo(1) ? T1l : nullptr; g.c_stride = istr; g.divide = 0;
+    item_tabs(-1, -1, -1, TB_VTTH, TB_VTTL, -1);
     if (run(0, O_PAD_T)) return fail(MOFEM_E_HIP, "gemm launch");
     // G2: S' = (V_s^T T ./ D)^T
     g.M = p->qs; g.N = p->qt; g.K = p->qs;
     g.a64 = nullptr; g.a_hi = p->VsT_h; g.a_lo = p->VsT_l; g.a_stride = 0;
     g.b_hi = T1h; g.b_lo = T1l; g.b_stride = istr;
     g.c_hi = T2h; g.c_lo = b_lo(2) ? T2l : nullptr; g.c_stride = istr; g.divide = 1;
+    item_tabs(TB_VSTH, TB_VSTL, -1, -1, -1, -1);
     if (run(1, O_PAD_T)) return fail(MOFEM_E_HIP, "gemm launch");
     // G3: W = V_s S
     g.M = p->qs; g.N = p->qt; g.K = p->qs;
     g.a_hi = p->Vs_h; g.a_lo = p->Vs_l; g.a_stride = 0;
     g.b_hi = T2h; g.b_lo = T2l; g.b_stride = istr;
     g.c_hi = T1h; g.c_lo = a_lo(3) ? T1l : nullptr; g.c_stride = istr; g.divide = 0;
+    item_tabs(TB_VSH, TB_VSL, -1, -1, -1, -1);
     if (run(2, O_PAD_N)) return fail(MOFEM_E_HIP, "gemm launch");
     // G4: Z = W V_t^T
     g.M = p->qs; g.N = p->qt; g.K = p->qt;
     g.a_hi = T1h; g.a_lo = T1l; g.a_stride = istr;
     g.b_hi = p->Vt_h; g.b_lo = p->Vt_l; g.b_stride = 0;
     g.c64 = Z; g.c_hi = z32; g.c_lo = nullptr; g.c_stride = stride; g.divide = 0;
+    item_tabs(-1, -1, -1, TB_VTH, TB_VTL, -1);
     if (run(3, z32 ? O_F32_RAW : O_F64_RAW)) return fail(MOFEM_E_HIP, "gemm launch");
   }
   hipError_t e = hipGetLastError();
@@ -1306,12 +1356,13 @@ struct PcgWs {
   size_t prec_bytes;
 };
 
-size_t pcg_bytes(mofem_op_t op, mofem_prec_t prec, int batch, size_t* prec_part) {
+// np: operator partial sums per item (0: op's tile count)
+size_t pcg_bytes(mofem_op_t op, mofem_prec_t prec, int batch, size_t* prec_part, int np = 0) {
   size_t n = (size_t)op->qs * op->qt;
   size_t b = 0;
   b += 4 * align_up(n * batch * 8, 256);
   b += 2 * align_up((size_t)batch * kVecBlocks * 8, 256);
-  b += align_up((size_t)batch * op->n_tiles * 8, 256);
+  b += align_up((size_t)batch * (np > 0 ? np : op->n_tiles) * 8, 256);
   b += 11 * align_up((size_t)batch * 8, 256);
   b += 6 * align_up((size_t)batch * 4, 256);
   size_t pp = mofem_prec_workspace_size(prec, batch);
@@ -1319,7 +1370,7 @@ size_t pcg_bytes(mofem_op_t op, mofem_prec_t prec, int batch, size_t* prec_part)
   return b + pp + 4096;
 }
 
-bool carve_pcg(mofem_op_t op, mofem_prec_t prec, int batch, void* ws, size_t bytes, PcgWs* w) {
+bool carve_pcg(mofem_op_t op, mofem_prec_t prec, int batch, void* ws, size_t bytes, PcgWs* w, int np = 0) {
   Carve c(ws, bytes);
   size_t n = (size_t)op->qs * op->qt;
   w->R = c.take<double>(n * batch);
@@ -1328,7 +1379,7 @@ bool carve_pcg(mofem_op_t op, mofem_prec_t prec, int batch, void* ws, size_t byt
   w->Y = c.take<double>(n * batch);
   w->part_a = c.take<double>((size_t)batch * kVecBlocks);
   w->part_b = c.take<double>((size_t)batch * kVecBlocks);
-  w->part_op = c.take<double>((size_t)batch * op->n_tiles);
+  w->part_op = c.take<double>((size_t)batch * (np > 0 ? np : op->n_tiles));
   double** scal[] = {&w->rz, &w->rz_new, &w->qy, &w->rr, &w->zy, &w->alpha, &w->beta, &w->rhs2, &w->tr,
                      &w->target2};
   for (double** x : scal) *x = c.take<double>(batch);
@@ -1386,6 +1437,29 @@ struct PcgRun {
   float* z32 = nullptr;  // FP32 Z (in w.Z's memory) for FP32 / BF16 preconditioners
   int n_trace;  // item count recorded with traced launches
   double rec_band = 0, rec_prec = 0;
+  // grouped solve: items [b0, b1) use operator `op` (their own bases come
+  // through tabs); np operator partial sums per item
+  struct OpRange {
+    mofem_op_t op;
+    int b0, b1;
+  };
+  std::vector<OpRange> ranges;
+  int np = 0;
+  const void* const* tabs = nullptr;
+
+  int n_partial() const { return np > 0 ? np : op->n_tiles; }
+  // Y = L(X) over every item (one launch per operator of a grouped solve)
+  int run_op(const double* X, long long xs, double* Y, long long ys, double* partial, const int* act, int ntr) {
+    if (ranges.empty()) return op_launch(op, X, xs, Y, ys, batch, item_scale, partial, act, s, ntr);
+    for (size_t k = 0; k < ranges.size(); ++k) {
+      const OpRange& R = ranges[k];
+      int rc = op_launch(R.op, X + (size_t)R.b0 * xs, xs, Y + (size_t)R.b0 * ys, ys, R.b1 - R.b0,
+                         item_scale ? item_scale + R.b0 : nullptr, partial ? partial + (size_t)R.b0 * np : nullptr,
+                         act ? act + R.b0 : nullptr, s, k == 0 ? ntr : 0, np);
+      if (rc != MOFEM_OK) return rc;
+    }
+    return MOFEM_OK;
+  }
 
   int launch_fail() { return fail(MOFEM_E_HIP, "pcg_solve: launch failed"); }
 #define PCG_LTRY(x)                                       \
@@ -1408,14 +1482,14 @@ struct PcgRun {
       PCG_LTRY(launch_copy(Rhs, w.R, n, stride, n, batch, s));
       PCG_LTRY(launch_dot_partial(w.R, w.R, n, n, batch, w.part_a, nullptr, s));
     } else {
-      PCG_TRY(op_launch(op, U, stride, w.Y, n, batch, item_scale, nullptr, nullptr, s, n_trace));
+      PCG_TRY(run_op(U, stride, w.Y, n, nullptr, nullptr, n_trace));
       PCG_LTRY(launch_residual(Rhs, w.Y, w.R, n, n, stride, batch, w.part_a, nullptr, s));
     }
     PCG_LTRY(launch_reduce(w.part_a, vec_blocks(n), w.rr, batch, s));
     PCG_LTRY(launch_pcg_init(w.rhs2, w.rr, w.target2, w.active, w.claim, w.restart, w.status, w.iters, tol * tol,
                              (flags & MOFEM_PCG_TAU_STOP) ? 1 : 0, batch, s));
     PCG_TRY(prec_launch(prec, w.R, w.Z, n, batch, item_scale, w.prec_ws, w.prec_bytes, w.active, s, n_trace, 0,
-                        z32));
+                        z32, tabs));
     rec_prec += n_trace;
     if (z32) {
       PCG_LTRY(launch_dot_partial(w.R, z32, n, n, batch, w.part_a, w.active, s));
@@ -1433,9 +1507,9 @@ struct PcgRun {
 
   int iteration() {
     // Y = L(Q), <Q, Y>
-    PCG_TRY(op_launch(op, w.Q, n, w.Y, n, batch, item_scale, w.part_op, w.active, s, n_trace));
+    PCG_TRY(run_op(w.Q, n, w.Y, n, w.part_op, w.active, n_trace));
     rec_band += n_trace;
-    PCG_LTRY(launch_reduce(w.part_op, op->n_tiles, w.qy, batch, s));
+    PCG_LTRY(launch_reduce(w.part_op, n_partial(), w.qy, batch, s));
     // alpha = <R, Z> / <Q, Y>; R -= alpha Y; ||R||^2; R's padded transform operand.
     // U += alpha Q is deferred to the direction pass of this iteration (which
     // reads Q anyway), for every item whose step is valid (live)
@@ -1446,7 +1520,7 @@ struct PcgRun {
     // items that claim convergence: confirm on the true residual of U + alpha Q,
     // Rhs - L(U) - alpha Y (Y = L(Q)); where it fails, continue from the true
     // residual with a fresh direction
-    PCG_TRY(op_launch(op, U, stride, w.Z, n, batch, item_scale, nullptr, w.claim, s, 0));
+    PCG_TRY(run_op(U, stride, w.Z, n, nullptr, w.claim, 0));
     PCG_LTRY(launch_residual_step(Rhs, w.Z, w.Y, w.alpha, w.Z, n, n, stride, batch, w.part_b, w.claim, s));
     PCG_LTRY(launch_confirm(w.part_b, vec_blocks(n), w.tr, w.target2, w.active, w.claim, w.restart, batch, s));
     PCG_LTRY(launch_copy_masked(w.Z, w.R, n, n, n, batch, w.restart, s));
@@ -1455,7 +1529,7 @@ struct PcgRun {
                                   (pin.hi != nullptr) ? 1 : 0, batch, w.restart, s));
     // Z = P^{-1}(R); <R, Z>, <Z, Y>; beta (zero after a restart); Q = Z + beta Q
     PCG_TRY(prec_launch(prec, w.R, w.Z, n, batch, item_scale, w.prec_ws, w.prec_bytes, w.active, s, n_trace, 1,
-                        z32));
+                        z32, tabs));
     rec_prec += n_trace;
     if (z32) {
       PCG_LTRY(launch_zdots_partial(w.R, z32, w.Y, n, n, batch, w.part_a, w.part_b, w.active, s));
@@ -1475,7 +1549,7 @@ struct PcgRun {
 
   // final true residuals of every item and the per-item result on the device
   int finish(int* iters_dev, int* status_dev, double* relres_dev) {
-    PCG_TRY(op_launch(op, U, stride, w.Z, n, batch, item_scale, nullptr, nullptr, s, batch));
+    PCG_TRY(run_op(U, stride, w.Z, n, nullptr, nullptr, batch));
     PCG_LTRY(launch_residual(Rhs, w.Z, w.Z, n, n, stride, batch, w.part_b, nullptr, s));
     PCG_LTRY(launch_reduce(w.part_b, vec_blocks(n), w.tr, batch, s));
     PCG_LTRY(launch_pcg_final(w.tr, w.rhs2, w.target2, w.status, w.iters, iters_dev, status_dev, relres_dev, batch,
@@ -1635,124 +1709,304 @@ extern "C" int mofem_pcg_solve(mofem_op_t op, mofem_prec_t prec, const double* R
   return status_error(result);
 }
 
+namespace {
+// Per-run results on the host after advance_runs.
+struct RunOut {
+  std::vector<int> it, st;
+  std::vector<double> rr;
+};
+
+// Advance prepared and begun runs together: each run's iteration is queued on
+// its stream in turn, so the runs overlap on the device, and each run's
+// active flags are read one iteration behind, as in mofem_pcg_solve.  Then
+// the final true residuals and per-item results of every run.
+int advance_runs(const std::vector<PcgRun*>& runs, const std::vector<int>& maxit, std::vector<RunOut>& out) {
+  const size_t nr = runs.size();
+  out.assign(nr, RunOut());
+  std::vector<int> live(nr, 0);
+  std::vector<hipEvent_t> ev(2 * nr, nullptr);
+  std::vector<int*> hflag(nr, nullptr);   // two slots (alternate iterations) per run
+  std::vector<char*> hres(nr, nullptr);   // iters, status, relres
+  int rc = MOFEM_OK;
+  for (size_t i = 0; i < nr && !rc; ++i) {
+    const int B = runs[i]->batch;
+    if (B == 0) continue;
+    if (hipHostMalloc((void**)&hflag[i], sizeof(int) * 2 * (size_t)B) != hipSuccess ||
+        hipHostMalloc((void**)&hres[i], (sizeof(int) * 2 + sizeof(double)) * (size_t)B) != hipSuccess ||
+        hipEventCreateWithFlags(&ev[2 * i], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ev[2 * i + 1], hipEventDisableTiming) != hipSuccess)
+      rc = fail(MOFEM_E_NOMEM, "pcg_solve_many: host buffers");
+    live[i] = maxit[i] > 0 ? 1 : 0;
+  }
+  for (int it = 0; !rc; ++it) {
+    int any = 0;
+    for (size_t i = 0; i < nr && !rc; ++i) {
+      if (!live[i]) continue;
+      PcgRun& r = *runs[i];
+      int* slot = hflag[i] + (it & 1) * r.batch;
+      rc = r.iteration();
+      if (!rc && (hipMemcpyAsync(slot, r.w.active, sizeof(int) * r.batch, hipMemcpyDeviceToHost, r.s) != hipSuccess ||
+                  hipEventRecord(ev[2 * i + (it & 1)], r.s) != hipSuccess))
+        rc = fail(MOFEM_E_HIP, "pcg_solve_many: flags");
+      any = 1;
+    }
+    if (rc || !any) break;
+    for (size_t i = 0; i < nr && !rc; ++i) {
+      if (!live[i]) continue;
+      if (it + 1 >= maxit[i]) {
+        live[i] = 0;
+        continue;
+      }
+      if (it == 0) continue;
+      if (hipEventSynchronize(ev[2 * i + ((it - 1) & 1)]) != hipSuccess) {
+        rc = fail(MOFEM_E_HIP, "pcg_solve_many: event");
+        break;
+      }
+      const int* slot = hflag[i] + ((it - 1) & 1) * runs[i]->batch;
+      int na = 0;
+      for (int b = 0; b < runs[i]->batch; ++b) na += slot[b] != 0;
+      runs[i]->n_trace = na;
+      if (na == 0) live[i] = 0;
+    }
+  }
+  // results: device scratch of each run, then to the host
+  for (size_t i = 0; i < nr && !rc; ++i) {
+    PcgRun& r = *runs[i];
+    if (r.batch == 0) continue;
+    int* hit = (int*)hres[i];
+    int* hst = hit + r.batch;
+    double* hrr = (double*)(hst + r.batch);
+    rc = r.finish(r.w.claim, r.w.restart, r.w.rr);
+    if (!rc && (hipMemcpyAsync(hit, r.w.claim, sizeof(int) * r.batch, hipMemcpyDeviceToHost, r.s) != hipSuccess ||
+                hipMemcpyAsync(hst, r.w.restart, sizeof(int) * r.batch, hipMemcpyDeviceToHost, r.s) != hipSuccess ||
+                hipMemcpyAsync(hrr, r.w.rr, sizeof(double) * r.batch, hipMemcpyDeviceToHost, r.s) != hipSuccess))
+      rc = fail(MOFEM_E_HIP, "pcg_solve_many: results");
+  }
+  for (size_t i = 0; i < nr && !rc; ++i) {
+    PcgRun& r = *runs[i];
+    if (r.batch == 0) continue;
+    if (hipStreamSynchronize(r.s) != hipSuccess) {
+      rc = fail(MOFEM_E_HIP, "pcg_solve_many: synchronise");
+      break;
+    }
+    const int* hit = (const int*)hres[i];
+    const int* hst = hit + r.batch;
+    const double* hrr = (const double*)(hst + r.batch);
+    out[i].it.assign(hit, hit + r.batch);
+    out[i].st.assign(hst, hst + r.batch);
+    out[i].rr.assign(hrr, hrr + r.batch);
+  }
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  for (int* h : hflag)
+    if (h) (void)hipHostFree(h);
+  for (char* h : hres)
+    if (h) (void)hipHostFree(h);
+  return rc;
+}
+}  // namespace
+
 // Several independent batched solves (uneven shapes, each its own operator,
-// preconditioner and stream) advanced together: each group's iteration is
-// queued on its stream in turn, so the groups overlap on the device, and
-// each group's flags are read one iteration behind, as in mofem_pcg_solve.
+// preconditioner and stream) advanced together (advance_runs).
 extern "C" int mofem_pcg_solve_many(int n_groups, const mofem_pcg_group* groups, void* const* streams,
                                     int* status_out) {
   clear_error();
   if (n_groups < 0 || (n_groups > 0 && (!groups || !streams))) return fail(MOFEM_E_ARG, "pcg_solve_many: bad argument");
   std::vector<PcgRun> runs(n_groups);
-  std::vector<int> live(n_groups, 0);
-  std::vector<hipEvent_t> ev(2 * (size_t)n_groups, nullptr);
-  struct Res {
-    int *it = nullptr, *st = nullptr;
-    double* rr = nullptr;
-  };
-  std::vector<Res> res(n_groups);
-  int rc = MOFEM_OK;
-  auto cleanup = [&]() {
-    for (auto& e : ev)
-      if (e) (void)hipEventDestroy(e);
-    for (auto& r : res) {
-      if (r.it) (void)hipHostFree(r.it);
-      if (r.rr) (void)hipHostFree(r.rr);
-    }
-  };
-  for (int gi = 0; gi < n_groups && !rc; ++gi) {
+  std::vector<PcgRun*> rp;
+  std::vector<int> maxit;
+  for (int gi = 0; gi < n_groups; ++gi) {
     const mofem_pcg_group& G = groups[gi];
-    hipStream_t s = (hipStream_t)streams[gi];
-    rc = pcg_prepare(runs[gi], G.op, G.prec, G.rhs, G.u, G.stride, G.batch, G.item_scale, G.tol, G.maxit, G.flags,
-                     G.workspace, G.ws_bytes, s);
-    if (rc || G.batch == 0) continue;
-    if (hipHostMalloc((void**)&res[gi].it, sizeof(int) * 2 * (size_t)G.batch) != hipSuccess ||
-        hipHostMalloc((void**)&res[gi].rr, sizeof(double) * (size_t)G.batch) != hipSuccess ||
-        hipEventCreateWithFlags(&ev[2 * gi], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&ev[2 * gi + 1], hipEventDisableTiming) != hipSuccess) {
-      rc = fail(MOFEM_E_NOMEM, "pcg_solve_many: host buffers");
-      break;
-    }
-    res[gi].st = res[gi].it + G.batch;
-    rc = runs[gi].begin();
-    live[gi] = G.maxit > 0 ? 1 : 0;
-  }
-  if (rc) {
-    cleanup();
-    return rc;
-  }
-  // flags in pinned memory: two slots (alternate iterations) per group
-  std::vector<int*> hflag(2 * (size_t)n_groups, nullptr);
-  for (int gi = 0; gi < n_groups; ++gi)
-    if (groups[gi].batch > 0 && hipHostMalloc((void**)&hflag[2 * gi], sizeof(int) * 2 * (size_t)groups[gi].batch) != hipSuccess)
-      rc = fail(MOFEM_E_NOMEM, "pcg_solve_many: host buffers");
-  for (int it = 0; !rc; ++it) {
-    int any = 0;
-    for (int gi = 0; gi < n_groups && !rc; ++gi) {
-      if (!live[gi]) continue;
-      const mofem_pcg_group& G = groups[gi];
-      hipStream_t s = runs[gi].s;
-      int* slot = hflag[2 * gi] + (it & 1) * G.batch;
-      rc = runs[gi].iteration();
-      if (!rc && (hipMemcpyAsync(slot, runs[gi].w.active, sizeof(int) * G.batch, hipMemcpyDeviceToHost, s) != hipSuccess ||
-                  hipEventRecord(ev[2 * gi + (it & 1)], s) != hipSuccess))
-        rc = fail(MOFEM_E_HIP, "pcg_solve_many: flags");
-      any = 1;
-    }
-    if (rc || !any) break;
-    for (int gi = 0; gi < n_groups && !rc; ++gi) {
-      if (!live[gi]) continue;
-      const mofem_pcg_group& G = groups[gi];
-      if (it + 1 >= G.maxit) {
-        live[gi] = 0;
-        continue;
-      }
-      if (it == 0) continue;
-      if (hipEventSynchronize(ev[2 * gi + ((it - 1) & 1)]) != hipSuccess) {
-        rc = fail(MOFEM_E_HIP, "pcg_solve_many: event");
-        break;
-      }
-      const int* slot = hflag[2 * gi] + ((it - 1) & 1) * G.batch;
-      int na = 0;
-      for (int b = 0; b < G.batch; ++b) na += slot[b] != 0;
-      runs[gi].n_trace = na;
-      if (na == 0) live[gi] = 0;
-    }
-  }
-  // results: device scratch of each run, then to the host
-  for (int gi = 0; gi < n_groups && !rc; ++gi) {
-    const mofem_pcg_group& G = groups[gi];
+    int rc = pcg_prepare(runs[gi], G.op, G.prec, G.rhs, G.u, G.stride, G.batch, G.item_scale, G.tol, G.maxit,
+                         G.flags, G.workspace, G.ws_bytes, (hipStream_t)streams[gi]);
+    if (rc) return rc;
     if (G.batch == 0) continue;
-    PcgRun& r = runs[gi];
-    rc = r.finish(r.w.claim, r.w.restart, r.w.rr);
-    if (!rc && (hipMemcpyAsync(res[gi].it, r.w.claim, sizeof(int) * G.batch, hipMemcpyDeviceToHost, r.s) != hipSuccess ||
-                hipMemcpyAsync(res[gi].st, r.w.restart, sizeof(int) * G.batch, hipMemcpyDeviceToHost, r.s) != hipSuccess ||
-                hipMemcpyAsync(res[gi].rr, r.w.rr, sizeof(double) * G.batch, hipMemcpyDeviceToHost, r.s) != hipSuccess))
-      rc = fail(MOFEM_E_HIP, "pcg_solve_many: results");
+    rc = runs[gi].begin();
+    if (rc) return rc;
+    rp.push_back(&runs[gi]);
+    maxit.push_back(G.maxit);
   }
+  std::vector<RunOut> out;
+  int rc = advance_runs(rp, maxit, out);
+  if (rc) return rc;
   int result = MOFEM_OK;
-  for (int gi = 0; gi < n_groups && !rc; ++gi) {
+  for (int gi = 0, k = 0; gi < n_groups; ++gi) {
     const mofem_pcg_group& G = groups[gi];
-    if (G.batch == 0) {
-      if (status_out) status_out[gi] = MOFEM_OK;
-      continue;
-    }
-    if (hipStreamSynchronize(runs[gi].s) != hipSuccess) {
-      rc = fail(MOFEM_E_HIP, "pcg_solve_many: synchronise");
-      break;
-    }
     int gst = MOFEM_OK;
-    for (int b = 0; b < G.batch; ++b) {
-      if (G.iters_out) G.iters_out[b] = res[gi].it[b];
-      if (G.relres_out) G.relres_out[b] = res[gi].rr[b];
-      if (res[gi].st[b] != MOFEM_OK && gst == MOFEM_OK) gst = res[gi].st[b];
+    if (G.batch > 0) {
+      const RunOut& o = out[k++];
+      for (int b = 0; b < G.batch; ++b) {
+        if (G.iters_out) G.iters_out[b] = o.it[b];
+        if (G.relres_out) G.relres_out[b] = o.rr[b];
+        if (o.st[b] != MOFEM_OK && gst == MOFEM_OK) gst = o.st[b];
+      }
     }
     if (status_out) status_out[gi] = gst;
     if (gst != MOFEM_OK && result == MOFEM_OK) result = gst;
   }
-  for (int* h : hflag)
-    if (h) (void)hipHostFree(h);
-  cleanup();
+  return status_error(result);
+}
+
+// Grouped solves: the groups of one shape (and the same precision, preconditioner
+// coefficients, tolerance, iteration limit and flags) form one class, solved
+// as ONE batched solve whose every stage is one launch over all the class's
+// items (the operator: one launch per distinct operator); the items reach
+// their own preconditioner bases through per-item pointer tables.  Classes
+// advance together on the streams of their first groups (advance_runs).
+extern "C" int mofem_pcg_solve_grouped(int n_groups, const mofem_pcg_group* groups, void* const* streams,
+                                       int* status_out) {
+  clear_error();
+  if (n_groups < 0 || (n_groups > 0 && (!groups || !streams))) return fail(MOFEM_E_ARG, "pcg_solve_grouped: bad argument");
+  for (int gi = 0; gi < n_groups; ++gi) {
+    const mofem_pcg_group& G = groups[gi];
+    if (!G.op || !G.prec) return fail(MOFEM_E_ARG, "pcg_solve_grouped: NULL handle");
+    if (G.batch < 0 || G.maxit < 0 || !(G.tol >= 0.0)) return fail(MOFEM_E_ARG, "pcg_solve_grouped: bad batch/maxit/tol");
+    if (G.batch > 0 && (!G.rhs || !G.u)) return fail(MOFEM_E_ARG, "pcg_solve_grouped: NULL argument");
+    if (G.op->full_input || G.op->full_output || G.op->qs != G.prec->qs || G.op->qt != G.prec->qt)
+      return fail(MOFEM_E_ARG, "pcg_solve_grouped: operator and preconditioner must map unknowns of one shape");
+    if (G.stride < (long long)G.op->qs * G.op->qt) return fail(MOFEM_E_ARG, "pcg_solve_grouped: stride smaller than one item");
+    if (G.prec->banded) return fail(MOFEM_E_UNSUPPORTED, "pcg_solve_grouped: banded product preconditioners");
+  }
+  // classes: groups whose items can share every launch
+  auto same_class = [&](const mofem_pcg_group& a, const mofem_pcg_group& b) {
+    const mofem_prec_s &p = *a.prec, &q = *b.prec;
+    return a.op->qs == b.op->qs && a.op->qt == b.op->qt && p.precision == q.precision && p.alpha == q.alpha &&
+           p.bs == q.bs && p.bt == q.bt && p.dl == q.dl && a.tol == b.tol && a.maxit == b.maxit &&
+           a.flags == b.flags && (a.item_scale != nullptr) == (b.item_scale != nullptr);
+  };
+  std::vector<int> cls(n_groups, -1);
+  std::vector<std::vector<int>> members;
+  for (int gi = 0; gi < n_groups; ++gi) {
+    if (groups[gi].batch == 0) continue;
+    for (size_t c = 0; c < members.size() && cls[gi] < 0; ++c)
+      if (same_class(groups[members[c][0]], groups[gi])) {
+        cls[gi] = (int)c;
+        members[c].push_back(gi);
+      }
+    if (cls[gi] < 0) {
+      cls[gi] = (int)members.size();
+      members.push_back({gi});
+    }
+  }
+  const size_t nc = members.size();
+  std::vector<PcgRun> runs(nc);
+  std::vector<void*> bufs(nc, nullptr);
+  std::vector<std::vector<const void*>> htabs(nc);
+  std::vector<PcgRun*> rp;
+  std::vector<int> maxit;
+  int rc = MOFEM_OK;
+  for (size_t c = 0; c < nc && !rc; ++c) {
+    const mofem_pcg_group& G0 = groups[members[c][0]];
+    hipStream_t s = (hipStream_t)streams[members[c][0]];
+    int B = 0, np = 0;
+    for (int gi : members[c]) {
+      B += groups[gi].batch;
+      np = std::max(np, groups[gi].op->n_tiles);
+    }
+    const long long n = (long long)G0.op->qs * G0.op->qt;
+    // class buffer: right-hand sides, solutions, item scales, pointer tables, PCG workspace
+    const size_t ws = pcg_bytes(G0.op, G0.prec, B, nullptr, np);
+    const size_t bytes = 2 * align_up((size_t)B * n * 8, 256) + align_up((size_t)B * 8, 256) +
+                         align_up((size_t)TB_COUNT * B * sizeof(void*), 256) + ws + 1024;
+    char* buf = nullptr;
+    rc = dev_alloc(&buf, bytes);
+    if (rc) break;
+    bufs[c] = buf;
+    Carve cv(buf, bytes);
+    double* Rhs = cv.take<double>((size_t)B * n);
+    double* U = cv.take<double>((size_t)B * n);
+    double* isc = cv.take<double>((size_t)B);
+    const void** dtab = cv.take<const void*>((size_t)TB_COUNT * B);
+    void* pws = cv.take<char>(ws);
+    std::vector<const void*>& ht = htabs[c];
+    ht.assign((size_t)TB_COUNT * B, nullptr);
+    int b0 = 0;
+    for (int gi : members[c]) {
+      const mofem_pcg_group& G = groups[gi];
+      const void* e[TB_COUNT];
+      prec_tab_entries(G.prec, e);
+      for (int b = 0; b < G.batch; ++b)
+        for (int k = 0; k < TB_COUNT; ++k) ht[(size_t)k * B + b0 + b] = e[k];
+      if (hipMemcpy2DAsync(Rhs + (size_t)b0 * n, n * 8, G.rhs, G.stride * 8, n * 8, G.batch, hipMemcpyDeviceToDevice,
+                           s) != hipSuccess ||
+          (!(G.flags & MOFEM_PCG_ZERO_GUESS) &&
+           hipMemcpy2DAsync(U + (size_t)b0 * n, n * 8, G.u, G.stride * 8, n * 8, G.batch, hipMemcpyDeviceToDevice,
+                            s) != hipSuccess) ||
+          (G.item_scale && hipMemcpyAsync(isc + b0, G.item_scale, G.batch * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)) {
+        rc = fail(MOFEM_E_HIP, "pcg_solve_grouped: gather");
+        break;
+      }
+      b0 += G.batch;
+    }
+    if (rc) break;
+    if (hipMemcpyAsync(dtab, ht.data(), ht.size() * sizeof(void*), hipMemcpyHostToDevice, s) != hipSuccess) {
+      rc = fail(MOFEM_E_HIP, "pcg_solve_grouped: tables");
+      break;
+    }
+    PcgRun& r = runs[c];
+    rc = pcg_prepare(r, G0.op, G0.prec, Rhs, U, n, B, G0.item_scale ? isc : nullptr, G0.tol, G0.maxit, G0.flags,
+                     pws, ws, s);
+    if (rc) break;
+    // pcg_prepare carved with the first operator's tile count: carve again with np
+    if (!carve_pcg(G0.op, G0.prec, B, pws, ws, &r.w, np)) {
+      rc = fail(MOFEM_E_ARG, "pcg_solve_grouped: workspace");
+      break;
+    }
+    r.pin = prec_input(G0.prec, r.w.prec_ws, r.w.prec_bytes, B);
+    if (r.z32) r.z32 = reinterpret_cast<float*>(r.w.Z);
+    r.np = np;
+    r.tabs = dtab;
+    b0 = 0;
+    for (int gi : members[c]) {
+      const mofem_pcg_group& G = groups[gi];
+      if (!r.ranges.empty() && r.ranges.back().op == G.op) r.ranges.back().b1 += G.batch;
+      else r.ranges.push_back({G.op, b0, b0 + G.batch});
+      b0 += G.batch;
+    }
+    // operators with fewer tiles than np leave their items' last partial sums unwritten
+    if (launch_fill(r.w.part_op, 0.0, (long long)B * np, (long long)B * np, 1, s)) {
+      rc = fail(MOFEM_E_HIP, "pcg_solve_grouped: launch failed");
+      break;
+    }
+    rc = r.begin();
+    if (rc) break;
+    rp.push_back(&r);
+    maxit.push_back(G0.maxit);
+  }
+  std::vector<RunOut> out;
+  if (!rc) rc = advance_runs(rp, maxit, out);
+  // solutions back to the groups, per-item results to the callers
+  int result = MOFEM_OK;
+  for (size_t c = 0; c < nc && !rc; ++c) {
+    PcgRun& r = runs[c];
+    int b0 = 0;
+    for (int gi : members[c]) {
+      const mofem_pcg_group& G = groups[gi];
+      if (hipMemcpy2DAsync(G.u, G.stride * 8, r.U + (size_t)b0 * r.n, r.n * 8, r.n * 8, G.batch,
+                           hipMemcpyDeviceToDevice, r.s) != hipSuccess) {
+        rc = fail(MOFEM_E_HIP, "pcg_solve_grouped: scatter");
+        break;
+      }
+      int gst = MOFEM_OK;
+      for (int b = 0; b < G.batch; ++b) {
+        if (G.iters_out) G.iters_out[b] = out[c].it[b0 + b];
+        if (G.relres_out) G.relres_out[b] = out[c].rr[b0 + b];
+        if (out[c].st[b0 + b] != MOFEM_OK && gst == MOFEM_OK) gst = out[c].st[b0 + b];
+      }
+      if (status_out) status_out[gi] = gst;
+      if (gst != MOFEM_OK && result == MOFEM_OK) result = gst;
+      b0 += G.batch;
+    }
+    if (!rc && hipStreamSynchronize(r.s) != hipSuccess) rc = fail(MOFEM_E_HIP, "pcg_solve_grouped: synchronise");
+  }
+  if (status_out)
+    for (int gi = 0; gi < n_groups; ++gi)
+      if (groups[gi].batch == 0) status_out[gi] = MOFEM_OK;
+  for (size_t c = 0; c < nc; ++c)
+    if (bufs[c]) {
+      (void)hipStreamSynchronize(runs[c].s ? runs[c].s : (hipStream_t)streams[members[c][0]]);
+      (void)hipFree(bufs[c]);
+    }
   if (rc) return rc;
   return status_error(result);
 }

@@ -88,8 +88,10 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmArgs g) {
 
   const int lda = pad_up(g.K);
   const int ldb = pad_up(g.K);
-  const double* __restrict__ A = g.a64 + (size_t)b * g.a_stride;
-  const double* __restrict__ B = g.b64 + (size_t)b * g.b_stride;
+  const double* __restrict__ A = g.a_item ? (const double*)g.a_item[b] : g.a64 + (size_t)b * g.a_stride;
+  const double* __restrict__ B = g.b_item ? (const double*)g.b_item[b] : g.b64 + (size_t)b * g.b_stride;
+  const double* __restrict__ lam = g.lam_item ? g.lam_item[b] : g.lam;
+  const double* __restrict__ mu = g.mu_item ? g.mu_item[b] : g.mu;
 
   // global -> register staging: TPR threads per tile row, HK values each
   constexpr int TPR = 256 / TB;
@@ -149,9 +151,9 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmArgs g) {
 #pragma unroll
     for (int i = 0; i < WT; ++i)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) el[i][r] = g.lam[min(m0 + wm * (16 * WT) + i * 16 + 4 * r + (lane >> 4), g.M - 1)];
+      for (int r = 0; r < 4; ++r) el[i][r] = lam[min(m0 + wm * (16 * WT) + i * 16 + 4 * r + (lane >> 4), g.M - 1)];
 #pragma unroll
-    for (int j = 0; j < WT; ++j) em[j] = g.mu[min(n0 + wn * (16 * WT) + j * 16 + (lane & 15), g.N - 1)];
+    for (int j = 0; j < WT; ++j) em[j] = mu[min(n0 + wn * (16 * WT) + j * 16 + (lane & 15), g.N - 1)];
   }
 #pragma unroll
   for (int i = 0; i < WT; ++i)
@@ -196,8 +198,10 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g) {
   const int wm = wave >> 1, wn = wave & 1;
 
   const int Kp = pad_up(g.K);
-  const float* __restrict__ A = (const float*)g.a_hi + (size_t)b * g.a_stride;
-  const float* __restrict__ B = (const float*)g.b_hi + (size_t)b * g.b_stride;
+  const float* __restrict__ A = g.a_item ? (const float*)g.a_item[b] : (const float*)g.a_hi + (size_t)b * g.a_stride;
+  const float* __restrict__ B = g.b_item ? (const float*)g.b_item[b] : (const float*)g.b_hi + (size_t)b * g.b_stride;
+  const double* __restrict__ lam = g.lam_item ? g.lam_item[b] : g.lam;
+  const double* __restrict__ mu = g.mu_item ? g.mu_item[b] : g.mu;
 
   // global -> register staging: TPR threads per tile row, NV 16-byte loads each
   constexpr int TPR = 256 / TB;
@@ -260,12 +264,12 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g) {
     for (int i = 0; i < WT; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const double l = g.lam[min(m0 + wm * (16 * WT) + i * 16 + 4 * (lane >> 4) + r, g.M - 1)];
+        const double l = lam[min(m0 + wm * (16 * WT) + i * 16 + 4 * (lane >> 4) + r, g.M - 1)];
         da[i][r] = (float)(g.alpha + s * g.beta_s * l);
         db[i][r] = (float)(s * (g.beta_t + g.delta * l));
       }
 #pragma unroll
-    for (int j = 0; j < WT; ++j) dm[j] = (float)g.mu[min(n0 + wn * (16 * WT) + j * 16 + (lane & 15), g.N - 1)];
+    for (int j = 0; j < WT; ++j) dm[j] = (float)mu[min(n0 + wn * (16 * WT) + j * 16 + (lane & 15), g.N - 1)];
   }
   const float osc = (float)g.out_scale;
   const int Mp = pad_up(g.M), Np = pad_up(g.N);
@@ -350,10 +354,16 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
   const int wm = wave >> 1, wn = wave & 1;
 
   const int Kp = pad_up(g.K);
-  const unsigned short* __restrict__ Ahg = (const unsigned short*)g.a_hi + (size_t)b * g.a_stride;
-  const unsigned short* __restrict__ Alg = (const unsigned short*)g.a_lo + (size_t)b * g.a_stride;
-  const unsigned short* __restrict__ Bhg = (const unsigned short*)g.b_hi + (size_t)b * g.b_stride;
-  const unsigned short* __restrict__ Blg = (const unsigned short*)g.b_lo + (size_t)b * g.b_stride;
+  const unsigned short* __restrict__ Ahg =
+      g.a_item ? (const unsigned short*)g.a_item[b] : (const unsigned short*)g.a_hi + (size_t)b * g.a_stride;
+  const unsigned short* __restrict__ Alg =
+      g.a_item ? (const unsigned short*)g.a_item_lo[b] : (const unsigned short*)g.a_lo + (size_t)b * g.a_stride;
+  const unsigned short* __restrict__ Bhg =
+      g.b_item ? (const unsigned short*)g.b_item[b] : (const unsigned short*)g.b_hi + (size_t)b * g.b_stride;
+  const unsigned short* __restrict__ Blg =
+      g.b_item ? (const unsigned short*)g.b_item_lo[b] : (const unsigned short*)g.b_lo + (size_t)b * g.b_stride;
+  const double* __restrict__ lam = g.lam_item ? g.lam_item[b] : g.lam;
+  const double* __restrict__ mu = g.mu_item ? g.mu_item[b] : g.mu;
 
   constexpr int CPR = BK / 8;  // 16-byte chunks per row
 
@@ -454,12 +464,12 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
     for (int i = 0; i < WT; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const double l = g.lam[min(m0 + wm * (16 * WT) + i * 16 + 4 * (lane >> 4) + r, g.M - 1)];
+        const double l = lam[min(m0 + wm * (16 * WT) + i * 16 + 4 * (lane >> 4) + r, g.M - 1)];
         da[i][r] = (float)(g.alpha + s * g.beta_s * l);
         db[i][r] = (float)(s * (g.beta_t + g.delta * l));
       }
 #pragma unroll
-    for (int j = 0; j < WT; ++j) dm[j] = (float)g.mu[min(n0 + wn * (16 * WT) + j * 16 + (lane & 15), g.N - 1)];
+    for (int j = 0; j < WT; ++j) dm[j] = (float)mu[min(n0 + wn * (16 * WT) + j * 16 + (lane & 15), g.N - 1)];
   }
   const float osc = (float)g.out_scale;
   double* __restrict__ C64 = g.c64 + (size_t)b * g.c_stride;

@@ -118,8 +118,8 @@ __global__ __launch_bounds__(256, 2) void gemm_i8_kernel(GemmArgs g) {
   const int wm = wave >> 1, wn = wave & 1;
   const int wv = __builtin_amdgcn_readfirstlane(wave);
 
-  const signed char* __restrict__ Ag = g.a_i8 + (size_t)b * g.a_stride;
-  const signed char* __restrict__ Bg = g.b_i8 + (size_t)b * g.b_stride;
+  const signed char* __restrict__ Ag = g.a_item ? (const signed char*)g.a_item[b] : g.a_i8 + (size_t)b * g.a_stride;
+  const signed char* __restrict__ Bg = g.b_item ? (const signed char*)g.b_item[b] : g.b_i8 + (size_t)b * g.b_stride;
   const size_t a_plane = (size_t)Mp * Kp, b_plane = (size_t)Np * Kp;
 
   // One wave instruction moves 16 rows x 64 bytes of one slice tile: wave w
@@ -182,8 +182,10 @@ __global__ __launch_bounds__(256, 2) void gemm_i8_kernel(GemmArgs g) {
   // epilogue: acc[d][i][j][r] = diagonal p + q = d + 2 of C[row][col],
   // row = 4 (lane / 16) + r, col = lane % 16 within the 16 x 16 tile
   const double s = g.item_scale ? g.item_scale[b] : 1.0;
-  const int* __restrict__ ea = g.a_exp + (size_t)b * g.a_exp_stride;
-  const int* __restrict__ eb = g.b_exp + (size_t)b * g.b_exp_stride;
+  const int* __restrict__ ea = g.a_exp_item ? g.a_exp_item[b] : g.a_exp + (size_t)b * g.a_exp_stride;
+  const int* __restrict__ eb = g.b_exp_item ? g.b_exp_item[b] : g.b_exp + (size_t)b * g.b_exp_stride;
+  const double* __restrict__ lam = g.lam_item ? g.lam_item[b] : g.lam;
+  const double* __restrict__ mu = g.mu_item ? g.mu_item[b] : g.mu;
   double* __restrict__ C = g.c64 + (size_t)b * g.c_stride;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -200,7 +202,7 @@ __global__ __launch_bounds__(256, 2) void gemm_i8_kernel(GemmArgs g) {
         v = ldexp(v, ea[row] + eb[col]);
         v *= g.out_scale;
         if (g.divide) {
-          const double l = g.lam[min(row, g.M - 1)], m = g.mu[min(col, g.N - 1)];
+          const double l = lam[min(row, g.M - 1)], m = mu[min(col, g.N - 1)];
           v /= g.alpha + s * (g.beta_s * l + g.beta_t * m + g.delta * l * m);
         }
         if (!in) v = 0.0;

@@ -104,6 +104,18 @@ struct GemmArgs {
   const int* a_exp;
   const int* b_exp;
   long long a_exp_stride, b_exp_stride;
+  // grouped solves (instances of one shape, each with its own bases): when
+  // set, item b reads that operand from a_item[b] (lo half a_item_lo[b],
+  // digit exponents a_exp_item[b]) instead of base + b * stride, and its
+  // eigenvalues from lam_item[b] / mu_item[b]
+  const void* const* a_item;
+  const void* const* a_item_lo;
+  const int* const* a_exp_item;
+  const void* const* b_item;
+  const void* const* b_item_lo;
+  const int* const* b_exp_item;
+  const double* const* lam_item;
+  const double* const* mu_item;
 };
 // tile: block tile edge, 128 (4 waves of 64 x 64) or 64 (4 waves of 32 x 32)
 int launch_gemm(const GemmArgs& g, int prec, int omode, int batch, int tile, hipStream_t s);

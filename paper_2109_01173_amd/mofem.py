@@ -167,6 +167,8 @@ mofem_imex_graph_result = _proto("mofem_imex_graph_result", ctypes.c_int, [_vp, 
 mofem_imex_graph_destroy = _proto("mofem_imex_graph_destroy", ctypes.c_int, [_vp])
 mofem_pcg_solve_many = _proto("mofem_pcg_solve_many", ctypes.c_int,
                               [ctypes.c_int, ctypes.POINTER(PcgGroup), ctypes.POINTER(_vp), _vp])
+mofem_pcg_solve_grouped = _proto("mofem_pcg_solve_grouped", ctypes.c_int,
+                                 [ctypes.c_int, ctypes.POINTER(PcgGroup), ctypes.POINTER(_vp), _vp])
 mofem_trace_enable = _proto("mofem_trace_enable", ctypes.c_int, [ctypes.c_int])
 mofem_trace_select = _proto("mofem_trace_select", ctypes.c_int, [ctypes.c_uint])
 mofem_trace_read = _proto("mofem_trace_read", ctypes.c_int,
@@ -183,7 +185,7 @@ EXPORTS = ["mofem_version", "mofem_last_error", "mofem_assemble_1d", "mofem_gene
            "mofem_pcg_solve",
            "mofem_imex_workspace_size", "mofem_imex_step", "mofem_dot_accumulate",
            "mofem_imex_adjoint_workspace_size", "mofem_imex_adjoint_step", "mofem_pcg_solve_async",
-           "mofem_pcg_solve_many",
+           "mofem_pcg_solve_many", "mofem_pcg_solve_grouped",
            "mofem_imex_graph_create", "mofem_imex_graph_launch", "mofem_imex_graph_result",
            "mofem_imex_graph_destroy", "mofem_trace_enable", "mofem_trace_select", "mofem_trace_read"]
 
@@ -512,8 +514,11 @@ def pcg_solve_async(op, prec, rhs, U, workspace, iters, status, relres, tol=1e-1
     _check(rc, "mofem_pcg_solve_async")
 
 
-def pcg_solve_many(groups, streams, raise_on_error=True):
-    """Solve several batched systems of uneven shapes together (mofem_pcg_solve_many).
+def pcg_solve_many(groups, streams, raise_on_error=True, grouped=False):
+    """Solve several batched systems of uneven shapes together
+    (mofem_pcg_solve_many; with grouped=True mofem_pcg_solve_grouped, which
+    fuses the groups of one shape into one batched solve and ignores the
+    workspaces).
 
     groups: list of dicts with op, prec, rhs, U and optionally tol, maxit,
     flags, item_scale, workspace; streams: one torch.cuda.Stream per group
@@ -529,7 +534,8 @@ def pcg_solve_many(groups, streams, raise_on_error=True):
         batch = rhs.shape[0]
         ws = g.get("workspace")
         if ws is None:
-            ws = pcg_workspace(op, prec, batch, rhs.device)
+            ws = torch.empty(1, dtype=torch.uint8, device=rhs.device) if grouped else \
+                pcg_workspace(op, prec, batch, rhs.device)
         its = np.zeros(batch, dtype=np.int32)
         rr = np.zeros(batch)
         keep.append(ws)
@@ -544,9 +550,10 @@ def pcg_solve_many(groups, streams, raise_on_error=True):
         a.iters_out, a.relres_out = its.ctypes.data, rr.ctypes.data
     sarr = (_vp * max(n, 1))(*[_vp(st.cuda_stream) for st in streams])
     status = np.zeros(max(n, 1), dtype=np.int32)
-    rc = mofem_pcg_solve_many(n, arr, sarr, _hptr(status))
+    fn = mofem_pcg_solve_grouped if grouped else mofem_pcg_solve_many
+    rc = fn(n, arr, sarr, _hptr(status))
     if raise_on_error:
-        _check(rc, "mofem_pcg_solve_many")
+        _check(rc, "mofem_pcg_solve_grouped" if grouped else "mofem_pcg_solve_many")
     for st in streams:
         cur.wait_stream(st)
     return outs, status[:n].tolist()
