@@ -67,14 +67,15 @@ def cpu_baseline(F0, k, m, gamma, tol, U_gpu0):
 
 
 # HBM traffic of the transform GEMM, from two rocprofv3 --pmc passes over
-# "bench.py --steps 1 --warmup 0 --no-cpu-baseline --fp64-steps 0 --imex-steps 0 --uneven 0" (FETCH_SIZE,
+# "bench.py --steps 1 --warmup 0 --no-cpu-baseline --fp64-steps 0 --int8-steps 0 --heat-steps 0 --dib-steps 0
+# --adjoint 0 --imex-steps 0 --uneven 0 --paper-prec 0" (FETCH_SIZE,
 # then WRITE_SIZE, KiB per dispatch, averaged over that kernel's dispatches),
 # each scaled by the ratio true bytes / counter reading of a plain 512 MiB
 # copy ("bench.py --copy-calibration").  The figures hold for the kernel
 # source they were taken on: if k_gemm.hip changes, traffic is reported null.
 TRAFFIC = {
     # mixed mode -> (sha256 of k_gemm.hip, (q, batch), bytes per launch)
-    "bf16fwd": ("0c0cdc478b2efa069a1799a7ef5fe39cd27b3ac423b341903b1c0882ad0a1ee5", (2047, 16), 1.736e9),
+    "bf16fwd": ("cf5a7650a5ea8a5c2e613334e17261b29ccb85d81238330bf5c6e31d2ada75de", (2047, 16), 1.755e9),
 }
 FETCH_SCALE = 2.000   # 512 MiB copy: true bytes / FETCH_SIZE reading
 WRITE_SCALE = 1.000   # 512 MiB copy: true bytes / WRITE_SIZE reading
