@@ -190,7 +190,8 @@ extern "C" int mofem_trace_read(int cls, double* total_ms, long long* launches, 
 // kb <= 2, 4 above); an operator with more (distinct) terms runs several
 // passes, the later ones adding to Y.
 struct OpPass {
-  int nt = 0, scaled_mask = 0, pattern = 0, n_rowblk = 0, n_tiles = 0;
+  int nt = 0, scaled_mask = 0, pattern = 0;
+  int n_rowblk[2] = {0, 0}, n_tiles[2] = {0, 0};  // default and small row blocks
   double* d_left = nullptr;   // [ns_in][nt][2kb+1]: left bands by input row (transposed)
   double* d_right = nullptr;  // [nt][2kb+1][qt]
 };
@@ -200,7 +201,8 @@ struct mofem_op_s {
   int n_terms = 0;              // distinct terms after merging
   int n_pass = 0;
   OpPass pass[2];               // at most 8 terms, at least 4 per pass
-  int n_tiles = 0;              // tiles of the last pass (the one that forms <X, Y>)
+  int n_tiles_max = 0;          // most tiles of the last pass (the one that forms <X, Y>) in any variant
+  int n_cu = 256;               // compute units of the device (grid-fill rule of op_variant)
   double* d_partial = nullptr;  // dot partials for mofem_op_apply
   int partial_batch = 0;
 };
@@ -370,9 +372,12 @@ extern "C" int mofem_op_create(const mofem_op_desc* desc, mofem_op_t* out) {
       }
     }
     t0 += take;
-    int TI = band_rows_per_block(kb, nt), SW = band_cols_per_block(kb);
-    P.n_rowblk = (qs + op->ph_s + TI - 1) / TI;
-    P.n_tiles = ((qt + SW - 1) / SW) * P.n_rowblk;
+    const int SW = band_cols_per_block(kb);
+    for (int v = 0; v < 2; ++v) {
+      const int TI = band_rows_per_block(kb, nt, v);
+      P.n_rowblk[v] = (qs + op->ph_s + TI - 1) / TI;
+      P.n_tiles[v] = ((qt + SW - 1) / SW) * P.n_rowblk[v];
+    }
     int rc = dev_alloc(&P.d_left, leftT.size());
     if (rc == MOFEM_OK) rc = dev_alloc(&P.d_right, right.size());
     if (rc != MOFEM_OK) {
@@ -385,7 +390,13 @@ extern "C" int mofem_op_create(const mofem_op_desc* desc, mofem_op_t* out) {
       return fail(MOFEM_E_HIP, "op_create: upload failed");
     }
   }
-  op->n_tiles = op->pass[n_pass - 1].n_tiles;
+  op->n_tiles_max = std::max(op->pass[n_pass - 1].n_tiles[0], op->pass[n_pass - 1].n_tiles[1]);
+  {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+      op->n_cu = ncu;
+  }
   *out = op;
   return MOFEM_OK;
 }
@@ -412,12 +423,26 @@ extern "C" int mofem_op_shape(mofem_op_t op, int* qs, int* qt, int* in_s, int* i
 }
 
 namespace {
-// partial_stride: entries between items of `partial` (0: the operator's own
+// Row-block variant of a launch over `batch` items: the small row blocks when
+// the default grid would give fewer than two blocks per compute unit (two
+// items share a lane where they can, so the default grid has tiles x
+// ceil(batch / 2) blocks).  Every launch of one operator over one batch size
+// takes the same variant, so its tile count (op_tiles) is known beforehand.
+int op_variant(mofem_op_t op, int batch) {
+  if (!band_has_small(op->kb)) return 0;
+  const long long blocks = (long long)op->pass[op->n_pass - 1].n_tiles[0] * ((batch + 1) / 2);
+  return blocks < 2LL * op->n_cu ? 1 : 0;
+}
+// partial sums per item of the fused <X, Y> of a launch over `batch` items
+int op_tiles(mofem_op_t op, int batch) { return op->pass[op->n_pass - 1].n_tiles[op_variant(op, batch)]; }
+
+// partial_stride: entries between items of `partial` (0: the launch's own
 // tile count; a grouped solve of several operators uses their maximum)
 int op_launch(mofem_op_t op, const double* X, long long in_stride, double* Y, long long stride, int batch,
               const double* item_scale, double* partial, const int* active, hipStream_t s,
               int n_items = -1, int partial_stride = 0) {
   TraceScope trace(MOFEM_TRACE_BAND, n_items < 0 ? batch : n_items, s);
+  const int v = op_variant(op, batch);
   for (int ps = 0; ps < op->n_pass; ++ps) {
     const OpPass& P = op->pass[ps];
     const bool last = ps == op->n_pass - 1;
@@ -435,17 +460,17 @@ int op_launch(mofem_op_t op, const double* X, long long in_stride, double* Y, lo
     a.off_s = op->off_s;
     a.off_t = op->off_t;
     a.ph_s = op->ph_s;
-    a.n_rowblk = P.n_rowblk;
+    a.n_rowblk = P.n_rowblk[v];
     a.left = P.d_left;
     a.right = P.d_right;
     a.scaled_mask = P.scaled_mask;
     a.item_scale = item_scale;
     a.dot_partial = last ? partial : nullptr;
-    a.n_partial = partial_stride > 0 ? partial_stride : P.n_tiles;
+    a.n_partial = partial_stride > 0 ? partial_stride : P.n_tiles[v];
     a.active = active;
     a.accumulate = ps > 0;  // later passes add to the earlier passes' Y
     a.batch = batch;
-    if (launch_band_apply(a, op->kb, P.nt, batch, P.pattern != 0, s) != 0)
+    if (launch_band_apply(a, op->kb, P.nt, batch, P.pattern != 0, v, s) != 0)
       return fail(MOFEM_E_UNSUPPORTED, "op_apply: unsupported band/term combination");
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(MOFEM_E_HIP, std::string("op_apply launch: ") + hipGetErrorString(e));
@@ -474,7 +499,7 @@ extern "C" int mofem_op_apply(mofem_op_t op, const double* X, long long in_strid
         (void)hipFree(op->d_partial);
         op->d_partial = nullptr;
       }
-      int rc = dev_alloc(&op->d_partial, (size_t)batch * op->n_tiles);
+      int rc = dev_alloc(&op->d_partial, (size_t)batch * op->n_tiles_max);
       if (rc != MOFEM_OK) return rc;
       op->partial_batch = batch;
     }
@@ -482,7 +507,7 @@ extern "C" int mofem_op_apply(mofem_op_t op, const double* X, long long in_strid
   }
   int rc = op_launch(op, X, in_stride, Y, stride, batch, item_scale, partial, nullptr, s);
   if (rc != MOFEM_OK) return rc;
-  if (dot_xy && launch_reduce(partial, op->n_tiles, dot_xy, batch, s) != 0)
+  if (dot_xy && launch_reduce(partial, op_tiles(op, batch), dot_xy, batch, s) != 0)
     return fail(MOFEM_E_HIP, "op_apply: reduce launch failed");
   return MOFEM_OK;
 }
@@ -532,7 +557,7 @@ extern "C" int mofem_op_apply_noalloc(mofem_op_t op, const double* X, long long 
     return fail(MOFEM_E_ARG, "op_apply_noalloc: <X, Y> needs a square operator");
   double* partial = nullptr;
   if (dot_xy) {
-    const size_t need = (size_t)batch * op->n_tiles;
+    const size_t need = (size_t)batch * op_tiles(op, batch);
     if (need > kScratchDoubles)
       return fail(MOFEM_E_ARG, "op_apply_noalloc: batch * tiles = " + std::to_string(need) +
                                    " partial sums exceed the static scratch of " +
@@ -545,7 +570,7 @@ extern "C" int mofem_op_apply_noalloc(mofem_op_t op, const double* X, long long 
   // every tile of every item writes its partial sum, so nothing needs clearing
   int rc = op_launch(op, X, in_stride, Y, stride, batch, item_scale, partial, nullptr, s);
   if (rc != MOFEM_OK) return rc;
-  if (dot_xy && launch_reduce(partial, op->n_tiles, dot_xy, batch, s) != 0)
+  if (dot_xy && launch_reduce(partial, op_tiles(op, batch), dot_xy, batch, s) != 0)
     return fail(MOFEM_E_HIP, "op_apply_noalloc: reduce launch failed");
   return MOFEM_OK;
 }
@@ -1362,7 +1387,7 @@ size_t pcg_bytes(mofem_op_t op, mofem_prec_t prec, int batch, size_t* prec_part,
   size_t b = 0;
   b += 4 * align_up(n * batch * 8, 256);
   b += 2 * align_up((size_t)batch * kVecBlocks * 8, 256);
-  b += align_up((size_t)batch * (np > 0 ? np : op->n_tiles) * 8, 256);
+  b += align_up((size_t)batch * (np > 0 ? np : op->n_tiles_max) * 8, 256);
   b += 11 * align_up((size_t)batch * 8, 256);
   b += 6 * align_up((size_t)batch * 4, 256);
   size_t pp = mofem_prec_workspace_size(prec, batch);
@@ -1379,7 +1404,7 @@ bool carve_pcg(mofem_op_t op, mofem_prec_t prec, int batch, void* ws, size_t byt
   w->Y = c.take<double>(n * batch);
   w->part_a = c.take<double>((size_t)batch * kVecBlocks);
   w->part_b = c.take<double>((size_t)batch * kVecBlocks);
-  w->part_op = c.take<double>((size_t)batch * (np > 0 ? np : op->n_tiles));
+  w->part_op = c.take<double>((size_t)batch * (np > 0 ? np : op->n_tiles_max));
   double** scal[] = {&w->rz, &w->rz_new, &w->qy, &w->rr, &w->zy, &w->alpha, &w->beta, &w->rhs2, &w->tr,
                      &w->target2};
   for (double** x : scal) *x = c.take<double>(batch);
@@ -1447,7 +1472,7 @@ struct PcgRun {
   int np = 0;
   const void* const* tabs = nullptr;
 
-  int n_partial() const { return np > 0 ? np : op->n_tiles; }
+  int n_partial() const { return np > 0 ? np : op_tiles(op, batch); }
   // Y = L(X) over every item (one launch per operator of a grouped solve)
   int run_op(const double* X, long long xs, double* Y, long long ys, double* partial, const int* act, int ntr) {
     if (ranges.empty()) return op_launch(op, X, xs, Y, ys, batch, item_scale, partial, act, s, ntr);
@@ -1898,11 +1923,17 @@ extern "C" int mofem_pcg_solve_grouped(int n_groups, const mofem_pcg_group* grou
   for (size_t c = 0; c < nc && !rc; ++c) {
     const mofem_pcg_group& G0 = groups[members[c][0]];
     hipStream_t s = (hipStream_t)streams[members[c][0]];
+    // item ranges of one operator (consecutive groups with the same operator
+    // merged); each range's launches take the row-block variant of its size
+    std::vector<PcgRun::OpRange> ranges;
     int B = 0, np = 0;
     for (int gi : members[c]) {
-      B += groups[gi].batch;
-      np = std::max(np, groups[gi].op->n_tiles);
+      const mofem_pcg_group& G = groups[gi];
+      if (!ranges.empty() && ranges.back().op == G.op) ranges.back().b1 += G.batch;
+      else ranges.push_back({G.op, B, B + G.batch});
+      B += G.batch;
     }
+    for (const auto& R : ranges) np = std::max(np, op_tiles(R.op, R.b1 - R.b0));
     const long long n = (long long)G0.op->qs * G0.op->qt;
     // class buffer: right-hand sides, solutions, item scales, pointer tables, PCG workspace
     const size_t ws = pcg_bytes(G0.op, G0.prec, B, nullptr, np);
@@ -1956,13 +1987,7 @@ extern "C" int mofem_pcg_solve_grouped(int n_groups, const mofem_pcg_group* grou
     if (r.z32) r.z32 = reinterpret_cast<float*>(r.w.Z);
     r.np = np;
     r.tabs = dtab;
-    b0 = 0;
-    for (int gi : members[c]) {
-      const mofem_pcg_group& G = groups[gi];
-      if (!r.ranges.empty() && r.ranges.back().op == G.op) r.ranges.back().b1 += G.batch;
-      else r.ranges.push_back({G.op, b0, b0 + G.batch});
-      b0 += G.batch;
-    }
+    r.ranges = ranges;
     // operators with fewer tiles than np leave their items' last partial sums unwritten
     if (launch_fill(r.w.part_op, 0.0, (long long)B * np, (long long)B * np, 1, s)) {
       rc = fail(MOFEM_E_HIP, "pcg_solve_grouped: launch failed");

@@ -386,6 +386,15 @@ void launch_kb_nt(const BandArgs& a, int batch, bool pat, hipStream_t s) {
                        a.Y, a.left, a.right);
 }
 
+// Row groups per block of the small-block variant (a quarter of the default
+// rows) for band widths up to 2; launches whose default grid would leave
+// compute units idle (few items, small q) take it.  0 where none is compiled
+// (KB >= 3, where smaller row blocks measured slower).
+template <int KB>
+constexpr int band_small_groups() {
+  return KB <= 2 ? ((160 / BandRing<KB>::UG) / 4 > 0 ? (160 / BandRing<KB>::UG) / 4 : 1) : 0;
+}
+
 // Terms one launch takes for band half-width KB (more run as several passes,
 // the later ones accumulating): up to 6 for KB <= 2; up to 4 for KB >= 3,
 // where 5 or 6 terms in one launch need more than 256 registers per lane.
@@ -408,5 +417,18 @@ constexpr int band_max_pass_terms(int kb) { return kb <= 2 ? 6 : 4; }
 #define MOFEM_BAND_INSTANTIATE_WIDE(KB)                                                   \
   MOFEM_BAND_INSTANTIATE_NT(KB, 5)                                                        \
   MOFEM_BAND_INSTANTIATE_NT(KB, 6)
+// the small-block variants (band widths 1 and 2)
+#define MOFEM_BAND_SMALL_NT(KB, NT, ACC, IPL) \
+  launch_kb_nt<KB, NT, ACC, IPL, band_small_groups<KB>()>(const BandArgs&, int, bool, hipStream_t);
+#define MOFEM_BAND_SMALL_LIST(P, KB)                                                                      \
+  P MOFEM_BAND_SMALL_NT(KB, 1, false, 1) P MOFEM_BAND_SMALL_NT(KB, 1, false, 2)                          \
+  P MOFEM_BAND_SMALL_NT(KB, 2, false, 1) P MOFEM_BAND_SMALL_NT(KB, 2, false, 2)                          \
+  P MOFEM_BAND_SMALL_NT(KB, 3, false, 1) P MOFEM_BAND_SMALL_NT(KB, 3, false, 2)                          \
+  P MOFEM_BAND_SMALL_NT(KB, 4, false, 1) P MOFEM_BAND_SMALL_NT(KB, 4, false, 2)                          \
+  P MOFEM_BAND_SMALL_NT(KB, 5, false, 1) P MOFEM_BAND_SMALL_NT(KB, 5, false, 2)                          \
+  P MOFEM_BAND_SMALL_NT(KB, 6, false, 1) P MOFEM_BAND_SMALL_NT(KB, 6, false, 2)                          \
+  P MOFEM_BAND_SMALL_NT(KB, 2, true, 1) P MOFEM_BAND_SMALL_NT(KB, 3, true, 1)                            \
+  P MOFEM_BAND_SMALL_NT(KB, 4, true, 1)
+#define MOFEM_BAND_INSTANTIATE_SMALL(KB) MOFEM_BAND_SMALL_LIST(template void, KB)
 
 }  // namespace mofem

@@ -4,4 +4,5 @@
 namespace mofem {
 MOFEM_BAND_INSTANTIATE_COMMON(1)
 MOFEM_BAND_INSTANTIATE_WIDE(1)
+MOFEM_BAND_INSTANTIATE_SMALL(1)
 }  // namespace mofem

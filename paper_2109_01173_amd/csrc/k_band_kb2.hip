@@ -4,4 +4,5 @@
 namespace mofem {
 MOFEM_BAND_INSTANTIATE_COMMON(2)
 MOFEM_BAND_INSTANTIATE_WIDE(2)
+MOFEM_BAND_INSTANTIATE_SMALL(2)
 }  // namespace mofem

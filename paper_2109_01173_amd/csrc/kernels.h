@@ -33,10 +33,14 @@ struct BandArgs {
   int accumulate;          // 1: Y += result (a later pass of a many-term operator)
   int batch;               // items (the launch may pair them: two per lane)
 };
-int band_rows_per_block(int kb, int nt);
+// rows per block of the default (small = 0) or the small-block variant
+// (small = 1, band widths with band_has_small only): a quarter of the rows,
+// for grids that would otherwise leave compute units idle
+int band_rows_per_block(int kb, int nt, int small);
+int band_has_small(int kb);
 int band_cols_per_block(int kb);
 int band_pass_terms(int kb);  // terms one launch takes (more run as passes)
-int launch_band_apply(const BandArgs& a, int kb, int nt, int batch, bool pattern, hipStream_t s);
+int launch_band_apply(const BandArgs& a, int kb, int nt, int batch, bool pattern, int small, hipStream_t s);
 
 // ---- banded Cholesky solves of the product preconditioners (k_bchol.hip) -----
 // Out^T = S^{-1} X per item: X is n_rows x n_cols (row length ld_x), S = L L^T
