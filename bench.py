@@ -194,9 +194,10 @@ def uneven_leg(mf, torch, np, n_inst, prec, prec_name, rds_steps=100):
     dt_many = time.perf_counter() - t
     its = np.concatenate([o[0] for o in outs]) if outs else np.zeros(1)
     # grouped: one batched solve per shape class (one launch per stage over its
-    # instances of every k), the classes on their own streams
+    # instances of every k), each class on its own stream
     shape_of = sorted({int(g["rhs"].shape[1]) for g in groups})
-    gstreams = [streams[shape_of.index(int(g["rhs"].shape[1])) % 4] for g in groups]
+    cstreams = [torch.cuda.Stream() for _ in shape_of]   # one stream per shape class
+    gstreams = [cstreams[shape_of.index(int(g["rhs"].shape[1]))] for g in groups]
     mf.pcg_solve_many(groups, gstreams, grouped=True)   # warm-up
     torch.cuda.synchronize()
     t = time.perf_counter()

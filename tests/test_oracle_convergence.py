@@ -38,10 +38,11 @@ def test_xnormal_manufactured_order(k):
         U = direct_solve(P.kron(), P.rhs(F))
         errs.append(l2_error(extend(U, P.n, "dirichlet"), k, m, exact_u, L_profile))
     r = rates(errs)
-    # Table 2 of the paper reports rates k + 1 within 0.01 on finer meshes
+    # the same P_k discretisation's L2 rate that Table 2 of the paper measures
+    # (there on the heat test, on finer meshes): the oracle's rate on these
+    # coarser meshes lies within 0.12 of it
     key = "P%d" % k
-    assert abs(GOLDEN["table2_heat_convergence_rates"][key][1] - (k + 1)) < 0.01
-    assert r[-1] > k + 1 - 0.12, (errs, r)
+    assert abs(r[-1] - GOLDEN["table2_heat_convergence_rates"][key][1]) < 0.12, (errs, r)
 
 
 def test_lumped_p1_order_two():
@@ -52,7 +53,8 @@ def test_lumped_p1_order_two():
         F = elliptic_F(P.n, gamma)
         U = direct_solve(P.kron(), P.rhs(F))
         errs.append(l2_error(extend(U, P.n, "dirichlet"), 1, m, exact_u, L_profile))
-    assert rates(errs)[-1] > 1.9
+    # Table 2's lumped P1 rates are 1.9953 and 2.0509
+    assert abs(rates(errs)[-1] - GOLDEN["table2_heat_convergence_rates"]["lumped_P1"][0]) < 0.1
 
 
 @pytest.mark.parametrize("k", [1, 2, 3, 4])
