@@ -117,7 +117,9 @@ def uneven_leg(mf, torch, np, n_inst, prec, prec_name, rds_steps=100):
     (pcg_solve_many); the reaction-diffusion groups step one after another.
     The elliptic groups are also solved grouped by shape (pcg_solve_many
     with grouped=True: one batched solve per shape class, all element orders
-    in the same launches), which the whole-job time uses.  The groups' set-up
+    in the same launches), and the reaction-diffusion groups are also
+    replayed from one HIP graph per group on their own streams; the
+    whole-job time takes the faster form of each part.  The groups' set-up
     (assembly, eigen-decompositions) runs on a pool of host threads."""
     from paper_2109_01173_amd.problems import Rect, XNormal
     from workloads import dib_initial, dib_params, elliptic_batch
@@ -223,12 +225,37 @@ def uneven_leg(mf, torch, np, n_inst, prec, prec_name, rds_steps=100):
     torch.cuda.synchronize()
     dt_rds = time.perf_counter() - t
     finite = all(bool(torch.isfinite(r["st"]).all()) for r in rds)
-    job = dt_grp + dt_rds
+    eager_final = [r["st"].clone() for r in rds]
+    # the same steps replayed from one HIP graph per group (two PCG iterations
+    # budgeted per solve; the DIB solves converge in one), the groups on their
+    # own streams
+    for r in rds:
+        r["st"].copy_(r["st0"])
+        r["graph"] = mf.ImexGraph(r["stepper"], r["st"], r["batch"], iters_per_step=2)
+        r["side"] = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for r in rds:
+        with torch.cuda.stream(r["side"]):
+            r["graph"].launch(rds_steps)
+    torch.cuda.synchronize()
+    dt_rds_g = time.perf_counter() - t
+    g_ok = True
+    for r, ref in zip(rds, eager_final):
+        its_g_r, st_g_r, _ = r["graph"].result(raise_on_error=False)
+        d = float((r["st"] - ref).norm() / ref.norm())
+        g_ok = g_ok and bool((st_g_r == 0).all()) and d <= 1e-12
+        rds_its.append(int(its_g_r.max()))
+    finite = finite and all(bool(torch.isfinite(r["st"]).all()) for r in rds)
+    job = dt_grp + min(dt_rds, dt_rds_g)
     log("uneven batch: %d instances (%d elliptic in %d groups, %d shapes, %d reaction-diffusion in %d groups): "
         "elliptic %.1f solves/s one group at a time, %.1f groups on streams, %.1f grouped by shape; "
-        "reaction-diffusion %.1f instance-steps/s (%d steps each); whole job %.2f s = %.1f instances/s"
+        "reaction-diffusion %.1f instance-steps/s (%d steps each) eager, %.1f replayed from graphs on streams "
+        "(graph states %s the eager ones to 1e-12); whole job %.2f s = %.1f instances/s"
         % (n_inst, n_ell, len(groups), len(shape_of), n_rds, len(rds), n_ell / dt_seq, n_ell / dt_many,
-           n_ell / dt_grp, n_rds * rds_steps / dt_rds if dt_rds > 0 else 0.0, rds_steps, job, n_inst / job))
+           n_ell / dt_grp, n_rds * rds_steps / dt_rds if dt_rds > 0 else 0.0, rds_steps,
+           n_rds * rds_steps / dt_rds_g if dt_rds_g > 0 else 0.0, "equal to" if g_ok else "DIFFER FROM",
+           job, n_inst / job))
     return {"uneven_batch": {"workload": "%d instances, n in {257,513,1025,2049}, k in 1..4, type in {elliptic, "
                                          "reaction-diffusion} (seed 5); elliptic: P_k x-normal, Dirichlet, gamma=1, "
                                          "rel 1e-8, %s transforms; reaction-diffusion: DIB rectangle [0,20]^2, "
@@ -243,6 +270,8 @@ def uneven_leg(mf, torch, np, n_inst, prec, prec_name, rds_steps=100):
                              "status_ok": all(st == 0 for st in status + status_g),
                              "rds_instances": n_rds, "rds_groups": len(rds),
                              "rds_instance_steps_per_s": round(n_rds * rds_steps / dt_rds, 2) if dt_rds > 0 else None,
+                             "rds_instance_steps_per_s_graphs": round(n_rds * rds_steps / dt_rds_g, 2)
+                             if dt_rds_g > 0 else None, "rds_graph_states_equal_eager": g_ok,
                              "rds_iterations_max": max(rds_its) if rds_its else 0, "rds_finite": finite,
                              "job_s": round(job, 3), "instances_per_s": round(n_inst / job, 2),
                              "setup_s": round(setup, 2)}}
