@@ -213,8 +213,9 @@ int mofem_op_apply(mofem_op_t op, const double* X, long long in_stride, double* 
    the handle allocates, and no timing events are recorded.  Calls no
    hipMalloc, hipFree or other allocating routine.  Limit: with dot_xy,
    batch * tiles partial sums (8 bytes each) must fit the array, where tiles =
-   ceil(q_t / (4 (64 - 2 kb))) * ceil(q_s / rows) and rows is about 160 (117
-   tiles at q = 2047 and kb = 2, so batch <= 1120); larger requests fail with
+   ceil(q_t / (4 (64 - 2 kb))) * ceil(q_s / rows) and rows is about 160 (a
+   quarter of that for batches too small to fill the GPU otherwise; 117 tiles
+   at q = 2047 and kb = 2, so batch <= 1120); larger requests fail with
    MOFEM_E_ARG.  Every call on one GPU shares that array:
    calls that overlap on one GPU (other streams or threads) race and must be
    serialised by the caller.  Without dot_xy the array is not used. */

@@ -149,3 +149,18 @@ def test_unattainable_tolerance_restarts(precision, flags):
         assert abs(true - relres[b]) <= 1e-6 * true + 1e-18
         assert true < 1e-13
         assert rel(Uh[b], direct_solve(K, Rh[b])) < 1e-11
+
+
+@pytest.mark.parametrize("precision", ["F64", "BF16_FWD", "F64_INT8"])
+def test_empty_batches(precision):
+    """Zero items: the solve, the preconditioner and the operator return at
+    once and touch nothing."""
+    import torch
+    from paper_2109_01173_amd import mofem as mf
+    G = gpu_xnormal(2, 20, "dirichlet", 1.0, precision=getattr(mf, "PREC_" + precision))
+    R = torch.zeros((0, G.q, G.q), dtype=torch.float64, device="cuda")
+    U = torch.zeros_like(R)
+    its, rr, rc = mf.pcg_solve(G.op, G.prec, R, U, tol=1e-10, maxit=10, raise_on_error=False)
+    assert rc == mf.OK and its.size == 0
+    assert G.prec.apply(R).shape == (0, G.q, G.q)
+    assert G.op.apply(R).shape == (0, G.q, G.q)

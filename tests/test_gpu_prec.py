@@ -95,7 +95,7 @@ def test_prec_tiny_and_errors():
         G.prec.set_precision(99)
 
 
-@pytest.mark.parametrize("precision", ["F64", "F32", "BF16X3", "BF16X2", "BF16", "BF16_FWD"])
+@pytest.mark.parametrize("precision", ["F64", "F32", "BF16X3", "BF16X2", "BF16", "BF16_FWD", "F64_INT8"])
 def test_block_tiles_agree_and_tuner(precision):
     """Both block tiles of the transforms compute the same products in the same
     k order (BF16 on 128-row tiles loads through LDS directly, on 64-row tiles
