@@ -348,8 +348,9 @@ void band_apply_kernel(
       for (int it = 0; it < IPL; ++it) {
         if constexpr (ACC) y[it] += band_load(yr[it], yoff[it], yrow_off);
         band_store(y[it], yr[it], yoff[it], yrow_off);
-        // X of output row i (square operators) is input row p - KB
-        dot[it] = fma(own ? y[it] : 0.0, xq[it][(p_mod + NQ - KB) % NQ], dot[it]);
+        // X of output row i (square operators) is input row p - KB; every lane
+        // accumulates, the halo lanes' sums are discarded once at the end
+        dot[it] = fma(y[it], xq[it][(p_mod + NQ - KB) % NQ], dot[it]);
       }
       __builtin_amdgcn_sched_barrier(0);
     });
@@ -358,7 +359,7 @@ void band_apply_kernel(
   if (a.dot_partial) {
 #pragma unroll
     for (int it = 0; it < IPL; ++it) {
-      const double dw = wave_sum(dot[it]);
+      const double dw = wave_sum(own ? dot[it] : 0.0);
       if (lane == 0) dsum[it][wave] = dw;
     }
     __syncthreads();

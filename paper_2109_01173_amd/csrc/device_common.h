@@ -86,4 +86,29 @@ __device__ __forceinline__ void grouped_tile(int id, int tm, int tn, int G, int*
   *tc = w / rows;
 }
 
+// Item b and tile (row, column) of dispatch (bx, by) of a grid of tm x tn
+// tiles per item and gridDim.y items.  When the grid splits evenly (tm a
+// multiple of 8, tm tn of 64, all tiles of 512), the dispatches an XCD receives
+// in turn (every eighth) take consecutive 8 x 8 blocks of one item's tiles,
+// and the eight XCDs hold eight such blocks of two items at a time; otherwise
+// b = by and the tile comes from grouped_tile with bands of G rows.  Bijective.
+__device__ __forceinline__ void item_tile(int bx, int by, int tm, int tn, int G, bool blocks8, int* b, int* tr,
+                                          int* tc) {
+  const int nti = tm * tn;
+  if (blocks8 && tm % 8 == 0 && nti % 64 == 0 && (nti * (int)gridDim.y) % 512 == 0) {
+    const int L = bx + nti * by;
+    const int x = L % 8, slot = L / 8;
+    const int T = ((slot / 64) * 8 + x) * 64 + slot % 64;  // chunk (slot / 64, x), then its tile
+    *b = T / nti;
+    const int t = T - *b * nti;
+    const int band = t / (8 * tn);
+    const int w = t - band * 8 * tn;
+    *tr = band * 8 + w % 8;
+    *tc = w / 8;
+  } else {
+    *b = by;
+    grouped_tile(bx, tm, tn, G, tr, tc);
+  }
+}
+
 }  // namespace mofem

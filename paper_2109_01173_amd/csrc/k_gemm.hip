@@ -35,8 +35,9 @@
 // registers; FP32 and FP64: through registers); in the split products the
 // three passes run one after the other over all 16 accumulators, so
 // back-to-back MFMAs are independent.
-// Block order is XCD-aware: each XCD takes a compact block of tiles, about
-// four (128 tiles) or eight (64 tiles) tile rows high, of one item.
+// Block order is XCD-aware: each XCD takes a compact block of tiles of one
+// item, about four (128 tiles) or eight (64 tiles) tile rows high; the BF16
+// products with 128 tiles take 8 x 8 blocks where the grid splits evenly.
 // Intermediates are padded to multiples of 128 in both dimensions and the
 // epilogue writes zeros into the padding, so consumers read whole tiles
 // without bounds checks.
@@ -343,12 +344,13 @@ __global__ __launch_bounds__(256, MINW) void gemm_bf16_kernel(GemmArgs g) {
   // chunk index XOR (r / 2) % 8 (rocprofv3 SQ_LDS_BANK_CONFLICT: none)
   auto sw = [](int r, int k) { return (((k >> 3) ^ ((r >> 1) % (BK / 8))) << 3); };
 
-  const int b = blockIdx.y;
-  if (g.active && !g.active[b]) return;
   // tiles cover the padded extent, so every padded output entry is written
   const int tm = pad_up(g.M) / TB, tn = pad_up(g.N) / TB;
-  int tr, tc;
-  grouped_tile(blockIdx.x, tm, tn, TB == 128 ? 4 : 8, &tr, &tc);
+  // 128-row tiles: 8 x 8 tile blocks per XCD (1-3 % faster than 4 x 8 blocks
+  // of two items per XCD, at the same fetched bytes)
+  int b, tr, tc;
+  item_tile(blockIdx.x, blockIdx.y, tm, tn, TB == 128 ? 4 : 8, TB == 128, &b, &tr, &tc);
+  if (g.active && !g.active[b]) return;
   const int m0 = tr * TB, n0 = tc * TB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;

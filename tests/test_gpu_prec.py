@@ -113,3 +113,24 @@ def test_block_tiles_agree_and_tuner(precision):
     assert G.prec.tune(2) in (64, 128)
     assert rel(to_host(G.prec.apply(R)), out[128]) <= 1e-15
     G.prec.set_precision(mf.PREC_F64)
+
+
+@pytest.mark.parametrize("precision", ["BF16_FWD", "BF16X3"])
+def test_block_tiles_agree_on_whole_chunks(precision):
+    """q = 1023, batch 8: the 128-row BF16 tiles then fill 64-tile chunks (8 x 8
+    tile blocks per XCD, two items at a time), the 64-row tiles keep the banded
+    order; every item must still get exactly its own products."""
+    from paper_2109_01173_amd import mofem as mf
+    G = gpu_xnormal(2, 512, "dirichlet", 1.0)   # q = 1023: 8 x 8 tiles of 128 per item
+    G.prec.set_precision(getattr(mf, "PREC_" + precision))
+    R = to_dev(np.random.default_rng(6).standard_normal((8, G.q, G.q)))
+    out = {}
+    for tile in (64, 128):
+        G.prec.set_tile(8, tile)
+        out[tile] = to_host(G.prec.apply(R))
+    assert rel(out[64], out[128]) <= 1e-15
+    # each item alone (batch 1 never fills a chunk) gives the same result
+    G.prec.set_tile(1, 128)
+    for i in (0, 5):
+        assert rel(to_host(G.prec.apply(R[i:i + 1]))[0], out[128][i]) <= 1e-15
+    G.prec.set_precision(mf.PREC_F64)
