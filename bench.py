@@ -72,10 +72,11 @@ def cpu_baseline(F0, k, m, gamma, tol, U_gpu0):
 # then WRITE_SIZE, KiB per dispatch, averaged over that kernel's dispatches),
 # each scaled by the ratio true bytes / counter reading of a plain 512 MiB
 # copy ("bench.py --copy-calibration").  The figures hold for the kernel
-# source they were taken on: if k_gemm.hip changes, traffic is reported null.
+# source they were taken on: if k_gemm.hip or device_common.h (its tile
+# order) changes, traffic is reported null.
 TRAFFIC = {
-    # mixed mode -> (sha256 of k_gemm.hip, (q, batch), bytes per launch)
-    "bf16fwd": ("cf5a7650a5ea8a5c2e613334e17261b29ccb85d81238330bf5c6e31d2ada75de", (2047, 16), 1.755e9),
+    # mixed mode -> (sha256 of k_gemm.hip + device_common.h, (q, batch), bytes per launch)
+    "bf16fwd": ("3957875db4dfee21859442486a46ee6bd5e95f6dde6dda13de43b7757296fafb", (2047, 16), 1.769e9),
 }
 FETCH_SCALE = 2.000   # 512 MiB copy: true bytes / FETCH_SIZE reading
 WRITE_SCALE = 1.000   # 512 MiB copy: true bytes / WRITE_SIZE reading
@@ -86,9 +87,11 @@ def measured_traffic(mode, q, batch):
     rec = TRAFFIC.get(mode)
     if rec is None:
         return None
-    src = os.path.join(ROOT, "paper_2109_01173_amd", "csrc", "k_gemm.hip")
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for name in ("k_gemm.hip", "device_common.h"):
+        with open(os.path.join(ROOT, "paper_2109_01173_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    sha = h.hexdigest()
     if sha != rec[0] or tuple(rec[1]) != (q, batch):
         return None
     return rec[2]
