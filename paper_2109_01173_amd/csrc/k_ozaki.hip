@@ -35,11 +35,14 @@
 // wave holds the current tile's fragments in registers (as the BF16
 // kernel); the products of the first A digit are issued before that
 // barrier, so they overlap the other waves' fragment reads (7 % faster
-// than issuing every product after it).  LDS rows of 64 bytes with their 16-byte chunks XOR-swizzled by
-// (row / 4) % 4, so the 16 rows one fragment read touches fall on distinct
-// banks.  Within an MFMA the hardware's assignment of k to lanes is the same
-// for both operands, and integer sums do not depend on their order, so the
-// fragments are read with any common k order.
+// than issuing every product after it).  LDS rows of 64 bytes with their
+// 16-byte chunks XOR-swizzled by ((row / 2) ^ (row / 4)) % 4: any 8
+// consecutive rows of a fragment read cover a 128-byte bank window once and
+// any 16 a 256-byte window (rocprofv3 SQ_LDS_BANK_CONFLICT: none; the swizzle
+// (row / 4) % 4 conflicted in half the LDS-active cycles).  Within an MFMA
+// the hardware's assignment of k to lanes is the same for both operands, and
+// integer sums do not depend on their order, so the fragments are read with
+// any common k order.
 #include "device_common.h"
 #include "kernels.h"
 #include "mofem_internal.h"
@@ -129,7 +132,7 @@ __global__ __launch_bounds__(256, 2) void gemm_i8_kernel(GemmArgs g) {
   // fetches the global chunk that the swizzle places in that slot (the
   // swizzle of row 16 w + lrow depends on lrow only).
   const int lrow = lane >> 2;
-  const int lchunk = (lane & 3) ^ ((lrow >> 2) & 3);
+  const int lchunk = (lane & 3) ^ (((lrow >> 1) ^ (lrow >> 2)) & 3);
   const unsigned a_off = (unsigned)((m0 + 16 * wv + lrow) * Kp + lchunk * 16);
   const unsigned b_off = (unsigned)((n0 + 16 * wv + lrow) * Kp + lchunk * 16);
   signed char* const lds_w = lds + wv * 16 * BK;
@@ -143,7 +146,7 @@ __global__ __launch_bounds__(256, 2) void gemm_i8_kernel(GemmArgs g) {
   // fragment of tile row block rb (16 rows from rb) of a slice tile
   auto frag = [&](const signed char* tile, int rb) {
     const int r = rb + (lane & 15);
-    const int c = (lane >> 4) ^ ((r >> 2) & 3);
+    const int c = (lane >> 4) ^ (((r >> 1) ^ (r >> 2)) & 3);
     return *reinterpret_cast<const i4_t*>(tile + r * BK + c * 16);
   };
 
