@@ -164,3 +164,30 @@ def test_empty_batches(precision):
     assert rc == mf.OK and its.size == 0
     assert G.prec.apply(R).shape == (0, G.q, G.q)
     assert G.op.apply(R).shape == (0, G.q, G.q)
+
+
+def test_masked_items_in_whole_chunk_batches():
+    """q = 1023, batch 8: the BF16 transforms then take 8 x 8 tile blocks of
+    two items at a time.  The items' right-hand sides differ (noise levels from
+    none to dominant, a random one, a zero one that is inactive from the
+    start), so they leave the solve at different iterations and later launches
+    run with some items masked off; every item must match its own batch-1
+    solve."""
+    from paper_2109_01173_amd import mofem as mf
+    G = gpu_xnormal(2, 512, "dirichlet", 1.0, precision=mf.PREC_BF16_FWD)
+    n, q = G.n, G.q
+    F = np.stack([elliptic_F(n, 1.0, s, 77 + b) for b, s in enumerate((0.0, 1e-3, 1e-2, 1e-1, 1.0, 1e-3))])
+    F = np.concatenate([F, np.zeros((1, n, n)), np.random.default_rng(3).standard_normal((1, n, n))])
+    Rhs = G.rhs_op.apply(to_dev(F))
+    U = to_dev(np.zeros((8, q, q)))
+    flags = mf.PCG_FLEXIBLE | mf.PCG_ZERO_GUESS
+    its, rr, rc = mf.pcg_solve(G.op, G.prec, Rhs, U, tol=1e-8, maxit=300, flags=flags)
+    assert rc == mf.OK and (rr <= 1e-8).all()
+    assert its[6] == 0 and not to_host(U[6]).any()
+    assert len(set(its.tolist())) >= 3
+    Ub = to_host(U)
+    for b in (0, 3, 4, 7):
+        U1 = to_dev(np.zeros((1, q, q)))
+        its1, rr1, rc1 = mf.pcg_solve(G.op, G.prec, Rhs[b:b + 1].contiguous(), U1, tol=1e-8, maxit=300, flags=flags)
+        assert rc1 == mf.OK and abs(int(its1[0]) - int(its[b])) <= 1
+        assert rel(Ub[b], to_host(U1)[0]) <= 1e-9
