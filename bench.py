@@ -315,7 +315,11 @@ def heat_leg(mf, torch, np, nsteps, eager_steps):
     its = [int(stepper.step(st, 1, workspace=ws)[0]) for _ in range(eager_steps)]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
-    budget = max(its) + 2
+    # the rough initial data need the most iterations in the first steps (35
+    # falling to 14 over the ten eager steps); the budget covers the later
+    # eager steps with two to spare, and a replayed step that ran out of it
+    # would show in the graph's status
+    budget = max(its[len(its) // 2:]) + 2
     g = mf.ImexGraph(mk(), st, 1, iters_per_step=budget)
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -332,6 +336,7 @@ def heat_leg(mf, torch, np, nsteps, eager_steps):
         "graph_max_iterations": int(gi.max()), "graph_status_ok": bool(np.all(gst == 0)),
         "last_step_relres": float(np.max(grr)),
         "eager_steps_per_s": round(eager_steps / dt, 3), "eager_iterations_per_step": round(float(np.mean(its)), 2),
+        "eager_iterations": its,
         "transforms": "f32", "setup_s": round(setup, 2),
         "mass_drift_rel": abs(mass1 - mass0) / abs(mass0),
         "time_reached": round(1e-3 * (nsteps + eager_steps), 4)}}
