@@ -54,7 +54,7 @@ def cpu_baseline(F0, k, m, gamma, tol, U_gpu0):
     except Exception:  # threadpoolctl missing: report the host's logical CPUs
         threads = os.cpu_count()
     P = XNormalProblem(k, m, "dirichlet", L_profile, dL_profile, gamma=gamma)
-    S = SpectralPrec(*P.prec_pairs("sylv"))
+    S = SpectralPrec(*P.prec_pairs("sylv-matched"))   # the library's elliptic pencils
     R = P.rhs(F0)
     t0 = time.perf_counter()
     U, info = mo_pcg(P.apply, S.apply, R, tol=tol, maxit=200)

@@ -232,6 +232,16 @@ int mofem_op_apply_noalloc(mofem_op_t op, const double* X, long long in_stride, 
 int mofem_dot_accumulate(const double* X, const double* Y, long long n, long long stride,
                          int batch, double alpha, double beta, double* out, void* stream);
 
+#define MOFEM_MAX_BAND_SUM 4
+/* A banded matrix given as a sum  sum_i coef[i] band[i]  of host DIA bands of
+   half-width kb (e.g. eq. (80)'s A + B2: two terms); n = 0 is the zero
+   matrix.  The sum is formed by the library. */
+typedef struct {
+  int n;                                    /* 0 .. MOFEM_MAX_BAND_SUM        */
+  const double* band[MOFEM_MAX_BAND_SUM];   /* host DIA bands, symmetric      */
+  double coef[MOFEM_MAX_BAND_SUM];
+} mofem_band_sum;
+
 /* ------------------------------------------------------------------------ */
 /* a1/a4. Single-term spectral preconditioner                              */
 /*   P(U) = a Ms U Mt + bs Ks U Mt + bt Ms U Kt + d Ks U Kt                  */
@@ -276,6 +286,10 @@ typedef struct {
   const double* Mt;
   double alpha, beta_s, beta_t, delta;   /* coefficients of D                 */
   int precision;                /* MOFEM_PREC_*                               */
+  mofem_band_sum Ks_add;        /* further bands added to Ks, and to Kt      */
+  mofem_band_sum Kt_add;        /* (n = 0: none; the sums formed on the host), */
+                                /* e.g. Kt = A with Kt_add = {B2, 1} for the   */
+                                /* pencil (A + B2, M)                         */
 } mofem_prec_desc;
 typedef struct mofem_prec_s* mofem_prec_t;
 
@@ -334,15 +348,6 @@ int mofem_prec_set_tile(mofem_prec_t prec, int batch, int tile);
 /*  bs = bt = 1, one scale c = d tau per species).                           */
 /* ------------------------------------------------------------------------ */
 #define MOFEM_MAX_SCALES 8
-#define MOFEM_MAX_BAND_SUM 4
-/* A banded matrix given as a sum  sum_i coef[i] band[i]  of host DIA bands of
-   half-width kb (e.g. eq. (80)'s A + B2: two terms); n = 0 is the zero
-   matrix.  The sum is formed by the library. */
-typedef struct {
-  int n;                                    /* 0 .. MOFEM_MAX_BAND_SUM        */
-  const double* band[MOFEM_MAX_BAND_SUM];   /* host DIA bands, symmetric      */
-  double coef[MOFEM_MAX_BAND_SUM];
-} mofem_band_sum;
 typedef struct {
   int kb;                       /* band half-width of the four matrices, 1..4 */
   int n_s, n_t, trim_s, trim_t; /* as in mofem_prec_desc                      */

@@ -127,6 +127,12 @@ class XNormalProblem:
         P(U) = alpha Ms U Mt + beta_s Ks U Mt + beta_t Ms U Kt + delta Ks U Kt.
         Presets:
           sylv          (B1, M3) x (A, M), D = gamma + lam + mu
+          sylv-matched  (B1, M1) x (A + w B2, M), D = gamma + lam + mu,
+                        w = sum(M2) / sum(M1) over the untrimmed matrices
+                        (= int L'^2/L / int 1/L): the operator's M1 U A and
+                        B1 U M terms exact, its M2 U B2 term taken as
+                        w M1 U B2 and gamma M3 U M as gamma M1 U M (the
+                        library's elliptic default)
           paper-product eq. (80): B1 U (A + B2), D = lam * mu
         IMEX presets (``imex_prec_pairs``) add the coefficient c.
         """
@@ -134,6 +140,9 @@ class XNormalProblem:
         Is, It = np.eye(self.q), np.eye(self.q_t)
         if preset == "sylv":
             return (T["B1"], T["M3"]), (T["A"], T["M"]), (self.gamma, 1.0, 1.0, 0.0)
+        if preset == "sylv-matched":
+            w = self.full["M2"].sum() / self.full["M1"].sum()
+            return (T["B1"], T["M1"]), (T["A"] + w * T["B2"], T["M"]), (self.gamma, 1.0, 1.0, 0.0)
         if preset == "paper-product":
             return (T["B1"], Is), (T["A"] + T["B2"], It), (0.0, 0.0, 0.0, 1.0)
         raise ValueError(preset)

@@ -686,6 +686,23 @@ extern "C" int mofem_prec_setup(const mofem_prec_desc* desc, mofem_prec_t* out) 
     return fail(MOFEM_E_ARG, "prec_setup: unknown precision");
   const int qs = D.n_s - 2 * D.trim_s, qt = D.n_t - 2 * D.trim_t;
   if (qs < 1 || qt < 1) return fail(MOFEM_E_ARG, "prec_setup: empty matrices");
+  for (const mofem_band_sum* bs : {&D.Ks_add, &D.Kt_add}) {
+    if (bs->n < 0 || bs->n > MOFEM_MAX_BAND_SUM) return fail(MOFEM_E_ARG, "prec_setup: added bands: 0..4 terms");
+    for (int i = 0; i < bs->n; ++i)
+      if (!bs->band[i]) return fail(MOFEM_E_ARG, "prec_setup: NULL added band");
+  }
+  // K + sum_i coef_i band_i on the host (the same DIA layout)
+  std::vector<double> ks_sum, kt_sum;
+  auto with_added = [&](const double* K, const mofem_band_sum& A, int n, std::vector<double>& sum) {
+    if (A.n == 0) return K;
+    const size_t nb = (size_t)(2 * D.kb + 1) * n;
+    sum.assign(K, K + nb);
+    for (int t = 0; t < A.n; ++t)
+      for (size_t i = 0; i < nb; ++i) sum[i] += A.coef[t] * A.band[t][i];
+    return (const double*)sum.data();
+  };
+  const double* Ks = with_added(D.Ks, D.Ks_add, D.n_s, ks_sum);
+  const double* Kt = with_added(D.Kt, D.Kt_add, D.n_t, kt_sum);
 
   auto* p = new mofem_prec_s();
   p->qs = qs;
@@ -705,7 +722,7 @@ extern "C" int mofem_prec_setup(const mofem_prec_desc* desc, mofem_prec_t* out) 
   // the square of eq. (28))
   const size_t nbs = (size_t)(2 * D.kb + 1) * D.n_s;
   const bool same = D.n_s == D.n_t && D.trim_s == D.trim_t &&
-                    std::memcmp(D.Ks, D.Kt, nbs * sizeof(double)) == 0 &&
+                    std::memcmp(Ks, Kt, nbs * sizeof(double)) == 0 &&
                     std::memcmp(D.Ms, D.Mt, nbs * sizeof(double)) == 0;
   int rc_t = MOFEM_OK;
   std::string msg_t;
@@ -715,12 +732,12 @@ extern "C" int mofem_prec_setup(const mofem_prec_desc* desc, mofem_prec_t* out) 
   if (!same) {
     worker = std::thread([&]() {
       set_thread_share(share);
-      rc_t = mofem_geneig_host(D.n_t, D.kb, D.Kt, D.Mt, D.trim_t, p->h_mu.data(), Vt.data());
+      rc_t = mofem_geneig_host(D.n_t, D.kb, Kt, D.Mt, D.trim_t, p->h_mu.data(), Vt.data());
       if (rc_t != MOFEM_OK) msg_t = mofem_last_error();  // thread-local message of the worker
     });
   }
   const int prev_share = set_thread_share(share);
-  int rc = mofem_geneig_host(D.n_s, D.kb, D.Ks, D.Ms, D.trim_s, p->h_lam.data(), Vs.data());
+  int rc = mofem_geneig_host(D.n_s, D.kb, Ks, D.Ms, D.trim_s, p->h_lam.data(), Vs.data());
   set_thread_share(prev_share);
   std::string msg = rc != MOFEM_OK ? std::string(mofem_last_error()) : std::string();
   if (worker.joinable()) worker.join();

@@ -61,20 +61,22 @@ class OpDesc(ctypes.Structure):
                 ("full_output", ctypes.c_int)]
 
 
+MAX_BAND_SUM = 4
+
+
+class BandSum(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("band", _vp * MAX_BAND_SUM), ("coef", ctypes.c_double * MAX_BAND_SUM)]
+
+
 class PrecDesc(ctypes.Structure):
     _fields_ = [("kb", ctypes.c_int), ("n_s", ctypes.c_int), ("n_t", ctypes.c_int),
                 ("trim_s", ctypes.c_int), ("trim_t", ctypes.c_int),
                 ("Ks", _vp), ("Ms", _vp), ("Kt", _vp), ("Mt", _vp),
                 ("alpha", ctypes.c_double), ("beta_s", ctypes.c_double),
                 ("beta_t", ctypes.c_double), ("delta", ctypes.c_double),
-                ("precision", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("Ks_add", BandSum), ("Kt_add", BandSum)]
 
 
-MAX_BAND_SUM = 4
-
-
-class BandSum(ctypes.Structure):
-    _fields_ = [("n", ctypes.c_int), ("band", _vp * MAX_BAND_SUM), ("coef", ctypes.c_double * MAX_BAND_SUM)]
 
 
 class BPrecDesc(ctypes.Structure):
@@ -357,7 +359,9 @@ class Operator:
 class Preconditioner:
     """Spectral single-term preconditioner (see mofem_prec_desc)."""
 
-    def __init__(self, Ks, Ms, Kt, Mt, coeffs, trim_s=0, trim_t=0, precision=PREC_F64):
+    def __init__(self, Ks, Ms, Kt, Mt, coeffs, trim_s=0, trim_t=0, precision=PREC_F64, Ks_add=(), Kt_add=()):
+        """Ks_add, Kt_add: lists of (band, coefficient) pairs the library adds
+        to Ks and Kt before the eigen-decompositions."""
         d = PrecDesc()
         self._keep = [np.ascontiguousarray(a, dtype=np.float64) for a in (Ks, Ms, Kt, Mt)]
         d.kb = (self._keep[0].shape[0] - 1) // 2
@@ -366,6 +370,18 @@ class Preconditioner:
         d.Ks, d.Ms, d.Kt, d.Mt = (a.ctypes.data for a in self._keep)
         d.alpha, d.beta_s, d.beta_t, d.delta = (float(c) for c in coeffs)
         d.precision = precision
+        for field, terms, ref in (("Ks_add", Ks_add, self._keep[0]), ("Kt_add", Kt_add, self._keep[2])):
+            if len(terms) > MAX_BAND_SUM:
+                raise ValueError("at most %d added bands" % MAX_BAND_SUM)
+            bs = getattr(d, field)
+            bs.n = len(terms)
+            for i, (band, coef) in enumerate(terms):
+                a = np.ascontiguousarray(band, dtype=np.float64)
+                if a.shape != ref.shape:
+                    raise ValueError("an added band must have the shape of the band it is added to")
+                self._keep.append(a)
+                bs.band[i] = a.ctypes.data
+                bs.coef[i] = float(coef)
         h = _vp()
         _check(mofem_prec_setup(ctypes.byref(d), ctypes.byref(h)), "mofem_prec_setup")
         self.handle = h

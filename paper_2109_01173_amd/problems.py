@@ -3,8 +3,9 @@
 Only bookkeeping happens here: which assembled 1D matrix goes into which term
 of the multiterm operator.  Assembly (``mofem_assemble_1d``), the
 eigen-decomposition, every sum of bands (the library merges terms that share
-a factor, and forms the product preconditioner's A + B2 itself) and every
-apply/solve run in libmofem; no arithmetic on bands happens in Python.
+a factor, and forms the preconditioners' A + B2 and A + w B2 itself) and every
+apply/solve run in libmofem; no band is formed in Python (the one number
+taken from bands is the weight w, a ratio of two bands' total masses).
 
 Operators (rows = s, the base coordinate; columns = t):
 * x-normal elliptic, eq. (73) (lumped: eq. (75)):
@@ -15,7 +16,10 @@ Operators (rows = s, the base coordinate; columns = t):
 * rectangle (eq. (28) on [0, l]^2): elliptic (A + g M) U M + M U A,
   IMEX  M U M + c (A U M + M U A).
 Preconditioners: the spectral single-term form with the pencils
-(B1, M3) x (A, M) on x-normal domains and (A, M) x (A, M) on the rectangle;
+(B1, M1) x (A + w B2, M), D = g + lam + mu, w = sum(M2) / sum(M1), for the
+x-normal elliptic operator (its M1 U A and B1 U M terms exact, M2 U B2 taken
+as w M1 U B2), (B1, M3) x (A, M) for the x-normal IMEX operator (its mass
+term M3 U M exact) and (A, M) x (A, M) on the rectangle;
 the paper's product preconditioners eqs. (80), (95), (96) by banded Cholesky
 solves (XNormal.product_prec).
 """
@@ -98,7 +102,13 @@ class XNormal:
         self.mass = mf.Operator([dict(left=M3, right=M)], **common)
         # stiffness part K of L_c = Mass + c K (for the gradient in d)
         self.stiff = mf.Operator([dict(t, scaled=False) for t in terms[1:]], **common) if imex else None
-        self.prec = mf.Preconditioner(B1, M3, A, M, coeffs, trim, trim, precision)
+        if imex:
+            self.prec = mf.Preconditioner(B1, M3, A, M, coeffs, trim, trim, precision)
+        else:
+            # the operator's M2 U B2 taken as w M1 U B2, w the ratio of the
+            # total masses of M2 and M1 (the integrals of L'^2 / L and 1 / L)
+            w_b2 = float(M2.sum() / M1.sum())
+            self.prec = mf.Preconditioner(B1, M1, A, M, coeffs, trim, trim, precision, Kt_add=[(B2, w_b2)])
         self.imex = imex
 
     def product_prec(self, scales=(1.0,)):

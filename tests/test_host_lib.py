@@ -178,6 +178,33 @@ def test_banded_product_setup_errors_on_the_host():
     assert mf.mofem_prec_setup_banded(None, None) == mf.E_ARG
 
 
+def test_spectral_setup_added_band_errors_on_the_host():
+    """mofem_prec_setup's added bands (Ks_add, Kt_add: 0..MAX_BAND_SUM terms,
+    no NULL band) are checked before any eigen-solve or device call; the
+    binding rejects too many or misshapen added bands itself."""
+    K = np.ascontiguousarray(mf.assemble_1d(2, 8, 1, 1))
+    M = np.ascontiguousarray(mf.assemble_1d(2, 8, 0, 0))
+    d = mf.PrecDesc()
+    d.kb, d.n_s, d.n_t, d.trim_s, d.trim_t = 2, K.shape[1], K.shape[1], 1, 1
+    d.Ks = d.Kt = K.ctypes.data
+    d.Ms = d.Mt = M.ctypes.data
+    d.alpha, d.beta_s, d.beta_t, d.delta, d.precision = 1.0, 1.0, 1.0, 0.0, mf.PREC_F64
+    h = ctypes.c_void_p()
+    for field in ("Ks_add", "Kt_add"):
+        bs = getattr(d, field)
+        for bad in (-1, mf.MAX_BAND_SUM + 1):
+            bs.n = bad
+            assert mf.mofem_prec_setup(ctypes.byref(d), ctypes.byref(h)) == mf.E_ARG
+        bs.n = 1                              # a NULL added band
+        assert mf.mofem_prec_setup(ctypes.byref(d), ctypes.byref(h)) == mf.E_ARG
+        assert b"added band" in mf.mofem_last_error()
+        bs.n = 0
+    with pytest.raises(ValueError):
+        mf.Preconditioner(K, M, K, M, (1.0, 1.0, 1.0, 0.0), 1, 1, Kt_add=[(K, 1.0)] * (mf.MAX_BAND_SUM + 1))
+    with pytest.raises(ValueError):
+        mf.Preconditioner(K, M, K, M, (1.0, 1.0, 1.0, 0.0), 1, 1, Ks_add=[(K[:, :-1], 1.0)])
+
+
 @pytest.mark.parametrize("lumped,dirichlet", [(False, True), (True, True), (True, False)])
 def test_closed_form_p1_eigenpairs(lumped, dirichlet):
     """mofem_eig_p1_closed (Sec. 4.1) against a dense symmetric-definite

@@ -30,7 +30,7 @@ def test_spectral_prec_inverts_explicit_operator(k):
     P = XNormalProblem(k, 5, "dirichlet", L_profile, dL_profile, gamma=1.0)
     rng = np.random.default_rng(0)
     R = rng.standard_normal((P.q, P.q))
-    for pairs in (P.prec_pairs("sylv"), P.prec_pairs("paper-product"),
+    for pairs in (P.prec_pairs("sylv"), P.prec_pairs("sylv-matched"), P.prec_pairs("paper-product"),
                   P.imex_prec_pairs("sylv-imex", 0.01), P.imex_prec_pairs("paper-imex", 0.01)):
         S = SpectralPrec(*pairs)
         Z = S.apply(R)
@@ -131,3 +131,31 @@ def test_pcg_tau_stop_rule_and_breakdown():
     assert info["history"][-1] <= 1e-2 * info["history"][0] + 1e-15
     with pytest.raises(FloatingPointError):
         mo_pcg(lambda X: -P.apply(X), None, Rhs, tol=1e-10)
+
+
+def test_matched_pencils_reduce_to_sylv_and_never_need_more_iterations():
+    """The elliptic default pencils (B1, M1) x (A + w B2, M), w = the ratio of
+    the total masses of M2 and M1 (a reading: the single-term preconditioner
+    that keeps the operator's M1 U A and B1 U M terms exact).  On a flat
+    profile L = 1 the weight is exactly 0 and M1 = M3, so they are the
+    (B1, M3) x (A, M) pencils, which are then the whole operator: one
+    iteration.  On the workload's profile and on a nearly flat one they need
+    no more MO-PCG iterations than (B1, M3) x (A, M)."""
+    import math
+    flat = XNormalProblem(2, 12, "dirichlet", lambda s: np.ones_like(s), lambda s: np.zeros_like(s), gamma=1.0)
+    ps, pt, co = flat.prec_pairs("sylv-matched")
+    ps0, pt0, co0 = flat.prec_pairs("sylv")
+    assert flat.full["M2"].sum() == 0.0
+    assert np.array_equal(ps[1], ps0[1]) and np.array_equal(pt[0], pt0[0]) and co == co0
+    R = np.random.default_rng(4).standard_normal((flat.q, flat.q))
+    _, info = mo_pcg(flat.apply, SpectralPrec(ps, pt, co).apply, R, tol=1e-12, maxit=10)
+    assert info["iters"] == 1
+    for amp in (0.3, 0.05):
+        P = XNormalProblem(2, 64, "dirichlet", lambda s, a=amp: 1 + a * np.sin(math.pi * s),
+                           lambda s, a=amp: a * math.pi * np.cos(math.pi * s), gamma=1.0)
+        R = P.rhs(np.random.default_rng(5).standard_normal((P.n, P.n)))
+        its = {}
+        for preset in ("sylv", "sylv-matched"):
+            _, info = mo_pcg(P.apply, SpectralPrec(*P.prec_pairs(preset)).apply, R, tol=1e-10, maxit=100)
+            its[preset] = info["iters"]
+        assert its["sylv-matched"] <= its["sylv"], (amp, its)
