@@ -76,7 +76,7 @@ def cpu_baseline(F0, k, m, gamma, tol, U_gpu0):
 # order) changes, traffic is reported null.
 TRAFFIC = {
     # mixed mode -> (sha256 of k_gemm.hip + device_common.h, (q, batch), bytes per launch)
-    "bf16fwd": ("3957875db4dfee21859442486a46ee6bd5e95f6dde6dda13de43b7757296fafb", (2047, 16), 1.769e9),
+    "bf16fwd": ("3957875db4dfee21859442486a46ee6bd5e95f6dde6dda13de43b7757296fafb", (2047, 16), 1.761e9),
 }
 FETCH_SCALE = 2.000   # 512 MiB copy: true bytes / FETCH_SIZE reading
 WRITE_SCALE = 1.000   # 512 MiB copy: true bytes / WRITE_SIZE reading
