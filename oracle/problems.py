@@ -134,7 +134,13 @@ class XNormalProblem:
                         w M1 U B2 and gamma M3 U M as gamma M1 U M (the
                         library's elliptic default)
           paper-product eq. (80): B1 U (A + B2), D = lam * mu
-        IMEX presets (``imex_prec_pairs``) add the coefficient c.
+        IMEX presets (``imex_prec_pairs``) add the coefficient c:
+          sylv-imex          (B1, M3) x (A, M), D = 1 + c (lam + mu)
+          sylv-imex-matched  (B1, M3) x (A + w3 B2, M), w3 = sum(M2) / sum(M3)
+                             (untrimmed): the mass term M3 U M exact, the
+                             stiffness part's M2 U B2 taken as w3 M3 U B2
+                             (the library's IMEX default)
+          paper-imex         eq. (95)
         """
         T = self.mat
         Is, It = np.eye(self.q), np.eye(self.q_t)
@@ -151,6 +157,9 @@ class XNormalProblem:
         T = self.mat
         if preset == "sylv-imex":
             return (T["B1"], T["M3"]), (T["A"], T["M"]), (1.0, c, c, 0.0)
+        if preset == "sylv-imex-matched":
+            w3 = self.full["M2"].sum() / self.full["M3"].sum()
+            return (T["B1"], T["M3"]), (T["A"] + w3 * T["B2"], T["M"]), (1.0, c, c, 0.0)
         if preset == "paper-imex":
             # eq. (95): (M3 + c B1)^-1 U (M + c (A + B2))^-1
             return ((T["M3"] + c * T["B1"], np.eye(self.q)), (T["M"] + c * (T["A"] + T["B2"]), np.eye(self.q_t)),

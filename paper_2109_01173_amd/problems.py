@@ -4,8 +4,8 @@ Only bookkeeping happens here: which assembled 1D matrix goes into which term
 of the multiterm operator.  Assembly (``mofem_assemble_1d``), the
 eigen-decomposition, every sum of bands (the library merges terms that share
 a factor, and forms the preconditioners' A + B2 and A + w B2 itself) and every
-apply/solve run in libmofem; no band is formed in Python (the one number
-taken from bands is the weight w, a ratio of two bands' total masses).
+apply/solve run in libmofem; no band is formed in Python (the numbers taken
+from bands are the weights w, ratios of two bands' total masses).
 
 Operators (rows = s, the base coordinate; columns = t):
 * x-normal elliptic, eq. (73) (lumped: eq. (75)):
@@ -18,8 +18,9 @@ Operators (rows = s, the base coordinate; columns = t):
 Preconditioners: the spectral single-term form with the pencils
 (B1, M1) x (A + w B2, M), D = g + lam + mu, w = sum(M2) / sum(M1), for the
 x-normal elliptic operator (its M1 U A and B1 U M terms exact, M2 U B2 taken
-as w M1 U B2), (B1, M3) x (A, M) for the x-normal IMEX operator (its mass
-term M3 U M exact) and (A, M) x (A, M) on the rectangle;
+as w M1 U B2), (B1, M3) x (A + w3 B2, M), w3 = sum(M2) / sum(M3), for the
+x-normal IMEX operator (its mass term M3 U M exact) and (A, M) x (A, M) on
+the rectangle;
 the paper's product preconditioners eqs. (80), (95), (96) by banded Cholesky
 solves (XNormal.product_prec).
 """
@@ -103,7 +104,9 @@ class XNormal:
         # stiffness part K of L_c = Mass + c K (for the gradient in d)
         self.stiff = mf.Operator([dict(t, scaled=False) for t in terms[1:]], **common) if imex else None
         if imex:
-            self.prec = mf.Preconditioner(B1, M3, A, M, coeffs, trim, trim, precision)
+            # the stiffness part's M2 U B2 taken as w3 M3 U B2, w3 = sum(M2) / sum(M3)
+            w3_b2 = float(M2.sum() / M3.sum())
+            self.prec = mf.Preconditioner(B1, M3, A, M, coeffs, trim, trim, precision, Kt_add=[(B2, w3_b2)])
         else:
             # the operator's M2 U B2 taken as w M1 U B2, w the ratio of the
             # total masses of M2 and M1 (the integrals of L'^2 / L and 1 / L)

@@ -31,7 +31,8 @@ def test_spectral_prec_inverts_explicit_operator(k):
     rng = np.random.default_rng(0)
     R = rng.standard_normal((P.q, P.q))
     for pairs in (P.prec_pairs("sylv"), P.prec_pairs("sylv-matched"), P.prec_pairs("paper-product"),
-                  P.imex_prec_pairs("sylv-imex", 0.01), P.imex_prec_pairs("paper-imex", 0.01)):
+                  P.imex_prec_pairs("sylv-imex", 0.01), P.imex_prec_pairs("sylv-imex-matched", 0.01),
+                  P.imex_prec_pairs("paper-imex", 0.01)):
         S = SpectralPrec(*pairs)
         Z = S.apply(R)
         # backward error of a two-sided spectral solve: a few eps times cond(D)
@@ -140,7 +141,8 @@ def test_matched_pencils_reduce_to_sylv_and_never_need_more_iterations():
     profile L = 1 the weight is exactly 0 and M1 = M3, so they are the
     (B1, M3) x (A, M) pencils, which are then the whole operator: one
     iteration.  On the workload's profile and on a nearly flat one they need
-    no more MO-PCG iterations than (B1, M3) x (A, M)."""
+    no more MO-PCG iterations than (B1, M3) x (A, M); likewise the IMEX
+    pencils (B1, M3) x (A + w3 B2, M) against (B1, M3) x (A, M)."""
     import math
     flat = XNormalProblem(2, 12, "dirichlet", lambda s: np.ones_like(s), lambda s: np.zeros_like(s), gamma=1.0)
     ps, pt, co = flat.prec_pairs("sylv-matched")
@@ -159,3 +161,14 @@ def test_matched_pencils_reduce_to_sylv_and_never_need_more_iterations():
             _, info = mo_pcg(P.apply, SpectralPrec(*P.prec_pairs(preset)).apply, R, tol=1e-10, maxit=100)
             its[preset] = info["iters"]
         assert its["sylv-matched"] <= its["sylv"], (amp, its)
+        # the IMEX pencils with w3 B2 (heat-like c = 1e-4, and 1e-2)
+        for c in (1e-4, 1e-2):
+            its = {}
+            for preset in ("sylv-imex", "sylv-imex-matched"):
+                S = SpectralPrec(*P.imex_prec_pairs(preset, c))
+                _, info = mo_pcg(lambda X: P.apply_imex(X, c), S.apply, R, tol=1e-10, maxit=100)
+                its[preset] = info["iters"]
+            assert its["sylv-imex-matched"] <= its["sylv-imex"], (amp, c, its)
+    ps, pt, co = flat.imex_prec_pairs("sylv-imex-matched", 0.1)
+    ps0, pt0, co0 = flat.imex_prec_pairs("sylv-imex", 0.1)
+    assert np.array_equal(pt[0], pt0[0]) and co == co0
