@@ -288,14 +288,16 @@ typedef struct {
   int precision;                /* MOFEM_PREC_*                               */
   mofem_band_sum Ks_add;        /* further bands added to Ks, and to Kt      */
   mofem_band_sum Kt_add;        /* (n = 0: none; the sums formed on the host), */
-                                /* e.g. Kt = A with Kt_add = {B2, 1} for the   */
-                                /* pencil (A + B2, M)                         */
+                                /* e.g. Kt = A with Kt_add = {B2, w} for the   */
+                                /* pencil (A + w B2, M)                       */
 } mofem_prec_desc;
 typedef struct mofem_prec_s* mofem_prec_t;
 
-/* Solve the two generalised eigenproblems in FP64 on the host (once per
-   geometry), upload V_s, V_t and their transposes in FP64 and in the working
-   precision.  Errors: MOFEM_E_ARG, MOFEM_E_NUMERIC, MOFEM_E_NOMEM, MOFEM_E_HIP. */
+/* Solve the two generalised eigenproblems (Ks + Ks_add, Ms) and
+   (Kt + Kt_add, Mt) in FP64 on the host (once per geometry), upload V_s, V_t
+   and their transposes in FP64 and in the working precision.  Errors:
+   MOFEM_E_ARG (also an added-band count outside 0..MOFEM_MAX_BAND_SUM or a
+   NULL added band), MOFEM_E_NUMERIC, MOFEM_E_NOMEM, MOFEM_E_HIP. */
 int mofem_prec_setup(const mofem_prec_desc* desc, mofem_prec_t* prec);
 int mofem_prec_destroy(mofem_prec_t prec);
 /* The same preconditioner from given generalised eigenpairs (host arrays:
