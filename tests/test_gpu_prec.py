@@ -135,3 +135,25 @@ def test_block_tiles_agree_on_whole_chunks(precision):
     for i in (0, 5):
         assert rel(to_host(G.prec.apply(R[i:i + 1]))[0], out[128][i]) <= 1e-15
     G.prec.set_precision(mf.PREC_F64)
+
+
+def test_added_bands_form_the_pencils():
+    """Bands added to Ks and Kt (summed by the library before the eigen-
+    solves) give the preconditioner of the summed bands: Ks = B1 given as
+    (B1 - M3/2) + M3/2, Kt = A + w B2 given as A with B2 added at weight w,
+    against the oracle's pencils (B1, M1) x (A + w B2, M)."""
+    from paper_2109_01173_amd import mofem as mf
+    G = gpu_xnormal(2, 60, "dirichlet", 1.0)      # q = 119
+    P = oracle_xnormal(2, 60, "dirichlet", 1.0)
+    b = G.bands
+    w = float(b["M2"].sum() / b["M1"].sum())
+    pr = mf.Preconditioner(b["B1"] - 0.5 * b["M3"], b["M1"], b["A"], b["M"], (1.0, 1.0, 1.0, 0.0), 1, 1,
+                           Ks_add=[(b["M3"], 0.5)], Kt_add=[(b["B2"], w)])
+    S = SpectralPrec(*P.prec_pairs("sylv-matched"))
+    lam, mu = pr.eigenvalues()
+    assert np.abs(lam - S.lam).max() <= 1e-12 * S.lam.max()
+    assert np.abs(mu - S.mu).max() <= 1e-12 * S.mu.max()
+    R = np.random.default_rng(11).standard_normal((2, P.q, P.q))
+    Z = to_host(pr.apply(to_dev(R)))
+    for i in range(2):
+        assert rel(Z[i], S.apply(R[i])) < 1e-10
