@@ -151,12 +151,15 @@ def uneven_leg(mf, torch, np, n_inst, prec, prec_name, rds_steps=100):
                            flags=mf.PCG_FLEXIBLE | mf.PCG_ZERO_GUESS, _keep=G,
                            workspace=mf.pcg_workspace(G.op, G.prec, cnt))
         lumped = k == 1
-        G = Rect(k, m, "neumann", length=20.0, lumped=lumped, imex=True, closed_form=lumped)
+        # split-BF16 transforms: three flexible PCG iterations per solve to rel
+        # 1e-10 cost less than one with FP64 transforms
+        G = Rect(k, m, "neumann", length=20.0, lumped=lumped, imex=True, closed_form=lumped,
+                 precision=mf.PREC_BF16X3)
         init = [dib_initial(G.q, seed=7000 + 100 * gi + j) for j in range(cnt)]
         # species-major state: eta of every item, then theta of every item
         st0 = torch.from_numpy(np.stack([e for e, _ in init] + [t for _, t in init])).cuda()
         stepper = mf.Imex(G.op, G.prec, G.mass, 1e-2, [1.0, p["d_theta"]], kinetics=mf.KIN_DIB, kin=kin,
-                          tol=1e-10, maxit=50)
+                          tol=1e-10, maxit=50, flags=mf.PCG_FLEXIBLE)
         r = dict(G=G, st0=st0, st=st0.clone(), stepper=stepper, batch=cnt, ws=stepper.workspace(cnt))
         torch.cuda.synchronize()
         return 1, r
@@ -262,7 +265,7 @@ def uneven_leg(mf, torch, np, n_inst, prec, prec_name, rds_steps=100):
     return {"uneven_batch": {"workload": "%d instances, n in {257,513,1025,2049}, k in 1..4, type in {elliptic, "
                                          "reaction-diffusion} (seed 5); elliptic: P_k x-normal, Dirichlet, gamma=1, "
                                          "rel 1e-8, %s transforms; reaction-diffusion: DIB rectangle [0,20]^2, "
-                                         "Neumann, tau=1e-2, %d steps, rel 1e-10, f64 transforms"
+                                         "Neumann, tau=1e-2, %d steps, rel 1e-10, bf16x3 transforms, flexible PCG"
                                          % (n_inst, prec_name, rds_steps),
                              "elliptic_instances": n_ell, "elliptic_groups": len(groups),
                              "solves_per_s_sequential": round(n_ell / dt_seq, 2),
@@ -350,9 +353,11 @@ def dib_leg(mf, torch, np, nsteps):
     """Two-species reaction-diffusion (Sec. 7, eqs. (98)-(103)): DIB kinetics on
     the rectangle [0,20]^2, Neumann, n = 1025 (lumped P1 with m = 1024 and P2
     with m = 512), d_theta / d_eta = 20, tau = 1e-2, equilibrium + U[-1e-3,
-    1e-3) (seed 7), rectangle preconditioner (FP64 transforms, one iteration
-    per solve) at rel 1e-10 per step; `nsteps` steps (10^4: T = 100) replayed
-    from a HIP graph, plus the Turing pattern's statistics at the end."""
+    1e-3) (seed 7), rectangle preconditioner (exact in FP64) with split-BF16
+    transforms and the flexible PCG at rel 1e-10 per step (three iterations
+    per solve cost less than one with FP64 transforms); `nsteps` steps (10^4:
+    T = 100) replayed from a HIP graph, plus the Turing pattern's statistics
+    at the end."""
     from paper_2109_01173_amd.problems import Rect
     from workloads import dib_initial, dib_params
     p = dib_params()
@@ -360,12 +365,13 @@ def dib_leg(mf, torch, np, nsteps):
     out = {}
     for key, k, m, lumped in (("imex_dib_p1", 1, 1024, True), ("imex_dib_p2", 2, 512, False)):
         t0 = time.perf_counter()
-        G = Rect(k, m, "neumann", length=20.0, lumped=lumped, imex=True, closed_form=lumped)
+        G = Rect(k, m, "neumann", length=20.0, lumped=lumped, imex=True, closed_form=lumped,
+                 precision=mf.PREC_BF16X3)
         setup = time.perf_counter() - t0
         eta, theta = dib_initial(G.q, seed=7)
         st = torch.from_numpy(np.stack([eta, theta])).cuda()
         mk = lambda: mf.Imex(G.op, G.prec, G.mass, 1e-2, [1.0, p["d_theta"]], kinetics=mf.KIN_DIB, kin=kin,
-                             tol=1e-10, maxit=50)
+                             tol=1e-10, maxit=50, flags=mf.PCG_FLEXIBLE)
         stepper = mk()
         ws = stepper.workspace(1)
         warm = 10
@@ -374,8 +380,9 @@ def dib_leg(mf, torch, np, nsteps):
         its = [int(stepper.step(st, 1, workspace=ws).max()) for _ in range(warm)]
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
-        # one iteration confirms convergence on the true residual inside the
-        # replay; a step needing more would show in the graph's status
+        # as many iterations as the eager steps needed (the last one confirms
+        # convergence on the true residual inside the replay); a step needing
+        # more would show in the graph's status
         g = mf.ImexGraph(mk(), st, 1, iters_per_step=max(its))
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -385,13 +392,13 @@ def dib_leg(mf, torch, np, nsteps):
         gi, gst, _ = g.result(raise_on_error=False)
         e, th = st.cpu().numpy()
         name = "lumped P1" if lumped else "P2"
-        out[key] = {"workload": "DIB %s rectangle [0,20]^2, Neumann, n=1025, tau=1e-2, two species, rel 1e-10 per "
+        out[key] = {"workload": "DIB %s rectangle [0,20]^2, Neumann, n=1025, tau=1e-2, two species, bf16x3 transforms, rel 1e-10 per "
                                 "step, T=%g (%d steps: %d eager, the rest replayed from a HIP graph)"
                                 % (name, 1e-2 * nsteps, nsteps, warm),
                     "graph_steps_per_s": round((nsteps - warm) / dtg, 2), "steps": nsteps,
                     "eager_steps_per_s": round(warm / dt, 2), "iterations_per_step": max(its),
                     "graph_max_iterations": int(gi.max()), "graph_status_ok": bool(np.all(gst == 0)),
-                    "transforms": "f64", "eigenbasis": "closed form" if lumped else "dense eigen-solve",
+                    "transforms": "bf16x3", "eigenbasis": "closed form" if lumped else "dense eigen-solve",
                     "setup_s": round(setup, 2),
                     "final_state": {"eta_mean": float(e.mean()), "eta_var": float(e.var()),
                                     "theta_mean": float(th.mean()), "theta_var": float(th.var()),
