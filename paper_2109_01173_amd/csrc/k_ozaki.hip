@@ -57,7 +57,10 @@ __device__ __forceinline__ void lds_load16(const signed char* src, signed char* 
   __builtin_amdgcn_global_load_lds((const void*)src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
 }
 
-// One block per (padded) row of an item: exponent, then S digit planes.
+// One block per (padded) row of an item: exponent, then S digit planes.  Rows
+// of at most 2048 padded entries are read once into registers (eight per
+// thread, 16-byte loads where the row start allows) and leave as one 8-byte
+// store per digit plane and thread; longer rows take two passes.
 template <int S>
 __global__ __launch_bounds__(256) void slice_rows_kernel(const double* __restrict__ X, long long xs, int ld, int M,
                                                          int K, signed char* __restrict__ out, long long os,
@@ -68,13 +71,63 @@ __global__ __launch_bounds__(256) void slice_rows_kernel(const double* __restric
   const int Kp = pad_up(K), Mp = pad_up(M);
   const bool live = row < M;
   const double* __restrict__ x = X + (size_t)b * xs + (size_t)(live ? row : 0) * ld;
+  // rows of at most 2048 (padded) entries stay in registers: eight
+  // consecutive entries per thread, read once with 16-byte loads
+  __shared__ double wmax[4];
+  if (Kp <= 2048) {
+    double v[8];
+    const int k8 = 8 * tid;
+    const bool al = (((size_t)x) % 16) == 0;  // the row start (uniform in the block)
+    double mx = 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; u += 2) {
+      const int k = k8 + u;
+      if (live && al && k + 1 < K) {
+        const double2 w = *reinterpret_cast<const double2*>(x + k);
+        v[u] = w.x;
+        v[u + 1] = w.y;
+      } else {
+        v[u] = (live && k < K) ? x[k] : 0.0;
+        v[u + 1] = (live && k + 1 < K) ? x[k + 1] : 0.0;
+      }
+      mx = fmax(mx, fmax(fabs(v[u]), fabs(v[u + 1])));
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+    if ((tid & 63) == 0) wmax[tid >> 6] = mx;
+    __syncthreads();
+    mx = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+    int e = 0;
+    if (mx > 0.0) {
+      const double f = frexp(mx, &e);
+      if (f > 127.0 / 128.0) ++e;
+    }
+    if (tid == 0) ex[(size_t)b * es + row] = e;
+    if (k8 >= Kp) return;
+    signed char* __restrict__ o = out + (size_t)b * os + (size_t)row * Kp;
+    const size_t plane = (size_t)Mp * Kp;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = ldexp(v[u], -e);
+#pragma unroll
+    for (int p = 0; p < S; ++p) {
+      unsigned long long w = 0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const double y = v[u] * 128.0;
+        const double d = rint(y);
+        v[u] = y - d;
+        w |= ((unsigned long long)((unsigned)(int)d & 0xFFu)) << (8 * u);
+      }
+      *reinterpret_cast<unsigned long long*>(o + p * plane + k8) = w;
+    }
+    return;
+  }
   // 1. row maximum of |x|
   double mx = 0.0;
   if (live)
     for (int k = tid; k < K; k += 256) mx = fmax(mx, fabs(x[k]));
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
-  __shared__ double wmax[4];
   if ((tid & 63) == 0) wmax[tid >> 6] = mx;
   __syncthreads();
   mx = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
