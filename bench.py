@@ -76,7 +76,7 @@ def cpu_baseline(F0, k, m, gamma, tol, U_gpu0):
 # order) changes, traffic is reported null.
 TRAFFIC = {
     # mixed mode -> (sha256 of k_gemm.hip + device_common.h, (q, batch), bytes per launch)
-    "bf16fwd": ("3957875db4dfee21859442486a46ee6bd5e95f6dde6dda13de43b7757296fafb", (2047, 16), 1.761e9),
+    "bf16fwdvs": ("6cc5159f7964d1cd36946228fa206c9343bd0ef25742071d2eb2c447c3fd0029", (2047, 16), 1.780e9),
 }
 FETCH_SCALE = 2.000   # 512 MiB copy: true bytes / FETCH_SIZE reading
 WRITE_SCALE = 1.000   # 512 MiB copy: true bytes / WRITE_SIZE reading
@@ -584,7 +584,7 @@ def main():
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--n", type=int, default=2049)
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--mixed", default="bf16fwd", choices=["bf16x2", "bf16x3", "bf16", "bf16fwd"],
+    ap.add_argument("--mixed", default="bf16fwdvs", choices=["bf16x2", "bf16x3", "bf16", "bf16fwd", "bf16fwdvs"],
                     help="transform precision of the mixed path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--heat-steps", type=int, default=1000,
@@ -629,7 +629,9 @@ def main():
              "bf16": (mf.PREC_BF16, mf.TRACE_GEMM_BF16, 1, "gemm_bf16_kernel<BF_HH,*>"),
              # forward transforms one BF16 product, back transforms split: the
              # roofline is taken on the split (dominant) back-transform kernel
-             "bf16fwd": (mf.PREC_BF16_FWD, mf.TRACE_GEMM_BF16X3, 3, "gemm_bf16_kernel<BF_X3,*>")}[args.mixed]
+             "bf16fwd": (mf.PREC_BF16_FWD, mf.TRACE_GEMM_BF16X3, 3, "gemm_bf16_kernel<BF_X3,*>"),
+             # as bf16fwd, the first back transform splitting V_s only (S in BF16)
+             "bf16fwdvs": (mf.PREC_BF16_FWD_VS, mf.TRACE_GEMM_BF16X3, 3, "gemm_bf16_kernel<BF_X3,*>")}[args.mixed]
     G = XNormal(k, m, "dirichlet", gamma=gamma, precision=mixed[0])
     setup_s = time.perf_counter() - t0
     q = G.q

@@ -265,7 +265,7 @@ enum {
                              product), back transforms (V_s (.) V_t^T) in
                              split BF16 (three); FP32 accumulation.  Not
                              symmetric: use the flexible PCG.               */
-  MOFEM_PREC_F64_INT8 = 6 /* FP64-accurate transforms on INT8 MFMA: every
+  MOFEM_PREC_F64_INT8 = 6, /* FP64-accurate transforms on INT8 MFMA: every
                              row of an operand cut into 7 exact signed
                              base-128 digits (round to nearest) below its
                              power-of-two exponent, the 28 digit products
@@ -276,6 +276,13 @@ enum {
                              FP64 intermediates and Z; operand widths
                              (padded) up to 16384, else MOFEM_E_UNSUPPORTED
                              at set-up or on mofem_prec_set_precision.      */
+  MOFEM_PREC_BF16_FWD_VS = 7 /* as MOFEM_PREC_BF16_FWD, but the first back
+                             transform (V_s S) splits only the eigenbasis:
+                             S in plain BF16, two products; its lo half is
+                             never formed.  The flexible PCG absorbs the
+                             rounding of S as it does that of the forward
+                             transforms.  Not symmetric: use the flexible
+                             PCG.                                           */
 };
 typedef struct {
   int kb;                       /* band half-width of the four matrices       */
@@ -566,7 +573,7 @@ enum {
   MOFEM_TRACE_GEMM_BF16X3 = 2,  /* one split-BF16 transform product            */
   MOFEM_TRACE_GEMM_BF16 = 3,    /* one BF16 transform product                  */
   MOFEM_TRACE_VEC = 4,          /* PCG vector kernels and reductions           */
-  MOFEM_TRACE_GEMM_BF16X2 = 5,  /* one two-product transform (BF16 basis)      */
+  MOFEM_TRACE_GEMM_BF16X2 = 5,  /* one two-product transform                   */
   MOFEM_TRACE_GEMM_F32 = 6,     /* one FP32 transform product                  */
   MOFEM_TRACE_BCHOL = 7,        /* one banded Cholesky solve (two per product-
                                    preconditioner application)               */

@@ -172,5 +172,6 @@ MODES = {
     "BF16X3": ("x3",) * 4,
     "BF16X2": ("x2a", "x2b", "x2b", "x2a"),
     "BF16_FWD": ("hh", "hh", "x3", "x3"),
+    "BF16_FWD_VS": ("hh", "hh", "x2a", "x3"),
     "F64_INT8": ("oz7",) * 4,
 }

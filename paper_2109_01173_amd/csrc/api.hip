@@ -682,7 +682,7 @@ extern "C" int mofem_prec_setup(const mofem_prec_desc* desc, mofem_prec_t* out) 
   if (!D.Ks || !D.Ms || !D.Kt || !D.Mt) return fail(MOFEM_E_ARG, "prec_setup: NULL band");
   if ((D.trim_s != 0 && D.trim_s != 1) || (D.trim_t != 0 && D.trim_t != 1))
     return fail(MOFEM_E_ARG, "prec_setup: trim flags must be 0 or 1");
-  if (D.precision < MOFEM_PREC_F64 || D.precision > MOFEM_PREC_F64_INT8)
+  if (D.precision < MOFEM_PREC_F64 || D.precision > MOFEM_PREC_BF16_FWD_VS)
     return fail(MOFEM_E_ARG, "prec_setup: unknown precision");
   const int qs = D.n_s - 2 * D.trim_s, qt = D.n_t - 2 * D.trim_t;
   if (qs < 1 || qt < 1) return fail(MOFEM_E_ARG, "prec_setup: empty matrices");
@@ -771,7 +771,7 @@ extern "C" int mofem_prec_setup_eig(int q_s, int q_t, const double* lam, const d
   if (!out || !lam || !Vs || !mu || !Vt) return fail(MOFEM_E_ARG, "prec_setup_eig: NULL argument");
   *out = nullptr;
   if (q_s < 1 || q_t < 1) return fail(MOFEM_E_ARG, "prec_setup_eig: empty matrices");
-  if (precision < MOFEM_PREC_F64 || precision > MOFEM_PREC_F64_INT8)
+  if (precision < MOFEM_PREC_F64 || precision > MOFEM_PREC_BF16_FWD_VS)
     return fail(MOFEM_E_ARG, "prec_setup_eig: unknown precision");
   auto* p = new mofem_prec_s();
   p->qs = q_s;
@@ -929,7 +929,7 @@ extern "C" int mofem_prec_set_coeffs(mofem_prec_t p, double a, double bs, double
 extern "C" int mofem_prec_set_precision(mofem_prec_t p, int precision) {
   clear_error();
   if (!p) return fail(MOFEM_E_ARG, "prec_set_precision: NULL handle");
-  if (precision < MOFEM_PREC_F64 || precision > MOFEM_PREC_F64_INT8) return fail(MOFEM_E_ARG, "unknown precision");
+  if (precision < MOFEM_PREC_F64 || precision > MOFEM_PREC_BF16_FWD_VS) return fail(MOFEM_E_ARG, "unknown precision");
   if (precision == MOFEM_PREC_F64_INT8 && !p->banded && (p->ps > kOzMaxK || p->pt > kOzMaxK))
     return fail(MOFEM_E_UNSUPPORTED, "prec_set_precision: INT8 transforms take padded widths up to 16384");
   if (p->banded && precision != MOFEM_PREC_F64)
@@ -963,7 +963,9 @@ void split_modes(int precision, int* mode) {
                 : precision == MOFEM_PREC_BF16X2 ? GEMM_BF16X2
                                                  : GEMM_BF16X3;
   for (int i = 0; i < 4; ++i) mode[i] = m;
-  if (precision == MOFEM_PREC_BF16_FWD) mode[0] = mode[1] = GEMM_BF16;  // forward in BF16
+  if (precision == MOFEM_PREC_BF16_FWD || precision == MOFEM_PREC_BF16_FWD_VS)
+    mode[0] = mode[1] = GEMM_BF16;  // forward in BF16
+  if (precision == MOFEM_PREC_BF16_FWD_VS) mode[2] = GEMM_BF16X2;  // V_s split, S plain
 }
 int split_trace_class(int gemm_mode) {
   return gemm_mode == GEMM_BF16 ? MOFEM_TRACE_GEMM_BF16
@@ -1095,7 +1097,7 @@ int prec_launch(mofem_prec_t p, const double* R, double* Z, long long stride, in
                    : p->precision == MOFEM_PREC_BF16     ? GEMM_BF16
                    : p->precision == MOFEM_PREC_BF16X2   ? GEMM_BF16X2
                    : p->precision == MOFEM_PREC_F64_INT8 ? GEMM_I8
-                                                         : GEMM_BF16X3;  // BF16X3, BF16_FWD: split branch
+                                                         : GEMM_BF16X3;  // BF16X3 and both forward-BF16 modes: split branch
   const int tcls = prec == GEMM_F64      ? MOFEM_TRACE_GEMM_F64
                    : prec == GEMM_F32    ? MOFEM_TRACE_GEMM_F32
                    : prec == GEMM_BF16   ? MOFEM_TRACE_GEMM_BF16
@@ -1235,11 +1237,15 @@ int prec_launch(mofem_prec_t p, const double* R, double* Z, long long stride, in
     // product mode of each transform G1..G4 and whether it reads its operands' lo halves
     int mode[4];
     split_modes(p->precision, mode);
+    // A two-product transform splits the data operand (exact-BF16 bases) or,
+    // in the first back transform of MOFEM_PREC_BF16_FWD_VS, the eigenbasis.
     const int data_is_a[4] = {1, 0, 0, 1};
-    auto a_lo = [&](int i) { return mode[i] == GEMM_BF16X3 || (mode[i] == GEMM_BF16X2 && data_is_a[i]); };
-    auto b_lo = [&](int i) { return mode[i] == GEMM_BF16X3 || (mode[i] == GEMM_BF16X2 && !data_is_a[i]); };
+    const bool basis_split = p->precision == MOFEM_PREC_BF16_FWD_VS;
+    auto split_a = [&](int i) { return basis_split ? !data_is_a[i] : (bool)data_is_a[i]; };
+    auto a_lo = [&](int i) { return mode[i] == GEMM_BF16X3 || (mode[i] == GEMM_BF16X2 && split_a(i)); };
+    auto b_lo = [&](int i) { return mode[i] == GEMM_BF16X3 || (mode[i] == GEMM_BF16X2 && !split_a(i)); };
     auto run = [&](int i, int omode) -> int {
-      g.data_is_a = data_is_a[i];
+      g.split_a = split_a(i);
       TraceScope trace(split_trace_class(mode[i]), items_done, s);
       return launch_gemm(g, mode[i], omode, batch, tile, s);
     };
@@ -1735,9 +1741,11 @@ extern "C" int mofem_pcg_solve(mofem_op_t op, mofem_prec_t prec, const double* R
       ex_prec += cnt[j];
     }
     trace_add_items(MOFEM_TRACE_BAND, ex_band - r.rec_band);
-    if (prec->precision == MOFEM_PREC_BF16_FWD) {
+    if (prec->precision == MOFEM_PREC_BF16_FWD || prec->precision == MOFEM_PREC_BF16_FWD_VS) {
+      const bool vs = prec->precision == MOFEM_PREC_BF16_FWD_VS;
       trace_add_items(MOFEM_TRACE_GEMM_BF16, 2.0 * (ex_prec - r.rec_prec));
-      trace_add_items(MOFEM_TRACE_GEMM_BF16X3, 2.0 * (ex_prec - r.rec_prec));
+      trace_add_items(MOFEM_TRACE_GEMM_BF16X3, (vs ? 1.0 : 2.0) * (ex_prec - r.rec_prec));
+      if (vs) trace_add_items(MOFEM_TRACE_GEMM_BF16X2, ex_prec - r.rec_prec);
     } else {
       trace_add_items(trace_class_of(prec), (prec->banded ? 2.0 : 4.0) * (ex_prec - r.rec_prec));
     }

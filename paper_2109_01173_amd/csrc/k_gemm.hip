@@ -18,9 +18,12 @@
 //   GEMM_BF16X3  v_mfma_f32_16x16x32_bf16 with split operands x = hi + lo
 //                (hi = bf16(x), lo = bf16(x - hi)); A B ~ Ah Bh + Ah Bl + Al Bh,
 //                FP32 accumulation, FP32-level accuracy.
-//   GEMM_BF16X2  the data operand split, the eigenbasis operand exactly
+//   GEMM_BF16X2  one operand split, the other taken in BF16: two products.
+//                The data operand split with the eigenbasis exactly
 //                representable in BF16 (the preconditioner is defined with
-//                the BF16-rounded basis): two products per transform.
+//                the BF16-rounded basis), or the eigenbasis split with plain
+//                BF16 data (the first back transform of the forward-BF16
+//                variant that rounds S).
 //   GEMM_BF16    the hi * hi product only.
 // A transform writes the lo half of a split output only when its consumer
 // reads it (c_lo set).
@@ -556,7 +559,7 @@ static void launch_mode(const GemmArgs& g, int prec, int batch, hipStream_t s) {
     hipLaunchKernelGGL((gemm_f32_kernel<OMODE, WT>), grid, dim3(256), 0, s, g);
   else if (prec == GEMM_BF16X3)
     hipLaunchKernelGGL((gemm_bf16_kernel<BF_X3, OMODE, 64, 2, WT>), grid, dim3(256), 0, s, g);
-  else if (prec == GEMM_BF16X2 && g.data_is_a)
+  else if (prec == GEMM_BF16X2 && g.split_a)
     hipLaunchKernelGGL((gemm_bf16_kernel<BF_X2A, OMODE, 64, 2, WT>), grid, dim3(256), 0, s, g);
   else if (prec == GEMM_BF16X2)
     hipLaunchKernelGGL((gemm_bf16_kernel<BF_X2B, OMODE, 64, 2, WT>), grid, dim3(256), 0, s, g);

@@ -99,7 +99,7 @@ struct GemmArgs {
   const double* item_scale;  // [batch] or null
   double out_scale;        // multiply the result (before the epilogue division)
   const int* active;
-  int data_is_a;           // GEMM_BF16X2: the split (data) operand is A (else B)
+  int split_a;             // GEMM_BF16X2: the split operand is A (else B)
   // GEMM_I8 (k_ozaki.hip): kOzSlices digit planes per operand and item,
   // [plane][pad_up(rows)][pad_up(K)] int8, a_stride / b_stride in bytes; row
   // exponents [pad_up(rows)] per item (stride 0 = shared)

@@ -31,7 +31,7 @@ E_ARG, E_HIP, E_NOMEM, E_BREAKDOWN, E_MAXIT, E_UNSUPPORTED, E_NOTFINITE, E_NUMER
     -1, -2, -3, -4, -5, -6, -7, -8)
 W_ONE, W_POLY, W_PROFILE, W_PROFILE_D, W_PROFILE_INV, W_PROFILE_D2L, W_CALLBACK = range(7)
 W_PPROFILE_D, W_PPROFILE_INV, W_PPROFILE_D2L = 7, 8, 9
-PREC_F64, PREC_F32, PREC_BF16, PREC_BF16X3, PREC_BF16X2, PREC_BF16_FWD, PREC_F64_INT8 = range(7)
+PREC_F64, PREC_F32, PREC_BF16, PREC_BF16X3, PREC_BF16X2, PREC_BF16_FWD, PREC_F64_INT8, PREC_BF16_FWD_VS = range(8)
 PCG_FLEXIBLE, PCG_ZERO_GUESS, PCG_TAU_STOP = 1, 2, 4
 KIN_NONE, KIN_DIB = 0, 1
 (TRACE_BAND, TRACE_GEMM_F64, TRACE_GEMM_BF16X3, TRACE_GEMM_BF16, TRACE_VEC, TRACE_GEMM_BF16X2, TRACE_GEMM_F32,

@@ -1,7 +1,9 @@
 """Parity at the headline size, in the launch configuration of the bench:
 P2 x-normal, n = 2049 (q = 2047), Dirichlet, gamma = 1, manufactured load
-plus noise, batch 16, forward-BF16 transforms, flexible MO-PCG to a relative
-residual of 1e-8 (128 x 128 transform tiles, 16-item batched launches).
+plus noise, batch 16, forward-BF16 transforms (the bench's variant that also
+rounds S to BF16 in the first back transform, and the one that splits it),
+flexible MO-PCG to a relative residual of 1e-8 (128 x 128 transform tiles,
+16-item batched launches).
 
 The oracle's operators are dense NumPy products (about a second per item at
 this size), so whole items 0 and 15 of the batch are compared: the load and
@@ -24,13 +26,14 @@ pytestmark = pytest.mark.gpu
 EPS = np.finfo(float).eps
 ITEMS = (0, 15)
 B = 16
+MIXED = ("BF16_FWD_VS", "BF16_FWD")   # the bench's mixed mode first
 
 
 @pytest.fixture(scope="module")
 def full():
     from paper_2109_01173_amd import mofem as mf
     from paper_2109_01173_amd.problems import XNormal
-    G = XNormal(2, 1024, "dirichlet", gamma=1.0, amp=GEOM_AMP, precision=mf.PREC_BF16_FWD)
+    G = XNormal(2, 1024, "dirichlet", gamma=1.0, amp=GEOM_AMP, precision=getattr(mf, "PREC_" + MIXED[0]))
     P = XNormalProblem(2, 1024, "dirichlet", L_profile, dL_profile, gamma=1.0)
     F = elliptic_batch(G.n, 1.0, B, sigma=1e-3, seed0=1234)
     S = SpectralPrec(*P.prec_pairs("sylv-matched"))   # the library's elliptic pencils
@@ -51,10 +54,11 @@ def test_fullsize_load_and_operator(full):
         assert np.all(np.abs(Y[b] - ref) <= bound), np.abs(Y[b] - ref).max()
 
 
-def test_fullsize_preconditioner(full):
+@pytest.mark.parametrize("mode", MIXED)
+def test_fullsize_preconditioner(full, mode):
     """FP64 transforms of the library's own preconditioner backward through
     the oracle's explicit single-term operator (items 0 and 15).  The
-    forward-BF16 transforms of the bench against the oracle's CPU emulation
+    forward-BF16 transforms (both variants) against the oracle's CPU emulation
     of that mode (oracle/precision.py) on every item of the batch, on a
     shared eigenbasis (the oracle's, handed to the library through
     mofem_prec_setup_eig): the GPU must reproduce the emulated rounding
@@ -70,7 +74,16 @@ def test_fullsize_preconditioner(full):
     preconditioner must then have the emulated error level (within a factor
     1.25) against the exact inverse.  (The error itself varies from item to
     item by a factor of about two: the few lowest modes, divided by the
-    smallest D, dominate Z.)"""
+    smallest D, dominate Z.)
+
+    The variant that also rounds S (the divided coefficients) to BF16 makes
+    the rounding pattern of those dominant modes depend on the FP32
+    summation order: the blocked and the exact-sum emulations differ by up
+    to 29 % of the error on one item, and the GPU's order, a third one,
+    lands as far from the blocked one on a few items.  For that mode every
+    item is held to the emulated error level (factor 1.25) and the median
+    item to the emulated pattern (AGREE_FRAC); the pattern is checked item
+    by item at q = 299 (tests/test_gpu_prec.py)."""
     from oracle import precision as em
     from paper_2109_01173_amd import mofem as mf
     from test_oracle_precision import AGREE_FRAC
@@ -79,28 +92,38 @@ def test_fullsize_preconditioner(full):
     G.prec.set_precision(mf.PREC_F64)
     try:
         Z64 = to_host(G.prec.apply(to_dev(R)))
+        G.prec.set_precision(getattr(mf, "PREC_" + mode))
+        Zown = to_host(G.prec.apply(to_dev(R)))
     finally:
-        G.prec.set_precision(mf.PREC_BF16_FWD)
-    Zown = to_host(G.prec.apply(to_dev(R)))
+        G.prec.set_precision(getattr(mf, "PREC_" + MIXED[0]))
     condD = np.abs(S.D).max() / np.abs(S.D).min()
     for b in ITEMS:
         assert rel(S.forward(Z64[b]), R[b]) < 50 * EPS * condD
-    shared = mf.Preconditioner.from_eigen(S.lam, S.Vs, S.mu, S.Vt, S.coeffs, precision=mf.PREC_BF16_FWD)
+    shared = mf.Preconditioner.from_eigen(S.lam, S.Vs, S.mu, S.Vt, S.coeffs, precision=getattr(mf, "PREC_" + mode))
     Zmx = to_host(shared.apply(to_dev(R)))
     del shared
-    emulate = em.prec_apply(S, em.MODES["BF16_FWD"], "f32")
-    emulate_exact = em.prec_apply(S, em.MODES["BF16_FWD"], "exact")
+    emulate = em.prec_apply(S, em.MODES[mode], "f32")
+    emulate_exact = em.prec_apply(S, em.MODES[mode], "exact")
+    ratios = []
     for b in range(B):
         Zx = S.apply(R[b])
         Zem = emulate(R[b])
         err_em = rel(Zem, Zx)
         d = rel(Zmx[b], Zem)
+        if mode == "BF16_FWD_VS":
+            assert rel(Zmx[b], Zx) <= 1.25 * err_em, (b, rel(Zmx[b], Zx), err_em)
+            ratios.append(d / err_em)
+            if b in ITEMS:
+                assert rel(Zown[b], Zx) <= 1.25 * err_em, (b, rel(Zown[b], Zx), err_em)
+            continue
         bar = AGREE_FRAC * err_em
         if d > bar:
             bar = max(bar, 2 * rel(emulate_exact(R[b]), Zem))
         assert d <= bar, (b, d, err_em, bar)
         if b in ITEMS:
             assert rel(Zown[b], Zx) <= 1.25 * err_em, (b, rel(Zown[b], Zx), err_em)
+    if ratios:
+        assert np.median(ratios) <= AGREE_FRAC, ratios
 
 
 @pytest.fixture(scope="module")
@@ -143,14 +166,19 @@ def _backward_under_oracle(G, P, F, Uh, b):
     return back, diff, scale
 
 
-def test_fullsize_solve(full, oracle_ref):
+@pytest.mark.parametrize("mode", MIXED)
+def test_fullsize_solve(full, oracle_ref, mode):
     import torch
     from paper_2109_01173_amd import mofem as mf
     G, P, F, S = full
     rhs = G.rhs_op.apply(to_dev(F))
     U = torch.empty_like(rhs)
-    its, relres, _ = mf.pcg_solve(G.op, G.prec, rhs, U, tol=1e-8, maxit=300,
-                                  flags=mf.PCG_FLEXIBLE | mf.PCG_ZERO_GUESS)
+    G.prec.set_precision(getattr(mf, "PREC_" + mode))
+    try:
+        its, relres, _ = mf.pcg_solve(G.op, G.prec, rhs, U, tol=1e-8, maxit=300,
+                                      flags=mf.PCG_FLEXIBLE | mf.PCG_ZERO_GUESS)
+    finally:
+        G.prec.set_precision(getattr(mf, "PREC_" + MIXED[0]))
     assert np.all(relres <= 1e-8) and its.max() <= 30
     Uh = to_host(U)
     for b in ITEMS:
@@ -179,7 +207,7 @@ def test_fullsize_solve_fp64(full, oracle_ref, precision):
     try:
         its, relres, _ = mf.pcg_solve(G.op, G.prec, rhs, U, tol=1e-10, maxit=300, flags=mf.PCG_ZERO_GUESS)
     finally:
-        G.prec.set_precision(mf.PREC_BF16_FWD)
+        G.prec.set_precision(getattr(mf, "PREC_" + MIXED[0]))
     assert np.all(relres <= 1e-10) and its.max() <= 40
     Uh = to_host(U)
     for b in ITEMS:

@@ -16,7 +16,8 @@ pytestmark = pytest.mark.gpu
 SHAPES = [(1, 60, 2), (2, 30, 1), (3, 20, 3), (4, 15, 2), (2, 40, 2)]   # (k, m, batch): q = 59 x4, then q = 79
 
 
-@pytest.mark.parametrize("precision,flags,tol,bar", [("F64", 0, 1e-11, 1e-9), ("BF16_FWD", 1, 1e-9, 1e-7)])
+@pytest.mark.parametrize("precision,flags,tol,bar", [("F64", 0, 1e-11, 1e-9), ("BF16_FWD", 1, 1e-9, 1e-7),
+                                                ("BF16_FWD_VS", 1, 1e-9, 1e-7)])
 def test_grouped_solve_vs_oracle(precision, flags, tol, bar):
     import torch
     from paper_2109_01173_amd import mofem as mf

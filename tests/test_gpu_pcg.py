@@ -44,7 +44,7 @@ def test_elliptic_small_fp64():
 
 @pytest.mark.parametrize("precision,flags,tol,bar", [
     ("F64", 0, 1e-10, 1e-10), ("F32", 1, 1e-8, 1e-8), ("BF16X3", 1, 1e-8, 1e-8), ("BF16X2", 1, 1e-8, 1e-8),
-    ("BF16", 1, 1e-8, 1e-8), ("BF16_FWD", 1, 1e-8, 1e-8)])
+    ("BF16", 1, 1e-8, 1e-8), ("BF16_FWD", 1, 1e-8, 1e-8), ("BF16_FWD_VS", 1, 1e-8, 1e-8)])
 def test_p2_batch(precision, flags, tol, bar):
     from paper_2109_01173_amd import mofem as mf
     k, m = 2, 150

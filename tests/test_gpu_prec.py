@@ -45,7 +45,7 @@ def test_prec_fp64(k, m, bc):
     _ = mf
 
 
-@pytest.mark.parametrize("precision", ["F32", "BF16X3", "BF16X2", "BF16", "BF16_FWD"])
+@pytest.mark.parametrize("precision", ["F32", "BF16X3", "BF16X2", "BF16", "BF16_FWD", "BF16_FWD_VS"])
 def test_prec_low_precision_vs_emulation(precision):
     """Each low-precision transform mode against the oracle's CPU emulation of
     that mode (oracle/precision.py: RNE BF16 / FP32 rounding of the operands,
@@ -96,7 +96,8 @@ def test_prec_tiny_and_errors():
         G.prec.set_precision(99)
 
 
-@pytest.mark.parametrize("precision", ["F64", "F32", "BF16X3", "BF16X2", "BF16", "BF16_FWD", "F64_INT8"])
+@pytest.mark.parametrize("precision", ["F64", "F32", "BF16X3", "BF16X2", "BF16", "BF16_FWD", "BF16_FWD_VS",
+                                       "F64_INT8"])
 def test_block_tiles_agree_and_tuner(precision):
     """Both block tiles of the transforms compute the same products in the same
     k order (BF16 on 128-row tiles loads through LDS directly, on 64-row tiles

@@ -81,7 +81,7 @@ AGREE_FRAC = 0.05
 LEVEL_FACTOR = 2.0
 
 
-@pytest.mark.parametrize("mode", ["F32", "BF16", "BF16X3", "BF16X2", "BF16_FWD"])
+@pytest.mark.parametrize("mode", ["F32", "BF16", "BF16X3", "BF16X2", "BF16_FWD", "BF16_FWD_VS"])
 def test_accumulation_order_sensitivity(mode):
     P = XNormalProblem(2, 150, "dirichlet", L_profile, dL_profile, gamma=1.0)
     S = SpectralPrec(*P.prec_pairs("sylv"))
