@@ -296,17 +296,22 @@ def radial_spectrum_peak(np, U):
     return int(spec[1:].argmax() + 1)
 
 
-def heat_leg(mf, torch, np, nsteps, eager_steps):
+HEAT_PREC = {"f32": "PREC_F32", "bf16x3": "PREC_BF16X3", "bf16fwdvs": "PREC_BF16_FWD_VS"}
+
+
+def heat_leg(mf, torch, np, nsteps, eager_steps, prec_name="f32"):
     """Heat equation (eqs. (89)-(96)): P4 on the x-normal domain, Neumann,
-    n = 2049, d = 0.1, tau = 1e-3, U0 ~ U[0,1) (seed 42), f = 0; FP32
-    transforms (FP32 operands and accumulation) with the FP64 residual and
-    recurrence, flexible PCG to rel 1e-10 per step.  `eager_steps` steps
+    n = 2049, d = 0.1, tau = 1e-3, U0 ~ U[0,1) (seed 42), f = 0; transforms
+    in prec_name (f32: FP32 operands and accumulation; bf16x3: split BF16;
+    bf16fwdvs: plain BF16 forward, S rounded to BF16, last back transform
+    split) with the FP64 residual and recurrence, flexible PCG to rel 1e-10
+    per step.  `eager_steps` steps
     through mofem_imex_step (they also fix the graph's iteration budget),
     then `nsteps` steps replayed from the captured HIP graph."""
     from paper_2109_01173_amd.problems import XNormal
     from workloads import heat_initial
     t0 = time.perf_counter()
-    G = XNormal(4, 512, "neumann", gamma=0.0, imex=True, precision=mf.PREC_F32)
+    G = XNormal(4, 512, "neumann", gamma=0.0, imex=True, precision=getattr(mf, HEAT_PREC[prec_name]))
     setup = time.perf_counter() - t0
     st = torch.from_numpy(heat_initial(G.q, seed=42)[None]).cuda()
     mk = lambda: mf.Imex(G.op, G.prec, G.mass, 1e-3, [0.1], tol=1e-10, maxit=200, flags=mf.PCG_FLEXIBLE)
@@ -332,19 +337,20 @@ def heat_leg(mf, torch, np, nsteps, eager_steps):
     gi, gst, grr = g.result(raise_on_error=False)
     mass1 = float(G.mass.apply(st).sum())
     out = {"imex_heat_p4": {
-        "workload": "heat P4 x-normal, Neumann, n=2049, d=0.1, tau=1e-3, U0 ~ U[0,1) seed 42, FP32 transforms, "
+        "workload": "heat P4 x-normal, Neumann, n=2049, d=0.1, tau=1e-3, U0 ~ U[0,1) seed 42, %s transforms, "
                     "FP64 residual, rel 1e-10 per step, %d graph-replayed steps after %d eager steps"
-                    % (nsteps, eager_steps),
+                    % (prec_name, nsteps, eager_steps),
         "graph_steps_per_s": round(nsteps / dtg, 3), "steps": nsteps, "graph_iteration_budget": budget,
         "graph_max_iterations": int(gi.max()), "graph_status_ok": bool(np.all(gst == 0)),
         "last_step_relres": float(np.max(grr)),
         "eager_steps_per_s": round(eager_steps / dt, 3), "eager_iterations_per_step": round(float(np.mean(its)), 2),
         "eager_iterations": its,
-        "transforms": "f32", "setup_s": round(setup, 2),
+        "transforms": prec_name, "setup_s": round(setup, 2),
         "mass_drift_rel": abs(mass1 - mass0) / abs(mass0),
         "time_reached": round(1e-3 * (nsteps + eager_steps), 4)}}
-    log("heat P4 (FP32 transforms): %.1f steps/s replayed (%d steps, budget %d, max %d iterations), %.1f eager; "
-        "mass drift %.2e" % (nsteps / dtg, nsteps, budget, gi.max(), eager_steps / dt, abs(mass1 - mass0) / abs(mass0)))
+    log("heat P4 (%s transforms): %.1f steps/s replayed (%d steps, budget %d, max %d iterations), %.1f eager; "
+        "mass drift %.2e" % (prec_name, nsteps / dtg, nsteps, budget, gi.max(), eager_steps / dt,
+                             abs(mass1 - mass0) / abs(mass0)))
     del g
     return out
 
@@ -589,6 +595,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--heat-steps", type=int, default=1000,
                     help="graph-replayed steps of the heat P4 leg (0 skips it)")
+    ap.add_argument("--heat-prec", default="f32,bf16fwdvs",
+                    help="comma list of transform precisions of the heat P4 leg (%s); the first is the "
+                         "configured one, the others are reported beside it" % ", ".join(sorted(HEAT_PREC)))
     ap.add_argument("--dib-steps", type=int, default=10000,
                     help="steps of each DIB leg (10^4 reaches T = 100; 0 skips them)")
     ap.add_argument("--adjoint", type=int, default=1, help="run the gradient leg (0 skips it)")
@@ -601,6 +610,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
+    bad = [hp for hp in args.heat_prec.split(",") if hp not in HEAT_PREC]
+    if bad:
+        ap.error("--heat-prec: unknown precision(s) %s" % ", ".join(bad))
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs every instance batch on a single "
               "MI355X; a multi-GPU run is not provided (use --gpus 1).", file=sys.stderr)
@@ -742,7 +754,9 @@ def main():
 
     extra = {}
     if args.heat_steps > 0:
-        extra.update(heat_leg(mf, torch, np, args.heat_steps, max(args.imex_steps, 2)))
+        for i, hp in enumerate(args.heat_prec.split(",")):
+            r = heat_leg(mf, torch, np, args.heat_steps, max(args.imex_steps, 2), hp)
+            extra.update(r if i == 0 else {"imex_heat_p4_" + hp: r["imex_heat_p4"]})
     if args.dib_steps > 0:
         extra.update(dib_leg(mf, torch, np, args.dib_steps))
     if args.adjoint > 0:

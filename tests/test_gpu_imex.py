@@ -196,15 +196,17 @@ def test_dib_turing_pattern_to_T100():
     assert eta.var() > 1e-4   # a pattern formed (the equilibrium is unstable)
 
 
-def test_heat_p4_full_size_fp32_transforms():
+@pytest.mark.parametrize("precision", ["F32", "BF16_FWD_VS"])
+def test_heat_p4_full_size(precision):
     """The heat workload at its configured size (P4, Neumann, n = 2049, d = 0.1,
-    tau = 1e-3, U0 ~ U[0,1) seed 42) with the FP32 transforms it names and the
+    tau = 1e-3, U0 ~ U[0,1) seed 42) with the FP32 transforms it names, or the
+    forward-BF16 transforms that round S (the bench's heat leg), and the
     flexible PCG to rel 1e-10 per step: two steps against the oracle's steps
     (spectral MO-PCG on its own dense operators to a recurrence residual of
     1e-13) at rel 1e-10, plus the discrete mass invariant."""
     from paper_2109_01173_amd import mofem as mf
     k, m, d, tau = 4, 512, 0.1, 1e-3
-    G = gpu_xnormal(k, m, "neumann", 0.0, imex=True, precision=mf.PREC_F32)
+    G = gpu_xnormal(k, m, "neumann", 0.0, imex=True, precision=getattr(mf, "PREC_" + precision))
     P = oracle_xnormal(k, m, "neumann", 0.0)
     assert G.q == 2049
     U0 = heat_initial(P.q, seed=42)
