@@ -93,6 +93,32 @@ def test_imex_graph_heat_and_budget_too_small():
     assert status[0] == 0
 
 
+def test_imex_graph_heat_forward_bf16_rounding_s():
+    """Heat steps replayed from a graph with the forward-BF16 transforms that
+    round S (flexible PCG, as in the bench's second heat leg): the replay
+    reproduces the eager steps, the masked iterations after convergence change
+    nothing, and both follow the oracle's steps to the solve tolerance."""
+    import torch
+    from paper_2109_01173_amd import mofem as mf
+    G = gpu_xnormal(2, 16, "neumann", 0.0, imex=True, precision=mf.PREC_BF16_FWD_VS)
+    U0 = heat_initial(G.q, seed=42)
+    s_eager, s_graph = to_dev(U0[None]), to_dev(U0[None])
+    mk = lambda: mf.Imex(G.op, G.prec, G.mass, 1e-3, [0.1], tol=1e-11, maxit=60, flags=mf.PCG_FLEXIBLE)
+    eager = mk()
+    g = mf.ImexGraph(mk(), s_graph, 1, iters_per_step=40)
+    its = [int(eager.step(s_eager, 1)[0]) for _ in range(3)]
+    g.launch(3)
+    torch.cuda.synchronize()
+    assert rel(to_host(s_graph), to_host(s_eager)) <= 1e-14
+    max_its, status, _ = g.result()
+    assert status[0] == 0 and max_its[0] == max(its)
+    P = oracle_xnormal(2, 16, "neumann", 0.0)
+    U = U0.copy()
+    for _ in range(3):
+        U = imex.imex_step(P, U, 1e-3, 0.1, oracle_solver(P, "sylv-imex"))
+    assert rel(to_host(s_graph)[0], U) < 1e-9
+
+
 def test_pcg_async_uneven_shapes_on_two_streams():
     import torch
     from paper_2109_01173_amd import mofem as mf
